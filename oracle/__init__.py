@@ -1,0 +1,177 @@
+"""ctypes wrapper of the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE: imported only by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The device library never imports, links or
+calls anything here, and this package never touches the device library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OPS_ALL = 0x1F
+NOT_A_MOVE = 0xFF
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into liboracle.so (next to the source)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-pthread", "-shared", "-fPIC",
+                               "-Wall", "-Wno-unused-function", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        lib.oracle_eval.restype = ctypes.c_int
+        lib.oracle_eval.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i32, P, P, P, P, P]
+        lib.oracle_apply.restype = ctypes.c_int
+        lib.oracle_apply.argtypes = [i32, P, P, i64, i32, i32, P, P, u32]
+        lib.oracle_cost.restype = i64
+        lib.oracle_cost.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P]
+        lib.oracle_check_full.restype = i64
+        lib.oracle_check_full.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P, u32, i64]
+        lib.oracle_ls.restype = ctypes.c_int
+        lib.oracle_ls.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i32, i32, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _inst_args(inst):
+    D = np.ascontiguousarray(inst.dist, dtype=np.int32)
+    nd = np.ascontiguousarray(inst.node4, dtype=np.int32)
+    return D, nd
+
+
+@dataclass
+class Best:
+    found: bool
+    delta: int
+    id: int
+    moves: int
+
+
+def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
+                       dump: bool = False):
+    """Best admissible move of N(S) (and, with dump=True, per-move delta and
+    feasibility arrays indexed by move id; non-moves keep delta 0 and feas
+    0xFF)."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
+    Q = inst.n + off.shape[0] - 1
+    dd = df = None
+    if dump:
+        dd = np.zeros(20 * Q * Q, np.int32)
+        df = np.full(20 * Q * Q, NOT_A_MOVE, np.uint8)
+    bd = np.zeros(1, np.int64)
+    bid = np.zeros(1, np.uint32)
+    mv = np.zeros(1, np.int64)
+    found = lib.oracle_eval(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                            off.shape[0] - 1, _p(off), _p(cust), op_mask, threads,
+                            _p(dd) if dump else None, _p(df) if dump else None,
+                            _p(bd), _p(bid), _p(mv))
+    best = Best(bool(found), int(bd[0]), int(bid[0]), int(mv[0]))
+    if dump:
+        return best, dd, df
+    return best
+
+
+class Routes:
+    """Routes in CSR form (offsets[R+1], customers[n])."""
+
+    def __init__(self, offsets, customers):
+        self.offsets = np.asarray(offsets, dtype=np.int32)
+        self.customers = np.asarray(customers, dtype=np.int32)
+
+    @property
+    def R(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    def routes(self):
+        o = self.offsets
+        return [self.customers[o[r]:o[r + 1]].tolist() for r in range(self.R)]
+
+
+def apply_move(inst, sol, move_id: int):
+    """New routes after applying move_id; raises ValueError for a non-move."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.array(sol.offsets, dtype=np.int32)
+    cust = np.array(sol.customers, dtype=np.int32)
+    rc = lib.oracle_apply(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                          off.shape[0] - 1, _p(off), _p(cust), move_id)
+    if rc != 0:
+        raise ValueError("not a move of N(S): %d" % move_id)
+    return Routes(off, cust)
+
+
+def cost(inst, sol):
+    """(total distance, #capacity-violating routes, #window-violating routes)."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
+    cb = np.zeros(1, np.int32)
+    tb = np.zeros(1, np.int32)
+    c = lib.oracle_cost(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                        off.shape[0] - 1, _p(off), _p(cust), _p(cb), _p(tb))
+    return int(c), int(cb[0]), int(tb[0])
+
+
+def check_full(inst, sol, dump_delta, dump_feas, op_mask: int = OPS_ALL,
+               sample_every: int = 1) -> int:
+    """Number of moves whose delta differs from a whole-solution recompute."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
+    return int(lib.oracle_check_full(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                     off.shape[0] - 1, _p(off), _p(cust), _p(dump_delta),
+                                     _p(dump_feas), op_mask, sample_every))
+
+
+def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
+                 threads: int = 0):
+    """Best-improvement local search.  Returns (final Solution, ids, deltas,
+    total moves evaluated)."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.array(sol.offsets, dtype=np.int32)
+    cust = np.array(sol.customers, dtype=np.int32)
+    ids = np.zeros(max(1, max_steps), np.uint32)
+    deltas = np.zeros(max(1, max_steps), np.int32)
+    mv = np.zeros(1, np.int64)
+    steps = lib.oracle_ls(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                          off.shape[0] - 1, _p(off), _p(cust), op_mask, max_steps, threads,
+                          _p(ids), _p(deltas), _p(mv))
+    return Routes(off, cust), ids[:steps].copy(), deltas[:steps].copy(), int(mv[0])
+
+
+def decode(Q: int, move_id: int):
+    """(op, k, a, b) of a move id."""
+    qq = Q * Q
+    opk, rem = divmod(int(move_id), qq)
+    return opk // 4, opk % 4, rem // Q, rem % Q

@@ -1,0 +1,605 @@
+/*
+ * CPU oracle for full-neighbourhood move evaluation in VRP local search.
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use this file.  It shares no code, header, table or
+ * helper with the device library.
+ *
+ * What it computes is the plain definition of the result (no blocking, no
+ * incremental attributes, no concatenation algebra):
+ *
+ *   for every move m of the canonical move space N(S)
+ *       build the touched routes of S' = m(S) explicitly (erase / insert /
+ *       reverse / exchange on node lists),
+ *       recompute each touched route from scratch:
+ *         distance  = sum of c_ij over consecutive nodes, both depot edges
+ *                     included (the objective with mu1 = 0, mu2 = 1; Section 2,
+ *                     eq. objective),
+ *         load      = sum of delivery demands, feasible iff <= capacity
+ *                     (Section 2; Section 4.3, load concatenation with p = 0),
+ *         windows   = forward simulation: leave the depot at e_0, wait when
+ *                     early, infeasible when arriving after l_i, back at the
+ *                     depot by l_0 (Section 2),
+ *       delta(m) = sum of new distances - sum of old distances of the touched
+ *                  route slots,
+ *       feas(m)  = bit0 capacity of every touched route, bit1 windows of
+ *                  every touched route (always 1 when windows are off),
+ *   best = lexicographic minimum of (delta, id) over moves with feas == 3
+ *          (Section 5.3.4, eq. scoring_tensor / eq. mask / eq. min_obj with
+ *          the score equal to the distance delta and an infinite score for
+ *          infeasible moves; lowest id breaks ties).
+ *
+ * Operators (Section 4.1, Fig. 2; the move space is the reading recorded in
+ * the design notes):
+ *   op 0 RELOCATE  k=1  a = customer u, b = any ref v of another route:
+ *                       u leaves its route and is inserted right after v.
+ *   op 1 SWAP      k=1  a < b customers (same or different routes):
+ *                       u and v exchange places.
+ *   op 2 2OPT*     k=0  a < b refs of different routes: the two tails after
+ *                       them are exchanged; each head keeps its slot.
+ *   op 3 2OPT      k=0  a < b customers of one route: the part between them
+ *                       (inclusive) is reversed.
+ *   op 4 OR-OPT    k=1..3  a = customer starting a k-node segment, b = ref of
+ *                       the same route not inside [pred(a), last of segment]:
+ *                       the segment is moved, in its orientation, to right
+ *                       after b.
+ * Refs: customer c -> c - 1; start depot of route r -> n + r; Q = n + R.
+ * Move id = ((op * 4 + k) * Q + a) * Q + b.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+typedef struct {
+    int n;
+    const int32_t *D;     /* (n+1) x (n+1), row-major */
+    const int32_t *node4; /* (n+1) x {demand, e, l, s} */
+    int64_t cap;
+    int has_tw;
+} Inst;
+
+typedef struct {
+    int R;
+    const int32_t *off;  /* R + 1 */
+    const int32_t *cust; /* n */
+} Sol;
+
+typedef struct {
+    int64_t delta;
+    uint32_t id;
+    int32_t feas;
+    int32_t found;
+} Best;
+
+static inline int64_t dist(const Inst *I, int i, int j) {
+    return I->D[(int64_t)i * (I->n + 1) + j];
+}
+
+/* Distance of the closed route 0, c[0], ..., c[L-1], 0. */
+static int64_t route_distance(const Inst *I, const int32_t *c, int L) {
+    int64_t d = 0;
+    int prev = 0;
+    for (int i = 0; i < L; i++) {
+        d += dist(I, prev, c[i]);
+        prev = c[i];
+    }
+    return d + dist(I, prev, 0);
+}
+
+static int64_t route_load(const Inst *I, const int32_t *c, int L) {
+    int64_t q = 0;
+    for (int i = 0; i < L; i++) q += I->node4[4 * c[i] + 0];
+    return q;
+}
+
+/* Hard time windows, simulated forward (Section 2). */
+static int route_windows_ok(const Inst *I, const int32_t *c, int L) {
+    if (!I->has_tw) return 1;
+    const int32_t *nd = I->node4;
+    int64_t t = nd[1]; /* service start at the depot = e_0 */
+    int prev = 0;
+    for (int i = 0; i < L; i++) {
+        int x = c[i];
+        int64_t arrive = t + nd[4 * prev + 3] + dist(I, prev, x);
+        if (arrive > nd[4 * x + 2]) return 0;
+        t = arrive > nd[4 * x + 1] ? arrive : nd[4 * x + 1];
+        prev = x;
+    }
+    int64_t back = t + nd[4 * prev + 3] + dist(I, prev, 0);
+    return back <= nd[2];
+}
+
+static int route_feas(const Inst *I, const int32_t *c, int L) {
+    int f = 0;
+    if (route_load(I, c, L) <= I->cap) f |= 1;
+    if (route_windows_ok(I, c, L)) f |= 2;
+    return f;
+}
+
+/* ------------------------------------------------------------------ moves */
+
+typedef struct {
+    int op, k, a, b;
+} Move;
+
+static uint32_t move_id(int Q, int op, int k, int a, int b) {
+    return (uint32_t)((((uint64_t)(op * 4 + k) * Q + a) * Q) + b);
+}
+
+static Move move_decode(int Q, uint32_t id) {
+    Move m;
+    uint64_t qq = (uint64_t)Q * Q;
+    uint64_t opk = id / qq, rem = id % qq;
+    m.op = (int)(opk / 4);
+    m.k = (int)(opk % 4);
+    m.a = (int)(rem / Q);
+    m.b = (int)(rem % Q);
+    return m;
+}
+
+/* Where every node sits: route and 1-based position (0 = start depot). */
+typedef struct {
+    int n, R, Q;
+    int32_t *route_of; /* by customer id, 1..n */
+    int32_t *pos_of;
+    int64_t *rdist;    /* current distance per route */
+} Index;
+
+static void index_build(const Inst *I, const Sol *S, Index *X) {
+    X->n = I->n;
+    X->R = S->R;
+    X->Q = I->n + S->R;
+    X->route_of = calloc((size_t)I->n + 1, sizeof(int32_t));
+    X->pos_of = calloc((size_t)I->n + 1, sizeof(int32_t));
+    X->rdist = calloc((size_t)S->R + 1, sizeof(int64_t));
+    for (int r = 0; r < S->R; r++) {
+        int L = S->off[r + 1] - S->off[r];
+        for (int p = 0; p < L; p++) {
+            int c = S->cust[S->off[r] + p];
+            X->route_of[c] = r;
+            X->pos_of[c] = p + 1;
+        }
+        X->rdist[r] = route_distance(I, S->cust + S->off[r], L);
+    }
+}
+
+static void index_free(Index *X) {
+    free(X->route_of);
+    free(X->pos_of);
+    free(X->rdist);
+}
+
+/* Route and position of a ref. */
+static void ref_where(const Index *X, int ref, int *r, int *p) {
+    if (ref < X->n) {
+        *r = X->route_of[ref + 1];
+        *p = X->pos_of[ref + 1];
+    } else {
+        *r = ref - X->n;
+        *p = 0;
+    }
+}
+
+/* Literal list edits.  Each writes the new customer list(s) of the touched
+ * route slot(s) and returns how many slots it touched (1 or 2).  out1 gets
+ * slot *r1, out2 gets slot *r2.  Buffers hold at least n entries. */
+static int find_node(const int32_t *c, int L, int node) {
+    for (int i = 0; i < L; i++)
+        if (c[i] == node) return i;
+    return -1;
+}
+
+static int edit_move(const Inst *I, const Sol *S, const Index *X, Move m,
+                     int *r1, int32_t *out1, int *L1, int *r2, int32_t *out2, int *L2) {
+    const int n = I->n;
+    int ra, pa, rb, pb;
+    ref_where(X, m.a, &ra, &pa);
+    ref_where(X, m.b, &rb, &pb);
+    const int32_t *A = S->cust + S->off[ra];
+    const int LA = S->off[ra + 1] - S->off[ra];
+    const int32_t *B = S->cust + S->off[rb];
+    const int LB = S->off[rb + 1] - S->off[rb];
+    *r1 = ra;
+    *r2 = rb;
+    if (m.op == 0) { /* RELOCATE u after v, other route */
+        int u = m.a + 1;
+        int l = 0;
+        for (int i = 0; i < LA; i++)
+            if (A[i] != u) out1[l++] = A[i];
+        *L1 = l;
+        l = 0;
+        if (m.b >= n) out2[l++] = u; /* after the start depot */
+        for (int i = 0; i < LB; i++) {
+            out2[l++] = B[i];
+            if (B[i] == m.b + 1) out2[l++] = u;
+        }
+        *L2 = l;
+        return 2;
+    }
+    if (m.op == 1) { /* SWAP u and v */
+        int u = m.a + 1, v = m.b + 1;
+        if (ra == rb) {
+            memcpy(out1, A, sizeof(int32_t) * LA);
+            int iu = find_node(out1, LA, u), iv = find_node(out1, LA, v);
+            out1[iu] = v;
+            out1[iv] = u;
+            *L1 = LA;
+            return 1;
+        }
+        memcpy(out1, A, sizeof(int32_t) * LA);
+        memcpy(out2, B, sizeof(int32_t) * LB);
+        out1[find_node(out1, LA, u)] = v;
+        out2[find_node(out2, LB, v)] = u;
+        *L1 = LA;
+        *L2 = LB;
+        return 2;
+    }
+    if (m.op == 2) { /* 2OPT*: head(a) + tail after b ; head(b) + tail after a */
+        int l = 0;
+        for (int i = 0; i < pa; i++) out1[l++] = A[i];
+        for (int i = pb; i < LB; i++) out1[l++] = B[i];
+        *L1 = l;
+        l = 0;
+        for (int i = 0; i < pb; i++) out2[l++] = B[i];
+        for (int i = pa; i < LA; i++) out2[l++] = A[i];
+        *L2 = l;
+        return 2;
+    }
+    if (m.op == 3) { /* 2OPT: reverse positions lo..hi */
+        int lo = pa < pb ? pa : pb, hi = pa < pb ? pb : pa;
+        memcpy(out1, A, sizeof(int32_t) * LA);
+        for (int i = lo - 1, j = hi - 1; i < j; i++, j--) {
+            int32_t t = out1[i];
+            out1[i] = out1[j];
+            out1[j] = t;
+        }
+        *L1 = LA;
+        return 1;
+    }
+    /* op 4 OR-OPT: remove segment of k starting at a, reinsert after b */
+    {
+        int k = m.k;
+        int32_t seg[3];
+        for (int q = 0; q < k; q++) seg[q] = A[pa - 1 + q];
+        int32_t rest[LA > 0 ? LA : 1];
+        int l = 0;
+        for (int i = 0; i < LA; i++)
+            if (i < pa - 1 || i >= pa - 1 + k) rest[l++] = A[i];
+        int o = 0;
+        if (m.b >= n)
+            for (int q = 0; q < k; q++) out1[o++] = seg[q];
+        for (int i = 0; i < l; i++) {
+            out1[o++] = rest[i];
+            if (rest[i] == m.b + 1)
+                for (int q = 0; q < k; q++) out1[o++] = seg[q];
+        }
+        *L1 = o;
+        return 1;
+    }
+}
+
+/* --------------------------------------------------------- enumeration --- */
+
+typedef struct {
+    const Inst *I;
+    const Sol *S;
+    const Index *X;
+    uint32_t op_mask;
+    int32_t *dump_delta;
+    uint8_t *dump_feas;
+    int64_t *count;      /* per-thread move counts */
+    Best *best;          /* per-thread */
+    int ntasks;
+    int next_task;       /* atomic */
+    int nthreads;
+} Ctx;
+
+typedef struct {
+    Ctx *C;
+    int tid;
+} Arg;
+
+static void consider(Ctx *C, int tid, Move m, int32_t *b1, int32_t *b2) {
+    const Inst *I = C->I;
+    int r1, r2, L1, L2;
+    int touched = edit_move(I, C->S, C->X, m, &r1, b1, &L1, &r2, b2, &L2);
+    int64_t delta = route_distance(I, b1, L1) - C->X->rdist[r1];
+    int feas = route_feas(I, b1, L1);
+    if (touched == 2) {
+        delta += route_distance(I, b2, L2) - C->X->rdist[r2];
+        feas &= route_feas(I, b2, L2);
+    }
+    uint32_t id = move_id(C->X->Q, m.op, m.k, m.a, m.b);
+    if (C->dump_delta) C->dump_delta[id] = (int32_t)delta;
+    if (C->dump_feas) C->dump_feas[id] = (uint8_t)feas;
+    C->count[tid]++;
+    if (feas == 3) {
+        Best *bt = &C->best[tid];
+        if (!bt->found || delta < bt->delta || (delta == bt->delta && id < bt->id)) {
+            bt->found = 1;
+            bt->delta = delta;
+            bt->id = id;
+            bt->feas = feas;
+        }
+    }
+}
+
+/* Task t covers operator op = t / n and first ref a = t % n (customers), or
+ * for 2OPT* any first ref; OR-OPT tasks run over (k, a). */
+static void run_task(Ctx *C, int tid, int t, int32_t *b1, int32_t *b2) {
+    const int n = C->I->n, Q = C->X->Q, R = C->X->R;
+    const Sol *S = C->S;
+    const Index *X = C->X;
+    int op = t / Q, a = t % Q;
+    if (op > 6) return;
+    if (op == 0 && (C->op_mask & 1) && a < n) {
+        int ra = X->route_of[a + 1];
+        for (int b = 0; b < Q; b++) {
+            int rb, pb;
+            ref_where(X, b, &rb, &pb);
+            if (rb == ra) continue;
+            consider(C, tid, (Move){0, 1, a, b}, b1, b2);
+        }
+    } else if (op == 1 && (C->op_mask & 2) && a < n) {
+        for (int b = a + 1; b < n; b++) consider(C, tid, (Move){1, 1, a, b}, b1, b2);
+    } else if (op == 2 && (C->op_mask & 4)) {
+        int ra, pa;
+        ref_where(X, a, &ra, &pa);
+        for (int b = a + 1; b < Q; b++) {
+            int rb, pb;
+            ref_where(X, b, &rb, &pb);
+            if (rb == ra) continue;
+            consider(C, tid, (Move){2, 0, a, b}, b1, b2);
+        }
+    } else if (op == 3 && (C->op_mask & 8) && a < n) {
+        int ra = X->route_of[a + 1];
+        for (int b = a + 1; b < n; b++)
+            if (X->route_of[b + 1] == ra) consider(C, tid, (Move){3, 0, a, b}, b1, b2);
+    } else if (op >= 4 && (C->op_mask & 16) && a < n) {
+        int k = op - 3; /* 1..3 */
+        int r = X->route_of[a + 1], i = X->pos_of[a + 1];
+        int L = S->off[r + 1] - S->off[r];
+        if (i + k - 1 > L) return;
+        for (int j = 0; j <= L; j++) {
+            if (j >= i - 1 && j <= i + k - 1) continue;
+            int b = j == 0 ? n + r : S->cust[S->off[r] + j - 1] - 1;
+            consider(C, tid, (Move){4, k, a, b}, b1, b2);
+        }
+    }
+    (void)R;
+}
+
+static void *worker(void *p) {
+    Arg *A = (Arg *)p;
+    Ctx *C = A->C;
+    int32_t *b1 = malloc(sizeof(int32_t) * (C->I->n + 4));
+    int32_t *b2 = malloc(sizeof(int32_t) * (C->I->n + 4));
+    for (;;) {
+        int t = __atomic_fetch_add(&C->next_task, 1, __ATOMIC_RELAXED);
+        if (t >= C->ntasks) break;
+        run_task(C, A->tid, t, b1, b2);
+    }
+    free(b1);
+    free(b2);
+    return NULL;
+}
+
+static int resolve_threads(int nthreads) {
+    if (nthreads > 0) return nthreads;
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    return c > 0 ? (int)c : 1;
+}
+
+/* ------------------------------------------------------------ exported --- */
+
+/* Evaluate N(S) restricted to op_mask.  Returns 1 if an admissible move
+ * exists (written to *best_*), 0 otherwise.  Optional dumps are indexed by
+ * move id and must hold 20 * Q * Q entries; entries that are not moves are
+ * left untouched.  *moves receives |N(S)| for the enabled operators. */
+int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
+    Inst I = {n, D, node4, cap, has_tw};
+    Sol S = {R, off, cust};
+    Index X;
+    index_build(&I, &S, &X);
+    int T = resolve_threads(nthreads);
+    Ctx C;
+    memset(&C, 0, sizeof C);
+    C.I = &I;
+    C.S = &S;
+    C.X = &X;
+    C.op_mask = op_mask;
+    C.dump_delta = dump_delta;
+    C.dump_feas = dump_feas;
+    C.nthreads = T;
+    C.ntasks = 7 * X.Q;
+    C.best = calloc((size_t)T, sizeof(Best));
+    C.count = calloc((size_t)T, sizeof(int64_t));
+    pthread_t *th = malloc(sizeof(pthread_t) * T);
+    Arg *args = malloc(sizeof(Arg) * T);
+    for (int t = 0; t < T; t++) {
+        args[t].C = &C;
+        args[t].tid = t;
+        if (T == 1)
+            worker(&args[0]);
+        else
+            pthread_create(&th[t], NULL, worker, &args[t]);
+    }
+    if (T > 1)
+        for (int t = 0; t < T; t++) pthread_join(th[t], NULL);
+    Best b = {0, 0, 0, 0};
+    int64_t total = 0;
+    for (int t = 0; t < T; t++) {
+        total += C.count[t];
+        Best *x = &C.best[t];
+        if (!x->found) continue;
+        if (!b.found || x->delta < b.delta || (x->delta == b.delta && x->id < b.id)) b = *x;
+    }
+    if (moves) *moves = total;
+    if (b.found) {
+        *best_delta = b.delta;
+        *best_id = b.id;
+    }
+    free(th);
+    free(args);
+    free(C.best);
+    free(C.count);
+    index_free(&X);
+    return b.found;
+}
+
+/* Apply move `id` to (off, cust) in place.  Returns 0 on success, -1 if the
+ * id does not name a move of N(S). */
+int oracle_apply(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                 int R, int32_t *off, int32_t *cust, uint32_t id) {
+    Inst I = {n, D, node4, cap, has_tw};
+    Sol S = {R, off, cust};
+    Index X;
+    index_build(&I, &S, &X);
+    int Q = X.Q;
+    Move m = move_decode(Q, id);
+    int ok = 1;
+    if (m.a >= Q || m.b >= Q || m.op > 4) ok = 0;
+    int ra = 0, pa = 0, rb = 0, pb = 0;
+    if (ok) {
+        ref_where(&X, m.a, &ra, &pa);
+        ref_where(&X, m.b, &rb, &pb);
+        int La = off[ra + 1] - off[ra];
+        switch (m.op) {
+        case 0: ok = m.k == 1 && m.a < n && rb != ra; break;
+        case 1: ok = m.k == 1 && m.a < m.b && m.b < n; break;
+        case 2: ok = m.k == 0 && m.a < m.b && ra != rb; break;
+        case 3: ok = m.k == 0 && m.a < m.b && m.b < n && ra == rb; break;
+        case 4:
+            ok = m.k >= 1 && m.k <= 3 && m.a < n && ra == rb && pa + m.k - 1 <= La &&
+                 !(pb >= pa - 1 && pb <= pa + m.k - 1);
+            break;
+        }
+    }
+    if (!ok) {
+        index_free(&X);
+        return -1;
+    }
+    int32_t *b1 = malloc(sizeof(int32_t) * (n + 4));
+    int32_t *b2 = malloc(sizeof(int32_t) * (n + 4));
+    int r1, r2, L1, L2;
+    int touched = edit_move(&I, &S, &X, m, &r1, b1, &L1, &r2, b2, &L2);
+    /* Rebuild the whole CSR with the touched slots replaced. */
+    int32_t *noff = malloc(sizeof(int32_t) * (R + 1));
+    int32_t *ncust = malloc(sizeof(int32_t) * (n + 1));
+    int w = 0;
+    for (int r = 0; r < R; r++) {
+        noff[r] = w;
+        if (r == r1) {
+            memcpy(ncust + w, b1, sizeof(int32_t) * L1);
+            w += L1;
+        } else if (touched == 2 && r == r2) {
+            memcpy(ncust + w, b2, sizeof(int32_t) * L2);
+            w += L2;
+        } else {
+            int L = off[r + 1] - off[r];
+            memcpy(ncust + w, cust + off[r], sizeof(int32_t) * L);
+            w += L;
+        }
+    }
+    noff[R] = w;
+    memcpy(off, noff, sizeof(int32_t) * (R + 1));
+    memcpy(cust, ncust, sizeof(int32_t) * n);
+    free(noff);
+    free(ncust);
+    free(b1);
+    free(b2);
+    index_free(&X);
+    return 0;
+}
+
+/* Total distance of S (eq. objective, mu1 = 0, mu2 = 1) and the number of
+ * routes that violate capacity (*cap_bad) or windows (*tw_bad). */
+int64_t oracle_cost(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                    int R, const int32_t *off, const int32_t *cust, int *cap_bad, int *tw_bad) {
+    Inst I = {n, D, node4, cap, has_tw};
+    int64_t c = 0;
+    int cb = 0, tb = 0;
+    for (int r = 0; r < R; r++) {
+        int L = off[r + 1] - off[r];
+        c += route_distance(&I, cust + off[r], L);
+        int f = route_feas(&I, cust + off[r], L);
+        if (!(f & 1)) cb++;
+        if (!(f & 2)) tb++;
+    }
+    if (cap_bad) *cap_bad = cb;
+    if (tw_bad) *tw_bad = tb;
+    return c;
+}
+
+/* Check mode: for every move, build the whole S' and recompute its full
+ * cost; count moves where cost(S') - cost(S) differs from the dumped delta.
+ * dump_delta must come from oracle_eval on the same (S, op_mask). */
+int64_t oracle_check_full(int n, const int32_t *D, const int32_t *node4, int64_t cap,
+                          int has_tw, int R, const int32_t *off, const int32_t *cust,
+                          const int32_t *dump_delta, const uint8_t *dump_feas,
+                          uint32_t op_mask, int64_t sample_every) {
+    Inst I = {n, D, node4, cap, has_tw};
+    Sol S = {R, off, cust};
+    Index X;
+    index_build(&I, &S, &X);
+    int64_t base = oracle_cost(n, D, node4, cap, has_tw, R, off, cust, NULL, NULL);
+    int Q = X.Q;
+    uint64_t total = 20ull * Q * Q;
+    int32_t *o2 = malloc(sizeof(int32_t) * (R + 1));
+    int32_t *c2 = malloc(sizeof(int32_t) * (n + 1));
+    int64_t bad = 0, seen = 0;
+    for (uint64_t id = 0; id < total; id++) {
+        if (dump_feas[id] == 0xFF) continue; /* not a move */
+        Move m = move_decode(Q, (uint32_t)id);
+        if (!((op_mask >> m.op) & 1)) continue;
+        if (sample_every > 1 && (seen++ % sample_every) != 0) continue;
+        memcpy(o2, off, sizeof(int32_t) * (R + 1));
+        memcpy(c2, cust, sizeof(int32_t) * n);
+        if (oracle_apply(n, D, node4, cap, has_tw, R, o2, c2, (uint32_t)id) != 0) {
+            bad++;
+            continue;
+        }
+        int64_t after = oracle_cost(n, D, node4, cap, has_tw, R, o2, c2, NULL, NULL);
+        if (after - base != dump_delta[id]) bad++;
+    }
+    free(o2);
+    free(c2);
+    index_free(&X);
+    return bad;
+}
+
+typedef struct {
+    uint32_t id;
+    int32_t delta;
+} Step;
+
+/* Best-improvement local search (the loop of the feasible-and-infeasible
+ * search, Appendix Alg. A2, with hard feasibility): evaluate, accept the best
+ * move while its delta is negative, stop at a local optimum or after
+ * max_steps.  Writes the accepted moves to `traj` (max_steps entries) and
+ * updates (off, cust) in place.  Returns the number of accepted moves. */
+int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+              int R, int32_t *off, int32_t *cust, uint32_t op_mask, int max_steps,
+              int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
+    int steps = 0;
+    int64_t mv_sum = 0;
+    while (steps < max_steps) {
+        int64_t bd = 0, mv = 0;
+        uint32_t bid = 0;
+        int found = oracle_eval(n, D, node4, cap, has_tw, R, off, cust, op_mask, nthreads,
+                                NULL, NULL, &bd, &bid, &mv);
+        mv_sum += mv;
+        if (!found || bd >= 0) break;
+        if (oracle_apply(n, D, node4, cap, has_tw, R, off, cust, bid) != 0) break;
+        traj_id[steps] = bid;
+        traj_delta[steps] = (int32_t)bd;
+        steps++;
+    }
+    if (moves_total) *moves_total = mv_sum;
+    return steps;
+}

@@ -1,0 +1,206 @@
+/*
+ * tga.h — C ABI of the MI355X (gfx950) full-neighbourhood move evaluator for
+ * VRP local search.
+ *
+ * The library evaluates, for one solution (or a batch of solutions) held on
+ * the GPU, every move of the canonical neighbourhood N(S) built from the
+ * paper's operators (Section 4.1, Fig. 2: relocate, swap, 2-opt*, 2-opt, and
+ * or-opt as the intra-route segment relocation), gives each move its exact
+ * integer distance delta and a capacity / time-window feasibility mask,
+ * reduces to the best admissible move (Section 5.3.4, eq. scoring_tensor,
+ * eq. mask, eq. min_obj: infeasible moves score +infinity, argmin with the
+ * lowest move id winning ties), applies it and rebuilds the route attributes
+ * (Section 5.3.5) on the device.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All integers are int32 unless stated.  Every value on the path is an
+ *   integer; no floating point is used.
+ * - Return value: TGA_OK (0) on success, TGA_ENOMOVE (1) when no move is
+ *   admissible (not an error), a negative TGA_E* code on failure.  On failure
+ *   tga_last_error() returns a message (thread-local, valid until the next
+ *   call on the same thread).  Validation happens before any device work.
+ * - Device memory is owned by the caller (typically PyTorch tensors).  The
+ *   library borrows the buffers for the lifetime of the handle that received
+ *   them and never frees them.  Host arrays are read during the call only.
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).  A
+ *   handle must be used from one stream at a time.
+ * - Instance data: node 0 is the depot, customers are 1..n.  Travel time is
+ *   the distance (one matrix).  The matrix must be symmetric with a zero
+ *   diagonal (2-opt reversal relies on symmetry, as Section 4.1 requires).
+ * - Refs: customer c is ref c-1; the start depot of route slot r is ref n+r;
+ *   Q = n + R.  Move id = ((op*4 + k)*Q + a)*Q + b with (a, b) refs:
+ *     op 0 RELOCATE k=1: customer a moves right after ref b (other route)
+ *     op 1 SWAP     k=1: customers a < b exchange places (any routes)
+ *     op 2 2OPT*    k=0: refs a < b in different routes exchange their tails
+ *     op 3 2OPT     k=0: customers a < b of one route: reverse a..b
+ *     op 4 OR-OPT   k=1..3: the k-segment starting at customer a moves,
+ *                   orientation kept, right after ref b of the same route
+ *   Q <= 14654 keeps every id below 2^32.
+ * - Objective: total distance (eq. objective with mu1 = 0, mu2 = 1).
+ *   feas bit0: every touched route respects the capacity; bit1: every touched
+ *   route respects the windows (depart the depot at e_0, wait when early,
+ *   infeasible when arriving after l_i, back by l_0; Section 2).  A move is
+ *   admissible when feas == 3.
+ */
+#ifndef TGA_H
+#define TGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TGA_OK = 0,
+    TGA_ENOMOVE = 1,   /* no admissible move; not an error */
+    TGA_EINVAL = -1,   /* bad argument (null pointer, bad partition, bad move) */
+    TGA_ERANGE = -2,   /* a size or value outside the supported range */
+    TGA_ENOMEM = -3,   /* workspace too small */
+    TGA_EDEVICE = -4,  /* a HIP runtime call failed */
+    TGA_ESTALE = -5    /* move record not produced for this solution version */
+};
+
+enum {
+    TGA_OP_RELOCATE = 1u << 0,
+    TGA_OP_SWAP = 1u << 1,
+    TGA_OP_2OPTSTAR = 1u << 2,
+    TGA_OP_2OPT = 1u << 3,
+    TGA_OP_OROPT = 1u << 4,
+    TGA_OP_ALL = 0x1Fu
+};
+
+#define TGA_MAX_Q 14654
+
+typedef struct tga_instance *tga_instance_t;
+typedef struct tga_solution *tga_solution_t;
+typedef struct tga_batch *tga_batch_t;
+
+/* Best-move record (32 bytes).  op/k/a/b decode `id`; feas is 3 for a
+ * returned best move; version is the solution version it was computed on. */
+typedef struct {
+    int32_t op, k, a, b, delta;
+    uint32_t feas, id, version;
+} tga_move_t;
+
+/* Device workspace sizes (bytes) for an instance of n customers and for a
+ * solution with R route slots.  Returns 0 when n or R is out of range. */
+size_t tga_instance_workspace_bytes(int32_t n);
+size_t tga_solution_workspace_bytes(int32_t n, int32_t R);
+
+/* Section 5.1 (the solution tensor lives on the GPU) and Section 2 (instance
+ * data).  Registers an instance.
+ *   dist   device, (n+1)*(n+1) int32, row-major, symmetric, zero diagonal,
+ *          0 <= d < 2^24.
+ *   node4  device, (n+1) x {demand, e, l, s} int32; node 0 is the depot with
+ *          demand 0 and s = 0; 0 <= e <= l; s >= 0.
+ *   capacity  vehicle capacity (>= 0).   has_tw  0 = CVRP, 1 = VRPTW.
+ *   ws     device workspace of tga_instance_workspace_bytes(n) bytes.
+ * Values are checked on the device before the handle is returned
+ * (TGA_EINVAL for asymmetry / negative values, TGA_ERANGE when sums along a
+ * route could leave the exact int32 range).  Synchronises `stream`. */
+int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *node4, int32_t capacity,
+                      int32_t has_tw, void *ws, size_t ws_bytes, void *stream,
+                      tga_instance_t *out);
+
+/* Section 5.1 and Alg. A2 (initialise the solution tensor from S), Section
+ * 5.2 and the positional tensors of Section 5.3.1 (route id and position of
+ * every node).  Uploads a solution and builds its attribute arrays.
+ *   offsets    host, R+1, offsets[0] = 0, nondecreasing, offsets[R] = n.
+ *   customers  host, n; route r holds customers[offsets[r] .. offsets[r+1]);
+ *              must be a permutation of 1..n.  Empty routes are allowed.
+ *   ws         device workspace of tga_solution_workspace_bytes(n, R).
+ * Requires n + R <= TGA_MAX_Q.  Synchronises `stream`. */
+int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                     const int32_t *customers, void *ws, size_t ws_bytes, void *stream,
+                     tga_solution_t *out);
+
+/* Sections 5.3.1-5.3.4: evaluate every move of N(S) whose operator bit is in
+ * op_mask and return the best admissible one in *best (host).  Returns
+ * TGA_ENOMOVE when none is admissible (then *best is zeroed).
+ * Optional per-move dump (testing): dump_delta (int32) and dump_feas (uint8)
+ * are device arrays of 20*Q*Q entries indexed by move id; the library writes
+ * only entries that are moves, the caller pre-fills the rest.  Both NULL, or
+ * both set.  Synchronises `stream` (the returned record is the best-move
+ * latency). */
+int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best,
+                          int32_t *dump_delta, uint8_t *dump_feas, void *stream);
+
+/* Section 5.3.5 and Alg. A2: apply a move to the solution on the device and
+ * rebuild every attribute.  The move need not be improving or admissible.
+ * Returns TGA_ESTALE if move->version is not the solution's current version
+ * and TGA_EINVAL if move->id is not a move of N(S).  On success the version
+ * increases by one and *new_cost (nullable) receives the total distance.
+ * Synchronises `stream`. */
+int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream);
+
+/* Alg. A2 run on the device: repeat {evaluate, apply the best move if its
+ * delta < 0} until a local optimum or max_steps accepted moves.  The host
+ * does not inspect any step.  *steps_done (nullable) = accepted moves,
+ * *moves_evaluated (nullable) = sum of |N(S_t)| over the evaluations run,
+ * *cost (nullable) = final distance.  Synchronises `stream`. */
+int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_steps, int32_t *steps_done,
+               int64_t *moves_evaluated, int64_t *cost, void *stream);
+
+/* Read the current solution back: offsets (host, R+1), customers (host, n),
+ * *cost (nullable) = total distance.  Synchronises `stream`. */
+int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, int64_t *cost,
+                     void *stream);
+
+/* |N(S)| per operator for the current solution (5 entries, host). */
+int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream);
+
+/* Current version counter of a solution (number of applied moves). */
+uint32_t tga_solution_version(tga_solution_t sol);
+
+int tga_free_solution(tga_solution_t sol);
+int tga_free_instance(tga_instance_t inst);
+const char *tga_last_error(void);
+
+/* Compute units of the current device and the LDS bytes one evaluation
+ * workgroup may use (which bounds n: a workgroup stages at least three
+ * distance rows of 4(n+1) bytes). */
+int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes);
+
+/* ---------------------------------------------------------------- batch --
+ * Many independent solutions (instances of different sizes, CVRP and VRPTW
+ * mixed) evaluated in one persistent launch per step; the step loop is
+ * captured once into a HIP graph and replayed.  A solution may belong to at
+ * most one batch and must not be used through the single-solution calls
+ * while the batch exists. */
+
+/* Device workspace bytes for a batch of `count` solutions. */
+size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t count);
+
+/* tile_rows: rows per inter-route work item (0 = choose from n);
+ * col_split: column segments per row block (0 = choose).  Both only change
+ * the schedule, never a result. */
+int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t tile_rows,
+                     int32_t col_split, void *ws, size_t ws_bytes, void *stream,
+                     tga_batch_t *out);
+
+/* Run `steps` local-search steps on every solution of the batch (solutions
+ * already at a local optimum skip their work).  use_graph != 0 captures the
+ * step loop into a HIP graph on first use and replays it.  Per solution
+ * (host arrays of `count`, nullable): accepted moves, moves evaluated, cost. */
+int tga_batch_ls_run(tga_batch_t b, uint32_t op_mask, int32_t steps, int32_t use_graph,
+                     int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
+                     void *stream);
+
+/* One evaluation of every solution in the batch (no apply); best moves to a
+ * host array of `count` records; per-solution status to status (nullable). */
+int tga_batch_eval(tga_batch_t b, uint32_t op_mask, tga_move_t *best, int32_t *status,
+                   void *stream);
+
+/* Clear the per-solution "converged" flags and step counters. */
+int tga_batch_reset(tga_batch_t b, void *stream);
+
+int tga_batch_free(tga_batch_t b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TGA_H */

@@ -1,0 +1,800 @@
+// Host runtime of the C ABI declared in include/tga.h: argument validation,
+// workspace layout on caller-owned device memory, work-item lists, kernel
+// launches, HIP-graph capture of the batched step loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tga.h"
+#include "kernels.hip"
+
+using namespace tga;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local tga_move_t *g_pin = nullptr;  // pinned staging, 4 KiB per host thread
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(TGA_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+int pinned(void **p) {
+    if (!g_pin) {
+        hipError_t e = hipHostMalloc((void **)&g_pin, 4096, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g_pin = nullptr;
+            return fail(TGA_EDEVICE, "hipHostMalloc: %s", hipGetErrorString(e));
+        }
+    }
+    *p = g_pin;
+    return TGA_OK;
+}
+
+struct DevProps {
+    int ok = 0, cus = 0, max_lds = 0, attr_ok = 0;
+};
+
+DevProps g_props;
+std::mutex g_props_mu;
+
+int props(DevProps *out) {
+    std::lock_guard<std::mutex> lk(g_props_mu);
+    if (!g_props.ok) {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&g_props.cus, hipDeviceAttributeMultiprocessorCount, dev));
+        int lds = 0;
+        HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        // Let the evaluation kernels use the device's full LDS for dynamic
+        // shared memory (their static LDS is a few bytes).  If the runtime
+        // refuses, stay within the 64 KiB every launch may use.
+        const int dyn = lds - 1024;
+        const void *fns[] = {(const void *)k_eval_inter<false, false>, (const void *)k_eval_inter<true, false>,
+                             (const void *)k_eval_inter<false, true>, (const void *)k_eval_inter<true, true>,
+                             (const void *)k_eval_mixed};
+        bool ok = dyn > 65536;
+        for (const void *f : fns)
+            if (ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) ok = false;
+        (void)hipGetLastError();  // do not leave a refused attribute as the sticky error
+        g_props.attr_ok = ok;
+        g_props.max_lds = ok ? dyn : std::min(lds, 65536);
+        g_props.ok = 1;
+    }
+    *out = g_props;
+    return TGA_OK;
+}
+
+constexpr size_t kLdsBudget = 64 * 1024;  // default per-item LDS: two workgroups per CU
+
+size_t row_bytes(int np1) { return (size_t)np1 * 4 + 64; }
+
+int default_tile_rows(int np1) {
+    long t = (long)(kLdsBudget / row_bytes(np1)) - 2;
+    return (int)std::max(1L, std::min(32L, t));
+}
+
+size_t item_lds(int np1, int tile_rows) { return (size_t)(tile_rows + 2) * row_bytes(np1); }
+
+struct SolLayout {
+    size_t desc, a4, b4, t4, w4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, best_key, rec,
+        state, acc, items, intra, total;
+    int max_items;
+};
+
+SolLayout sol_layout(int n, int R) {
+    SolLayout L;
+    const size_t Q = (size_t)n + R, S = Q + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.desc = take(sizeof(SolDev));
+    L.a4 = take(16 * S);
+    L.b4 = take(16 * S);
+    L.t4 = take(16 * S);
+    L.w4 = take(16 * S);
+    L.pdist = take(4 * S);
+    L.ref2slot = take(4 * Q);
+    L.roff = take(4 * (R + 1));
+    L.rdist = take(4 * std::max(R, 1));
+    L.nr_alt = take(8 * S);
+    L.roff_alt = take(4 * (R + 1));
+    L.best_key = take(8);
+    L.rec = take(32);
+    L.state = take(4 * 16);
+    L.acc = take(8 * kAccCount);
+    L.max_items = (int)(8 * Q + 8);
+    L.items = take(sizeof(InterItem) * L.max_items);
+    L.intra = take(sizeof(IntraItem) * std::max(R, 1));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct tga_instance {
+    int32_t n, cap, has_tw;
+    const int32_t *D;
+    const int4 *node4;
+    int32_t maxD, maxE, maxL, maxS, maxDem;
+};
+
+struct tga_solution {
+    tga_instance *inst;
+    int32_t n, R, Q;
+    SolDev h;          // host copy of the descriptor
+    SolDev *d;         // device copy (1 entry)
+    InterItem *items;  // device
+    int nitems;
+    IntraItem *intra;  // device
+    int nintra;
+    int tile_rows, parts;
+    size_t lds;
+    uint32_t version;
+    int in_batch;
+};
+
+struct tga_batch {
+    std::vector<tga_solution *> sols;
+    SolDev *d;
+    InterItem *items;
+    int nitems;
+    IntraItem *intra;
+    int nintra;
+    int *queue;  // [0] inter queue head, [1] intra queue head
+    size_t lds;
+    int grid_inter, grid_intra;
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    int graph_steps;
+    uint32_t graph_mask;
+    hipStream_t graph_stream;
+};
+
+// ----------------------------------------------------------------- misc ----
+
+extern "C" const char *tga_last_error(void) { return g_err.c_str(); }
+
+extern "C" int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes) {
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    if (compute_units) *compute_units = P.cus;
+    if (max_lds_bytes) *max_lds_bytes = P.max_lds;
+    return TGA_OK;
+}
+
+extern "C" size_t tga_instance_workspace_bytes(int32_t n) {
+    if (n < 1 || n > TGA_MAX_Q) return 0;
+    return 256;
+}
+
+extern "C" size_t tga_solution_workspace_bytes(int32_t n, int32_t R) {
+    if (n < 1 || R < 1 || (int64_t)n + R > TGA_MAX_Q) return 0;
+    return sol_layout(n, R).total;
+}
+
+// ------------------------------------------------------------- instance ----
+
+extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *node4,
+                                 int32_t capacity, int32_t has_tw, void *ws, size_t ws_bytes,
+                                 void *stream, tga_instance_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!dist || !node4 || !ws) return fail(TGA_EINVAL, "null device pointer");
+    if (n < 1 || n > TGA_MAX_Q - 1) return fail(TGA_ERANGE, "n = %d outside [1, %d]", n, TGA_MAX_Q - 1);
+    if (capacity < 0 || capacity >= (1 << 30)) return fail(TGA_ERANGE, "capacity %d", capacity);
+    if (has_tw != 0 && has_tw != 1) return fail(TGA_EINVAL, "has_tw must be 0 or 1");
+    if (ws_bytes < tga_instance_workspace_bytes(n)) return fail(TGA_ENOMEM, "instance workspace too small");
+    if (((uintptr_t)node4) & 15) return fail(TGA_EINVAL, "node4 must be 16-byte aligned");
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int np1 = n + 1;
+    int32_t *chk = (int32_t *)ws;
+    k_zero_i32<<<1, 64, 0, st>>>(chk, 8);
+    const int tiles = (np1 + 31) / 32;
+    k_check_dist<<<dim3(tiles, tiles), 256, 0, st>>>(dist, np1, chk);
+    k_check_nodes<<<(np1 + 255) / 256, 256, 0, st>>>((const int4 *)node4, np1, has_tw, chk);
+    HIPCHK(hipGetLastError());
+    void *pin;
+    if ((rc = pinned(&pin))) return rc;
+    HIPCHK(hipMemcpyAsync(pin, chk, 32, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t r[8];
+    memcpy(r, pin, 32);
+    if (r[0] & 1) return fail(TGA_EINVAL, "distance outside [0, 2^24)");
+    if (r[0] & 2) return fail(TGA_EINVAL, "distance matrix is not symmetric");
+    if (r[0] & 4) return fail(TGA_EINVAL, "distance matrix has a nonzero diagonal");
+    if (r[0] & 8) return fail(TGA_EINVAL, "bad node data (negative, e > l, or depot demand/service != 0)");
+    const int64_t maxD = r[1], maxE = r[2], maxL = r[3], maxS = r[4], maxDem = r[5];
+    if ((int64_t)n * maxDem >= (1 << 30)) return fail(TGA_ERANGE, "total demand may exceed 2^30");
+    if (has_tw && (int64_t)np1 * (maxS + maxD) + maxL + maxE >= (1 << 28))
+        return fail(TGA_ERANGE, "route durations may exceed 2^28");
+    tga_instance *I = new tga_instance;
+    I->n = n;
+    I->cap = capacity;
+    I->has_tw = has_tw;
+    I->D = dist;
+    I->node4 = (const int4 *)node4;
+    I->maxD = (int32_t)maxD;
+    I->maxE = (int32_t)maxE;
+    I->maxL = (int32_t)maxL;
+    I->maxS = (int32_t)maxS;
+    I->maxDem = (int32_t)maxDem;
+    *out = I;
+    return TGA_OK;
+}
+
+extern "C" int tga_free_instance(tga_instance_t inst) {
+    delete inst;
+    return TGA_OK;
+}
+
+// ------------------------------------------------------------- solution ----
+
+static void build_plain_items(tga_solution *S, std::vector<InterItem> &items,
+                              std::vector<IntraItem> &intra, int sol_index, int parts) {
+    const int Q = S->Q, tr = S->tile_rows;
+    for (int s0 = 0; s0 < Q; s0 += tr)
+        for (int p = 0; p < parts; ++p)
+            items.push_back(InterItem{sol_index, s0, std::min(Q, s0 + tr), p | (parts << 16)});
+    for (int r = 0; r < S->R; ++r) intra.push_back(IntraItem{sol_index, r});
+}
+
+extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                                const int32_t *customers, void *ws, size_t ws_bytes, void *stream,
+                                tga_solution_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!inst || !offsets || !customers || !ws) return fail(TGA_EINVAL, "null argument");
+    const int n = inst->n;
+    if (R < 1) return fail(TGA_ERANGE, "R = %d < 1", R);
+    if ((int64_t)n + R > TGA_MAX_Q) return fail(TGA_ERANGE, "n + R = %lld > %d", (long long)n + R, TGA_MAX_Q);
+    if ((int64_t)(n + R + 1) * inst->maxD >= (1 << 30)) return fail(TGA_ERANGE, "total distance may exceed 2^30");
+    if (offsets[0] != 0 || offsets[R] != n) return fail(TGA_EINVAL, "offsets must start at 0 and end at n");
+    for (int r = 0; r < R; ++r)
+        if (offsets[r + 1] < offsets[r]) return fail(TGA_EINVAL, "offsets decrease at route %d", r);
+    std::vector<char> seen(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const int c = customers[i];
+        if (c < 1 || c > n || seen[c]) return fail(TGA_EINVAL, "customers is not a permutation of 1..n (at %d)", i);
+        seen[c] = 1;
+    }
+    const SolLayout L = sol_layout(n, R);
+    if (ws_bytes < L.total) return fail(TGA_ENOMEM, "solution workspace %zu < %zu", ws_bytes, L.total);
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    const int Q = n + R, np1 = n + 1;
+    tga_solution *S = new tga_solution();
+    S->inst = inst;
+    S->n = n;
+    S->R = R;
+    S->Q = Q;
+    S->tile_rows = default_tile_rows(np1);
+    S->lds = item_lds(np1, S->tile_rows);
+    if (S->lds > (size_t)P.max_lds) {
+        delete S;
+        return fail(TGA_ERANGE, "n = %d needs %zu bytes of LDS per workgroup (device: %d)", n,
+                    item_lds(np1, 1), P.max_lds);
+    }
+    char *base = (char *)ws;
+    SolDev &h = S->h;
+    memset(&h, 0, sizeof h);
+    h.D = inst->D;
+    h.node4 = inst->node4;
+    h.n = n;
+    h.np1 = np1;
+    h.cap = inst->cap;
+    h.has_tw = inst->has_tw;
+    h.R = R;
+    h.Q = Q;
+    h.tile_rows = S->tile_rows;
+    h.a4 = (int4 *)(base + L.a4);
+    h.b4 = (int4 *)(base + L.b4);
+    h.t4 = (int4 *)(base + L.t4);
+    h.w4 = (int4 *)(base + L.w4);
+    h.pdist = (int32_t *)(base + L.pdist);
+    h.ref2slot = (int32_t *)(base + L.ref2slot);
+    h.roff = (int32_t *)(base + L.roff);
+    h.rdist = (int32_t *)(base + L.rdist);
+    h.nr_alt = (int2 *)(base + L.nr_alt);
+    h.roff_alt = (int32_t *)(base + L.roff_alt);
+    h.best_key = (unsigned long long *)(base + L.best_key);
+    h.rec = (int32_t *)(base + L.rec);
+    h.state = (int32_t *)(base + L.state);
+    h.acc = (long long *)(base + L.acc);
+    S->d = (SolDev *)(base + L.desc);
+    S->items = (InterItem *)(base + L.items);
+    S->intra = (IntraItem *)(base + L.intra);
+
+    // host-side layout: slots route-major with the start depot first
+    std::vector<int2> nr(Q + 1);
+    std::vector<int32_t> roff(R + 1);
+    int s = 0;
+    for (int r = 0; r < R; ++r) {
+        roff[r] = s;
+        nr[s++] = make_int2(0, r);
+        for (int i = offsets[r]; i < offsets[r + 1]; ++i) nr[s++] = make_int2(customers[i], r);
+    }
+    roff[R] = s;
+    nr[Q] = make_int2(0, R);
+    const int nrb = (Q + S->tile_rows - 1) / S->tile_rows;
+    S->parts = std::max(1, std::min(4, (2 * P.cus + nrb - 1) / nrb));
+    std::vector<InterItem> items;
+    std::vector<IntraItem> intra;
+    build_plain_items(S, items, intra, 0, S->parts);
+    S->nitems = (int)items.size();
+    S->nintra = (int)intra.size();
+    if (S->nitems > L.max_items) {
+        delete S;
+        return fail(TGA_ERANGE, "too many work items");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> state(16, 0);
+    std::vector<long long> acc(kAccCount, 0);
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(S->d, &h, sizeof h);
+    if (e == hipSuccess) e = up(h.nr_alt, nr.data(), sizeof(int2) * (Q + 1));
+    if (e == hipSuccess) e = up(h.roff_alt, roff.data(), sizeof(int32_t) * (R + 1));
+    if (e == hipSuccess) e = up(h.state, state.data(), sizeof(int32_t) * 16);
+    if (e == hipSuccess) e = up(h.acc, acc.data(), sizeof(long long) * kAccCount);
+    if (e == hipSuccess) e = up(S->items, items.data(), sizeof(InterItem) * items.size());
+    if (e == hipSuccess) e = up(S->intra, intra.data(), sizeof(IntraItem) * intra.size());
+    if (e == hipSuccess) {
+        k_build<<<1, kApplyThreads, 0, st>>>(S->d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete S;
+        return fail(TGA_EDEVICE, "set_solution: %s", hipGetErrorString(e));
+    }
+    *out = S;
+    return TGA_OK;
+}
+
+extern "C" int tga_free_solution(tga_solution_t sol) {
+    delete sol;
+    return TGA_OK;
+}
+
+extern "C" uint32_t tga_solution_version(tga_solution_t sol) { return sol ? sol->version : 0; }
+
+static void launch_eval(const SolDev *d, const InterItem *items, int nitems, const IntraItem *intra,
+                        int nintra, int has_tw, uint32_t op_mask, size_t lds, int grid_inter,
+                        int32_t *dd, uint8_t *df, hipStream_t st) {
+    const bool dump = dd != nullptr;
+    if ((op_mask & 7) && nitems > 0) {
+        const int grid = std::max(1, std::min(nitems, grid_inter));
+        if (has_tw) {
+            if (dump)
+                k_eval_inter<true, true><<<grid, kInterThreads, lds, st>>>(d, items, nitems, op_mask, dd, df);
+            else
+                k_eval_inter<true, false><<<grid, kInterThreads, lds, st>>>(d, items, nitems, op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_inter<false, true><<<grid, kInterThreads, lds, st>>>(d, items, nitems, op_mask, dd, df);
+            else
+                k_eval_inter<false, false><<<grid, kInterThreads, lds, st>>>(d, items, nitems, op_mask, dd, df);
+        }
+    }
+    if ((op_mask & (2 | 8 | 16)) && nintra > 0) {
+        const int grid = (nintra + 3) / 4;
+        if (has_tw) {
+            if (dump)
+                k_eval_intra<true, true><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+            else
+                k_eval_intra<true, false><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_intra<false, true><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+            else
+                k_eval_intra<false, false><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+        }
+    }
+}
+
+static void to_move(const int32_t *rec, tga_move_t *m) {
+    m->op = rec[0];
+    m->k = rec[1];
+    m->a = rec[2];
+    m->b = rec[3];
+    m->delta = rec[4];
+    m->feas = (uint32_t)rec[5];
+    m->id = (uint32_t)rec[6];
+    m->version = (uint32_t)rec[7];
+}
+
+extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best,
+                                     int32_t *dump_delta, uint8_t *dump_feas, void *stream) {
+    if (!sol || !best) return fail(TGA_EINVAL, "null argument");
+    if ((dump_delta == nullptr) != (dump_feas == nullptr))
+        return fail(TGA_EINVAL, "dump_delta and dump_feas must both be set or both be null");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    hipStream_t st = (hipStream_t)stream;
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    void *pin;
+    if ((rc = pinned(&pin))) return rc;
+    launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
+                sol->lds, sol->nitems, dump_delta, dump_feas, st);
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(pin, sol->h.rec, 32, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char *)pin + 32, sol->h.state, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int32_t *rec = (const int32_t *)pin;
+    const int32_t status = ((const int32_t *)pin)[8 + kStStatus];
+    if (status == 1) {
+        memset(best, 0, sizeof *best);
+        best->version = sol->version;
+        return TGA_ENOMOVE;
+    }
+    to_move(rec, best);
+    best->version = sol->version;
+    return TGA_OK;
+}
+
+extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream) {
+    if (!sol || !move) return fail(TGA_EINVAL, "null argument");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    if (move->version != sol->version)
+        return fail(TGA_ESTALE, "move version %u != solution version %u", move->version, sol->version);
+    const uint64_t qq = (uint64_t)sol->Q * sol->Q;
+    if ((uint64_t)move->id >= 20 * qq) return fail(TGA_EINVAL, "move id %u out of range", move->id);
+    hipStream_t st = (hipStream_t)stream;
+    void *pin;
+    int rc = pinned(&pin);
+    if (rc) return rc;
+    int32_t *p = (int32_t *)pin;
+    p[0] = move->op;
+    p[1] = move->k;
+    p[2] = move->a;
+    p[3] = move->b;
+    p[4] = move->delta;
+    p[5] = (int32_t)move->feas;
+    p[6] = (int32_t)move->id;
+    p[7] = (int32_t)move->version;
+    HIPCHK(hipMemcpyAsync(sol->h.rec, p, 32, hipMemcpyHostToDevice, st));
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeApplyRec, TGA_OP_ALL);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(p + 8, sol->h.state, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (p[8 + kStStatus] != 0) return fail(TGA_EINVAL, "move id %u is not a move of N(S)", move->id);
+    sol->version++;
+    if (new_cost) *new_cost = *(long long *)(p + 16);
+    return TGA_OK;
+}
+
+extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_steps, int32_t *steps_done,
+                          int64_t *moves_evaluated, int64_t *cost, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (max_steps < 0) return fail(TGA_EINVAL, "max_steps < 0");
+    hipStream_t st = (hipStream_t)stream;
+    void *pin;
+    int rc = pinned(&pin);
+    if (rc) return rc;
+    int32_t *p = (int32_t *)pin;
+    k_reset_state<<<1, 64, 0, st>>>(sol->d, 1, max_steps);
+    HIPCHK(hipGetLastError());
+    const int chunk = 16;
+    int launched = 0;
+    while (launched <= max_steps) {
+        // max_steps accepted moves need max_steps + 1 evaluations to see the last one stop
+        const int todo = std::min(chunk, max_steps + 1 - launched);
+        for (int i = 0; i < todo; ++i) {
+            launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
+                        sol->lds, sol->nitems, nullptr, nullptr, st);
+            k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask);
+        }
+        HIPCHK(hipGetLastError());
+        launched += todo;
+        HIPCHK(hipMemcpyAsync(p, sol->h.state, 64, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (p[kStDone]) break;
+    }
+    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const long long *acc = (const long long *)(p + 16);
+    sol->version = (uint32_t)p[kStVersion];
+    if (steps_done) *steps_done = p[kStSteps];
+    if (moves_evaluated) *moves_evaluated = acc[kAccMoves];
+    if (cost) *cost = acc[kAccCost];
+    return TGA_OK;
+}
+
+extern "C" int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, int64_t *cost,
+                                void *stream) {
+    if (!sol || !offsets || !customers) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int Q = sol->Q, R = sol->R;
+    std::vector<int4> a4(Q);
+    std::vector<int32_t> roff(R + 1);
+    long long c = 0;
+    HIPCHK(hipMemcpyAsync(a4.data(), sol->h.a4, sizeof(int4) * Q, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(roff.data(), sol->h.roff, sizeof(int32_t) * (R + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&c, sol->h.acc + kAccCost, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int w = 0;
+    for (int r = 0; r < R; ++r) {
+        offsets[r] = w;
+        for (int s = roff[r] + 1; s < roff[r + 1]; ++s) customers[w++] = a4[s].x & 0xFFFF;
+    }
+    offsets[R] = w;
+    if (cost) *cost = c;
+    return TGA_OK;
+}
+
+extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream) {
+    if (!sol || !counts) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    long long acc[kAccCount];
+    HIPCHK(hipMemcpyAsync(acc, sol->h.acc, sizeof acc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < 5; ++i) counts[i] = acc[kAccCnt0 + i];
+    return TGA_OK;
+}
+
+// ---------------------------------------------------------------- batch ----
+
+static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc, size_t *items,
+                           size_t *intra, size_t *queue, int max_items, int nintra) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    *desc = take(sizeof(SolDev) * sols.size());
+    *items = take(sizeof(InterItem) * std::max(max_items, 1));
+    *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
+    *queue = take(64);
+    return off;
+}
+
+static int batch_max_items(const std::vector<tga_solution *> &sols, int tile_rows, int col_split) {
+    long long m = 0;
+    for (auto *s : sols) {
+        const int tr = tile_rows > 0 ? tile_rows : s->tile_rows;
+        m += (long long)((s->Q + tr - 1) / tr) * std::max(1, col_split);
+    }
+    return (int)std::min<long long>(m, 1 << 30);
+}
+
+extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t count) {
+    if (!sols || count < 1) return 0;
+    std::vector<tga_solution *> v(sols, sols + count);
+    int nintra = 0;
+    for (auto *s : v) {
+        if (!s) return 0;
+        nintra += s->R;
+    }
+    size_t a, b, c, d;
+    // worst case over the schedules tga_batch_create accepts: one row per item, 8 parts
+    return batch_layout(v, &a, &b, &c, &d, batch_max_items(v, 1, 8), nintra);
+}
+
+extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t tile_rows,
+                                int32_t col_split, void *ws, size_t ws_bytes, void *stream,
+                                tga_batch_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
+    if (tile_rows < 0 || tile_rows > 64 || col_split < 0 || col_split > 8)
+        return fail(TGA_ERANGE, "tile_rows in [0, 64], col_split in [0, 8]");
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<tga_solution *> v(sols, sols + count);
+    for (auto *s : v) {
+        if (!s) return fail(TGA_EINVAL, "null solution in batch");
+        if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
+    }
+    for (size_t i = 0; i < v.size(); ++i)
+        for (size_t j = i + 1; j < v.size(); ++j)
+            if (v[i] == v[j]) return fail(TGA_EINVAL, "solution listed twice");
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    if (ws_bytes < tga_batch_workspace_bytes(sols, count)) return fail(TGA_ENOMEM, "batch workspace too small");
+    const int parts = col_split > 0 ? col_split : 1;
+    std::vector<InterItem> items;
+    std::vector<IntraItem> intra;
+    std::vector<SolDev> descs(count);
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        tga_solution *s = v[i];
+        descs[i] = s->h;
+        const int tr = tile_rows > 0 ? tile_rows : s->tile_rows;
+        descs[i].tile_rows = tr;
+        lds = std::max(lds, item_lds(s->h.np1, tr));
+        for (int s0 = 0; s0 < s->Q; s0 += tr)
+            for (int p = 0; p < parts; ++p)
+                items.push_back(InterItem{i, s0, std::min(s->Q, s0 + tr), p | (parts << 16)});
+        for (int r = 0; r < s->R; ++r) intra.push_back(IntraItem{i, r});
+    }
+    if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);
+    // largest first: rows x (columns to the right) estimates the work of an item
+    std::stable_sort(items.begin(), items.end(), [&](const InterItem &a, const InterItem &b) {
+        const long long wa = (long long)(a.s1 - a.s0) * (v[a.sol]->Q - a.s0) / (a.part_parts >> 16);
+        const long long wb = (long long)(b.s1 - b.s0) * (v[b.sol]->Q - b.s0) / (b.part_parts >> 16);
+        return wa > wb;
+    });
+    size_t odesc, oitems, ointra, oqueue;
+    batch_layout(v, &odesc, &oitems, &ointra, &oqueue, (int)items.size(), (int)intra.size());
+    char *base = (char *)ws;
+    tga_batch *B = new tga_batch();
+    B->sols = v;
+    B->d = (SolDev *)(base + odesc);
+    B->items = (InterItem *)(base + oitems);
+    B->nitems = (int)items.size();
+    B->intra = (IntraItem *)(base + ointra);
+    B->nintra = (int)intra.size();
+    B->queue = (int *)(base + oqueue);
+    B->lds = lds;
+    const int per_cu = std::max(1, (int)(160 * 1024 / std::max<size_t>(lds, 1)));
+    B->grid_inter = std::min(B->nitems, P.cus * std::min(per_cu, 4));
+    B->grid_intra = std::min((B->nintra + 3) / 4, P.cus * 8);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_steps = -1;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(B->d, descs.data(), sizeof(SolDev) * count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete B;
+        return fail(TGA_EDEVICE, "batch_create: %s", hipGetErrorString(e));
+    }
+    for (auto *s : v) s->in_batch = 1;
+    *out = B;
+    return TGA_OK;
+}
+
+static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
+    if ((op_mask & 7) || (op_mask & (2 | 8 | 16)))
+        k_eval_mixed<<<std::max(B->grid_inter, B->grid_intra), kInterThreads, B->lds, st>>>(
+            B->d, B->items, B->nitems, B->intra, B->nintra, op_mask, B->queue);
+    k_finalize_batch<<<(int)B->sols.size(), kApplyThreads, 0, st>>>(B->d, mode, op_mask, B->queue);
+}
+
+extern "C" int tga_batch_reset(tga_batch_t B, void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, 0);
+    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return TGA_OK;
+}
+
+static int batch_collect(tga_batch *B, int32_t *steps_done, int64_t *moves, int64_t *cost, hipStream_t st) {
+    const int n = (int)B->sols.size();
+    std::vector<int32_t> state(16 * n);
+    std::vector<long long> acc(kAccCount * n);
+    for (int i = 0; i < n; ++i) {
+        HIPCHK(hipMemcpyAsync(&state[16 * i], B->sols[i]->h.state, 64, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&acc[kAccCount * i], B->sols[i]->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        B->sols[i]->version = (uint32_t)state[16 * i + kStVersion];
+        if (steps_done) steps_done[i] = state[16 * i + kStSteps];
+        if (moves) moves[i] = acc[kAccCount * i + kAccMoves];
+        if (cost) cost[i] = acc[kAccCount * i + kAccCost];
+    }
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, int32_t use_graph,
+                                int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost, void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (steps < 0) return fail(TGA_EINVAL, "steps < 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, steps);
+    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
+    HIPCHK(hipGetLastError());
+    // steps accepted moves need steps + 1 evaluations to observe the stop
+    const int evals = steps + 1;
+    if (use_graph) {
+        if (!B->exec || B->graph_steps != evals || B->graph_mask != op_mask || B->graph_stream != st) {
+            if (B->exec) {
+                (void)hipGraphExecDestroy(B->exec);
+                B->exec = nullptr;
+            }
+            if (B->graph) {
+                (void)hipGraphDestroy(B->graph);
+                B->graph = nullptr;
+            }
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < evals; ++i) batch_step(B, op_mask, kModeLS, st);
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamEndCapture(st, &g));
+            B->graph = g;
+            HIPCHK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+            B->graph_steps = evals;
+            B->graph_mask = op_mask;
+            B->graph_stream = st;
+        }
+        HIPCHK(hipGraphLaunch(B->exec, st));
+    } else {
+        for (int i = 0; i < evals; ++i) batch_step(B, op_mask, kModeLS, st);
+        HIPCHK(hipGetLastError());
+    }
+    return batch_collect(B, steps_done, moves_evaluated, cost, st);
+}
+
+extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best, int32_t *status, void *stream) {
+    if (!B || !best) return fail(TGA_EINVAL, "null argument");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, 0);
+    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
+    batch_step(B, op_mask, kModeRecord, st);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> rec(8 * n), state(16 * n);
+    for (int i = 0; i < n; ++i) {
+        HIPCHK(hipMemcpyAsync(&rec[8 * i], B->sols[i]->h.rec, 32, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&state[16 * i], B->sols[i]->h.state, 64, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        to_move(&rec[8 * i], &best[i]);
+        best[i].version = B->sols[i]->version;
+        if (status) status[i] = state[16 * i + kStStatus];
+    }
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_free(tga_batch_t B) {
+    if (!B) return TGA_OK;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (auto *s : B->sols) s->in_batch = 0;
+    delete B;
+    return TGA_OK;
+}

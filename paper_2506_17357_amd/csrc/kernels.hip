@@ -1,0 +1,1088 @@
+// HIP kernels (gfx950) for full-neighbourhood move evaluation, best-move
+// reduction, move application and attribute rebuild.
+//
+// The paper evaluates moves by concatenating route subsequences whose
+// attributes are precomputed (Section 4.1; distance: eq. dist; load: the
+// zero-pickup form of the load concatenation; windows: Section 4.3.3), in
+// five steps per operator (Section 5.1): extraction, concatenation,
+// differencing, evaluation (argmin), update.  Here the five steps are fused
+// per pair of positions: the attribute "tensor" is a set of per-slot arrays
+// (route id and position, as the positional tensors of Section 5.3.1; prefix
+// load; edge to the successor; earliest departure; latest feasible arrival
+// at the successor), every concatenation is evaluated in registers, and the
+// argmin is a running (delta, id) minimum per lane followed by a wavefront and
+// workgroup reduction and one 64-bit atomicMin per solution.
+//
+// Time windows use the hard-window case of the time-warp algebra (Section
+// 4.3.3: a concatenation is feasible exactly when its time-window violation
+// T_V is zero): forward earliest service starts A, backward latest arrivals
+// Z, and (duration, earliest finish, latest arrival) summaries for the middle
+// segments of intra-route moves.
+
+#include "tga_internal.h"
+
+namespace tga {
+
+constexpr int kInterThreads = 256;  // 4 wavefronts
+constexpr int kInterWaves = kInterThreads / 64;
+constexpr int kColsPerWave = 62;    // lanes 1..62 own a column; 0 and 63 are halo
+constexpr int kIntraThreads = 256;
+constexpr int kApplyThreads = 1024;
+constexpr int kTwOff = 1 << 28;     // due time standing for "no window" (CVRP)
+
+__device__ __forceinline__ int nodeof(int x) { return x & 0xFFFF; }
+__device__ __forceinline__ int flagsof(int x) { return x >> 16; }
+
+__device__ __forceinline__ unsigned long long pack_key(int delta, uint32_t id) {
+    return ((unsigned long long)((uint32_t)delta ^ 0x80000000u) << 32) | id;
+}
+
+__device__ __forceinline__ bool better(int d, uint32_t id, int bd, uint32_t bid) {
+    return d < bd || (d == bd && id < bid);
+}
+
+__device__ __forceinline__ void consider(int d, uint32_t id, int &bd, uint32_t &bid) {
+    if (d != kNoDelta && better(d, id, bd, bid)) {
+        bd = d;
+        bid = id;
+    }
+}
+
+__device__ __forceinline__ void wave_argmin(int &bd, uint32_t &bid) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int od = __shfl_xor(bd, off);
+        const uint32_t oid = (uint32_t)__shfl_xor((int)bid, off);
+        if (better(od, oid, bd, bid)) {
+            bd = od;
+            bid = oid;
+        }
+    }
+}
+
+// Reduce the per-lane bests of a workgroup and fold the result into the
+// solution's key.  Every thread of the block must call it.
+__device__ void block_argmin_commit(int bd, uint32_t bid, unsigned long long *key,
+                                    unsigned long long *red) {
+    wave_argmin(bd, bid);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = bd == kNoDelta ? ~0ull : pack_key(bd, bid);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = ~0ull;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = red[w] < m ? red[w] : m;
+        if (m != ~0ull) atomicMin(key, m);
+    }
+    __syncthreads();
+}
+
+// Insert one node with window [e, l] and service s: arrive from a departure
+// time `dep` over `cin`, leave over `cout` to a successor whose latest
+// feasible arrival is `z`.
+__device__ __forceinline__ bool tw_insert(int dep, int cin, int e, int l, int s, int cout, int z) {
+    const int arr = dep + cin;
+    const int st = arr > e ? arr : e;
+    return (arr <= l) & (st + s + cout <= z);
+}
+
+// (duration, earliest finish, latest arrival) summary of a segment under hard
+// windows: arriving at time a <= la, the segment is served and left at
+// max(a + dur, ef).
+struct Seg {
+    int dur, ef, la;
+    bool ok;
+};
+
+__device__ __forceinline__ Seg seg_node(int e, int l, int s) { return Seg{s, e + s, l, true}; }
+
+// a then b, travelling c from the last node of a to the first node of b.
+__device__ __forceinline__ Seg seg_cat(const Seg &a, int c, const Seg &b) {
+    Seg r;
+    r.dur = a.dur + c + b.dur;
+    r.ef = max(a.ef + c + b.dur, b.ef);
+    r.la = min(a.la, b.la - c - a.dur);
+    r.ok = a.ok && b.ok && (a.ef + c <= b.la);
+    return r;
+}
+
+// Arrive at `arr`; returns the departure time, or kInf when infeasible.
+__device__ __forceinline__ int seg_pass(const Seg &g, int arr) {
+    if (!g.ok || arr > g.la) return kInf;
+    const int d = arr + g.dur;
+    return d > g.ef ? d : g.ef;
+}
+
+// ------------------------------------------------------------ rebuild ------
+// Segmented scans over the route-major slot array, one workgroup per
+// solution.  Forward: prefix load and prefix distance (sums) and the earliest
+// service start A (maps x -> x <= th ? max(x + al, be) : INF, closed under
+// composition).  Backward: latest feasible arrival Z (maps
+// y -> y >= th ? min(y + al, be) : NEG).  A reset flag marks a segment
+// boundary (a route start for the forward scans, a route end for the
+// backward scan).
+
+struct FwdElem {
+    int32_t rs;          // reset
+    int32_t load, dist;  // additive parts
+    int32_t th, al, be;  // A map
+};
+
+__device__ __forceinline__ FwdElem fwd_identity() { return FwdElem{0, 0, 0, kInf, 0, kNeg}; }
+
+// apply a, then b
+__device__ __forceinline__ FwdElem fwd_cat(const FwdElem &a, const FwdElem &b) {
+    if (b.rs) return b;
+    FwdElem r;
+    r.rs = a.rs;
+    r.load = a.load + b.load;
+    r.dist = a.dist + b.dist;
+    r.th = (a.be <= b.th) ? min(a.th, b.th - a.al) : -1;
+    r.al = a.al + b.al;
+    r.be = max(a.be + b.al, b.be);
+    return r;
+}
+
+__device__ __forceinline__ int fwd_apply(const FwdElem &m, int x) {
+    return (x <= m.th) ? max(x + m.al, m.be) : kInf;
+}
+
+struct BwdElem {
+    int32_t rs, th, al, be;
+};
+
+__device__ __forceinline__ BwdElem bwd_identity() { return BwdElem{0, kNeg, 0, kInf}; }
+
+// apply r (the part to the right) first, then l
+__device__ __forceinline__ BwdElem bwd_cat(const BwdElem &l, const BwdElem &r) {
+    if (l.rs) return l;
+    BwdElem o;
+    o.rs = r.rs;
+    o.th = (r.be >= l.th) ? max(r.th, l.th - r.al) : kInf;
+    o.al = r.al + l.al;
+    o.be = min(r.be + l.al, l.be);
+    return o;
+}
+
+__device__ __forceinline__ int bwd_apply(const BwdElem &m, int y) {
+    return (y >= m.th) ? min(y + m.al, m.be) : kNeg;
+}
+
+struct ApplyShared {
+    FwdElem f[kApplyThreads];
+    BwdElem b[kApplyThreads];
+    long long red[kApplyThreads / 64][5];
+    int mv[16];
+};
+
+// Forward element of slot s (reads what pass 1 and 2 wrote).
+__device__ __forceinline__ FwdElem fwd_elem(const SolDev &S, int s) {
+    const int4 a = S.a4[s];
+    FwdElem e;
+    if (s == S.roff[a.y]) {
+        e = fwd_identity();
+        e.rs = 1;
+        return e;
+    }
+    const int4 ap = S.a4[s - 1];
+    const int sp = S.w4[s - 1].z;
+    const int4 w = S.w4[s];
+    e.rs = 0;
+    e.load = S.b4[s].x;
+    e.dist = ap.z;
+    e.al = sp + ap.z;
+    e.th = w.y - e.al;
+    e.be = w.x;
+    return e;
+}
+
+__device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, int s) {
+    const int4 a = S.a4[s];
+    const int4 w = S.w4[s];
+    const int last = S.roff[a.y + 1] - 1;
+    const int b = w.z + a.z;
+    BwdElem e;
+    e.rs = s == last;
+    e.th = w.x + b;
+    e.al = -b;
+    e.be = w.y;
+    return e;
+}
+
+// Rebuild every attribute of S from the layout nr[] = {node, route} and
+// roffn[].  nr doubles as scratch for {A, Z} after the first two passes.
+// Requires blockDim.x == kApplyThreads.
+__device__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
+    const int Q = S.Q, R = S.R, n = S.n, np1 = S.np1;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int32_t *D = S.D;
+    const int4 *nd = S.node4;
+
+    for (int r = tid; r <= R; r += T) S.roff[r] = roffn[r];
+    // pass 1: node, route, edge, per-node data, ref map
+    for (int s = tid; s < Q; s += T) {
+        const int2 x = nr[s];
+        const int node = x.x, r = x.y;
+        const int first = roffn[r], last = roffn[r + 1] - 1;
+        const int succ = s < last ? nr[s + 1].x : 0;
+        int4 q = nd[node];
+        if (!S.has_tw) q = make_int4(q.x, 0, kTwOff, 0);
+        const int edge = D[(size_t)node * np1 + succ];
+        const bool cust = s != first;
+        S.a4[s] = make_int4(node | ((cust ? kFlagCustomer : 0) << 16), r, edge, 0);
+        S.w4[s] = make_int4(q.y, q.z, q.w, 0);
+        S.b4[s] = make_int4(cust ? q.x : 0, 0, 0, 0);
+        S.ref2slot[cust ? node - 1 : n + r] = s;
+    }
+    if (tid == 0) {
+        S.a4[Q] = make_int4(0, R, 0, 0);
+        S.b4[Q] = make_int4(0, 0, 0, 0);
+        S.w4[Q] = make_int4(S.has_tw ? nd[0].y : 0, S.has_tw ? nd[0].z : kTwOff, 0, 0);
+        S.t4[Q] = make_int4(kInf, kNeg, kInf, kNeg);
+        S.pdist[Q] = 0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pass 2: removal delta and incident-edge sums (customers)
+    for (int s = tid; s < Q; s += T) {
+        const int4 a = S.a4[s];
+        if (s == S.roff[a.y]) continue;
+        const int4 ap = S.a4[s - 1];
+        const int succ = s + 1 < S.roff[a.y + 1] ? nr[s + 1].x : 0;
+        const int dpw = D[(size_t)nodeof(ap.x) * np1 + succ];
+        S.a4[s].w = dpw - ap.z - a.z;
+        S.b4[s].w = ap.z + a.z;
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    const int C = (Q + T - 1) / T;
+    const int beg = min(Q, tid * C), end = min(Q, beg + C);
+    // forward scans (exclusive Hillis-Steele over the chunk aggregates)
+    {
+        FwdElem agg = fwd_identity();
+        for (int s = beg; s < end; ++s) agg = fwd_cat(agg, fwd_elem(S, s));
+        sh.f[tid] = agg;
+        __syncthreads();
+        for (int off = 1; off < T; off <<= 1) {
+            FwdElem x = tid >= off ? sh.f[tid - off] : fwd_identity();
+            __syncthreads();
+            if (tid >= off) sh.f[tid] = fwd_cat(x, sh.f[tid]);
+            __syncthreads();
+        }
+        FwdElem run = tid ? sh.f[tid - 1] : fwd_identity();
+        __syncthreads();
+        const int e0 = S.has_tw ? nd[0].y : 0;
+        for (int s = beg; s < end; ++s) {
+            run = fwd_cat(run, fwd_elem(S, s));
+            S.b4[s].y = run.load;
+            S.pdist[s] = run.dist;
+            nr[s].x = S.has_tw ? fwd_apply(run, e0) : 0;  // A[s]
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // backward scan, in reversed thread order (position p = T-1-tid); CVRP
+    // needs no window attributes
+    if (!S.has_tw) {
+        for (int s = beg; s < end; ++s) nr[s].y = kTwOff;
+    } else {
+        BwdElem agg = bwd_identity();
+        for (int s = end - 1; s >= beg; --s) agg = bwd_cat(bwd_elem(S, s), agg);
+        const int p = T - 1 - tid;
+        sh.b[p] = agg;
+        __syncthreads();
+        for (int off = 1; off < T; off <<= 1) {
+            BwdElem x = p >= off ? sh.b[p - off] : bwd_identity();
+            __syncthreads();
+            if (p >= off) sh.b[p] = bwd_cat(sh.b[p], x);
+            __syncthreads();
+        }
+        BwdElem run = p ? sh.b[p - 1] : bwd_identity();
+        __syncthreads();
+        const int l0 = S.has_tw ? nd[0].z : kTwOff;
+        for (int s = end - 1; s >= beg; --s) {
+            run = bwd_cat(bwd_elem(S, s), run);
+            nr[s].y = bwd_apply(run, l0);  // Z[s]
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pass 3: route totals (by the thread owning each route's last slot)
+    for (int s = tid; s < Q; s += T) {
+        const int r = S.a4[s].y;
+        if (s == S.roff[r + 1] - 1) S.rdist[r] = S.pdist[s] + S.a4[s].z;
+    }
+    // pass 4: derived per-slot values and flags
+    const int l0 = S.has_tw ? nd[0].z : kTwOff;
+    const int cap = S.cap;
+    for (int s = tid; s < Q; s += T) {
+        int4 a = S.a4[s];
+        const int first = S.roff[a.y], last = S.roff[a.y + 1] - 1;
+        const int rload = S.b4[last].y;
+        const int4 w = S.w4[s];
+        const int A = nr[s].x;
+        const int dep = A >= kInf ? kInf : A + w.z;
+        const int zn = s < last ? nr[s + 1].y : l0;
+        int adp = kInf;
+        int flags = flagsof(a.x);
+        int4 b = S.b4[s];
+        if (s != first) {
+            const int Ap = nr[s - 1].x;
+            adp = Ap >= kInf ? kInf : Ap + S.w4[s - 1].z;
+            if (rload - b.x <= cap) flags |= kFlagRemCap;
+            // without this node: predecessor departure + c(pred, succ) <= Z(succ)
+            const int dpw = a.w + b.w;  // removal delta + incident edges = c(pred, succ)
+            if (adp < kInf && adp + dpw <= zn) flags |= kFlagRemTw;
+        }
+        a.x = nodeof(a.x) | (flags << 16);
+        S.a4[s] = a;
+        b.z = rload;
+        S.b4[s] = b;
+        S.t4[s] = make_int4(dep, zn, adp, nr[s].y);
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pass 5: cost and |N(S)| per operator
+    long long v[5] = {0, 0, 0, 0, 0};
+    for (int r = tid; r < R; r += T) {
+        const long long L = S.roff[r + 1] - S.roff[r] - 1;
+        v[0] += S.rdist[r];
+        v[1] += L * (Q - L - 1);
+        v[2] += (L + 1) * (L + 1);
+        v[3] += L * (L - 1) / 2;
+        for (int k = 1; k <= 3; ++k)
+            if (k <= L) v[4] += (L - k + 1) * (L - k);
+    }
+    for (int i = 0; i < 5; ++i) {
+        long long x = v[i];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+        v[i] = x;
+    }
+    if ((tid & 63) == 0)
+        for (int i = 0; i < 5; ++i) sh.red[tid >> 6][i] = v[i];
+    __syncthreads();
+    if (tid == 0) {
+        long long t[5] = {0, 0, 0, 0, 0};
+        for (int w = 0; w < T / 64; ++w)
+            for (int i = 0; i < 5; ++i) t[i] += sh.red[w][i];
+        const long long qq = (long long)Q * Q;
+        S.acc[kAccCost] = t[0];
+        S.acc[kAccCnt0 + 0] = t[1];
+        S.acc[kAccCnt0 + 1] = (long long)n * (n - 1) / 2;
+        S.acc[kAccCnt0 + 2] = (qq - t[2]) / 2;
+        S.acc[kAccCnt0 + 3] = t[3];
+        S.acc[kAccCnt0 + 4] = t[4];
+    }
+    __threadfence_block();
+    __syncthreads();
+}
+
+// Build the attributes of a freshly uploaded layout (nr_alt, roff_alt).
+__global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restrict__ sols) {
+    __shared__ ApplyShared sh;
+    const SolDev &S = sols[blockIdx.x];
+    rebuild(S, S.nr_alt, S.roff_alt, sh);
+    if (threadIdx.x == 0) {
+        *S.best_key = ~0ull;
+        S.state[kStDone] = 0;
+        S.state[kStStatus] = 0;
+    }
+}
+
+// ------------------------------------------------------ inter-route eval ---
+// One work item = rows [s0, s1) (slots, route-major) against every column
+// slot of a later route (column part `part` of `parts`).  For each unordered
+// pair of slots (s, t) in different routes, route(s) < route(t), the fused
+// pass evaluates RELOCATE s->after t, RELOCATE t->after s, SWAP s<->t and
+// 2OPT*(s, t) (the node-based extraction of Section 5.3.1, eq. node_based1 and
+// eq. node_based2, over the positional attributes).
+//
+// The D rows of the item's slots (plus one halo row on each side) are staged
+// in LDS; a lane gathers D[row][node(t)] from LDS once per row and gets
+// D[row][succ(t)] and D[row][pred(t)] from its neighbour lanes, and
+// D[pred(s)][t], D[succ(s)][t] from the previous and next row of a register
+// window.
+
+// Whole-workgroup evaluation of one inter-route item.  smem4 is the dynamic
+// LDS area; red holds kInterWaves keys.
+template <bool TW, bool DUMP>
+__device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_mask,
+                           int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
+                           int4 *smem4, unsigned long long *red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool opRel = op_mask & 1, opSwap = op_mask & 2, op2s = op_mask & 4;
+    {
+        const int Q = S.Q, np1 = S.np1, n = S.n, cap = S.cap;
+        const int s0 = item.s0, s1 = item.s1, nrow = s1 - s0 + 2;
+        int4 *rowa = smem4;
+        int4 *rowb = rowa + nrow;
+        int4 *rowt = rowb + nrow;
+        int4 *roww = rowt + nrow;
+        int *rows = (int *)(roww + nrow);
+
+        if ((int)threadIdx.x < nrow) {
+            const int s = min(max(s0 - 1 + (int)threadIdx.x, 0), Q);
+            rowa[threadIdx.x] = S.a4[s];
+            rowb[threadIdx.x] = S.b4[s];
+            if (TW) {
+                rowt[threadIdx.x] = S.t4[s];
+                roww[threadIdx.x] = S.w4[s];
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < nrow; ++k) {
+            const int *src = S.D + (size_t)nodeof(rowa[k].x) * np1;
+            int *dst = rows + k * np1;
+            for (int c = threadIdx.x; c < np1; c += kInterThreads) dst[c] = src[c];
+        }
+        __syncthreads();
+
+        int bd = kNoDelta;
+        uint32_t bid = 0xFFFFFFFFu;
+        const int cstart = S.roff[rowa[1].y + 1];
+        const int ncols = Q - cstart;
+        const int parts = item.part_parts >> 16, part = item.part_parts & 0xFFFF;
+        const int per = (ncols + parts - 1) / parts;
+        const int cbeg = cstart + part * per;
+        const int cend = min(Q, cbeg + per);
+        const uint32_t uQ = (uint32_t)Q;
+
+        for (int cb = cbeg + wave * kColsPerWave; cb < cend; cb += kInterWaves * kColsPerWave) {
+            const int t = cb - 1 + lane;
+            const int tc = min(max(t, 0), Q);
+            const bool own = lane >= 1 && lane <= kColsPerWave && t < cend;
+            const int4 ta = S.a4[tc];
+            const int4 tb = S.b4[tc];
+            int4 tt = make_int4(0, 0, 0, 0), tw = make_int4(0, 0, 0, 0);
+            if (TW) {
+                tt = S.t4[tc];
+                tw = S.w4[tc];
+            }
+            const int lastLane = min(kColsPerWave, cend - cb);
+            const int routeLast = __shfl(ta.y, lastLane);
+            const int nodeT = nodeof(ta.x);
+            const int flT = flagsof(ta.x);
+            const bool tCust = flT & kFlagCustomer;
+            const uint32_t refT = tCust ? nodeT - 1 : n + ta.y;
+            int gp = rows[nodeT];
+            int g = rows[np1 + nodeT];
+            for (int k = 1; k <= nrow - 2; ++k) {
+                const int4 ra = rowa[k];
+                if (routeLast <= ra.y) break;
+                const int4 rb = rowb[k];
+                int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
+                if (TW) {
+                    rt = rowt[k];
+                    rw = roww[k];
+                }
+                const int gn = rows[(k + 1) * np1 + nodeT];
+                const int gR = __shfl_down(g, 1);  // D[s][succ(t)]
+                const int gL = __shfl_up(g, 1);    // D[s][pred(t)]
+                const bool pair = own && ta.y > ra.y;
+                const int flS = flagsof(ra.x);
+                const bool sCust = flS & kFlagCustomer;
+                const uint32_t refS = sCust ? nodeof(ra.x) - 1 : n + ra.y;
+                const uint32_t lo = min(refS, refT), hi = max(refS, refT);
+
+                // RELOCATE s -> right after t
+                int d1 = kNoDelta;
+                bool v1 = false, c1 = false, w1 = true;
+                if (opRel && sCust) {
+                    v1 = pair;
+                    d1 = ra.w + g + gR - ta.z;
+                    c1 = (flS & kFlagRemCap) && (tb.z + rb.x <= cap);
+                    if (TW) w1 = (flS & kFlagRemTw) && tw_insert(tt.x, g, rw.x, rw.y, rw.z, gR, tt.y);
+                }
+                // RELOCATE t -> right after s
+                int d2 = kNoDelta;
+                bool v2 = false, c2 = false, w2 = true;
+                if (opRel) {
+                    v2 = pair && tCust;
+                    d2 = ta.w + g + gn - ra.z;
+                    c2 = (flT & kFlagRemCap) && (rb.z + tb.x <= cap);
+                    if (TW) w2 = (flT & kFlagRemTw) && tw_insert(rt.x, g, tw.x, tw.y, tw.z, gn, rt.y);
+                }
+                // SWAP s <-> t
+                int d3 = kNoDelta;
+                bool v3 = false, c3 = false, w3 = true;
+                if (opSwap && sCust) {
+                    v3 = pair && tCust;
+                    d3 = gp + gn + gL + gR - rb.w - tb.w;
+                    c3 = (rb.z - rb.x + tb.x <= cap) && (tb.z - tb.x + rb.x <= cap);
+                    if (TW)
+                        w3 = tw_insert(rt.z, gp, tw.x, tw.y, tw.z, gn, rt.y) &&
+                             tw_insert(tt.z, gL, rw.x, rw.y, rw.z, gR, tt.y);
+                }
+                // 2OPT*(s, t): heads keep their slots, tails are exchanged
+                int d4 = kNoDelta;
+                bool v4 = false, c4 = false, w4 = true;
+                if (op2s) {
+                    v4 = pair;
+                    d4 = gR + gn - ra.z - ta.z;
+                    c4 = (rb.y + tb.z - tb.y <= cap) && (tb.y + rb.z - rb.y <= cap);
+                    if (TW) w4 = (rt.x + gR <= tt.y) && (tt.x + gn <= rt.y);
+                }
+                if (DUMP) {
+                    if (v1) {
+                        const uint32_t id = (uQ + refS) * uQ + refT;
+                        dump_delta[id] = d1;
+                        dump_feas[id] = (uint8_t)(c1 | (w1 << 1));
+                    }
+                    if (v2) {
+                        const uint32_t id = (uQ + refT) * uQ + refS;
+                        dump_delta[id] = d2;
+                        dump_feas[id] = (uint8_t)(c2 | (w2 << 1));
+                    }
+                    if (v3) {
+                        const uint32_t id = (5u * uQ + lo) * uQ + hi;
+                        dump_delta[id] = d3;
+                        dump_feas[id] = (uint8_t)(c3 | (w3 << 1));
+                    }
+                    if (v4) {
+                        const uint32_t id = (8u * uQ + lo) * uQ + hi;
+                        dump_delta[id] = d4;
+                        dump_feas[id] = (uint8_t)(c4 | (w4 << 1));
+                    }
+                }
+                const int m1 = (v1 && c1 && w1) ? d1 : kNoDelta;
+                const int m2 = (v2 && c2 && w2) ? d2 : kNoDelta;
+                const int m3 = (v3 && c3 && w3) ? d3 : kNoDelta;
+                const int m4 = (v4 && c4 && w4) ? d4 : kNoDelta;
+                const int m = min(min(m1, m2), min(m3, m4));
+                if (m != kNoDelta && m <= bd) {
+                    consider(m1, (uQ + refS) * uQ + refT, bd, bid);
+                    consider(m2, (uQ + refT) * uQ + refS, bd, bid);
+                    consider(m3, (5u * uQ + lo) * uQ + hi, bd, bid);
+                    consider(m4, (8u * uQ + lo) * uQ + hi, bd, bid);
+                }
+                gp = g;
+                g = gn;
+            }
+        }
+        block_argmin_commit(bd, bid, S.best_key, red);
+    }
+}
+
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(kInterThreads) void k_eval_inter(const SolDev *__restrict__ sols,
+                                                              const InterItem *__restrict__ items,
+                                                              int nitems, uint32_t op_mask,
+                                                              int32_t *__restrict__ dump_delta,
+                                                              uint8_t *__restrict__ dump_feas) {
+    extern __shared__ int4 smem4[];
+    __shared__ unsigned long long red[kInterWaves];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const InterItem item = items[it];
+        const SolDev &S = sols[item.sol];
+        if (S.state[kStDone]) continue;
+        inter_item<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, smem4, red);
+    }
+}
+
+// ------------------------------------------------------ intra-route eval ---
+// One wavefront per route (the route-based extraction of Section 5.3.1,
+// eq. 2_opt, eq. ext_intra_relocate, eq. ext_intra_swap).  Lane i takes the
+// first position i; the second position j walks the route while the
+// summaries of the middle segments grow by one node per step, so every move
+// costs O(1).  Distances come from D in global memory (L2 resident).
+
+// One wavefront evaluates every intra-route move of one route and commits
+// its best to the solution's key.
+template <bool TW, bool DUMP>
+__device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas) {
+    const int lane = threadIdx.x & 63;
+    const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
+    int bd = kNoDelta;
+    uint32_t bid = 0xFFFFFFFFu;
+    {
+        {
+            const int r = item.route;
+            const int off = S.roff[r];
+            const int L = S.roff[r + 1] - off - 1;
+            const int n = S.n, np1 = S.np1;
+            const uint32_t uQ = (uint32_t)S.Q;
+            const int32_t *D = S.D;
+            const bool capOK = S.b4[off].z <= S.cap;
+            const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
+            auto node = [&](int p) { return p <= L ? nodeof(S.a4[off + p].x) : 0; };
+            auto edge = [&](int p) { return S.a4[off + p].z; };
+            auto dep = [&](int p) { return S.t4[off + p].x; };
+            auto zat = [&](int p) { return p <= L ? S.t4[off + p].w : l0; };
+            auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(node(p) - 1); };
+            auto dd = [&](int x, int y) { return D[(size_t)x * np1 + y]; };
+            auto segAt = [&](int p) {
+                const int4 w = S.w4[off + p];
+                return seg_node(w.x, w.y, w.z);
+            };
+            for (int i = lane + 1; i <= L; i += 64) {
+                const int ci = node(i), cp = node(i - 1);
+                const int eP = edge(i - 1);  // c(c_{i-1}, c_i)
+                const int depP = TW ? dep(i - 1) : 0;
+                const uint32_t refI = ref(i);
+                const int cI1 = node(i + 1);
+                // ---- 2OPT(i, j) and SWAP(i, j), j > i
+                if (op2o || opSwap) {
+                    Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};
+                    Seg mid = Seg{0, 0, 0, true};
+                    for (int j = i + 1; j <= L; ++j) {
+                        const int cj = node(j), cj1 = node(j + 1);
+                        const int ej = edge(j), ejm = edge(j - 1);
+                        const int z1 = TW ? zat(j + 1) : 0;
+                        if (TW) rev = seg_cat(segAt(j), ejm, rev);
+                        const int d1 = dd(cp, cj), d2 = dd(ci, cj1);
+                        const int dlt2 = d1 + d2 - eP - ej;
+                        bool tw2 = true;
+                        if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= z1;
+                        const uint32_t refJ = ref(j);
+                        const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
+                        int dS = dlt2;
+                        bool twS = tw2;
+                        if (j > i + 1) {
+                            const int cjm = node(j - 1);
+                            const int dA = dd(cj, cI1), dB = dd(cjm, ci);
+                            dS = d1 + dA + dB + d2 - eP - edge(i) - ejm - ej;
+                            if (TW) {
+                                const int4 wj = S.w4[off + j], wi = S.w4[off + i];
+                                const int arr0 = depP + d1;
+                                bool ok = arr0 <= wj.y;
+                                const int t0 = max(arr0, wj.x) + wj.z;
+                                const int dM = seg_pass(mid, t0 + dA);
+                                const int arrI = dM + dB;
+                                ok = ok && dM < kInf && arrI <= wi.y;
+                                const int t2 = max(arrI, wi.x) + wi.z;
+                                twS = ok && (t2 + d2 <= z1);
+                            }
+                        }
+                        if (op2o) {
+                            const uint32_t id = (12u * uQ + lo) * uQ + hi;
+                            if (DUMP) {
+                                dump_delta[id] = dlt2;
+                                dump_feas[id] = (uint8_t)(capOK | (tw2 << 1));
+                            }
+                            if (capOK && tw2) consider(dlt2, id, bd, bid);
+                        }
+                        if (opSwap) {
+                            const uint32_t id = (5u * uQ + lo) * uQ + hi;
+                            if (DUMP) {
+                                dump_delta[id] = dS;
+                                dump_feas[id] = (uint8_t)(capOK | (twS << 1));
+                            }
+                            if (capOK && twS) consider(dS, id, bd, bid);
+                        }
+                        // middle c_{i+1} .. c_j for the next j
+                        if (TW) mid = (j == i + 1) ? segAt(j) : seg_cat(mid, ejm, segAt(j));
+                    }
+                }
+                if (!opOr) continue;
+                // ---- OR-OPT forward: segment c_i..c_{i+k-1} after c_j, j >= i+k
+                for (int k = 1; k <= 3; ++k) {
+                    if (i + k - 1 > L) break;
+                    const int f = ci, g = node(i + k - 1), w = node(i + k);
+                    const int eG = edge(i + k - 1);  // c(g, w)
+                    const int dPW = dd(cp, w);
+                    const int base = dPW - eP - eG;
+                    Seg sig = Seg{0, 0, 0, true};
+                    if (TW) {
+                        sig = segAt(i);
+                        for (int q = 1; q < k; ++q) sig = seg_cat(sig, edge(i + q - 1), segAt(i + q));
+                    }
+                    Seg mid = Seg{0, 0, 0, true};
+                    for (int j = i + k; j <= L; ++j) {
+                        const int v = node(j), v1 = node(j + 1);
+                        if (TW) mid = (j == i + k) ? segAt(j) : seg_cat(mid, edge(j - 1), segAt(j));
+                        const int dVF = dd(v, f), dGV = dd(g, v1);
+                        const int dlt = base + dVF + dGV - edge(j);
+                        bool tw = true;
+                        if (TW) {
+                            const int dm = seg_pass(mid, depP + dPW);
+                            const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
+                            tw = ds < kInf && ds + dGV <= zat(j + 1);
+                        }
+                        const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
+                        if (DUMP) {
+                            dump_delta[id] = dlt;
+                            dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                        }
+                        if (capOK && tw) consider(dlt, id, bd, bid);
+                    }
+                }
+                // ---- OR-OPT backward: after c_j, j <= i-2 (all k at once)
+                if (i >= 2) {
+                    int gk[3], wk[3], baseK[3], dGW[3], zK[3];
+                    Seg sigK[3];
+                    int kmax = 0;
+                    for (int k = 1; k <= 3; ++k) {
+                        if (i + k - 1 > L) break;
+                        kmax = k;
+                        gk[k - 1] = node(i + k - 1);
+                        wk[k - 1] = node(i + k);
+                        baseK[k - 1] = dd(cp, wk[k - 1]) - eP - edge(i + k - 1);
+                        if (TW) {
+                            dGW[k - 1] = dd(cp, wk[k - 1]);
+                            zK[k - 1] = zat(i + k);
+                            Seg sg = segAt(i);
+                            for (int q = 1; q < k; ++q) sg = seg_cat(sg, edge(i + q - 1), segAt(i + q));
+                            sigK[k - 1] = sg;
+                        }
+                    }
+                    Seg mid = Seg{0, 0, 0, true};
+                    for (int j = i - 2; j >= 0; --j) {
+                        const int v = node(j), v1 = node(j + 1);
+                        if (TW) mid = (j == i - 2) ? segAt(i - 1) : seg_cat(segAt(j + 1), edge(j + 1), mid);
+                        const int dVF = dd(v, ci);
+                        const int ej = edge(j);
+                        const int depJ = TW ? dep(j) : 0;
+                        const uint32_t refJ = ref(j);
+                        for (int k = 1; k <= kmax; ++k) {
+                            const int dGV = dd(gk[k - 1], v1);
+                            const int dlt = baseK[k - 1] + dVF + dGV - ej;
+                            bool tw = true;
+                            if (TW) {
+                                const int ds = seg_pass(sigK[k - 1], depJ + dVF);
+                                const int dm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
+                                tw = dm < kInf && dm + dGW[k - 1] <= zK[k - 1];
+                            }
+                            const uint32_t id = ((16u + k) * uQ + refI) * uQ + refJ;
+                            if (DUMP) {
+                                dump_delta[id] = dlt;
+                                dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                            }
+                            if (capOK && tw) consider(dlt, id, bd, bid);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // per-wave commit (waves of one block may serve different solutions)
+    wave_argmin(bd, bid);
+    if (lane == 0 && bd != kNoDelta) atomicMin(S.best_key, pack_key(bd, bid));
+}
+
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(kIntraThreads) void k_eval_intra(const SolDev *__restrict__ sols,
+                                                              const IntraItem *__restrict__ items,
+                                                              int nitems, uint32_t op_mask,
+                                                              int32_t *__restrict__ dump_delta,
+                                                              uint8_t *__restrict__ dump_feas) {
+    const int wave = threadIdx.x >> 6;
+    const int wpb = kIntraThreads / 64;
+    for (int itx = blockIdx.x * wpb + wave; itx < nitems; itx += gridDim.x * wpb) {
+        const IntraItem item = items[itx];
+        const SolDev &S = sols[item.sol];
+        if (S.state[kStDone]) continue;
+        intra_route<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas);
+    }
+}
+
+// Batched form: one persistent launch evaluates every solution of the batch.
+// Workgroups pull inter-route items from queue[0] (whole workgroup per item,
+// largest items first), then single routes from queue[1] (one wavefront per
+// route).  Solutions of both problem types share the launch; each item takes
+// the window-aware or the capacity-only path of its own solution.  The
+// finalize kernel that follows resets both queue heads.
+__global__ __launch_bounds__(kInterThreads) void k_eval_mixed(const SolDev *__restrict__ sols,
+                                                              const InterItem *__restrict__ items,
+                                                              int nitems,
+                                                              const IntraItem *__restrict__ intra,
+                                                              int nintra, uint32_t op_mask,
+                                                              int *__restrict__ queue) {
+    extern __shared__ int4 smem4[];
+    __shared__ unsigned long long red[kInterWaves];
+    __shared__ int cur;
+    if (op_mask & 7) {
+        for (;;) {
+            if (threadIdx.x == 0) cur = atomicAdd(&queue[0], 1);
+            __syncthreads();
+            const int it = cur;
+            __syncthreads();
+            if (it >= nitems) break;
+            const InterItem item = items[it];
+            const SolDev &S = sols[item.sol];
+            if (S.state[kStDone]) continue;
+            if (S.has_tw)
+                inter_item<true, false>(S, item, op_mask, nullptr, nullptr, smem4, red);
+            else
+                inter_item<false, false>(S, item, op_mask, nullptr, nullptr, smem4, red);
+        }
+    }
+    if (op_mask & (2 | 8 | 16)) {
+        const int lane = threadIdx.x & 63;
+        for (;;) {
+            int it = 0;
+            if (lane == 0) it = atomicAdd(&queue[1], 1);
+            it = __shfl(it, 0);
+            if (it >= nintra) break;
+            const IntraItem item = intra[it];
+            const SolDev &S = sols[item.sol];
+            if (S.state[kStDone]) continue;
+            if (S.has_tw)
+                intra_route<true, false>(S, item, op_mask, nullptr, nullptr);
+            else
+                intra_route<false, false>(S, item, op_mask, nullptr, nullptr);
+        }
+    }
+}
+
+// ------------------------------------------------- finalize / apply / LS ---
+
+enum { kModeRecord = 0, kModeLS = 1, kModeApplyRec = 2 };
+
+struct MoveInfo {
+    int op, k, a, b, ra, rb, pa, pb, La, Lb, nLa, nLb, valid, delta;
+    uint32_t id;
+};
+
+__device__ int old_node(const SolDev &S, int r, int p) {
+    return p == 0 ? 0 : nodeof(S.a4[S.roff[r] + p].x);
+}
+
+// Node at new position p of a touched route r (Section 4.1 operators).
+__device__ int new_node(const SolDev &S, const MoveInfo &m, int r, int p) {
+    if (p == 0) return 0;
+    switch (m.op) {
+    case 0:
+        if (r == m.ra) return p < m.pa ? old_node(S, r, p) : old_node(S, r, p + 1);
+        if (p <= m.pb) return old_node(S, r, p);
+        if (p == m.pb + 1) return m.a + 1;
+        return old_node(S, r, p - 1);
+    case 1:
+        if (r == m.ra && p == m.pa) return m.b + 1;
+        if (r == m.rb && p == m.pb) return m.a + 1;
+        return old_node(S, r, p);
+    case 2:
+        if (r == m.ra) return p <= m.pa ? old_node(S, r, p) : old_node(S, m.rb, m.pb + p - m.pa);
+        return p <= m.pb ? old_node(S, r, p) : old_node(S, m.ra, m.pa + p - m.pb);
+    case 3: {
+        const int i = min(m.pa, m.pb), j = max(m.pa, m.pb);
+        return (p >= i && p <= j) ? old_node(S, r, i + j - p) : old_node(S, r, p);
+    }
+    default: {
+        const int i = m.pa, j = m.pb, k = m.k;
+        if (j > i) {  // forward
+            if (p < i || p > j) return old_node(S, r, p);
+            if (p <= j - k) return old_node(S, r, p + k);
+            return old_node(S, r, i + p - (j - k + 1));
+        }
+        if (p <= j || p >= i + k) return old_node(S, r, p);
+        if (p <= j + k) return old_node(S, r, i + p - j - 1);
+        return old_node(S, r, p - k);
+    }
+    }
+}
+
+__device__ void decode_move(const SolDev &S, uint32_t id, MoveInfo &m) {
+    const uint32_t Q = (uint32_t)S.Q, qq = Q * Q;
+    const uint32_t opk = id / qq, rem = id % qq;
+    m.id = id;
+    m.op = (int)(opk >> 2);
+    m.k = (int)(opk & 3);
+    m.a = (int)(rem / Q);
+    m.b = (int)(rem % Q);
+    m.valid = 0;
+    if (m.op > 4) return;
+    const int sa = S.ref2slot[m.a], sb = S.ref2slot[m.b];
+    m.ra = S.a4[sa].y;
+    m.rb = S.a4[sb].y;
+    m.pa = sa - S.roff[m.ra];
+    m.pb = sb - S.roff[m.rb];
+    m.La = S.roff[m.ra + 1] - S.roff[m.ra] - 1;
+    m.Lb = S.roff[m.rb + 1] - S.roff[m.rb] - 1;
+    const int n = S.n;
+    const bool aC = m.a < n, bC = m.b < n;
+    bool ok = false;
+    m.nLa = m.La;
+    m.nLb = m.Lb;
+    switch (m.op) {
+    case 0:
+        ok = m.k == 1 && aC && m.ra != m.rb;
+        m.nLa = m.La - 1;
+        m.nLb = m.Lb + 1;
+        break;
+    case 1: ok = m.k == 1 && m.a < m.b && bC; break;
+    case 2:
+        ok = m.k == 0 && m.a < m.b && m.ra != m.rb;
+        m.nLa = m.pa + m.Lb - m.pb;
+        m.nLb = m.pb + m.La - m.pa;
+        break;
+    case 3: ok = m.k == 0 && m.a < m.b && bC && m.ra == m.rb; break;
+    case 4:
+        ok = m.k >= 1 && m.k <= 3 && aC && m.ra == m.rb && m.pa + m.k - 1 <= m.La &&
+             !(m.pb >= m.pa - 1 && m.pb <= m.pa + m.k - 1);
+        break;
+    }
+    m.valid = ok;
+}
+
+// Apply m (valid) and rebuild.  All threads of the block participate.
+__device__ void apply_move_block(const SolDev &S, const MoveInfo &m, ApplyShared &sh) {
+    const int R = S.R, Q = S.Q, T = blockDim.x, tid = threadIdx.x;
+    const bool inter = m.ra != m.rb;
+    const int dA = m.nLa - m.La, dB = inter ? m.nLb - m.Lb : 0;
+    auto shift = [&](int r) { return (r > m.ra ? dA : 0) + (inter && r > m.rb ? dB : 0); };
+    for (int r = tid; r <= R; r += T) S.roff_alt[r] = S.roff[r] + shift(r);
+    // untouched routes keep their nodes, shifted
+    for (int s = tid; s < Q; s += T) {
+        const int4 a = S.a4[s];
+        const int r = a.y;
+        if (r == m.ra || r == m.rb) continue;
+        S.nr_alt[s + shift(r)] = make_int2(nodeof(a.x), r);
+    }
+    // touched routes
+    const int baseA = S.roff[m.ra] + shift(m.ra);
+    for (int p = tid; p <= m.nLa; p += T) S.nr_alt[baseA + p] = make_int2(new_node(S, m, m.ra, p), m.ra);
+    if (inter) {
+        const int baseB = S.roff[m.rb] + shift(m.rb);
+        for (int p = tid; p <= m.nLb; p += T) S.nr_alt[baseB + p] = make_int2(new_node(S, m, m.rb, p), m.rb);
+    }
+    __threadfence_block();
+    __syncthreads();
+    rebuild(S, S.nr_alt, S.roff_alt, sh);
+}
+
+// One block per solution.  kModeRecord: publish the best move (status 1 if
+// none) and reset the key.  kModeLS: also apply it when its delta is negative
+// and the step cap allows, else mark the solution converged.  kModeApplyRec:
+// apply the move record the host wrote into S.rec.
+__device__ void finalize_block(const SolDev &S, int mode, uint32_t op_mask) {
+    __shared__ ApplyShared sh;
+    __shared__ MoveInfo mi;
+    __shared__ int act;
+    if (threadIdx.x == 0) {
+        act = 0;
+        if (mode == kModeApplyRec) {
+            decode_move(S, (uint32_t)S.rec[6], mi);
+            mi.delta = S.rec[4];
+            act = mi.valid;
+            S.state[kStStatus] = mi.valid ? 0 : -1;
+        } else if (!(mode == kModeLS && S.state[kStDone])) {
+            const unsigned long long key = *S.best_key;
+            *S.best_key = ~0ull;
+            if (mode == kModeLS) {
+                long long m = 0;
+                for (int op = 0; op < 5; ++op)
+                    if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
+                S.acc[kAccMoves] += m;
+            }
+            if (key == ~0ull) {
+                for (int q = 0; q < 8; ++q) S.rec[q] = 0;
+                S.rec[7] = S.state[kStVersion];
+                S.state[kStStatus] = 1;
+                if (mode == kModeLS) S.state[kStDone] = 1;
+            } else {
+                const uint32_t id = (uint32_t)(key & 0xFFFFFFFFu);
+                const int delta = (int)((uint32_t)(key >> 32) ^ 0x80000000u);
+                decode_move(S, id, mi);
+                mi.delta = delta;
+                S.rec[0] = mi.op;
+                S.rec[1] = mi.k;
+                S.rec[2] = mi.a;
+                S.rec[3] = mi.b;
+                S.rec[4] = delta;
+                S.rec[5] = 3;
+                S.rec[6] = (int)id;
+                S.rec[7] = S.state[kStVersion];
+                S.state[kStStatus] = 0;
+                if (mode == kModeLS) {
+                    if (delta < 0 && S.state[kStSteps] < S.state[kStMaxSteps] && mi.valid)
+                        act = 1;
+                    else
+                        S.state[kStDone] = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    const MoveInfo m = mi;
+    apply_move_block(S, m, sh);
+    if (threadIdx.x == 0) {
+        S.state[kStVersion] += 1;
+        S.state[kStSteps] += 1;
+        if (mode == kModeLS && S.state[kStSteps] >= S.state[kStMaxSteps]) S.state[kStDone] = 1;
+    }
+}
+
+__global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__restrict__ sols, int mode,
+                                                            uint32_t op_mask) {
+    finalize_block(sols[blockIdx.x], mode, op_mask);
+}
+
+__global__ __launch_bounds__(kApplyThreads) void k_finalize_batch(const SolDev *__restrict__ sols,
+                                                                  int mode, uint32_t op_mask,
+                                                                  int *__restrict__ queue) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        queue[0] = 0;
+        queue[1] = 0;
+    }
+    finalize_block(sols[blockIdx.x], mode, op_mask);
+}
+
+// ------------------------------------------------------ instance checks ----
+// out[0] |= 1 value out of range, 2 asymmetric, 4 nonzero diagonal,
+//           8 bad node data; out[1] = max distance; out[2] = max e;
+// out[3] = max l; out[4] = max s; out[5] = max demand.
+__global__ __launch_bounds__(256) void k_check_dist(const int32_t *__restrict__ D, int np1,
+                                                    int32_t *out) {
+    __shared__ int ta[32][33], tb[32][33];
+    const int I = blockIdx.y * 32, J = blockIdx.x * 32;
+    const int x = threadIdx.x & 31, y0 = threadIdx.x >> 5;
+    int bad = 0, mx = 0;
+    for (int y = y0; y < 32; y += 8) {
+        const int i = I + y, j = J + x;
+        ta[y][x] = (i < np1 && j < np1) ? D[(size_t)i * np1 + j] : 0;
+        const int i2 = J + y, j2 = I + x;
+        tb[y][x] = (i2 < np1 && j2 < np1) ? D[(size_t)i2 * np1 + j2] : 0;
+    }
+    __syncthreads();
+    for (int y = y0; y < 32; y += 8) {
+        const int i = I + y, j = J + x;
+        if (i >= np1 || j >= np1) continue;
+        const int d = ta[y][x];
+        if (d < 0 || d >= (1 << 24)) bad |= 1;
+        if (d != tb[x][y]) bad |= 2;
+        if (i == j && d != 0) bad |= 4;
+        mx = max(mx, d);
+    }
+    if (bad) atomicOr(&out[0], bad);
+    atomicMax(&out[1], mx);
+}
+
+__global__ __launch_bounds__(256) void k_check_nodes(const int4 *__restrict__ nd, int np1, int has_tw,
+                                                     int32_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np1) return;
+    const int4 q = nd[i];
+    const int lim = 1 << 26;
+    bool bad = q.x < 0 || q.x >= lim || (i == 0 && q.x != 0);
+    if (has_tw) {
+        bad = bad || q.y < 0 || q.z < q.y || q.w < 0 || q.z >= lim || q.w >= lim || (i == 0 && q.w != 0);
+        atomicMax(&out[2], q.y);
+        atomicMax(&out[3], q.z);
+        atomicMax(&out[4], q.w);
+    }
+    if (bad) atomicOr(&out[0], 8);
+    atomicMax(&out[5], q.x);
+}
+
+__global__ void k_zero_i32(int32_t *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// Reset per-solution state for a new run (no memset, so it can sit in a
+// captured graph).
+__global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int max_steps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsols) return;
+    const SolDev &S = sols[i];
+    S.state[kStDone] = 0;
+    S.state[kStSteps] = 0;
+    S.state[kStStatus] = 0;
+    S.state[kStMaxSteps] = max_steps;
+    S.acc[kAccMoves] = 0;
+    *S.best_key = ~0ull;
+}
+
+}  // namespace tga

@@ -1,0 +1,83 @@
+// Internal layout shared by the host runtime (api.hip) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tga {
+
+// Time sentinels (hard windows).  Every finite time on the path stays below
+// 2^28 (checked when an instance is loaded), so sums of a sentinel and a few
+// finite terms stay inside int32.
+constexpr int32_t kInf = 1 << 30;    // "cannot be reached in time"
+constexpr int32_t kNeg = -(1 << 30); // "no feasible arrival time"
+constexpr int32_t kNoDelta = 0x7FFFFFFF;
+
+// Slot flags (bits 16.. of a4.x; bits 0..15 hold the node, n < 2^14).
+constexpr int32_t kFlagCustomer = 1;
+constexpr int32_t kFlagRemCap = 2;  // route load - own demand <= capacity
+constexpr int32_t kFlagRemTw = 4;   // route stays window-feasible without this node
+
+// One solution as the kernels see it.  Slots are route-major: route r owns
+// slots roff[r] .. roff[r+1]-1, its start depot first; slot Q is a sentinel
+// holding node 0 (the end depot of the last route).
+struct SolDev {
+    // instance (borrowed)
+    const int32_t *D;     // (n+1)^2 row-major
+    const int4 *node4;    // {demand, e, l, s}
+    int32_t n, np1, cap, has_tw;
+    int32_t R, Q;
+    int32_t tile_rows;    // rows per inter-route work item for this solution
+    int32_t pad0;
+    // per slot, Q+1 entries
+    int4 *a4;    // {node | flags << 16, route, edge to successor, removal delta}
+    int4 *b4;    // {demand, prefix load (incl.), route load, sum of the two incident edges}
+    int4 *t4;    // {departure time, latest arrival at successor, departure of predecessor, latest arrival here}
+    int4 *w4;    // {e, l, s, 0}
+    int32_t *pdist;   // distance from the start depot along the route
+    // per ref (Q)
+    int32_t *ref2slot;
+    // per route
+    int32_t *roff;    // R+1
+    int32_t *rdist;   // R
+    // apply / build staging
+    int2 *nr_alt;     // Q+1 {node, route} of the next layout
+    int32_t *roff_alt;// R+1
+    // per-solution state
+    unsigned long long *best_key;  // running minimum of (delta, id) keys
+    int32_t *rec;     // 8 ints: the tga_move_t of the last finalize
+    int32_t *state;   // kState* below
+    long long *acc;   // kAcc* below
+};
+
+// state[] entries
+enum {
+    kStDone = 0,       // local optimum (or step cap) reached in LS mode
+    kStSteps = 1,      // accepted moves so far
+    kStStatus = 2,     // 0 ok, 1 no admissible move, -1 invalid move
+    kStVersion = 3,    // applied moves (host-visible version)
+    kStMaxSteps = 4,   // step cap for LS mode
+    kStCount
+};
+// acc[] entries
+enum {
+    kAccCost = 0,       // total distance of the current solution
+    kAccMoves = 1,      // sum of |N(S_t)| over evaluations run in LS mode
+    kAccCnt0 = 2,       // |N(S)| per operator, 5 entries
+    kAccCount = 8
+};
+
+// Inter-route work item: rows [s0, s1) against the columns of the later
+// routes, column part `part` of `parts`.
+struct InterItem {
+    int32_t sol, s0, s1, part_parts;  // part | parts << 16
+};
+
+struct IntraItem {
+    int32_t sol, route;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace tga

@@ -1,0 +1,280 @@
+"""Python binding of the C ABI in include/tga.h (argument marshalling only).
+
+PyTorch provides device memory (int32 / uint8 tensors on ``cuda``) and the
+stream (``torch.cuda.current_stream().cuda_stream``); every step of the path
+runs in the HIP kernels of ``libtga.so``.  There is no fallback: if the
+library is missing or fails to load, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtga.so")
+
+TGA_OK, TGA_ENOMOVE = 0, 1
+TGA_EINVAL, TGA_ERANGE, TGA_ENOMEM, TGA_EDEVICE, TGA_ESTALE = -1, -2, -3, -4, -5
+OP_RELOCATE, OP_SWAP, OP_2OPTSTAR, OP_2OPT, OP_OROPT = 1, 2, 4, 8, 16
+OPS_ALL = 0x1F
+MAX_Q = 14654
+
+_lib = None
+
+
+class TGAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("tga error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Move(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("k", ctypes.c_int32), ("a", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("delta", ctypes.c_int32), ("feas", ctypes.c_uint32),
+                ("id", ctypes.c_uint32), ("version", ctypes.c_uint32)]
+
+    def __repr__(self):
+        return ("Move(op=%d, k=%d, a=%d, b=%d, delta=%d, feas=%d, id=%d, version=%d)"
+                % (self.op, self.k, self.a, self.b, self.delta, self.feas, self.id, self.version))
+
+
+EXPORTS = [
+    "tga_instance_workspace_bytes", "tga_solution_workspace_bytes", "tga_load_instance",
+    "tga_set_solution", "tga_eval_neighborhood", "tga_apply_move", "tga_ls_run",
+    "tga_get_solution", "tga_move_counts", "tga_solution_version", "tga_free_solution",
+    "tga_free_instance", "tga_last_error", "tga_batch_workspace_bytes", "tga_batch_create",
+    "tga_batch_ls_run", "tga_batch_eval", "tga_batch_reset", "tga_batch_free",
+    "tga_device_limits",
+]
+
+
+def lib():
+    """Load libtga.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libtga.so is not built (run __graft_entry__.build() or "
+                           "python paper_2506_17357_amd/build_lib.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "tga_instance_workspace_bytes": (sz, [i32]),
+        "tga_solution_workspace_bytes": (sz, [i32, i32]),
+        "tga_load_instance": (i32, [i32, P, P, i32, i32, P, sz, P, pp]),
+        "tga_set_solution": (i32, [P, i32, P, P, P, sz, P, pp]),
+        "tga_eval_neighborhood": (i32, [P, u32, ctypes.POINTER(Move), P, P, P]),
+        "tga_apply_move": (i32, [P, ctypes.POINTER(Move), P, P]),
+        "tga_ls_run": (i32, [P, u32, i32, P, P, P, P]),
+        "tga_get_solution": (i32, [P, P, P, P, P]),
+        "tga_move_counts": (i32, [P, P, P]),
+        "tga_solution_version": (u32, [P]),
+        "tga_free_solution": (i32, [P]),
+        "tga_free_instance": (i32, [P]),
+        "tga_last_error": (ctypes.c_char_p, []),
+        "tga_batch_workspace_bytes": (sz, [P, i32]),
+        "tga_batch_create": (i32, [P, i32, i32, i32, P, sz, P, pp]),
+        "tga_batch_ls_run": (i32, [P, u32, i32, i32, P, P, P, P]),
+        "tga_batch_eval": (i32, [P, u32, ctypes.POINTER(Move), P, P]),
+        "tga_batch_reset": (i32, [P, P]),
+        "tga_batch_free": (i32, [P]),
+        "tga_device_limits": (i32, [P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow=(TGA_OK,)):
+    if rc in allow:
+        return rc
+    raise TGAError(rc, lib().tga_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Instance:
+    """Device-resident instance: distance matrix and node data."""
+
+    def __init__(self, n: int, dist, node4, capacity: int, has_tw: int, device="cuda", stream=None):
+        L = lib()
+        self.n = int(n)
+        self.dist = torch.as_tensor(np.ascontiguousarray(dist, dtype=np.int32)).to(device) \
+            if not isinstance(dist, torch.Tensor) else dist
+        self.node4 = torch.as_tensor(np.ascontiguousarray(node4, dtype=np.int32)).to(device) \
+            if not isinstance(node4, torch.Tensor) else node4
+        self.capacity = int(capacity)
+        self.has_tw = int(has_tw)
+        nbytes = L.tga_instance_workspace_bytes(self.n)
+        if nbytes == 0:
+            raise TGAError(TGA_ERANGE, "n = %d out of range" % n)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(L.tga_load_instance(self.n, _dev_ptr(self.dist), _dev_ptr(self.node4), self.capacity,
+                                   self.has_tw, _dev_ptr(self.ws), nbytes, _stream(stream),
+                                   ctypes.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def from_workload(inst, device="cuda", stream=None) -> "Instance":
+        return Instance(inst.n, inst.dist, inst.node4, inst.capacity, inst.has_tw, device, stream)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tga_free_instance(self.h)
+            self.h = None
+
+
+class Solution:
+    """A solution held on the device with its attribute arrays."""
+
+    def __init__(self, inst: Instance, offsets, customers, stream=None):
+        L = lib()
+        self.inst = inst
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        cust = np.ascontiguousarray(customers, dtype=np.int32)
+        self.R = int(off.shape[0] - 1)
+        self.Q = inst.n + self.R
+        nbytes = L.tga_solution_workspace_bytes(inst.n, self.R)
+        if nbytes == 0:
+            raise TGAError(TGA_ERANGE, "n + R = %d out of range" % self.Q)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=inst.dist.device)
+        h = ctypes.c_void_p()
+        _check(L.tga_set_solution(inst.h, self.R, _np_ptr(off), _np_ptr(cust), _dev_ptr(self.ws),
+                                  nbytes, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def eval(self, op_mask: int = OPS_ALL, dump: bool = False, stream=None):
+        """Best admissible move (or None); with dump=True also the per-move
+        delta / feasibility tensors (non-moves keep 0 / 0xFF)."""
+        L = lib()
+        m = Move()
+        dd = df = None
+        if dump:
+            size = 20 * self.Q * self.Q
+            dd = torch.zeros(size, dtype=torch.int32, device=self.ws.device)
+            df = torch.full((size,), 0xFF, dtype=torch.uint8, device=self.ws.device)
+        rc = _check(L.tga_eval_neighborhood(self.h, op_mask, ctypes.byref(m),
+                                            _dev_ptr(dd) if dump else None,
+                                            _dev_ptr(df) if dump else None, _stream(stream)),
+                    allow=(TGA_OK, TGA_ENOMOVE))
+        best = None if rc == TGA_ENOMOVE else m
+        if dump:
+            return best, dd, df
+        return best
+
+    def apply(self, move: Move, stream=None) -> int:
+        cost = ctypes.c_int64()
+        _check(lib().tga_apply_move(self.h, ctypes.byref(move), ctypes.byref(cost), _stream(stream)))
+        return int(cost.value)
+
+    def ls_run(self, max_steps: int, op_mask: int = OPS_ALL, stream=None):
+        """Device-resident local search; returns (steps, moves evaluated, cost)."""
+        steps = ctypes.c_int32()
+        mv = ctypes.c_int64()
+        cost = ctypes.c_int64()
+        _check(lib().tga_ls_run(self.h, op_mask, max_steps, ctypes.byref(steps), ctypes.byref(mv),
+                                ctypes.byref(cost), _stream(stream)))
+        return int(steps.value), int(mv.value), int(cost.value)
+
+    def get(self, stream=None):
+        """(offsets, customers, cost) of the current solution."""
+        off = np.zeros(self.R + 1, np.int32)
+        cust = np.zeros(self.inst.n, np.int32)
+        cost = ctypes.c_int64()
+        _check(lib().tga_get_solution(self.h, _np_ptr(off), _np_ptr(cust), ctypes.byref(cost),
+                                      _stream(stream)))
+        return off, cust, int(cost.value)
+
+    def move_counts(self, stream=None) -> np.ndarray:
+        c = np.zeros(5, np.int64)
+        _check(lib().tga_move_counts(self.h, _np_ptr(c), _stream(stream)))
+        return c
+
+    @property
+    def version(self) -> int:
+        return int(lib().tga_solution_version(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tga_free_solution(self.h)
+            self.h = None
+
+
+class Batch:
+    """Many solutions stepped together by one persistent launch per step."""
+
+    def __init__(self, sols: list[Solution], tile_rows: int = 0, col_split: int = 0, stream=None):
+        L = lib()
+        self.sols = list(sols)
+        arr = (ctypes.c_void_p * len(self.sols))(*[s.h.value for s in self.sols])
+        self._arr = arr
+        nbytes = L.tga_batch_workspace_bytes(arr, len(self.sols))
+        if nbytes == 0:
+            raise TGAError(TGA_EINVAL, "bad batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.sols[0].ws.device)
+        h = ctypes.c_void_p()
+        _check(L.tga_batch_create(arr, len(self.sols), tile_rows, col_split, _dev_ptr(self.ws),
+                                  nbytes, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def ls_run(self, steps: int, op_mask: int = OPS_ALL, use_graph: bool = True, stream=None):
+        n = len(self.sols)
+        st = np.zeros(n, np.int32)
+        mv = np.zeros(n, np.int64)
+        cost = np.zeros(n, np.int64)
+        _check(lib().tga_batch_ls_run(self.h, op_mask, steps, int(use_graph), _np_ptr(st),
+                                      _np_ptr(mv), _np_ptr(cost), _stream(stream)))
+        return st, mv, cost
+
+    def eval(self, op_mask: int = OPS_ALL, stream=None):
+        n = len(self.sols)
+        moves = (Move * n)()
+        status = np.zeros(n, np.int32)
+        _check(lib().tga_batch_eval(self.h, op_mask, moves, _np_ptr(status), _stream(stream)))
+        return list(moves), status
+
+    def reset(self, stream=None):
+        _check(lib().tga_batch_reset(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tga_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def device_limits():
+    """(compute units, LDS bytes per evaluation workgroup)."""
+    cu = ctypes.c_int32()
+    lds = ctypes.c_int32()
+    _check(lib().tga_device_limits(ctypes.byref(cu), ctypes.byref(lds)))
+    return int(cu.value), int(lds.value)
+
+
+def decode(Q: int, move_id: int):
+    """(op, k, a, b) of a move id."""
+    qq = Q * Q
+    opk, rem = divmod(int(move_id), qq)
+    return opk // 4, opk % 4, rem // Q, rem % Q

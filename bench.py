@@ -1,0 +1,246 @@
+#!/usr/bin/env python
+"""Benchmark of the batched full-neighbourhood local search on one MI355X.
+
+Workload (the batched configuration): 256 independent solutions, sizes
+log-uniform over 100..2000 customers, even b = CVRP (demand 1..100, capacity
+1000), odd b = clustered VRPTW, seeds 4000 + b, sweep starting solutions.
+One step = one evaluation of every move of every active solution (one
+persistent launch) + best-move reduction, apply and attribute rebuild (one
+launch).  Inputs are resident in HBM before the timed region starts.
+
+Reported: GMoves/s of the batched form (HIP graph of the K-step loop), the
+same K steps run eagerly with HIP events around every evaluation launch (the
+roofline figures come from those events), the plain one-solution-per-launch
+form on the same solutions (same results, checked), the best-move latency
+of the plain form, and the CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GMoves/s evaluated + best-move latency; batched vs plain, same GPU, bit-exact"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def eval_bytes(inst, R):
+    """Algorithmic HBM bytes of one evaluation: the distance matrix read once
+    plus the slot attributes the kernels need (two int4 per slot for CVRP,
+    four with time windows)."""
+    Q = inst.n + R
+    return 4 * (inst.n + 1) ** 2 + (64 if inst.has_tw else 32) * (Q + 1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--count", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        log("bench.py: this build measures one GPU only (the batched solutions are independent; "
+            "see DESIGN.md for how the path would shard); run with --gpus 1")
+        sys.exit(2)
+    K, Wm = args.steps, args.warmup
+
+    from paper_2506_17357_amd import build_lib
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build(verbose=True)
+    import torch
+    from paper_2506_17357_amd import tga, workload as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cus, lds = tga.device_limits()
+    log("device: %s, %d CUs, %d B LDS per evaluation workgroup" % (torch.cuda.get_device_name(0), cus, lds))
+
+    t = time.time()
+    sizes = W.batch_sizes(args.count)
+    pairs = []
+    for b, n in enumerate(sizes):
+        inst = W.batch_instance(b, n)
+        pairs.append((inst, W.sweep(inst)))
+    log("workload generated in %.1f s: %d solutions, sum n = %d" % (time.time() - t, len(pairs), sum(sizes)))
+    insts = [tga.Instance.from_workload(i) for i, _ in pairs]
+    sols = [tga.Solution(I, s.offsets, s.customers) for I, (_, s) in zip(insts, pairs)]
+    ebytes = np.array([eval_bytes(i, s.R) for i, s in pairs], np.float64)
+    B = tga.Batch(sols)
+    torch.cuda.synchronize()
+    log("uploaded: %.1f MB of distance matrices resident" % (sum(4 * (i.n + 1) ** 2 for i, _ in pairs) / 1e6))
+
+    def reload_all():
+        for s, (_, sol) in zip(sols, pairs):
+            s.reload(sol.offsets, sol.customers)
+        torch.cuda.synchronize()
+
+    # ---- warmup: W eager steps from the initial state
+    reload_all()
+    B.begin(Wm)
+    for _ in range(Wm):
+        B.step_part(0)
+        B.step_part(1)
+    B.collect()
+    log("warmup: %d steps" % Wm)
+
+    # ---- timed eager pass with events around every evaluation launch
+    reload_all()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.begin(K)
+    for k in range(K):
+        ev0[k].record()
+        B.step_part(0)
+        ev1[k].record()
+        B.step_part(1)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    st_e, mv_e, cost_e = B.collect()
+    dur_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    evals = np.where(st_e < K, st_e + 1, K)
+    active = np.arange(K)[:, None] < evals[None, :]
+    bytes_per_launch = (active * ebytes[None, :]).sum(axis=1)
+    achieved_gbs = bytes_per_launch.sum() / (dur_ms.sum() * 1e-3) / 1e9
+    moves_total = int(mv_e.sum())
+    log("eager: %.3f s for %d steps, %d moves, eval launch avg %.1f us (first %.1f us, last %.1f us), "
+        "%.0f GB/s algorithmic" % (t_eager, K, moves_total, dur_ms.mean() * 1e3, dur_ms[0] * 1e3,
+                                    dur_ms[-1] * 1e3, achieved_gbs))
+
+    # ---- graph pass (the step loop captured once, replayed from the initial state)
+    reload_all()
+    B.ls_run(K, use_graph=True)  # capture + first replay, untimed
+    reload_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_g, mv_g, cost_g = B.ls_run(K, use_graph=True)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    assert np.array_equal(st_g, st_e) and np.array_equal(mv_g, mv_e) and np.array_equal(cost_g, cost_e), \
+        "graph and eager passes disagree"
+    value = moves_total / t_graph / 1e9
+    log("graph: %.3f s -> %.1f GMoves/s" % (t_graph, value))
+    B.close()
+
+    out_plain = None
+    bit_exact = None
+    if not args.no_plain:
+        # ---- plain form: one solution per launch sequence, same solutions
+        reload_all()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [s.ls_run(K) for s in sols]
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        st_p = np.array([r[0] for r in res])
+        mv_p = np.array([r[1] for r in res])
+        cost_p = np.array([r[2] for r in res])
+        bit_exact = bool(np.array_equal(st_p, st_e) and np.array_equal(mv_p, mv_e) and
+                         np.array_equal(cost_p, cost_e))
+        plain_value = int(mv_p.sum()) / t_plain / 1e9
+        log("plain: %.3f s -> %.2f GMoves/s, bit-exact with batched: %s" % (t_plain, plain_value, bit_exact))
+        # best-move latency of the plain form on the solution closest to n = 1000
+        b1k = int(np.argmin([abs(i.n - 1000) for i, _ in pairs]))
+        s = sols[b1k]
+        s.reload(pairs[b1k][1].offsets, pairs[b1k][1].customers)
+        lat = []
+        for _ in range(60):
+            t1 = time.perf_counter()
+            m = s.eval()
+            lat.append((time.perf_counter() - t1) * 1e6)
+            if m is None or m.delta >= 0:
+                break
+            s.apply(m)
+        lat = np.array(lat)
+        out_plain = {
+            "value": round(plain_value, 4), "unit": "GMoves/s", "seconds": round(t_plain, 4),
+            "form": "one solution per launch sequence (device-resident loop per solution)",
+            "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
+                                     "p99": round(float(np.percentile(lat, 99)), 1),
+                                     "n": pairs[b1k][0].n, "kind": pairs[b1k][0].kind,
+                                     "evals": int(lat.size)},
+        }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        sample = list(range(0, len(pairs), 2))[:64] + list(range(1, len(pairs), 2))[:64]
+        t0 = time.perf_counter()
+        mv = 0
+        for b in sample:
+            inst, sol = pairs[b]
+            r = oracle.eval_neighbourhood(inst, sol, threads=threads)
+            mv += r.moves
+            if time.perf_counter() - t0 > 25:
+                sample = sample[:sample.index(b) + 1]
+                break
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(mv / t_cpu / 1e9, 5), "unit": "GMoves/s", "cores": threads, "kind": "oracle",
+               "sample": "one full-neighbourhood evaluation of the initial state of %d of the 256 solutions "
+                         "(%d moves, %.1f s)" % (len(sample), mv, t_cpu)}
+        log("cpu oracle: %.4f GMoves/s on %d threads" % (cpu["value"], threads))
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "GMoves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(t_graph / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched: 256 solutions, 100..2000 customers log-uniform, CVRP (even b) / "
+                        "clustered VRPTW (odd b), seeds 4000+b, sweep start, %d local-search steps, "
+                        "all five operators" % K,
+            "global_batch": len(pairs),
+            "sum_customers": int(sum(sizes)),
+            "dist_bytes_resident": int(sum(4 * (i.n + 1) ** 2 for i, _ in pairs)),
+            "moves_evaluated": moves_total,
+            "accepted_moves": int(st_e.sum()),
+            "form": "batched: one persistent evaluation launch + one finalize launch per step, "
+                    "step loop captured in a HIP graph",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_eval_mixed",
+            "achieved": round(achieved_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(float(dur_ms.mean() * 1e3), 2),
+            "avg_bytes_per_launch": int(bytes_per_launch.mean()),
+        },
+        "eager_value": round(moves_total / t_eager / 1e9, 4),
+        "plain": out_plain,
+        "batched_over_plain": round(value / out_plain["value"], 3) if out_plain else None,
+        "bit_exact_batched_vs_plain": bit_exact,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -117,6 +117,13 @@ int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
                      const int32_t *customers, void *ws, size_t ws_bytes, void *stream,
                      tga_solution_t *out);
 
+/* Replace the routes of an existing solution (same instance, same R) and
+ * rebuild its attributes in place: the workspace, and every batch or captured
+ * graph that refers to the solution, stay valid.  Resets the version to 0.
+ * Same argument rules as tga_set_solution.  Synchronises `stream`. */
+int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, const int32_t *customers,
+                        void *stream);
+
 /* Sections 5.3.1-5.3.4: evaluate every move of N(S) whose operator bit is in
  * op_mask and return the best admissible one in *best (host).  Returns
  * TGA_ENOMOVE when none is admissible (then *best is zeroed).
@@ -174,11 +181,12 @@ int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes);
 /* Device workspace bytes for a batch of `count` solutions. */
 size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t count);
 
-/* tile_rows: rows per inter-route work item (0 = choose from n);
- * col_split: column segments per row block (0 = choose).  Both only change
- * the schedule, never a result. */
-int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t tile_rows,
-                     int32_t col_split, void *ws, size_t ws_bytes, void *stream,
+/* rows_per_item: slot rows per inter-route work item (0 = about 32);
+ * sub_rows: rows staged in LDS at a time (0 = as many as the LDS budget of a
+ * workgroup holds for the solution's n; larger values are clamped to it).
+ * Both only change the schedule, never a result. */
+int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
+                     int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
                      tga_batch_t *out);
 
 /* Run `steps` local-search steps on every solution of the batch (solutions
@@ -188,6 +196,19 @@ int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t tile_row
 int tga_batch_ls_run(tga_batch_t b, uint32_t op_mask, int32_t steps, int32_t use_graph,
                      int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
                      void *stream);
+
+/* The same loop driven by the caller, one step at a time, so that events or
+ * other work can sit between the two launches of a step.
+ * tga_batch_begin: clear converged flags and counters, set the step cap.
+ * tga_batch_step_part: part 0 launches the evaluation of every solution (one
+ *   persistent launch), part 1 the finalize launch (best move, apply when its
+ *   delta is negative and the cap allows, rebuild).  Asynchronous.
+ * tga_batch_collect: synchronise and read the per-solution results, as
+ *   tga_batch_ls_run does. */
+int tga_batch_begin(tga_batch_t b, int32_t max_steps, void *stream);
+int tga_batch_step_part(tga_batch_t b, uint32_t op_mask, int32_t part, void *stream);
+int tga_batch_collect(tga_batch_t b, int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
+                      void *stream);
 
 /* One evaluation of every solution in the batch (no apply); best moves to a
  * host array of `count` records; per-solution status to status (nullable). */

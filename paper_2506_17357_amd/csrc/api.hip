@@ -95,6 +95,20 @@ int default_tile_rows(int np1) {
 
 size_t item_lds(int np1, int tile_rows) { return (size_t)(tile_rows + 2) * row_bytes(np1); }
 
+// Inter-route items of one solution: row blocks of `rows` rows, each against
+// the column segments to its right.
+template <class F>
+void for_each_item(int Q, int rows, F f) {
+    for (int s0 = 0; s0 < Q; s0 += rows)
+        for (int c0 = s0 + 1; c0 < Q; c0 += kSegCols) f(s0, std::min(Q, s0 + rows), c0);
+}
+
+long long count_items(int Q, int rows) {
+    long long c = 0;
+    for_each_item(Q, rows, [&](int, int, int) { ++c; });
+    return c;
+}
+
 struct SolLayout {
     size_t desc, a4, b4, t4, w4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, best_key, rec,
         state, acc, items, intra, total;
@@ -125,7 +139,7 @@ SolLayout sol_layout(int n, int R) {
     L.rec = take(32);
     L.state = take(4 * 16);
     L.acc = take(8 * kAccCount);
-    L.max_items = (int)(8 * Q + 8);
+    L.max_items = (int)count_items((int)Q, default_tile_rows(n + 1));
     L.items = take(sizeof(InterItem) * L.max_items);
     L.intra = take(sizeof(IntraItem) * std::max(R, 1));
     L.total = off;
@@ -150,7 +164,7 @@ struct tga_solution {
     int nitems;
     IntraItem *intra;  // device
     int nintra;
-    int tile_rows, parts;
+    int tile_rows;
     size_t lds;
     uint32_t version;
     int in_batch;
@@ -170,7 +184,7 @@ struct tga_batch {
     hipGraph_t graph;
     int graph_steps;
     uint32_t graph_mask;
-    hipStream_t graph_stream;
+    hipStream_t cap_stream;  // library-owned stream used only for graph capture
 };
 
 // ----------------------------------------------------------------- misc ----
@@ -256,12 +270,12 @@ extern "C" int tga_free_instance(tga_instance_t inst) {
 
 // ------------------------------------------------------------- solution ----
 
+static int check_partition(int n, int R, const int32_t *offsets, const int32_t *customers);
+
 static void build_plain_items(tga_solution *S, std::vector<InterItem> &items,
-                              std::vector<IntraItem> &intra, int sol_index, int parts) {
-    const int Q = S->Q, tr = S->tile_rows;
-    for (int s0 = 0; s0 < Q; s0 += tr)
-        for (int p = 0; p < parts; ++p)
-            items.push_back(InterItem{sol_index, s0, std::min(Q, s0 + tr), p | (parts << 16)});
+                              std::vector<IntraItem> &intra, int sol_index) {
+    for_each_item(S->Q, S->tile_rows,
+                  [&](int s0, int s1, int c0) { items.push_back(InterItem{sol_index, s0, s1, c0}); });
     for (int r = 0; r < S->R; ++r) intra.push_back(IntraItem{sol_index, r});
 }
 
@@ -275,14 +289,9 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     if (R < 1) return fail(TGA_ERANGE, "R = %d < 1", R);
     if ((int64_t)n + R > TGA_MAX_Q) return fail(TGA_ERANGE, "n + R = %lld > %d", (long long)n + R, TGA_MAX_Q);
     if ((int64_t)(n + R + 1) * inst->maxD >= (1 << 30)) return fail(TGA_ERANGE, "total distance may exceed 2^30");
-    if (offsets[0] != 0 || offsets[R] != n) return fail(TGA_EINVAL, "offsets must start at 0 and end at n");
-    for (int r = 0; r < R; ++r)
-        if (offsets[r + 1] < offsets[r]) return fail(TGA_EINVAL, "offsets decrease at route %d", r);
-    std::vector<char> seen(n + 1, 0);
-    for (int i = 0; i < n; ++i) {
-        const int c = customers[i];
-        if (c < 1 || c > n || seen[c]) return fail(TGA_EINVAL, "customers is not a permutation of 1..n (at %d)", i);
-        seen[c] = 1;
+    {
+        int rc0 = check_partition(n, R, offsets, customers);
+        if (rc0) return rc0;
     }
     const SolLayout L = sol_layout(n, R);
     if (ws_bytes < L.total) return fail(TGA_ENOMEM, "solution workspace %zu < %zu", ws_bytes, L.total);
@@ -344,11 +353,9 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     }
     roff[R] = s;
     nr[Q] = make_int2(0, R);
-    const int nrb = (Q + S->tile_rows - 1) / S->tile_rows;
-    S->parts = std::max(1, std::min(4, (2 * P.cus + nrb - 1) / nrb));
     std::vector<InterItem> items;
     std::vector<IntraItem> intra;
-    build_plain_items(S, items, intra, 0, S->parts);
+    build_plain_items(S, items, intra, 0);
     S->nitems = (int)items.size();
     S->nintra = (int)intra.size();
     if (S->nitems > L.max_items) {
@@ -382,6 +389,46 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     return TGA_OK;
 }
 
+static int check_partition(int n, int R, const int32_t *offsets, const int32_t *customers) {
+    if (offsets[0] != 0 || offsets[R] != n) return fail(TGA_EINVAL, "offsets must start at 0 and end at n");
+    for (int r = 0; r < R; ++r)
+        if (offsets[r + 1] < offsets[r]) return fail(TGA_EINVAL, "offsets decrease at route %d", r);
+    std::vector<char> seen(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const int c = customers[i];
+        if (c < 1 || c > n || seen[c]) return fail(TGA_EINVAL, "customers is not a permutation of 1..n (at %d)", i);
+        seen[c] = 1;
+    }
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, const int32_t *customers,
+                                   void *stream) {
+    if (!sol || !offsets || !customers) return fail(TGA_EINVAL, "null argument");
+    const int n = sol->n, R = sol->R, Q = sol->Q;
+    int rc = check_partition(n, R, offsets, customers);
+    if (rc) return rc;
+    std::vector<int2> nr(Q + 1);
+    std::vector<int32_t> roff(R + 1);
+    int s = 0;
+    for (int r = 0; r < R; ++r) {
+        roff[r] = s;
+        nr[s++] = make_int2(0, r);
+        for (int i = offsets[r]; i < offsets[r + 1]; ++i) nr[s++] = make_int2(customers[i], r);
+    }
+    roff[R] = s;
+    nr[Q] = make_int2(0, R);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(sol->h.nr_alt, nr.data(), sizeof(int2) * (Q + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sol->h.roff_alt, roff.data(), sizeof(int32_t) * (R + 1), hipMemcpyHostToDevice, st));
+    k_reset_state<<<1, 64, 0, st>>>(sol->d, 1, 0);
+    k_build<<<1, kApplyThreads, 0, st>>>(sol->d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    sol->version = 0;
+    return TGA_OK;
+}
+
 extern "C" int tga_free_solution(tga_solution_t sol) {
     delete sol;
     return TGA_OK;
@@ -408,17 +455,18 @@ static void launch_eval(const SolDev *d, const InterItem *items, int nitems, con
         }
     }
     if ((op_mask & (2 | 8 | 16)) && nintra > 0) {
-        const int grid = (nintra + 3) / 4;
+        const int grid = (nintra + kInterWaves - 1) / kInterWaves;
+        const size_t ilds = (size_t)kInterWaves * kIntraRegionBytes;
         if (has_tw) {
             if (dump)
-                k_eval_intra<true, true><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+                k_eval_intra<true, true><<<grid, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
             else
-                k_eval_intra<true, false><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+                k_eval_intra<true, false><<<grid, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
         } else {
             if (dump)
-                k_eval_intra<false, true><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+                k_eval_intra<false, true><<<grid, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
             else
-                k_eval_intra<false, false><<<grid, kIntraThreads, 0, st>>>(d, intra, nintra, op_mask, dd, df);
+                k_eval_intra<false, false><<<grid, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
         }
     }
 }
@@ -513,9 +561,11 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
     HIPCHK(hipGetLastError());
     const int chunk = 16;
     int launched = 0;
-    while (launched <= max_steps) {
-        // max_steps accepted moves need max_steps + 1 evaluations to see the last one stop
-        const int todo = std::min(chunk, max_steps + 1 - launched);
+    // max_steps evaluations suffice: an evaluation either finds no improving
+    // move (converged) or leads to an accepted move, and the cap marks the
+    // solution converged after the max_steps-th accepted move
+    while (launched < max_steps) {
+        const int todo = std::min(chunk, max_steps - launched);
         for (int i = 0; i < todo; ++i) {
             launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
                         sol->lds, sol->nitems, nullptr, nullptr, st);
@@ -587,12 +637,9 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     return off;
 }
 
-static int batch_max_items(const std::vector<tga_solution *> &sols, int tile_rows, int col_split) {
+static int batch_max_items(const std::vector<tga_solution *> &sols, int rows_per_item) {
     long long m = 0;
-    for (auto *s : sols) {
-        const int tr = tile_rows > 0 ? tile_rows : s->tile_rows;
-        m += (long long)((s->Q + tr - 1) / tr) * std::max(1, col_split);
-    }
+    for (auto *s : sols) m += count_items(s->Q, rows_per_item > 0 ? rows_per_item : 1);
     return (int)std::min<long long>(m, 1 << 30);
 }
 
@@ -605,18 +652,18 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
         nintra += s->R;
     }
     size_t a, b, c, d;
-    // worst case over the schedules tga_batch_create accepts: one row per item, 8 parts
-    return batch_layout(v, &a, &b, &c, &d, batch_max_items(v, 1, 8), nintra);
+    // worst case over the schedules tga_batch_create accepts: one row per item
+    return batch_layout(v, &a, &b, &c, &d, batch_max_items(v, 1), nintra);
 }
 
-extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t tile_rows,
-                                int32_t col_split, void *ws, size_t ws_bytes, void *stream,
+extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
+                                int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
                                 tga_batch_t *out) {
     if (!out) return fail(TGA_EINVAL, "out is null");
     *out = nullptr;
     if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
-    if (tile_rows < 0 || tile_rows > 64 || col_split < 0 || col_split > 8)
-        return fail(TGA_ERANGE, "tile_rows in [0, 64], col_split in [0, 8]");
+    if (rows_per_item < 0 || rows_per_item > 256 || sub_rows < 0 || sub_rows > 64)
+        return fail(TGA_ERANGE, "rows_per_item in [0, 256], sub_rows in [0, 64]");
     if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
     std::vector<tga_solution *> v(sols, sols + count);
     for (auto *s : v) {
@@ -630,7 +677,6 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     int rc = props(&P);
     if (rc) return rc;
     if (ws_bytes < tga_batch_workspace_bytes(sols, count)) return fail(TGA_ENOMEM, "batch workspace too small");
-    const int parts = col_split > 0 ? col_split : 1;
     std::vector<InterItem> items;
     std::vector<IntraItem> intra;
     std::vector<SolDev> descs(count);
@@ -638,21 +684,26 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     for (int i = 0; i < count; ++i) {
         tga_solution *s = v[i];
         descs[i] = s->h;
-        const int tr = tile_rows > 0 ? tile_rows : s->tile_rows;
+        // LDS sub-block rows (bounded by the LDS budget of one workgroup) and
+        // rows per work item (a multiple of it, so column attributes loaded
+        // once per item serve about 32 rows)
+        const int tr = sub_rows > 0 ? std::min(sub_rows, s->tile_rows) : s->tile_rows;
+        const int ri = rows_per_item > 0 ? rows_per_item : tr * std::max(1, 32 / tr);
         descs[i].tile_rows = tr;
         lds = std::max(lds, item_lds(s->h.np1, tr));
-        for (int s0 = 0; s0 < s->Q; s0 += tr)
-            for (int p = 0; p < parts; ++p)
-                items.push_back(InterItem{i, s0, std::min(s->Q, s0 + tr), p | (parts << 16)});
+        for_each_item(s->Q, ri, [&](int s0, int s1, int c0) { items.push_back(InterItem{i, s0, s1, c0}); });
         for (int r = 0; r < s->R; ++r) intra.push_back(IntraItem{i, r});
     }
+    lds = std::max(lds, (size_t)kInterWaves * kIntraRegionBytes);  // the intra phase's regions
     if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);
-    // largest first: rows x (columns to the right) estimates the work of an item
-    std::stable_sort(items.begin(), items.end(), [&](const InterItem &a, const InterItem &b) {
-        const long long wa = (long long)(a.s1 - a.s0) * (v[a.sol]->Q - a.s0) / (a.part_parts >> 16);
-        const long long wb = (long long)(b.s1 - b.s0) * (v[b.sol]->Q - b.s0) / (b.part_parts >> 16);
-        return wa > wb;
-    });
+    // largest first (pairs of the item), ties in solution / row order so that
+    // the column segments of one row block run close together in time
+    auto work = [&](const InterItem &a) {
+        const long long cols = std::min<long long>(kSegCols, v[a.sol]->Q - a.c0);
+        return (long long)(a.s1 - a.s0) * cols;
+    };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
     size_t odesc, oitems, ointra, oqueue;
     batch_layout(v, &odesc, &oitems, &ointra, &oqueue, (int)items.size(), (int)intra.size());
     char *base = (char *)ws;
@@ -666,11 +717,12 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->queue = (int *)(base + oqueue);
     B->lds = lds;
     const int per_cu = std::max(1, (int)(160 * 1024 / std::max<size_t>(lds, 1)));
-    B->grid_inter = std::min(B->nitems, P.cus * std::min(per_cu, 4));
+    B->grid_inter = std::min(B->nitems, P.cus * std::min(per_cu, 2));
     B->grid_intra = std::min((B->nintra + 3) / 4, P.cus * 8);
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
+    B->cap_stream = nullptr;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(B->d, descs.data(), sizeof(SolDev) * count, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -691,11 +743,19 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     return TGA_OK;
 }
 
-static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
-    if ((op_mask & 7) || (op_mask & (2 | 8 | 16)))
+static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
+    if (op_mask & TGA_OP_ALL)
         k_eval_mixed<<<std::max(B->grid_inter, B->grid_intra), kInterThreads, B->lds, st>>>(
             B->d, B->items, B->nitems, B->intra, B->nintra, op_mask, B->queue);
-    k_finalize_batch<<<(int)B->sols.size(), kApplyThreads, 0, st>>>(B->d, mode, op_mask, B->queue);
+}
+
+static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
+    k_finalize<<<(int)B->sols.size(), kApplyThreads, 0, st>>>(B->d, mode, op_mask);
+}
+
+static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
+    batch_eval_launch(B, op_mask, st);
+    batch_finalize_launch(B, op_mask, mode, st);
 }
 
 extern "C" int tga_batch_reset(tga_batch_t B, void *stream) {
@@ -737,10 +797,11 @@ extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, 
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, steps);
     k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     HIPCHK(hipGetLastError());
-    // steps accepted moves need steps + 1 evaluations to observe the stop
-    const int evals = steps + 1;
+    // `steps` evaluations per solution suffice (see tga_ls_run)
+    const int evals = steps;
     if (use_graph) {
-        if (!B->exec || B->graph_steps != evals || B->graph_mask != op_mask || B->graph_stream != st) {
+        if (!B->cap_stream) HIPCHK(hipStreamCreate(&B->cap_stream));
+        if (!B->exec || B->graph_steps != evals || B->graph_mask != op_mask) {
             if (B->exec) {
                 (void)hipGraphExecDestroy(B->exec);
                 B->exec = nullptr;
@@ -749,15 +810,14 @@ extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, 
                 (void)hipGraphDestroy(B->graph);
                 B->graph = nullptr;
             }
-            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < evals; ++i) batch_step(B, op_mask, kModeLS, st);
+            HIPCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < evals; ++i) batch_step(B, op_mask, kModeLS, B->cap_stream);
             hipGraph_t g = nullptr;
-            HIPCHK(hipStreamEndCapture(st, &g));
+            HIPCHK(hipStreamEndCapture(B->cap_stream, &g));
             B->graph = g;
             HIPCHK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
             B->graph_steps = evals;
             B->graph_mask = op_mask;
-            B->graph_stream = st;
         }
         HIPCHK(hipGraphLaunch(B->exec, st));
     } else {
@@ -765,6 +825,36 @@ extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, 
         HIPCHK(hipGetLastError());
     }
     return batch_collect(B, steps_done, moves_evaluated, cost, st);
+}
+
+extern "C" int tga_batch_begin(tga_batch_t B, int32_t max_steps, void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    if (max_steps < 0) return fail(TGA_EINVAL, "max_steps < 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, max_steps);
+    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
+    HIPCHK(hipGetLastError());
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_step_part(tga_batch_t B, uint32_t op_mask, int32_t part, void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (part != 0 && part != 1) return fail(TGA_EINVAL, "part must be 0 (evaluate) or 1 (finalize)");
+    hipStream_t st = (hipStream_t)stream;
+    if (part == 0)
+        batch_eval_launch(B, op_mask, st);
+    else
+        batch_finalize_launch(B, op_mask, kModeLS, st);
+    HIPCHK(hipGetLastError());
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_collect(tga_batch_t B, int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
+                                 void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    return batch_collect(B, steps_done, moves_evaluated, cost, (hipStream_t)stream);
 }
 
 extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best, int32_t *status, void *stream) {
@@ -794,6 +884,7 @@ extern "C" int tga_batch_free(tga_batch_t B) {
     if (!B) return TGA_OK;
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
     for (auto *s : B->sols) s->in_batch = 0;
     delete B;
     return TGA_OK;

@@ -23,9 +23,11 @@
 
 namespace tga {
 
-constexpr int kInterThreads = 256;  // 4 wavefronts
-constexpr int kInterWaves = kInterThreads / 64;
+constexpr int kInterWaves = 8;      // wavefronts per inter-route workgroup
+constexpr int kInterThreads = kInterWaves * 64;
 constexpr int kColsPerWave = 62;    // lanes 1..62 own a column; 0 and 63 are halo
+constexpr int kChunks = 2;          // column chunks per wavefront
+constexpr int kSegCols = kInterWaves * kChunks * kColsPerWave;  // columns per work item
 constexpr int kIntraThreads = 256;
 constexpr int kApplyThreads = 1024;
 constexpr int kTwOff = 1 << 28;     // due time standing for "no window" (CVRP)
@@ -390,18 +392,63 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
 }
 
 // ------------------------------------------------------ inter-route eval ---
-// One work item = rows [s0, s1) (slots, route-major) against every column
-// slot of a later route (column part `part` of `parts`).  For each unordered
-// pair of slots (s, t) in different routes, route(s) < route(t), the fused
-// pass evaluates RELOCATE s->after t, RELOCATE t->after s, SWAP s<->t and
-// 2OPT*(s, t) (the node-based extraction of Section 5.3.1, eq. node_based1 and
-// eq. node_based2, over the positional attributes).
+// One work item = rows [s0, s1) (slots, route-major) against the column slots
+// [c0, c0 + kSegCols).  For each unordered pair of slots (s, t) in different
+// routes, route(s) < route(t), the fused pass evaluates RELOCATE s->after t,
+// RELOCATE t->after s, SWAP s<->t and 2OPT*(s, t) (the node-based extraction
+// of Section 5.3.1, eq. node_based1 and eq. node_based2, over the positional
+// attributes).
 //
-// The D rows of the item's slots (plus one halo row on each side) are staged
-// in LDS; a lane gathers D[row][node(t)] from LDS once per row and gets
-// D[row][succ(t)] and D[row][pred(t)] from its neighbour lanes, and
-// D[pred(s)][t], D[succ(s)][t] from the previous and next row of a register
-// window.
+// Each wavefront owns kChunks column chunks for the whole item and keeps their
+// attributes in registers.  Rows stream through LDS in sub-blocks of
+// S.tile_rows rows plus one halo row on each side, copied straight from HBM
+// into LDS (global_load_lds).  A lane gathers D[row][node(t)] from LDS once
+// per row and takes D[row][succ(t)] and D[row][pred(t)] from its neighbour
+// lanes (DPP wavefront shifts), D[pred(s)][t] and D[succ(s)][t] from the
+// previous and next row of a register window.
+
+typedef __attribute__((address_space(3))) void *lds_void_ptr;
+typedef __attribute__((address_space(1))) void *global_void_ptr;
+
+// lane i receives lane i+1 (lane 63 receives 0)
+__device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+// lane i receives lane i-1 (lane 0 receives 0)
+__device__ __forceinline__ int from_prev_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+
+struct LaneCol {
+    int4 ta, tb, tt, tw;
+    int node, fl, refT, routeLast;
+    bool own, cust;
+};
+
+// Stage rows [first, first + cnt) of S (clamped to the slot range) into LDS:
+// their attributes, then their D rows.  Caller synchronises afterwards.
+template <bool TW>
+__device__ __forceinline__ void stage_rows(const SolDev &S, int first, int cnt, int4 *rowa, int4 *rowb,
+                                           int4 *rowt, int4 *roww, int *rows) {
+    const int Q = S.Q, np1 = S.np1;
+    for (int k = threadIdx.x; k < cnt; k += kInterThreads) {
+        const int s = min(max(first + k, 0), Q);
+        rowa[k] = S.a4[s];
+        rowb[k] = S.b4[s];
+        if (TW) {
+            rowt[k] = S.t4[s];
+            roww[k] = S.w4[s];
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k < cnt; k += kInterWaves) {
+        const int s = min(max(first + k, 0), Q);
+        const int node = nodeof(S.a4[s].x);
+        const int *src = S.D + (size_t)node * np1;
+        int *dst = rows + k * np1;
+        for (int c = 0; c < np1; c += 64) {
+            if (c + lane < np1)
+                __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
 
 // Whole-workgroup evaluation of one inter-route item.  smem4 is the dynamic
 // LDS area; red holds kInterWaves keys.
@@ -411,64 +458,64 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
                            int4 *smem4, unsigned long long *red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool opRel = op_mask & 1, opSwap = op_mask & 2, op2s = op_mask & 4;
-    {
-        const int Q = S.Q, np1 = S.np1, n = S.n, cap = S.cap;
-        const int s0 = item.s0, s1 = item.s1, nrow = s1 - s0 + 2;
-        int4 *rowa = smem4;
-        int4 *rowb = rowa + nrow;
-        int4 *rowt = rowb + nrow;
-        int4 *roww = rowt + nrow;
-        int *rows = (int *)(roww + nrow);
+    const int Q = S.Q, np1 = S.np1, n = S.n, cap = S.cap, tr = S.tile_rows;
+    const uint32_t uQ = (uint32_t)Q;
+    const int cend = min(Q, item.c0 + kSegCols);
 
-        if ((int)threadIdx.x < nrow) {
-            const int s = min(max(s0 - 1 + (int)threadIdx.x, 0), Q);
-            rowa[threadIdx.x] = S.a4[s];
-            rowb[threadIdx.x] = S.b4[s];
-            if (TW) {
-                rowt[threadIdx.x] = S.t4[s];
-                roww[threadIdx.x] = S.w4[s];
-            }
+    // column chunks of this wavefront: attributes stay in registers
+    LaneCol col[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int cb = item.c0 + (c * kInterWaves + wave) * kColsPerWave;
+        const int t = cb - 1 + lane;
+        const int tc = min(max(t, 0), Q);
+        LaneCol &L = col[c];
+        L.own = lane >= 1 && lane <= kColsPerWave && t < cend;
+        L.ta = S.a4[tc];
+        L.tb = S.b4[tc];
+        if (TW) {
+            L.tt = S.t4[tc];
+            L.tw = S.w4[tc];
+        } else {
+            L.tt = make_int4(0, 0, 0, 0);
+            L.tw = make_int4(0, 0, 0, 0);
         }
-        __syncthreads();
-        for (int k = 0; k < nrow; ++k) {
-            const int *src = S.D + (size_t)nodeof(rowa[k].x) * np1;
-            int *dst = rows + k * np1;
-            for (int c = threadIdx.x; c < np1; c += kInterThreads) dst[c] = src[c];
-        }
-        __syncthreads();
+        L.node = nodeof(L.ta.x);
+        L.fl = flagsof(L.ta.x);
+        L.cust = L.fl & kFlagCustomer;
+        L.refT = L.cust ? L.node - 1 : n + L.ta.y;
+        // route of the last owned column (-1: chunk empty)
+        const int lastLane = min(kColsPerWave, cend - cb);
+        const int rl = __shfl(L.ta.y, max(lastLane, 0));
+        L.routeLast = lastLane >= 1 ? rl : -1;
+    }
 
-        int bd = kNoDelta;
-        uint32_t bid = 0xFFFFFFFFu;
-        const int cstart = S.roff[rowa[1].y + 1];
-        const int ncols = Q - cstart;
-        const int parts = item.part_parts >> 16, part = item.part_parts & 0xFFFF;
-        const int per = (ncols + parts - 1) / parts;
-        const int cbeg = cstart + part * per;
-        const int cend = min(Q, cbeg + per);
-        const uint32_t uQ = (uint32_t)Q;
+    int bd = kNoDelta;
+    uint32_t bid = 0xFFFFFFFFu;
+    int4 *rowa = smem4;
+    int4 *rowb = rowa + (tr + 2);
+    int4 *rowt = rowb + (tr + 2);
+    int4 *roww = rowt + (tr + 2);
+    int *rows = (int *)(roww + (tr + 2));
 
-        for (int cb = cbeg + wave * kColsPerWave; cb < cend; cb += kInterWaves * kColsPerWave) {
-            const int t = cb - 1 + lane;
-            const int tc = min(max(t, 0), Q);
-            const bool own = lane >= 1 && lane <= kColsPerWave && t < cend;
-            const int4 ta = S.a4[tc];
-            const int4 tb = S.b4[tc];
-            int4 tt = make_int4(0, 0, 0, 0), tw = make_int4(0, 0, 0, 0);
-            if (TW) {
-                tt = S.t4[tc];
-                tw = S.w4[tc];
-            }
-            const int lastLane = min(kColsPerWave, cend - cb);
-            const int routeLast = __shfl(ta.y, lastLane);
-            const int nodeT = nodeof(ta.x);
-            const int flT = flagsof(ta.x);
-            const bool tCust = flT & kFlagCustomer;
-            const uint32_t refT = tCust ? nodeT - 1 : n + ta.y;
+    for (int sb = item.s0; sb < item.s1; sb += tr) {
+        const int nr = min(tr, item.s1 - sb);  // rows of this sub-block
+        __syncthreads();                       // previous sub-block fully consumed
+        stage_rows<TW>(S, sb - 1, nr + 2, rowa, rowb, rowt, roww, rows);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const LaneCol &L = col[c];
+            const int4 ta = L.ta, tb = L.tb, tt = L.tt, tw = L.tw;
+            const int nodeT = L.node, flT = L.fl;
+            const bool tCust = L.cust;
+            const uint32_t refT = (uint32_t)L.refT;
+            if (L.routeLast <= rowa[1].y) continue;  // nothing to the right of this sub-block
             int gp = rows[nodeT];
             int g = rows[np1 + nodeT];
-            for (int k = 1; k <= nrow - 2; ++k) {
+            for (int k = 1; k <= nr; ++k) {
                 const int4 ra = rowa[k];
-                if (routeLast <= ra.y) break;
+                if (L.routeLast <= ra.y) break;
                 const int4 rb = rowb[k];
                 int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
                 if (TW) {
@@ -476,9 +523,9 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
                     rw = roww[k];
                 }
                 const int gn = rows[(k + 1) * np1 + nodeT];
-                const int gR = __shfl_down(g, 1);  // D[s][succ(t)]
-                const int gL = __shfl_up(g, 1);    // D[s][pred(t)]
-                const bool pair = own && ta.y > ra.y;
+                const int gR = from_next_lane(g);  // D[s][succ(t)]
+                const int gL = from_prev_lane(g);  // D[s][pred(t)]
+                const bool pair = L.own && ta.y > ra.y;
                 const int flS = flagsof(ra.x);
                 const bool sCust = flS & kFlagCustomer;
                 const uint32_t refS = sCust ? nodeof(ra.x) - 1 : n + ra.y;
@@ -559,12 +606,12 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
                 g = gn;
             }
         }
-        block_argmin_commit(bd, bid, S.best_key, red);
     }
+    block_argmin_commit(bd, bid, S.best_key, red);
 }
 
 template <bool TW, bool DUMP>
-__global__ __launch_bounds__(kInterThreads) void k_eval_inter(const SolDev *__restrict__ sols,
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_inter(const SolDev *__restrict__ sols,
                                                               const InterItem *__restrict__ items,
                                                               int nitems, uint32_t op_mask,
                                                               int32_t *__restrict__ dump_delta,
@@ -584,176 +631,222 @@ __global__ __launch_bounds__(kInterThreads) void k_eval_inter(const SolDev *__re
 // eq. 2_opt, eq. ext_intra_relocate, eq. ext_intra_swap).  Lane i takes the
 // first position i; the second position j walks the route while the
 // summaries of the middle segments grow by one node per step, so every move
-// costs O(1).  Distances come from D in global memory (L2 resident).
+// costs O(1).  Positions p = 0..L+1 index the route (0 and L+1 are the
+// depot).  A route that fits the wavefront's LDS region is staged there
+// first (per-position data and the (L+2)^2 distance sub-block), so the walks
+// never wait on global memory; a longer route reads the same values from
+// the slot arrays and D directly.
 
-// One wavefront evaluates every intra-route move of one route and commits
-// its best to the solution's key.
-template <bool TW, bool DUMP>
-__device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
-                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas) {
+constexpr int kIntraRegionBytes = 8192;  // LDS per wavefront in the intra phase
+constexpr int kIntraMaxPos = 40;         // positions (L + 2) staged in a region
+
+// Staged view: seven per-position arrays and the distance sub-block.
+struct RouteLds {
+    const int *pn, *pe, *pdep, *pz, *pe_, *pl, *ps, *dm;
+    int stride;
+    __device__ int node(int p) const { return pn[p]; }
+    __device__ int edge(int p) const { return pe[p]; }
+    __device__ int dep(int p) const { return pdep[p]; }
+    __device__ int z(int p) const { return pz[p]; }
+    __device__ int e(int p) const { return pe_[p]; }
+    __device__ int l(int p) const { return pl[p]; }
+    __device__ int s(int p) const { return ps[p]; }
+    __device__ int dd(int p, int q) const { return dm[p * stride + q]; }
+};
+
+// Direct view over the slot arrays of route r.
+struct RouteGlobal {
+    const SolDev *S;
+    int off, L, l0;
+    __device__ int node(int p) const { return p <= L ? nodeof(S->a4[off + p].x) : 0; }
+    __device__ int edge(int p) const { return S->a4[off + p].z; }
+    __device__ int dep(int p) const { return S->t4[off + p].x; }
+    __device__ int z(int p) const { return p <= L ? S->t4[off + p].w : l0; }
+    __device__ int e(int p) const { return S->w4[off + p].x; }
+    __device__ int l(int p) const { return S->w4[off + p].y; }
+    __device__ int s(int p) const { return S->w4[off + p].z; }
+    __device__ int dd(int p, int q) const { return S->D[(size_t)node(p) * S->np1 + node(q)]; }
+};
+
+template <bool TW, bool DUMP, class RV>
+__device__ void intra_moves(const SolDev &S, const RV &V, int r, int L, uint32_t op_mask,
+                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas, int &bd,
+                            uint32_t &bid) {
     const int lane = threadIdx.x & 63;
     const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
-    int bd = kNoDelta;
-    uint32_t bid = 0xFFFFFFFFu;
-    {
-        {
-            const int r = item.route;
-            const int off = S.roff[r];
-            const int L = S.roff[r + 1] - off - 1;
-            const int n = S.n, np1 = S.np1;
-            const uint32_t uQ = (uint32_t)S.Q;
-            const int32_t *D = S.D;
-            const bool capOK = S.b4[off].z <= S.cap;
-            const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
-            auto node = [&](int p) { return p <= L ? nodeof(S.a4[off + p].x) : 0; };
-            auto edge = [&](int p) { return S.a4[off + p].z; };
-            auto dep = [&](int p) { return S.t4[off + p].x; };
-            auto zat = [&](int p) { return p <= L ? S.t4[off + p].w : l0; };
-            auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(node(p) - 1); };
-            auto dd = [&](int x, int y) { return D[(size_t)x * np1 + y]; };
-            auto segAt = [&](int p) {
-                const int4 w = S.w4[off + p];
-                return seg_node(w.x, w.y, w.z);
-            };
-            for (int i = lane + 1; i <= L; i += 64) {
-                const int ci = node(i), cp = node(i - 1);
-                const int eP = edge(i - 1);  // c(c_{i-1}, c_i)
-                const int depP = TW ? dep(i - 1) : 0;
-                const uint32_t refI = ref(i);
-                const int cI1 = node(i + 1);
-                // ---- 2OPT(i, j) and SWAP(i, j), j > i
-                if (op2o || opSwap) {
-                    Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};
-                    Seg mid = Seg{0, 0, 0, true};
-                    for (int j = i + 1; j <= L; ++j) {
-                        const int cj = node(j), cj1 = node(j + 1);
-                        const int ej = edge(j), ejm = edge(j - 1);
-                        const int z1 = TW ? zat(j + 1) : 0;
-                        if (TW) rev = seg_cat(segAt(j), ejm, rev);
-                        const int d1 = dd(cp, cj), d2 = dd(ci, cj1);
-                        const int dlt2 = d1 + d2 - eP - ej;
-                        bool tw2 = true;
-                        if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= z1;
-                        const uint32_t refJ = ref(j);
-                        const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
-                        int dS = dlt2;
-                        bool twS = tw2;
-                        if (j > i + 1) {
-                            const int cjm = node(j - 1);
-                            const int dA = dd(cj, cI1), dB = dd(cjm, ci);
-                            dS = d1 + dA + dB + d2 - eP - edge(i) - ejm - ej;
-                            if (TW) {
-                                const int4 wj = S.w4[off + j], wi = S.w4[off + i];
-                                const int arr0 = depP + d1;
-                                bool ok = arr0 <= wj.y;
-                                const int t0 = max(arr0, wj.x) + wj.z;
-                                const int dM = seg_pass(mid, t0 + dA);
-                                const int arrI = dM + dB;
-                                ok = ok && dM < kInf && arrI <= wi.y;
-                                const int t2 = max(arrI, wi.x) + wi.z;
-                                twS = ok && (t2 + d2 <= z1);
-                            }
-                        }
-                        if (op2o) {
-                            const uint32_t id = (12u * uQ + lo) * uQ + hi;
-                            if (DUMP) {
-                                dump_delta[id] = dlt2;
-                                dump_feas[id] = (uint8_t)(capOK | (tw2 << 1));
-                            }
-                            if (capOK && tw2) consider(dlt2, id, bd, bid);
-                        }
-                        if (opSwap) {
-                            const uint32_t id = (5u * uQ + lo) * uQ + hi;
-                            if (DUMP) {
-                                dump_delta[id] = dS;
-                                dump_feas[id] = (uint8_t)(capOK | (twS << 1));
-                            }
-                            if (capOK && twS) consider(dS, id, bd, bid);
-                        }
-                        // middle c_{i+1} .. c_j for the next j
-                        if (TW) mid = (j == i + 1) ? segAt(j) : seg_cat(mid, ejm, segAt(j));
-                    }
-                }
-                if (!opOr) continue;
-                // ---- OR-OPT forward: segment c_i..c_{i+k-1} after c_j, j >= i+k
-                for (int k = 1; k <= 3; ++k) {
-                    if (i + k - 1 > L) break;
-                    const int f = ci, g = node(i + k - 1), w = node(i + k);
-                    const int eG = edge(i + k - 1);  // c(g, w)
-                    const int dPW = dd(cp, w);
-                    const int base = dPW - eP - eG;
-                    Seg sig = Seg{0, 0, 0, true};
+    const int n = S.n;
+    const uint32_t uQ = (uint32_t)S.Q;
+    const bool capOK = S.b4[S.roff[r]].z <= S.cap;
+    auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(V.node(p) - 1); };
+    auto segAt = [&](int p) { return seg_node(V.e(p), V.l(p), V.s(p)); };
+#pragma unroll 1
+    for (int i = lane + 1; i <= L; i += 64) {
+        const int eP = V.edge(i - 1);  // c(c_{i-1}, c_i)
+        const int depP = TW ? V.dep(i - 1) : 0;
+        const uint32_t refI = ref(i);
+        // ---- 2OPT(i, j) and SWAP(i, j), j > i
+        if (op2o || opSwap) {
+            Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};
+            Seg mid = Seg{0, 0, 0, true};
+#pragma unroll 1
+            for (int j = i + 1; j <= L; ++j) {
+                const int ej = V.edge(j), ejm = V.edge(j - 1);
+                if (TW) rev = seg_cat(segAt(j), ejm, rev);
+                const int d1 = V.dd(i - 1, j), d2 = V.dd(i, j + 1);
+                const int dlt2 = d1 + d2 - eP - ej;
+                bool tw2 = true;
+                if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
+                const uint32_t refJ = ref(j);
+                const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
+                int dS = dlt2;
+                bool twS = tw2;
+                if (j > i + 1) {
+                    const int dA = V.dd(j, i + 1), dB = V.dd(j - 1, i);
+                    dS = d1 + dA + dB + d2 - eP - V.edge(i) - ejm - ej;
                     if (TW) {
-                        sig = segAt(i);
-                        for (int q = 1; q < k; ++q) sig = seg_cat(sig, edge(i + q - 1), segAt(i + q));
-                    }
-                    Seg mid = Seg{0, 0, 0, true};
-                    for (int j = i + k; j <= L; ++j) {
-                        const int v = node(j), v1 = node(j + 1);
-                        if (TW) mid = (j == i + k) ? segAt(j) : seg_cat(mid, edge(j - 1), segAt(j));
-                        const int dVF = dd(v, f), dGV = dd(g, v1);
-                        const int dlt = base + dVF + dGV - edge(j);
-                        bool tw = true;
-                        if (TW) {
-                            const int dm = seg_pass(mid, depP + dPW);
-                            const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
-                            tw = ds < kInf && ds + dGV <= zat(j + 1);
-                        }
-                        const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
-                        if (DUMP) {
-                            dump_delta[id] = dlt;
-                            dump_feas[id] = (uint8_t)(capOK | (tw << 1));
-                        }
-                        if (capOK && tw) consider(dlt, id, bd, bid);
+                        const int arr0 = depP + d1;
+                        bool ok = arr0 <= V.l(j);
+                        const int t0 = max(arr0, V.e(j)) + V.s(j);
+                        const int dM = seg_pass(mid, t0 + dA);
+                        const int arrI = dM + dB;
+                        ok = ok && dM < kInf && arrI <= V.l(i);
+                        const int t2 = max(arrI, V.e(i)) + V.s(i);
+                        twS = ok && (t2 + d2 <= V.z(j + 1));
                     }
                 }
-                // ---- OR-OPT backward: after c_j, j <= i-2 (all k at once)
-                if (i >= 2) {
-                    int gk[3], wk[3], baseK[3], dGW[3], zK[3];
-                    Seg sigK[3];
-                    int kmax = 0;
-                    for (int k = 1; k <= 3; ++k) {
-                        if (i + k - 1 > L) break;
-                        kmax = k;
-                        gk[k - 1] = node(i + k - 1);
-                        wk[k - 1] = node(i + k);
-                        baseK[k - 1] = dd(cp, wk[k - 1]) - eP - edge(i + k - 1);
-                        if (TW) {
-                            dGW[k - 1] = dd(cp, wk[k - 1]);
-                            zK[k - 1] = zat(i + k);
-                            Seg sg = segAt(i);
-                            for (int q = 1; q < k; ++q) sg = seg_cat(sg, edge(i + q - 1), segAt(i + q));
-                            sigK[k - 1] = sg;
-                        }
+                if (op2o) {
+                    const uint32_t id = (12u * uQ + lo) * uQ + hi;
+                    if (DUMP) {
+                        dump_delta[id] = dlt2;
+                        dump_feas[id] = (uint8_t)(capOK | (tw2 << 1));
                     }
-                    Seg mid = Seg{0, 0, 0, true};
-                    for (int j = i - 2; j >= 0; --j) {
-                        const int v = node(j), v1 = node(j + 1);
-                        if (TW) mid = (j == i - 2) ? segAt(i - 1) : seg_cat(segAt(j + 1), edge(j + 1), mid);
-                        const int dVF = dd(v, ci);
-                        const int ej = edge(j);
-                        const int depJ = TW ? dep(j) : 0;
-                        const uint32_t refJ = ref(j);
-                        for (int k = 1; k <= kmax; ++k) {
-                            const int dGV = dd(gk[k - 1], v1);
-                            const int dlt = baseK[k - 1] + dVF + dGV - ej;
-                            bool tw = true;
-                            if (TW) {
-                                const int ds = seg_pass(sigK[k - 1], depJ + dVF);
-                                const int dm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
-                                tw = dm < kInf && dm + dGW[k - 1] <= zK[k - 1];
-                            }
-                            const uint32_t id = ((16u + k) * uQ + refI) * uQ + refJ;
-                            if (DUMP) {
-                                dump_delta[id] = dlt;
-                                dump_feas[id] = (uint8_t)(capOK | (tw << 1));
-                            }
-                            if (capOK && tw) consider(dlt, id, bd, bid);
-                        }
-                    }
+                    if (capOK && tw2) consider(dlt2, id, bd, bid);
                 }
+                if (opSwap) {
+                    const uint32_t id = (5u * uQ + lo) * uQ + hi;
+                    if (DUMP) {
+                        dump_delta[id] = dS;
+                        dump_feas[id] = (uint8_t)(capOK | (twS << 1));
+                    }
+                    if (capOK && twS) consider(dS, id, bd, bid);
+                }
+                // middle c_{i+1} .. c_j for the next j
+                if (TW) mid = (j == i + 1) ? segAt(j) : seg_cat(mid, ejm, segAt(j));
             }
         }
+        if (!opOr) continue;
+#pragma unroll 1
+        for (int k = 1; k <= 3; ++k) {
+            if (i + k - 1 > L) break;
+            // segment c_i..c_{i+k-1} (first f = i, last g = i+k-1), followed by w = i+k
+            const int g = i + k - 1, w = i + k;
+            const int eG = V.edge(g);  // c(g, w)
+            const int dPW = V.dd(i - 1, w);
+            const int base = dPW - eP - eG;
+            Seg sig = Seg{0, 0, 0, true};
+            if (TW) {
+                sig = segAt(i);
+#pragma unroll 1
+                for (int q = 1; q < k; ++q) sig = seg_cat(sig, V.edge(i + q - 1), segAt(i + q));
+            }
+            // ---- forward: right after c_j, j >= i+k (middle c_{i+k} .. c_j)
+            Seg mid = Seg{0, 0, 0, true};
+#pragma unroll 1
+            for (int j = w; j <= L; ++j) {
+                if (TW) mid = (j == w) ? segAt(j) : seg_cat(mid, V.edge(j - 1), segAt(j));
+                const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
+                const int dlt = base + dVF + dGV - V.edge(j);
+                bool tw = true;
+                if (TW) {
+                    const int dm = seg_pass(mid, depP + dPW);
+                    const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
+                    tw = ds < kInf && ds + dGV <= V.z(j + 1);
+                }
+                const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
+                if (DUMP) {
+                    dump_delta[id] = dlt;
+                    dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                }
+                if (capOK && tw) consider(dlt, id, bd, bid);
+            }
+            // ---- backward: right after c_j, j <= i-2 (middle c_{j+1} .. c_{i-1})
+            const int zW = TW ? V.z(w) : 0;
+            mid = Seg{0, 0, 0, true};
+#pragma unroll 1
+            for (int j = i - 2; j >= 0; --j) {
+                if (TW) mid = (j == i - 2) ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
+                const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
+                const int dlt = base + dVF + dGV - V.edge(j);
+                bool tw = true;
+                if (TW) {
+                    const int ds = seg_pass(sig, V.dep(j) + dVF);
+                    const int dmm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
+                    tw = dmm < kInf && dmm + dPW <= zW;
+                }
+                const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
+                if (DUMP) {
+                    dump_delta[id] = dlt;
+                    dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                }
+                if (capOK && tw) consider(dlt, id, bd, bid);
+            }
+        }
+    }
+}
+
+// One wavefront evaluates every intra-route move of one route and commits
+// its best to the solution's key.  region: this wavefront's LDS bytes
+// (kIntraRegionBytes).
+template <bool TW, bool DUMP>
+__device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
+                            int *region) {
+    const int lane = threadIdx.x & 63;
+    int bd = kNoDelta;
+    uint32_t bid = 0xFFFFFFFFu;
+    const int r = item.route;
+    const int off = S.roff[r];
+    const int L = S.roff[r + 1] - off - 1;
+    const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
+    const int P = L + 2;
+    if (P <= kIntraMaxPos) {
+        int *pn = region, *pe = pn + P, *pdep = pe + P, *pz = pdep + P, *pe_ = pz + P, *pl = pe_ + P,
+            *ps = pl + P, *dm = ps + P;
+        for (int p = lane; p < P; p += 64) {
+            if (p <= L) {
+                const int4 a = S.a4[off + p];
+                pn[p] = nodeof(a.x);
+                pe[p] = a.z;
+                if (TW) {
+                    const int4 t = S.t4[off + p];
+                    const int4 w = S.w4[off + p];
+                    pdep[p] = t.x;
+                    pz[p] = t.w;
+                    pe_[p] = w.x;
+                    pl[p] = w.y;
+                    ps[p] = w.z;
+                }
+            } else {
+                pn[p] = 0;
+                pe[p] = 0;
+                pz[p] = l0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        const int np1 = S.np1;
+        for (int x = lane; x < P * P; x += 64) {
+            const int p = x / P, q = x - p * P;
+            dm[x] = S.D[(size_t)pn[p] * np1 + pn[q]];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const RouteLds V{pn, pe, pdep, pz, pe_, pl, ps, dm, P};
+        intra_moves<TW, DUMP>(S, V, r, L, op_mask, dump_delta, dump_feas, bd, bid);
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        const RouteGlobal V{&S, off, L, l0};
+        intra_moves<TW, DUMP>(S, V, r, L, op_mask, dump_delta, dump_feas, bd, bid);
     }
     // per-wave commit (waves of one block may serve different solutions)
     wave_argmin(bd, bid);
@@ -761,18 +854,19 @@ __device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_
 }
 
 template <bool TW, bool DUMP>
-__global__ __launch_bounds__(kIntraThreads) void k_eval_intra(const SolDev *__restrict__ sols,
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_intra(const SolDev *__restrict__ sols,
                                                               const IntraItem *__restrict__ items,
                                                               int nitems, uint32_t op_mask,
                                                               int32_t *__restrict__ dump_delta,
                                                               uint8_t *__restrict__ dump_feas) {
+    extern __shared__ int4 smem4[];
     const int wave = threadIdx.x >> 6;
-    const int wpb = kIntraThreads / 64;
-    for (int itx = blockIdx.x * wpb + wave; itx < nitems; itx += gridDim.x * wpb) {
+    int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+    for (int itx = blockIdx.x * kInterWaves + wave; itx < nitems; itx += gridDim.x * kInterWaves) {
         const IntraItem item = items[itx];
         const SolDev &S = sols[item.sol];
         if (S.state[kStDone]) continue;
-        intra_route<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas);
+        intra_route<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
     }
 }
 
@@ -780,9 +874,10 @@ __global__ __launch_bounds__(kIntraThreads) void k_eval_intra(const SolDev *__re
 // Workgroups pull inter-route items from queue[0] (whole workgroup per item,
 // largest items first), then single routes from queue[1] (one wavefront per
 // route).  Solutions of both problem types share the launch; each item takes
-// the window-aware or the capacity-only path of its own solution.  The
-// finalize kernel that follows resets both queue heads.
-__global__ __launch_bounds__(kInterThreads) void k_eval_mixed(const SolDev *__restrict__ sols,
+// the window-aware or the capacity-only path of its own solution.  The last
+// workgroup to finish resets the queue heads, so consecutive launches (also
+// inside a captured graph) need no reset in between.
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_mixed(const SolDev *__restrict__ sols,
                                                               const InterItem *__restrict__ items,
                                                               int nitems,
                                                               const IntraItem *__restrict__ intra,
@@ -817,10 +912,23 @@ __global__ __launch_bounds__(kInterThreads) void k_eval_mixed(const SolDev *__re
             const IntraItem item = intra[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
+            int *region = (int *)smem4 + (threadIdx.x >> 6) * (kIntraRegionBytes / 4);
             if (S.has_tw)
-                intra_route<true, false>(S, item, op_mask, nullptr, nullptr);
+                intra_route<true, false>(S, item, op_mask, nullptr, nullptr, region);
             else
-                intra_route<false, false>(S, item, op_mask, nullptr, nullptr);
+                intra_route<false, false>(S, item, op_mask, nullptr, nullptr, region);
+        }
+    }
+    // every workgroup has taken its last item from both queues before it
+    // counts itself finished; the last one resets the queue for the next launch
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[2], 1) == (int)gridDim.x - 1) {
+            atomicExch(&queue[0], 0);
+            atomicExch(&queue[1], 0);
+            atomicExch(&queue[2], 0);
+            __threadfence();
         }
     }
 }
@@ -1009,15 +1117,6 @@ __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__rest
     finalize_block(sols[blockIdx.x], mode, op_mask);
 }
 
-__global__ __launch_bounds__(kApplyThreads) void k_finalize_batch(const SolDev *__restrict__ sols,
-                                                                  int mode, uint32_t op_mask,
-                                                                  int *__restrict__ queue) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        queue[0] = 0;
-        queue[1] = 0;
-    }
-    finalize_block(sols[blockIdx.x], mode, op_mask);
-}
 
 // ------------------------------------------------------ instance checks ----
 // out[0] |= 1 value out of range, 2 asymmetric, 4 nonzero diagonal,

@@ -68,10 +68,10 @@ enum {
     kAccCount = 8
 };
 
-// Inter-route work item: rows [s0, s1) against the columns of the later
-// routes, column part `part` of `parts`.
+// Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the
+// item's column span); only pairs whose column lies in a later route count.
 struct InterItem {
-    int32_t sol, s0, s1, part_parts;  // part | parts << 16
+    int32_t sol, s0, s1, c0;
 };
 
 struct IntraItem {

@@ -48,7 +48,8 @@ EXPORTS = [
     "tga_get_solution", "tga_move_counts", "tga_solution_version", "tga_free_solution",
     "tga_free_instance", "tga_last_error", "tga_batch_workspace_bytes", "tga_batch_create",
     "tga_batch_ls_run", "tga_batch_eval", "tga_batch_reset", "tga_batch_free",
-    "tga_device_limits",
+    "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
+    "tga_solution_reload",
 ]
 
 
@@ -84,6 +85,10 @@ def lib():
         "tga_batch_reset": (i32, [P, P]),
         "tga_batch_free": (i32, [P]),
         "tga_device_limits": (i32, [P, P]),
+        "tga_batch_begin": (i32, [P, i32, P]),
+        "tga_batch_step_part": (i32, [P, u32, i32, P]),
+        "tga_batch_collect": (i32, [P, P, P, P, P]),
+        "tga_solution_reload": (i32, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -163,6 +168,12 @@ class Solution:
                                   nbytes, _stream(stream), ctypes.byref(h)))
         self.h = h
 
+    def reload(self, offsets, customers, stream=None):
+        """Replace the routes in place (same workspace; batches stay valid)."""
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        cust = np.ascontiguousarray(customers, dtype=np.int32)
+        _check(lib().tga_solution_reload(self.h, _np_ptr(off), _np_ptr(cust), _stream(stream)))
+
     def eval(self, op_mask: int = OPS_ALL, dump: bool = False, stream=None):
         """Best admissible move (or None); with dump=True also the per-move
         delta / feasibility tensors (non-moves keep 0 / 0xFF)."""
@@ -223,7 +234,7 @@ class Solution:
 class Batch:
     """Many solutions stepped together by one persistent launch per step."""
 
-    def __init__(self, sols: list[Solution], tile_rows: int = 0, col_split: int = 0, stream=None):
+    def __init__(self, sols: list[Solution], rows_per_item: int = 0, sub_rows: int = 0, stream=None):
         L = lib()
         self.sols = list(sols)
         arr = (ctypes.c_void_p * len(self.sols))(*[s.h.value for s in self.sols])
@@ -233,7 +244,7 @@ class Batch:
             raise TGAError(TGA_EINVAL, "bad batch")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.sols[0].ws.device)
         h = ctypes.c_void_p()
-        _check(L.tga_batch_create(arr, len(self.sols), tile_rows, col_split, _dev_ptr(self.ws),
+        _check(L.tga_batch_create(arr, len(self.sols), rows_per_item, sub_rows, _dev_ptr(self.ws),
                                   nbytes, _stream(stream), ctypes.byref(h)))
         self.h = h
 
@@ -244,6 +255,20 @@ class Batch:
         cost = np.zeros(n, np.int64)
         _check(lib().tga_batch_ls_run(self.h, op_mask, steps, int(use_graph), _np_ptr(st),
                                       _np_ptr(mv), _np_ptr(cost), _stream(stream)))
+        return st, mv, cost
+
+    def begin(self, max_steps: int, stream=None):
+        _check(lib().tga_batch_begin(self.h, max_steps, _stream(stream)))
+
+    def step_part(self, part: int, op_mask: int = OPS_ALL, stream=None):
+        _check(lib().tga_batch_step_part(self.h, op_mask, part, _stream(stream)))
+
+    def collect(self, stream=None):
+        n = len(self.sols)
+        st = np.zeros(n, np.int32)
+        mv = np.zeros(n, np.int64)
+        cost = np.zeros(n, np.int64)
+        _check(lib().tga_batch_collect(self.h, _np_ptr(st), _np_ptr(mv), _np_ptr(cost), _stream(stream)))
         return st, mv, cost
 
     def eval(self, op_mask: int = OPS_ALL, stream=None):

@@ -1,0 +1,125 @@
+"""Batched form: one persistent launch per step over many solutions of
+uneven sizes, CVRP and VRPTW mixed, the step loop captured in a HIP graph.
+Each solution's result must equal its plain (one-solution-per-launch) result
+and the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_17357_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tga():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_17357_amd import tga as T
+    T.lib()
+    print("device limits", T.device_limits(), flush=True)
+    return T
+
+
+def small_mix(count=10, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        n = int(rng.integers(20, 260))
+        inst = W.make_cvrp(n, 100 + b) if b % 2 == 0 else W.make_vrptw(n, 100 + b)
+        out.append((inst, W.sweep(inst)))
+    return out
+
+
+def make_solutions(T, pairs):
+    insts = [T.Instance.from_workload(i) for i, _ in pairs]
+    sols = [T.Solution(I, s.offsets, s.customers) for I, (_, s) in zip(insts, pairs)]
+    return insts, sols
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_ls_equals_oracle(tga, use_graph):
+    pairs = small_mix()
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    steps, moves, cost = B.ls_run(40, use_graph=use_graph)
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, deltas, mv = oracle.local_search(inst, sol, max_steps=40)
+        assert steps[b] == len(ids), b
+        assert cost[b] == oracle.cost(inst, final)[0], b
+        assert moves[b] == mv, b
+    B.close()
+    for b, s in enumerate(sols):
+        off, cust, c = s.get()
+        ref, _, _, _ = oracle.local_search(pairs[b][0], pairs[b][1], max_steps=40)
+        assert off.tolist() == ref.offsets.tolist() and cust.tolist() == ref.customers.tolist()
+
+
+def test_batch_graph_replay_and_reset(tga):
+    """A captured graph replayed twice from fresh solutions gives the same
+    result; begin/step_part/collect gives the same result too."""
+    pairs = small_mix(6, seed=1)
+    results = []
+    for mode in ("graph", "graph", "parts"):
+        insts, sols = make_solutions(tga, pairs)
+        B = tga.Batch(sols)
+        if mode == "graph":
+            r = B.ls_run(30, use_graph=True)
+        else:
+            B.begin(30)
+            for _ in range(30):
+                B.step_part(0)
+                B.step_part(1)
+            r = B.collect()
+        results.append(tuple(x.tolist() for x in r))
+        B.close()
+    assert results[0] == results[1] == results[2]
+
+
+def test_batch_eval_equals_single(tga):
+    pairs = small_mix(8, seed=2)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols, rows_per_item=3, sub_rows=2)
+    best, status = B.eval()
+    for b, (inst, sol) in enumerate(pairs):
+        ob = oracle.eval_neighbourhood(inst, sol)
+        assert status[b] == (0 if ob.found else 1)
+        if ob.found:
+            assert (best[b].delta, best[b].id) == (ob.delta, ob.id), b
+
+
+@pytest.mark.parametrize("rows_per_item,sub_rows", [(1, 1), (2, 3), (5, 1), (0, 2), (7, 3), (0, 0), (100, 8)])
+def test_schedule_does_not_change_results(tga, rows_per_item, sub_rows):
+    pairs = small_mix(6, seed=3)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols, rows_per_item=rows_per_item, sub_rows=sub_rows)
+    steps, moves, cost = B.ls_run(25, use_graph=False)
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, _ = oracle.local_search(inst, sol, max_steps=25)
+        assert steps[b] == len(ids) and cost[b] == oracle.cost(inst, final)[0]
+
+
+def test_full_batched_workload_sampled(tga):
+    """The 256-solution mix (100..2000 customers) for 200 steps: every
+    solution equals its plain form; a sample equals the oracle."""
+    pairs = W.c4()
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    steps, moves, cost = B.ls_run(200, use_graph=True)
+    B.close()
+    finals = [s.get() for s in sols]
+    print("batched: total steps", int(steps.sum()), "moves", int(moves.sum()), flush=True)
+    # plain form on fresh copies
+    _, plain = make_solutions(tga, pairs)
+    for b, s in enumerate(plain):
+        st, mv, c = s.ls_run(200)
+        assert (st, mv, c) == (steps[b], moves[b], cost[b]), b
+    ns = np.array([i.n for i, _ in pairs])
+    sample = list(np.argsort(ns)[:6])
+    for b in sample:
+        inst, sol = pairs[b]
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=200)
+        assert steps[b] == len(ids) and moves[b] == mv
+        assert finals[b][0].tolist() == final.offsets.tolist()
+        assert finals[b][1].tolist() == final.customers.tolist()

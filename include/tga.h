@@ -151,10 +151,21 @@ int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost
 int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_steps, int32_t *steps_done,
                int64_t *moves_evaluated, int64_t *cost, void *stream);
 
+/* Clear the converged flag and the step / move counters of a solution and
+ * set its step cap, so that it can join a running batch (tga_batch_step_part)
+ * and stop on its own after max_steps accepted moves.  Asynchronous. */
+int tga_solution_begin(tga_solution_t sol, int32_t max_steps, void *stream);
+
 /* Read the current solution back: offsets (host, R+1), customers (host, n),
  * *cost (nullable) = total distance.  Synchronises `stream`. */
 int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, int64_t *cost,
                      void *stream);
+
+/* Counters of a solution (all nullable): accepted moves since the last
+ * begin / ls_run, converged flag, moves evaluated since then, current total
+ * distance.  Synchronises `stream`. */
+int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32_t *converged,
+                       int64_t *moves_evaluated, int64_t *cost, void *stream);
 
 /* |N(S)| per operator for the current solution (5 entries, host). */
 int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream);
@@ -209,6 +220,10 @@ int tga_batch_begin(tga_batch_t b, int32_t max_steps, void *stream);
 int tga_batch_step_part(tga_batch_t b, uint32_t op_mask, int32_t part, void *stream);
 int tga_batch_collect(tga_batch_t b, int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
                       void *stream);
+
+/* Converged flags of every solution of the batch (host array of `count`),
+ * gathered on the device and copied in one transfer.  Synchronises. */
+int tga_batch_poll(tga_batch_t b, int32_t *done, void *stream);
 
 /* One evaluation of every solution in the batch (no apply); best moves to a
  * host array of `count` records; per-solution status to status (nullable). */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -177,9 +178,11 @@ struct tga_batch {
     int nitems;
     IntraItem *intra;
     int nintra;
-    int *queue;  // [0] inter queue head, [1] intra queue head
+    int *queue;  // [0] inter queue head, [1] intra queue head, [2] finished workgroups
+    int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
     size_t lds;
     int grid_inter, grid_intra;
+    int chunk;  // 0: static schedule; > 0: dynamic, items per atomic
     hipGraphExec_t exec;
     hipGraph_t graph;
     int graph_steps;
@@ -429,6 +432,14 @@ extern "C" int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, c
     return TGA_OK;
 }
 
+extern "C" int tga_solution_begin(tga_solution_t sol, int32_t max_steps, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (max_steps < 0) return fail(TGA_EINVAL, "max_steps < 0");
+    k_reset_state<<<1, 64, 0, (hipStream_t)stream>>>(sol->d, 1, max_steps);
+    HIPCHK(hipGetLastError());
+    return TGA_OK;
+}
+
 extern "C" int tga_free_solution(tga_solution_t sol) {
     delete sol;
     return TGA_OK;
@@ -610,6 +621,26 @@ extern "C" int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *c
     return TGA_OK;
 }
 
+extern "C" int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32_t *converged,
+                                  int64_t *moves_evaluated, int64_t *cost, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    hipStream_t st = (hipStream_t)stream;
+    void *pin;
+    int rc = pinned(&pin);
+    if (rc) return rc;
+    int32_t *p = (int32_t *)pin;
+    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const long long *acc = (const long long *)(p + 16);
+    sol->version = (uint32_t)p[kStVersion];
+    if (steps_done) *steps_done = p[kStSteps];
+    if (converged) *converged = p[kStDone];
+    if (moves_evaluated) *moves_evaluated = acc[kAccMoves];
+    if (cost) *cost = acc[kAccCost];
+    return TGA_OK;
+}
+
 extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream) {
     if (!sol || !counts) return fail(TGA_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
@@ -622,6 +653,14 @@ extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stre
 
 // ---------------------------------------------------------------- batch ----
 
+// Work-item schedule of the batched evaluation: 0 = static round-robin,
+// k > 0 = dynamic, k items per atomic.  TGA_SCHEDULE overrides the default.
+static int schedule_chunk() {
+    const char *e = getenv("TGA_SCHEDULE");
+    if (e && *e) return std::max(0, std::min(64, atoi(e)));
+    return 0;
+}
+
 static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc, size_t *items,
                            size_t *intra, size_t *queue, int max_items, int nintra) {
     size_t off = 0;
@@ -633,7 +672,7 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     *desc = take(sizeof(SolDev) * sols.size());
     *items = take(sizeof(InterItem) * std::max(max_items, 1));
     *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    *queue = take(64);
+    *queue = take(64 + 4 * sols.size());
     return off;
 }
 
@@ -715,10 +754,13 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->intra = (IntraItem *)(base + ointra);
     B->nintra = (int)intra.size();
     B->queue = (int *)(base + oqueue);
+    B->done = B->queue + 16;
     B->lds = lds;
-    const int per_cu = std::max(1, (int)(160 * 1024 / std::max<size_t>(lds, 1)));
-    B->grid_inter = std::min(B->nitems, P.cus * std::min(per_cu, 2));
-    B->grid_intra = std::min((B->nintra + 3) / 4, P.cus * 8);
+    // one resident wave of workgroups: as many as LDS and registers allow
+    const int per_cu = std::max(1, std::min(2, (int)(P.max_lds / std::max<size_t>(lds, 1))));
+    B->grid_inter = std::max(1, P.cus * per_cu);
+    B->grid_intra = B->grid_inter;
+    B->chunk = schedule_chunk();
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
@@ -745,8 +787,8 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
 
 static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
     if (op_mask & TGA_OP_ALL)
-        k_eval_mixed<<<std::max(B->grid_inter, B->grid_intra), kInterThreads, B->lds, st>>>(
-            B->d, B->items, B->nitems, B->intra, B->nintra, op_mask, B->queue);
+        k_eval_mixed<<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
+                                                                   B->nintra, op_mask, B->queue, B->chunk);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
@@ -835,6 +877,17 @@ extern "C" int tga_batch_begin(tga_batch_t B, int32_t max_steps, void *stream) {
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, max_steps);
     k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     HIPCHK(hipGetLastError());
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_poll(tga_batch_t B, int32_t *done, void *stream) {
+    if (!B || !done) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    k_poll_done<<<(n + 255) / 256, 256, 0, st>>>(B->d, n, B->done);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(done, B->done, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return TGA_OK;
 }
 

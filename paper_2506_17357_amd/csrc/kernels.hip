@@ -32,6 +32,19 @@ constexpr int kIntraThreads = 256;
 constexpr int kApplyThreads = 1024;
 constexpr int kTwOff = 1 << 28;     // due time standing for "no window" (CVRP)
 
+// Loads through pointers kept in the solution descriptor: the pointee is
+// global memory, so say so (global_load instead of a generic flat load).
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+__device__ __forceinline__ int4 gld(const int4 *p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = *(const __attribute__((address_space(1))) v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ int nodeof(int x) { return x & 0xFFFF; }
 __device__ __forceinline__ int flagsof(int x) { return x >> 16; }
 
@@ -64,7 +77,7 @@ __device__ __forceinline__ void wave_argmin(int &bd, uint32_t &bid) {
 
 // Reduce the per-lane bests of a workgroup and fold the result into the
 // solution's key.  Every thread of the block must call it.
-__device__ void block_argmin_commit(int bd, uint32_t bid, unsigned long long *key,
+__device__ __forceinline__ void block_argmin_commit(int bd, uint32_t bid, unsigned long long *key,
                                     unsigned long long *red) {
     wave_argmin(bd, bid);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -213,7 +226,7 @@ __device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, int s) {
 // Rebuild every attribute of S from the layout nr[] = {node, route} and
 // roffn[].  nr doubles as scratch for {A, Z} after the first two passes.
 // Requires blockDim.x == kApplyThreads.
-__device__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
+__device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
     const int Q = S.Q, R = S.R, n = S.n, np1 = S.np1;
     const int tid = threadIdx.x, T = blockDim.x;
     const int32_t *D = S.D;
@@ -429,17 +442,17 @@ __device__ __forceinline__ void stage_rows(const SolDev &S, int first, int cnt, 
     const int Q = S.Q, np1 = S.np1;
     for (int k = threadIdx.x; k < cnt; k += kInterThreads) {
         const int s = min(max(first + k, 0), Q);
-        rowa[k] = S.a4[s];
-        rowb[k] = S.b4[s];
+        rowa[k] = gld(S.a4 + s);
+        rowb[k] = gld(S.b4 + s);
         if (TW) {
-            rowt[k] = S.t4[s];
-            roww[k] = S.w4[s];
+            rowt[k] = gld(S.t4 + s);
+            roww[k] = gld(S.w4 + s);
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = wave; k < cnt; k += kInterWaves) {
         const int s = min(max(first + k, 0), Q);
-        const int node = nodeof(S.a4[s].x);
+        const int node = nodeof(gld(S.a4 + s).x);
         const int *src = S.D + (size_t)node * np1;
         int *dst = rows + k * np1;
         for (int c = 0; c < np1; c += 64) {
@@ -450,10 +463,101 @@ __device__ __forceinline__ void stage_rows(const SolDev &S, int first, int cnt, 
     __builtin_amdgcn_s_waitcnt(0);
 }
 
+// The four inter-route moves of row slot s against the lane's column slot t.
+// g = D[s][t], gp = D[pred(s)][t], gn = D[succ(s)][t]; gR = D[s][succ(t)],
+// gL = D[s][pred(t)].
+template <bool TW, bool DUMP>
+__device__ __forceinline__ void pair_moves(const LaneCol &L, const int4 &ra, const int4 &rb, const int4 &rt,
+                                           const int4 &rw, int gp, int g, int gn, int gR, int gL, int n,
+                                           int cap, uint32_t uQ, bool opRel, bool opSwap, bool op2s,
+                                           int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
+                                           int &bd, uint32_t &bid) {
+    const int4 ta = L.ta, tb = L.tb, tt = L.tt, tw = L.tw;
+    const int flT = L.fl;
+    const bool tCust = L.cust;
+    const uint32_t refT = (uint32_t)L.refT;
+    const bool pair = L.own && ta.y > ra.y;
+    const int flS = flagsof(ra.x);
+    const bool sCust = flS & kFlagCustomer;
+    const uint32_t refS = sCust ? nodeof(ra.x) - 1 : n + ra.y;
+    const uint32_t lo = min(refS, refT), hi = max(refS, refT);
+
+    // RELOCATE s -> right after t
+    int d1 = kNoDelta;
+    bool v1 = false, c1 = false, w1 = true;
+    if (opRel && sCust) {
+        v1 = pair;
+        d1 = ra.w + g + gR - ta.z;
+        c1 = (flS & kFlagRemCap) && (tb.z + rb.x <= cap);
+        if (TW) w1 = (flS & kFlagRemTw) && tw_insert(tt.x, g, rw.x, rw.y, rw.z, gR, tt.y);
+    }
+    // RELOCATE t -> right after s
+    int d2 = kNoDelta;
+    bool v2 = false, c2 = false, w2 = true;
+    if (opRel) {
+        v2 = pair && tCust;
+        d2 = ta.w + g + gn - ra.z;
+        c2 = (flT & kFlagRemCap) && (rb.z + tb.x <= cap);
+        if (TW) w2 = (flT & kFlagRemTw) && tw_insert(rt.x, g, tw.x, tw.y, tw.z, gn, rt.y);
+    }
+    // SWAP s <-> t
+    int d3 = kNoDelta;
+    bool v3 = false, c3 = false, w3 = true;
+    if (opSwap && sCust) {
+        v3 = pair && tCust;
+        d3 = gp + gn + gL + gR - rb.w - tb.w;
+        c3 = (rb.z - rb.x + tb.x <= cap) && (tb.z - tb.x + rb.x <= cap);
+        if (TW)
+            w3 = tw_insert(rt.z, gp, tw.x, tw.y, tw.z, gn, rt.y) && tw_insert(tt.z, gL, rw.x, rw.y, rw.z, gR, tt.y);
+    }
+    // 2OPT*(s, t): heads keep their slots, tails are exchanged
+    int d4 = kNoDelta;
+    bool v4 = false, c4 = false, w4 = true;
+    if (op2s) {
+        v4 = pair;
+        d4 = gR + gn - ra.z - ta.z;
+        c4 = (rb.y + tb.z - tb.y <= cap) && (tb.y + rb.z - rb.y <= cap);
+        if (TW) w4 = (rt.x + gR <= tt.y) && (tt.x + gn <= rt.y);
+    }
+    if (DUMP) {
+        if (v1) {
+            const uint32_t id = (uQ + refS) * uQ + refT;
+            dump_delta[id] = d1;
+            dump_feas[id] = (uint8_t)(c1 | (w1 << 1));
+        }
+        if (v2) {
+            const uint32_t id = (uQ + refT) * uQ + refS;
+            dump_delta[id] = d2;
+            dump_feas[id] = (uint8_t)(c2 | (w2 << 1));
+        }
+        if (v3) {
+            const uint32_t id = (5u * uQ + lo) * uQ + hi;
+            dump_delta[id] = d3;
+            dump_feas[id] = (uint8_t)(c3 | (w3 << 1));
+        }
+        if (v4) {
+            const uint32_t id = (8u * uQ + lo) * uQ + hi;
+            dump_delta[id] = d4;
+            dump_feas[id] = (uint8_t)(c4 | (w4 << 1));
+        }
+    }
+    const int m1 = (v1 && c1 && w1) ? d1 : kNoDelta;
+    const int m2 = (v2 && c2 && w2) ? d2 : kNoDelta;
+    const int m3 = (v3 && c3 && w3) ? d3 : kNoDelta;
+    const int m4 = (v4 && c4 && w4) ? d4 : kNoDelta;
+    const int m = min(min(m1, m2), min(m3, m4));
+    if (m != kNoDelta && m <= bd) {
+        consider(m1, (uQ + refS) * uQ + refT, bd, bid);
+        consider(m2, (uQ + refT) * uQ + refS, bd, bid);
+        consider(m3, (5u * uQ + lo) * uQ + hi, bd, bid);
+        consider(m4, (8u * uQ + lo) * uQ + hi, bd, bid);
+    }
+}
+
 // Whole-workgroup evaluation of one inter-route item.  smem4 is the dynamic
 // LDS area; red holds kInterWaves keys.
 template <bool TW, bool DUMP>
-__device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_mask,
+__device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_mask,
                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
                            int4 *smem4, unsigned long long *red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -464,6 +568,8 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
 
     // column chunks of this wavefront: attributes stay in registers
     LaneCol col[kChunks];
+    int routeLast[kChunks];
+    int routeMax = -1;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
         const int cb = item.c0 + (c * kInterWaves + wave) * kColsPerWave;
@@ -471,11 +577,11 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
         const int tc = min(max(t, 0), Q);
         LaneCol &L = col[c];
         L.own = lane >= 1 && lane <= kColsPerWave && t < cend;
-        L.ta = S.a4[tc];
-        L.tb = S.b4[tc];
+        L.ta = gld(S.a4 + tc);
+        L.tb = gld(S.b4 + tc);
         if (TW) {
-            L.tt = S.t4[tc];
-            L.tw = S.w4[tc];
+            L.tt = gld(S.t4 + tc);
+            L.tw = gld(S.w4 + tc);
         } else {
             L.tt = make_int4(0, 0, 0, 0);
             L.tw = make_int4(0, 0, 0, 0);
@@ -484,10 +590,12 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
         L.fl = flagsof(L.ta.x);
         L.cust = L.fl & kFlagCustomer;
         L.refT = L.cust ? L.node - 1 : n + L.ta.y;
-        // route of the last owned column (-1: chunk empty)
+        // route of the last owned column (-1: chunk empty); the same for every
+        // lane of the wavefront, so keep it scalar
         const int lastLane = min(kColsPerWave, cend - cb);
         const int rl = __shfl(L.ta.y, max(lastLane, 0));
-        L.routeLast = lastLane >= 1 ? rl : -1;
+        routeLast[c] = __builtin_amdgcn_readfirstlane(lastLane >= 1 ? rl : -1);
+        routeMax = max(routeMax, routeLast[c]);
     }
 
     int bd = kNoDelta;
@@ -503,107 +611,34 @@ __device__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_m
         __syncthreads();                       // previous sub-block fully consumed
         stage_rows<TW>(S, sb - 1, nr + 2, rowa, rowb, rowt, roww, rows);
         __syncthreads();
+        if (routeMax <= rowa[1].y) continue;  // nothing to the right of this sub-block
+        int gp[kChunks], g[kChunks];
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            const LaneCol &L = col[c];
-            const int4 ta = L.ta, tb = L.tb, tt = L.tt, tw = L.tw;
-            const int nodeT = L.node, flT = L.fl;
-            const bool tCust = L.cust;
-            const uint32_t refT = (uint32_t)L.refT;
-            if (L.routeLast <= rowa[1].y) continue;  // nothing to the right of this sub-block
-            int gp = rows[nodeT];
-            int g = rows[np1 + nodeT];
-            for (int k = 1; k <= nr; ++k) {
-                const int4 ra = rowa[k];
-                if (L.routeLast <= ra.y) break;
-                const int4 rb = rowb[k];
-                int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
-                if (TW) {
-                    rt = rowt[k];
-                    rw = roww[k];
+            gp[c] = rows[col[c].node];
+            g[c] = rows[np1 + col[c].node];
+        }
+        for (int k = 1; k <= nr; ++k) {
+            const int4 ra = rowa[k];
+            if (routeMax <= ra.y) break;
+            const int4 rb = rowb[k];
+            int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
+            if (TW) {
+                rt = rowt[k];
+                rw = roww[k];
+            }
+            const int *rowNext = rows + (k + 1) * np1;
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int gn = rowNext[col[c].node];
+                if (routeLast[c] > ra.y) {
+                    const int gR = from_next_lane(g[c]);  // D[s][succ(t)]
+                    const int gL = from_prev_lane(g[c]);  // D[s][pred(t)]
+                    pair_moves<TW, DUMP>(col[c], ra, rb, rt, rw, gp[c], g[c], gn, gR, gL, n, cap, uQ, opRel,
+                                         opSwap, op2s, dump_delta, dump_feas, bd, bid);
                 }
-                const int gn = rows[(k + 1) * np1 + nodeT];
-                const int gR = from_next_lane(g);  // D[s][succ(t)]
-                const int gL = from_prev_lane(g);  // D[s][pred(t)]
-                const bool pair = L.own && ta.y > ra.y;
-                const int flS = flagsof(ra.x);
-                const bool sCust = flS & kFlagCustomer;
-                const uint32_t refS = sCust ? nodeof(ra.x) - 1 : n + ra.y;
-                const uint32_t lo = min(refS, refT), hi = max(refS, refT);
-
-                // RELOCATE s -> right after t
-                int d1 = kNoDelta;
-                bool v1 = false, c1 = false, w1 = true;
-                if (opRel && sCust) {
-                    v1 = pair;
-                    d1 = ra.w + g + gR - ta.z;
-                    c1 = (flS & kFlagRemCap) && (tb.z + rb.x <= cap);
-                    if (TW) w1 = (flS & kFlagRemTw) && tw_insert(tt.x, g, rw.x, rw.y, rw.z, gR, tt.y);
-                }
-                // RELOCATE t -> right after s
-                int d2 = kNoDelta;
-                bool v2 = false, c2 = false, w2 = true;
-                if (opRel) {
-                    v2 = pair && tCust;
-                    d2 = ta.w + g + gn - ra.z;
-                    c2 = (flT & kFlagRemCap) && (rb.z + tb.x <= cap);
-                    if (TW) w2 = (flT & kFlagRemTw) && tw_insert(rt.x, g, tw.x, tw.y, tw.z, gn, rt.y);
-                }
-                // SWAP s <-> t
-                int d3 = kNoDelta;
-                bool v3 = false, c3 = false, w3 = true;
-                if (opSwap && sCust) {
-                    v3 = pair && tCust;
-                    d3 = gp + gn + gL + gR - rb.w - tb.w;
-                    c3 = (rb.z - rb.x + tb.x <= cap) && (tb.z - tb.x + rb.x <= cap);
-                    if (TW)
-                        w3 = tw_insert(rt.z, gp, tw.x, tw.y, tw.z, gn, rt.y) &&
-                             tw_insert(tt.z, gL, rw.x, rw.y, rw.z, gR, tt.y);
-                }
-                // 2OPT*(s, t): heads keep their slots, tails are exchanged
-                int d4 = kNoDelta;
-                bool v4 = false, c4 = false, w4 = true;
-                if (op2s) {
-                    v4 = pair;
-                    d4 = gR + gn - ra.z - ta.z;
-                    c4 = (rb.y + tb.z - tb.y <= cap) && (tb.y + rb.z - rb.y <= cap);
-                    if (TW) w4 = (rt.x + gR <= tt.y) && (tt.x + gn <= rt.y);
-                }
-                if (DUMP) {
-                    if (v1) {
-                        const uint32_t id = (uQ + refS) * uQ + refT;
-                        dump_delta[id] = d1;
-                        dump_feas[id] = (uint8_t)(c1 | (w1 << 1));
-                    }
-                    if (v2) {
-                        const uint32_t id = (uQ + refT) * uQ + refS;
-                        dump_delta[id] = d2;
-                        dump_feas[id] = (uint8_t)(c2 | (w2 << 1));
-                    }
-                    if (v3) {
-                        const uint32_t id = (5u * uQ + lo) * uQ + hi;
-                        dump_delta[id] = d3;
-                        dump_feas[id] = (uint8_t)(c3 | (w3 << 1));
-                    }
-                    if (v4) {
-                        const uint32_t id = (8u * uQ + lo) * uQ + hi;
-                        dump_delta[id] = d4;
-                        dump_feas[id] = (uint8_t)(c4 | (w4 << 1));
-                    }
-                }
-                const int m1 = (v1 && c1 && w1) ? d1 : kNoDelta;
-                const int m2 = (v2 && c2 && w2) ? d2 : kNoDelta;
-                const int m3 = (v3 && c3 && w3) ? d3 : kNoDelta;
-                const int m4 = (v4 && c4 && w4) ? d4 : kNoDelta;
-                const int m = min(min(m1, m2), min(m3, m4));
-                if (m != kNoDelta && m <= bd) {
-                    consider(m1, (uQ + refS) * uQ + refT, bd, bid);
-                    consider(m2, (uQ + refT) * uQ + refS, bd, bid);
-                    consider(m3, (5u * uQ + lo) * uQ + hi, bd, bid);
-                    consider(m4, (8u * uQ + lo) * uQ + hi, bd, bid);
-                }
-                gp = g;
-                g = gn;
+                gp[c] = g[c];
+                g[c] = gn;
             }
         }
     }
@@ -658,25 +693,25 @@ struct RouteLds {
 struct RouteGlobal {
     const SolDev *S;
     int off, L, l0;
-    __device__ int node(int p) const { return p <= L ? nodeof(S->a4[off + p].x) : 0; }
-    __device__ int edge(int p) const { return S->a4[off + p].z; }
-    __device__ int dep(int p) const { return S->t4[off + p].x; }
-    __device__ int z(int p) const { return p <= L ? S->t4[off + p].w : l0; }
-    __device__ int e(int p) const { return S->w4[off + p].x; }
-    __device__ int l(int p) const { return S->w4[off + p].y; }
-    __device__ int s(int p) const { return S->w4[off + p].z; }
-    __device__ int dd(int p, int q) const { return S->D[(size_t)node(p) * S->np1 + node(q)]; }
+    __device__ int node(int p) const { return p <= L ? nodeof(gld(S->a4 + off + p).x) : 0; }
+    __device__ int edge(int p) const { return gld(S->a4 + off + p).z; }
+    __device__ int dep(int p) const { return gld(S->t4 + off + p).x; }
+    __device__ int z(int p) const { return p <= L ? gld(S->t4 + off + p).w : l0; }
+    __device__ int e(int p) const { return gld(S->w4 + off + p).x; }
+    __device__ int l(int p) const { return gld(S->w4 + off + p).y; }
+    __device__ int s(int p) const { return gld(S->w4 + off + p).z; }
+    __device__ int dd(int p, int q) const { return gld(S->D + (size_t)node(p) * S->np1 + node(q)); }
 };
 
 template <bool TW, bool DUMP, class RV>
-__device__ void intra_moves(const SolDev &S, const RV &V, int r, int L, uint32_t op_mask,
+__device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r, int L, uint32_t op_mask,
                             int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas, int &bd,
                             uint32_t &bid) {
     const int lane = threadIdx.x & 63;
     const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
     const int n = S.n;
     const uint32_t uQ = (uint32_t)S.Q;
-    const bool capOK = S.b4[S.roff[r]].z <= S.cap;
+    const bool capOK = gld(S.b4 + gld(S.roff + r)).z <= S.cap;
     auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(V.node(p) - 1); };
     auto segAt = [&](int p) { return seg_node(V.e(p), V.l(p), V.s(p)); };
 #pragma unroll 1
@@ -798,15 +833,15 @@ __device__ void intra_moves(const SolDev &S, const RV &V, int r, int L, uint32_t
 // its best to the solution's key.  region: this wavefront's LDS bytes
 // (kIntraRegionBytes).
 template <bool TW, bool DUMP>
-__device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+__device__ __forceinline__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
                             int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
                             int *region) {
     const int lane = threadIdx.x & 63;
     int bd = kNoDelta;
     uint32_t bid = 0xFFFFFFFFu;
     const int r = item.route;
-    const int off = S.roff[r];
-    const int L = S.roff[r + 1] - off - 1;
+    const int off = gld(S.roff + r);
+    const int L = gld(S.roff + r + 1) - off - 1;
     const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
     const int P = L + 2;
     if (P <= kIntraMaxPos) {
@@ -814,12 +849,12 @@ __device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_
             *ps = pl + P, *dm = ps + P;
         for (int p = lane; p < P; p += 64) {
             if (p <= L) {
-                const int4 a = S.a4[off + p];
+                const int4 a = gld(S.a4 + off + p);
                 pn[p] = nodeof(a.x);
                 pe[p] = a.z;
                 if (TW) {
-                    const int4 t = S.t4[off + p];
-                    const int4 w = S.w4[off + p];
+                    const int4 t = gld(S.t4 + off + p);
+                    const int4 w = gld(S.w4 + off + p);
                     pdep[p] = t.x;
                     pz[p] = t.w;
                     pe_[p] = w.x;
@@ -837,7 +872,7 @@ __device__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_
         const int np1 = S.np1;
         for (int x = lane; x < P * P; x += 64) {
             const int p = x / P, q = x - p * P;
-            dm[x] = S.D[(size_t)pn[p] * np1 + pn[q]];
+            dm[x] = gld(S.D + (size_t)pn[p] * np1 + pn[q]);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -871,27 +906,40 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // Batched form: one persistent launch evaluates every solution of the batch.
-// Workgroups pull inter-route items from queue[0] (whole workgroup per item,
-// largest items first), then single routes from queue[1] (one wavefront per
-// route).  Solutions of both problem types share the launch; each item takes
-// the window-aware or the capacity-only path of its own solution.  The last
-// workgroup to finish resets the queue heads, so consecutive launches (also
-// inside a captured graph) need no reset in between.
-__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_mixed(const SolDev *__restrict__ sols,
-                                                              const InterItem *__restrict__ items,
-                                                              int nitems,
-                                                              const IntraItem *__restrict__ intra,
-                                                              int nintra, uint32_t op_mask,
-                                                              int *__restrict__ queue) {
+// Phase 1: inter-route items (whole workgroup per item, largest first);
+// phase 2: single routes (one wavefront per route).  Solutions of both
+// problem types share the launch; each item takes the window-aware or the
+// capacity-only path of its own solution.
+// chunk == 0: static schedule, workgroup b takes items b, b + G, b + 2G, ...
+// (round-robin over the largest-first list).  chunk > 0: dynamic schedule,
+// workgroups take `chunk` consecutive items per atomic on queue[0] / queue[1];
+// the last workgroup to finish resets the queue heads, so consecutive
+// launches (also inside a captured graph) need no reset in between.
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_mixed(
+    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, int nitems,
+    const IntraItem *__restrict__ intra, int nintra, uint32_t op_mask, int *__restrict__ queue, int chunk) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int cur;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (op_mask & 7) {
+        int base = blockIdx.x, step = gridDim.x, left = 0;
         for (;;) {
-            if (threadIdx.x == 0) cur = atomicAdd(&queue[0], 1);
-            __syncthreads();
-            const int it = cur;
-            __syncthreads();
+            int it;
+            if (chunk == 0) {
+                it = base;
+                base += step;
+            } else {
+                if (left == 0) {
+                    if (threadIdx.x == 0) cur = atomicAdd(&queue[0], chunk);
+                    __syncthreads();
+                    base = cur;
+                    left = chunk;
+                    __syncthreads();
+                }
+                it = base++;
+                --left;
+            }
             if (it >= nitems) break;
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
@@ -903,23 +951,35 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         }
     }
     if (op_mask & (2 | 8 | 16)) {
-        const int lane = threadIdx.x & 63;
+        int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+        int base = blockIdx.x * kInterWaves + wave, step = gridDim.x * kInterWaves, left = 0;
         for (;;) {
-            int it = 0;
-            if (lane == 0) it = atomicAdd(&queue[1], 1);
-            it = __shfl(it, 0);
+            int it;
+            if (chunk == 0) {
+                it = base;
+                base += step;
+            } else {
+                if (left == 0) {
+                    int b0 = 0;
+                    if (lane == 0) b0 = atomicAdd(&queue[1], chunk);
+                    base = __shfl(b0, 0);
+                    left = chunk;
+                }
+                it = base++;
+                --left;
+            }
             if (it >= nintra) break;
             const IntraItem item = intra[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
-            int *region = (int *)smem4 + (threadIdx.x >> 6) * (kIntraRegionBytes / 4);
             if (S.has_tw)
                 intra_route<true, false>(S, item, op_mask, nullptr, nullptr, region);
             else
                 intra_route<false, false>(S, item, op_mask, nullptr, nullptr, region);
         }
     }
-    // every workgroup has taken its last item from both queues before it
+    if (chunk == 0) return;
+    // every workgroup has taken its last items from both queues before it
     // counts itself finished; the last one resets the queue for the next launch
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -942,12 +1002,12 @@ struct MoveInfo {
     uint32_t id;
 };
 
-__device__ int old_node(const SolDev &S, int r, int p) {
+__device__ __forceinline__ int old_node(const SolDev &S, int r, int p) {
     return p == 0 ? 0 : nodeof(S.a4[S.roff[r] + p].x);
 }
 
 // Node at new position p of a touched route r (Section 4.1 operators).
-__device__ int new_node(const SolDev &S, const MoveInfo &m, int r, int p) {
+__device__ __forceinline__ int new_node(const SolDev &S, const MoveInfo &m, int r, int p) {
     if (p == 0) return 0;
     switch (m.op) {
     case 0:
@@ -980,7 +1040,7 @@ __device__ int new_node(const SolDev &S, const MoveInfo &m, int r, int p) {
     }
 }
 
-__device__ void decode_move(const SolDev &S, uint32_t id, MoveInfo &m) {
+__device__ __forceinline__ void decode_move(const SolDev &S, uint32_t id, MoveInfo &m) {
     const uint32_t Q = (uint32_t)S.Q, qq = Q * Q;
     const uint32_t opk = id / qq, rem = id % qq;
     m.id = id;
@@ -1024,7 +1084,7 @@ __device__ void decode_move(const SolDev &S, uint32_t id, MoveInfo &m) {
 }
 
 // Apply m (valid) and rebuild.  All threads of the block participate.
-__device__ void apply_move_block(const SolDev &S, const MoveInfo &m, ApplyShared &sh) {
+__device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo &m, ApplyShared &sh) {
     const int R = S.R, Q = S.Q, T = blockDim.x, tid = threadIdx.x;
     const bool inter = m.ra != m.rb;
     const int dA = m.nLa - m.La, dB = inter ? m.nLb - m.Lb : 0;
@@ -1053,7 +1113,7 @@ __device__ void apply_move_block(const SolDev &S, const MoveInfo &m, ApplyShared
 // none) and reset the key.  kModeLS: also apply it when its delta is negative
 // and the step cap allows, else mark the solution converged.  kModeApplyRec:
 // apply the move record the host wrote into S.rec.
-__device__ void finalize_block(const SolDev &S, int mode, uint32_t op_mask) {
+__device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32_t op_mask) {
     __shared__ ApplyShared sh;
     __shared__ MoveInfo mi;
     __shared__ int act;
@@ -1168,6 +1228,12 @@ __global__ __launch_bounds__(256) void k_check_nodes(const int4 *__restrict__ nd
 __global__ void k_zero_i32(int32_t *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
+}
+
+// Gather the converged flags of a batch into one array (one copy to the host).
+__global__ void k_poll_done(const SolDev *__restrict__ sols, int nsols, int32_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsols) out[i] = sols[i].state[kStDone];
 }
 
 // Reset per-solution state for a new run (no memset, so it can sit in a

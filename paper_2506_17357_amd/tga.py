@@ -49,7 +49,7 @@ EXPORTS = [
     "tga_free_instance", "tga_last_error", "tga_batch_workspace_bytes", "tga_batch_create",
     "tga_batch_ls_run", "tga_batch_eval", "tga_batch_reset", "tga_batch_free",
     "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
-    "tga_solution_reload",
+    "tga_solution_reload", "tga_solution_begin", "tga_batch_poll", "tga_solution_stats",
 ]
 
 
@@ -89,6 +89,9 @@ def lib():
         "tga_batch_step_part": (i32, [P, u32, i32, P]),
         "tga_batch_collect": (i32, [P, P, P, P, P]),
         "tga_solution_reload": (i32, [P, P, P, P]),
+        "tga_solution_begin": (i32, [P, i32, P]),
+        "tga_batch_poll": (i32, [P, P, P]),
+        "tga_solution_stats": (i32, [P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -174,6 +177,10 @@ class Solution:
         cust = np.ascontiguousarray(customers, dtype=np.int32)
         _check(lib().tga_solution_reload(self.h, _np_ptr(off), _np_ptr(cust), _stream(stream)))
 
+    def begin(self, max_steps: int, stream=None):
+        """Clear counters and set the step cap before joining a running batch."""
+        _check(lib().tga_solution_begin(self.h, max_steps, _stream(stream)))
+
     def eval(self, op_mask: int = OPS_ALL, dump: bool = False, stream=None):
         """Best admissible move (or None); with dump=True also the per-move
         delta / feasibility tensors (non-moves keep 0 / 0xFF)."""
@@ -215,6 +222,16 @@ class Solution:
         _check(lib().tga_get_solution(self.h, _np_ptr(off), _np_ptr(cust), ctypes.byref(cost),
                                       _stream(stream)))
         return off, cust, int(cost.value)
+
+    def stats(self, stream=None):
+        """(accepted moves, converged, moves evaluated, cost) since the last begin/ls_run."""
+        st = ctypes.c_int32()
+        cv = ctypes.c_int32()
+        mv = ctypes.c_int64()
+        cost = ctypes.c_int64()
+        _check(lib().tga_solution_stats(self.h, ctypes.byref(st), ctypes.byref(cv), ctypes.byref(mv),
+                                        ctypes.byref(cost), _stream(stream)))
+        return int(st.value), bool(cv.value), int(mv.value), int(cost.value)
 
     def move_counts(self, stream=None) -> np.ndarray:
         c = np.zeros(5, np.int64)
@@ -270,6 +287,12 @@ class Batch:
         cost = np.zeros(n, np.int64)
         _check(lib().tga_batch_collect(self.h, _np_ptr(st), _np_ptr(mv), _np_ptr(cost), _stream(stream)))
         return st, mv, cost
+
+    def poll(self, stream=None) -> np.ndarray:
+        """Converged flag per solution (one device gather + one copy)."""
+        d = np.zeros(len(self.sols), np.int32)
+        _check(lib().tga_batch_poll(self.h, _np_ptr(d), _stream(stream)))
+        return d
 
     def eval(self, op_mask: int = OPS_ALL, stream=None):
         n = len(self.sols)

@@ -45,6 +45,103 @@ def eval_bytes(inst, R):
     return 4 * (inst.n + 1) ** 2 + (64 if inst.has_tw else 32) * (Q + 1)
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.hip", "tga_internal.h"):
+        with open(os.path.join(ROOT, "paper_2506_17357_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(alg_bytes_per_launch):
+    """HBM bytes per evaluation launch measured with rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (each scaled by the same counter on a copy of known size), as
+    committed in profiles/; None when missing or taken on other kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_eval_mixed_batched256.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return {"bytes_per_launch": t["bytes_per_launch"],
+            "vs_algorithmic": round(t["bytes_per_launch"] / alg_bytes_per_launch, 3),
+            "source": "profiles/traffic_k_eval_mixed_batched256.json"}
+
+
+def calibrate_copy():
+    """A plain device copy of exactly 1 GiB (read) + 1 GiB (write), so that a
+    profiler pass can scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def served(args):
+    """Served form: a Poisson stream of local-search requests (200..10000
+    customers, CVRP / VRPTW alternating, seeds 5000 + k, arrivals seed 5999)
+    served by continuous batching under an HBM budget."""
+    import torch
+    from paper_2506_17357_amd import serve, tga, workload as W
+    torch.cuda.set_device(0)
+    t = time.time()
+    base = W.request_stream(args.requests, qps=1.0, max_steps=args.served_steps)
+    reqs = []
+    for r in base:
+        inst = W.request_instance(r)
+        reqs.append(serve.ServeRequest(r.k, 0.0, inst, W.sweep(inst), r.max_steps))
+        log("request %d: n=%d %s" % (r.k, inst.n, inst.kind))
+    log("requests generated in %.1f s" % (time.time() - t))
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    # closed loop (everything queued at t = 0) measures the capacity
+    srv = serve.Server(budget)
+    t0 = time.perf_counter()
+    res0 = srv.run(reqs)
+    t_closed = time.perf_counter() - t0
+    cap_qps = len(reqs) / t_closed
+    qps = 0.7 * cap_qps
+    log("closed loop: %.2f s, capacity %.2f requests/s -> offered %.2f requests/s" % (t_closed, cap_qps, qps))
+    arrivals = W.request_stream(args.requests, qps=qps, max_steps=args.served_steps)
+    for q, a in zip(reqs, arrivals):
+        q.arrival_s = a.arrival_s
+    srv = serve.Server(budget)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, log=log)
+    t_open = time.perf_counter() - t0
+    same = all((a.steps, a.moves, a.cost) == (b.steps, b.moves, b.cost) and
+               a.customers.tolist() == b.customers.tolist() for a, b in zip(res0, res))
+    lat = np.array([r.latency_s for r in res]) * 1e3
+    moves = sum(r.moves for r in res)
+    line = {
+        "metric": "served: aggregate GMoves/s + p50/p99 request latency (continuous batching)",
+        "value": round(moves / t_open / 1e9, 4),
+        "unit": "GMoves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "served: %d requests, 200..10000 customers log-uniform, CVRP/VRPTW "
+                               "alternating, <= %d steps each, Poisson arrivals" % (len(reqs), args.served_steps),
+                   "qps": round(qps, 3), "capacity_qps": round(cap_qps, 3),
+                   "hbm_budget_bytes": budget, "moves_evaluated": moves},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                       "p99": round(float(np.percentile(lat, 99)), 2),
+                       "max": round(float(lat.max()), 2)},
+        "makespan_s": round(t_open, 3),
+        "peak_active_requests": srv.peak_active,
+        "peak_resident_bytes": srv.peak_used,
+        "ticks": srv.ticks,
+        "same_results_as_closed_loop": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,20 +150,30 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--count", type=int, default=256)
+    ap.add_argument("--served", action="store_true", help="benchmark the served form instead")
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--served-steps", type=int, default=100)
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py: this build measures one GPU only (the batched solutions are independent; "
             "see DESIGN.md for how the path would shard); run with --gpus 1")
         sys.exit(2)
     K, Wm = args.steps, args.warmup
-
     from paper_2506_17357_amd import build_lib
     if not os.path.exists(build_lib.LIB):
         build_lib.build(verbose=True)
+    if args.served:
+        served(args)
+        return
     import torch
     from paper_2506_17357_amd import tga, workload as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy()
     cus, lds = tga.device_limits()
     log("device: %s, %d CUs, %d B LDS per evaluation workgroup" % (torch.cuda.get_device_name(0), cus, lds))
 
@@ -197,6 +304,7 @@ def main():
                          "(%d moves, %.1f s)" % (len(sample), mv, t_cpu)}
         log("cpu oracle: %.4f GMoves/s on %d threads" % (cpu["value"], threads))
 
+    traffic = committed_traffic(bytes_per_launch.mean())
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -229,7 +337,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_us": round(float(dur_ms.mean() * 1e3), 2),
             "avg_bytes_per_launch": int(bytes_per_launch.mean()),
         },

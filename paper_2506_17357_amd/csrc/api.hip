@@ -85,13 +85,22 @@ int props(DevProps *out) {
     return TGA_OK;
 }
 
-constexpr size_t kLdsBudget = 64 * 1024;  // default per-item LDS: two workgroups per CU
+// LDS per inter-route workgroup used to size the row sub-blocks: 64 KiB
+// lets two workgroups share a CU.  TGA_LDS_KB overrides it (tuning).
+size_t lds_budget() {
+    static size_t b = [] {
+        const char *e = getenv("TGA_LDS_KB");
+        const long kb = (e && *e) ? atol(e) : 64;
+        return (size_t)std::max(16L, std::min(160L, kb)) * 1024;
+    }();
+    return b;
+}
 
 size_t row_bytes(int np1) { return (size_t)np1 * 4 + 64; }
 
 int default_tile_rows(int np1) {
-    long t = (long)(kLdsBudget / row_bytes(np1)) - 2;
-    return (int)std::max(1L, std::min(32L, t));
+    long t = (long)(lds_budget() / row_bytes(np1)) - 2;
+    return (int)std::max(1L, std::min(64L, t));
 }
 
 size_t item_lds(int np1, int tile_rows) { return (size_t)(tile_rows + 2) * row_bytes(np1); }
@@ -142,7 +151,7 @@ SolLayout sol_layout(int n, int R) {
     L.acc = take(8 * kAccCount);
     L.max_items = (int)count_items((int)Q, default_tile_rows(n + 1));
     L.items = take(sizeof(InterItem) * L.max_items);
-    L.intra = take(sizeof(IntraItem) * std::max(R, 1));
+    L.intra = take(sizeof(IntraItem) * std::max(R, 1));  // at most one group per route
     L.total = off;
     return L;
 }
@@ -275,11 +284,20 @@ extern "C" int tga_free_instance(tga_instance_t inst) {
 
 static int check_partition(int n, int R, const int32_t *offsets, const int32_t *customers);
 
+// Intra-route items: groups of consecutive routes whose customers typically
+// fill about 48 of a wavefront's 64 lanes (the kernel falls back to one route
+// at a time when a group has grown beyond what its wavefront can stage).
+static void push_intra_groups(int n, int R, int sol_index, std::vector<IntraItem> &intra) {
+    const int avgL = std::max(1, n / std::max(1, R));
+    const int G = std::max(1, std::min(kIntraMaxGroup, 48 / (avgL + 1)));
+    for (int r = 0; r < R; r += G) intra.push_back(IntraItem{sol_index, r, std::min(R, r + G), 0});
+}
+
 static void build_plain_items(tga_solution *S, std::vector<InterItem> &items,
                               std::vector<IntraItem> &intra, int sol_index) {
     for_each_item(S->Q, S->tile_rows,
                   [&](int s0, int s1, int c0) { items.push_back(InterItem{sol_index, s0, s1, c0}); });
-    for (int r = 0; r < S->R; ++r) intra.push_back(IntraItem{sol_index, r});
+    push_intra_groups(S->n, S->R, sol_index, intra);
 }
 
 extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
@@ -731,7 +749,7 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         descs[i].tile_rows = tr;
         lds = std::max(lds, item_lds(s->h.np1, tr));
         for_each_item(s->Q, ri, [&](int s0, int s1, int c0) { items.push_back(InterItem{i, s0, s1, c0}); });
-        for (int r = 0; r < s->R; ++r) intra.push_back(IntraItem{i, r});
+        push_intra_groups(s->n, s->R, i, intra);
     }
     lds = std::max(lds, (size_t)kInterWaves * kIntraRegionBytes);  // the intra phase's regions
     if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);

@@ -45,8 +45,35 @@ __device__ __forceinline__ int4 gld(const int4 *p) {
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ int2 gld(const int2 *p) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i v = *(const __attribute__((address_space(1))) v2i *)p;
+    return make_int2(v.x, v.y);
+}
+
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
+__device__ __forceinline__ void gst(int4 *p, int4 v) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i x = {v.x, v.y, v.z, v.w};
+    *(__attribute__((address_space(1))) v4i *)p = x;
+}
+
+__device__ __forceinline__ void gst(int2 *p, int2 v) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i x = {v.x, v.y};
+    *(__attribute__((address_space(1))) v2i *)p = x;
+}
+
 __device__ __forceinline__ int nodeof(int x) { return x & 0xFFFF; }
 __device__ __forceinline__ int flagsof(int x) { return x >> 16; }
+
+// Deltas at or above this are not admissible (inter-route moves carry a
+// penalty of 2^30; every admissible delta is far below 2^29).
+constexpr int kAdmissibleBound = 1 << 29;
 
 __device__ __forceinline__ unsigned long long pack_key(int delta, uint32_t id) {
     return ((unsigned long long)((uint32_t)delta ^ 0x80000000u) << 32) | id;
@@ -57,7 +84,7 @@ __device__ __forceinline__ bool better(int d, uint32_t id, int bd, uint32_t bid)
 }
 
 __device__ __forceinline__ void consider(int d, uint32_t id, int &bd, uint32_t &bid) {
-    if (d != kNoDelta && better(d, id, bd, bid)) {
+    if (d < kAdmissibleBound && better(d, id, bd, bid)) {
         bd = d;
         bid = id;
     }
@@ -81,7 +108,7 @@ __device__ __forceinline__ void block_argmin_commit(int bd, uint32_t bid, unsign
                                     unsigned long long *red) {
     wave_argmin(bd, bid);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = bd == kNoDelta ? ~0ull : pack_key(bd, bid);
+    if (lane == 0) red[wave] = bd >= kAdmissibleBound ? ~0ull : pack_key(bd, bid);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = ~0ull;
@@ -183,26 +210,90 @@ __device__ __forceinline__ int bwd_apply(const BwdElem &m, int y) {
 }
 
 struct ApplyShared {
-    FwdElem f[kApplyThreads];
-    BwdElem b[kApplyThreads];
+    FwdElem fw[kApplyThreads / 64];
+    BwdElem bw[kApplyThreads / 64];
     long long red[kApplyThreads / 64][5];
-    int mv[16];
 };
 
-// Forward element of slot s (reads what pass 1 and 2 wrote).
-__device__ __forceinline__ FwdElem fwd_elem(const SolDev &S, int s) {
-    const int4 a = S.a4[s];
+__device__ __forceinline__ FwdElem shfl_f(const FwdElem &e, int src) {
+    return FwdElem{__shfl(e.rs, src), __shfl(e.load, src), __shfl(e.dist, src),
+                   __shfl(e.th, src),  __shfl(e.al, src),   __shfl(e.be, src)};
+}
+
+__device__ __forceinline__ BwdElem shfl_b(const BwdElem &e, int src) {
+    return BwdElem{__shfl(e.rs, src), __shfl(e.th, src), __shfl(e.al, src), __shfl(e.be, src)};
+}
+
+// Exclusive prefix (in thread order) of per-thread forward aggregates:
+// wavefront shuffle scan, then a scan of the wavefront totals by wavefront 0.
+__device__ __forceinline__ FwdElem block_prefix_fwd(FwdElem v, FwdElem *wtot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    FwdElem x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const FwdElem y = shfl_f(x, lane - d < 0 ? lane : lane - d);
+        if (lane >= d) x = fwd_cat(y, x);
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        FwdElem w = lane < nw ? wtot[lane] : fwd_identity();
+        for (int d = 1; d < 64; d <<= 1) {
+            const FwdElem y = shfl_f(w, lane - d < 0 ? lane : lane - d);
+            if (lane >= d) w = fwd_cat(y, w);
+        }
+        if (lane < nw) wtot[lane] = w;
+    }
+    __syncthreads();
+    FwdElem ex = shfl_f(x, lane == 0 ? 0 : lane - 1);
+    if (lane == 0) ex = fwd_identity();
+    const FwdElem pre = wave > 0 ? wtot[wave - 1] : fwd_identity();
+    const FwdElem r = fwd_cat(pre, ex);
+    __syncthreads();
+    return r;
+}
+
+// Exclusive suffix (aggregate of the threads after this one) of backward
+// aggregates.
+__device__ __forceinline__ BwdElem block_suffix_bwd(BwdElem v, BwdElem *wtot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    BwdElem x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const BwdElem y = shfl_b(x, lane + d > 63 ? lane : lane + d);
+        if (lane + d < 64) x = bwd_cat(x, y);
+    }
+    if (lane == 0) wtot[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        BwdElem w = lane < nw ? wtot[lane] : bwd_identity();
+        for (int d = 1; d < 64; d <<= 1) {
+            const BwdElem y = shfl_b(w, lane + d > 63 ? lane : lane + d);
+            if (lane + d < nw) w = bwd_cat(w, y);
+        }
+        if (lane < nw) wtot[lane] = w;
+    }
+    __syncthreads();
+    BwdElem ex = shfl_b(x, lane == 63 ? 63 : lane + 1);
+    if (lane == 63) ex = bwd_identity();
+    const BwdElem post = wave < nw - 1 ? wtot[wave + 1] : bwd_identity();
+    const BwdElem r = bwd_cat(ex, post);
+    __syncthreads();
+    return r;
+}
+
+// Forward element of slot s (reads what passes 1 and 2 wrote).
+__device__ __forceinline__ FwdElem fwd_elem(const SolDev &S, const int32_t *roffn, int s) {
+    const int4 a = gld(S.a4 + s);
     FwdElem e;
-    if (s == S.roff[a.y]) {
+    if (s == gld(roffn + a.y)) {
         e = fwd_identity();
         e.rs = 1;
         return e;
     }
-    const int4 ap = S.a4[s - 1];
-    const int sp = S.w4[s - 1].z;
-    const int4 w = S.w4[s];
+    const int4 ap = gld(S.a4 + s - 1);
+    const int sp = gld(S.w4 + s - 1).z;
+    const int4 w = gld(S.w4 + s);
     e.rs = 0;
-    e.load = S.b4[s].x;
+    e.load = gld(S.b4 + s).x;
     e.dist = ap.z;
     e.al = sp + ap.z;
     e.th = w.y - e.al;
@@ -210,10 +301,10 @@ __device__ __forceinline__ FwdElem fwd_elem(const SolDev &S, int s) {
     return e;
 }
 
-__device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, int s) {
-    const int4 a = S.a4[s];
-    const int4 w = S.w4[s];
-    const int last = S.roff[a.y + 1] - 1;
+__device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, const int32_t *roffn, int s) {
+    const int4 a = gld(S.a4 + s);
+    const int4 w = gld(S.w4 + s);
+    const int last = gld(roffn + a.y + 1) - 1;
     const int b = w.z + a.z;
     BwdElem e;
     e.rs = s == last;
@@ -231,137 +322,132 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     const int tid = threadIdx.x, T = blockDim.x;
     const int32_t *D = S.D;
     const int4 *nd = S.node4;
+    const bool tw = S.has_tw;
 
-    for (int r = tid; r <= R; r += T) S.roff[r] = roffn[r];
+    for (int r = tid; r <= R; r += T) gst(S.roff + r, gld(roffn + r));
     // pass 1: node, route, edge, per-node data, ref map
     for (int s = tid; s < Q; s += T) {
-        const int2 x = nr[s];
+        const int2 x = gld(nr + s);
         const int node = x.x, r = x.y;
-        const int first = roffn[r], last = roffn[r + 1] - 1;
-        const int succ = s < last ? nr[s + 1].x : 0;
-        int4 q = nd[node];
-        if (!S.has_tw) q = make_int4(q.x, 0, kTwOff, 0);
-        const int edge = D[(size_t)node * np1 + succ];
+        const int first = gld(roffn + r), last = gld(roffn + r + 1) - 1;
+        const int succ = s < last ? gld(nr + s + 1).x : 0;
+        int4 q = gld(nd + node);
+        if (!tw) q = make_int4(q.x, 0, kTwOff, 0);
+        const int edge = gld(D + (size_t)node * np1 + succ);
         const bool cust = s != first;
-        S.a4[s] = make_int4(node | ((cust ? kFlagCustomer : 0) << 16), r, edge, 0);
-        S.w4[s] = make_int4(q.y, q.z, q.w, 0);
-        S.b4[s] = make_int4(cust ? q.x : 0, 0, 0, 0);
-        S.ref2slot[cust ? node - 1 : n + r] = s;
+        gst(S.a4 + s, make_int4(node | ((cust ? kFlagCustomer : 0) << 16), r, edge, 0));
+        gst(S.w4 + s, make_int4(q.y, q.z, q.w, 0));
+        gst(S.b4 + s, make_int4(cust ? q.x : 0, 0, 0, 0));
+        gst(S.ref2slot + (cust ? node - 1 : n + r), s);
     }
     if (tid == 0) {
-        S.a4[Q] = make_int4(0, R, 0, 0);
-        S.b4[Q] = make_int4(0, 0, 0, 0);
-        S.w4[Q] = make_int4(S.has_tw ? nd[0].y : 0, S.has_tw ? nd[0].z : kTwOff, 0, 0);
-        S.t4[Q] = make_int4(kInf, kNeg, kInf, kNeg);
-        S.pdist[Q] = 0;
+        gst(S.a4 + Q, make_int4(0, R, 0, 0));
+        gst(S.b4 + Q, make_int4(0, 0, 0, 0));
+        gst(S.w4 + Q, make_int4(tw ? gld(nd).y : 0, tw ? gld(nd).z : kTwOff, 0, 0));
+        gst(S.t4 + Q, make_int4(kInf, kNeg, kInf, kNeg));
+        gst(S.pdist + Q, 0);
     }
     __threadfence_block();
     __syncthreads();
     // pass 2: removal delta and incident-edge sums (customers)
     for (int s = tid; s < Q; s += T) {
-        const int4 a = S.a4[s];
-        if (s == S.roff[a.y]) continue;
-        const int4 ap = S.a4[s - 1];
-        const int succ = s + 1 < S.roff[a.y + 1] ? nr[s + 1].x : 0;
-        const int dpw = D[(size_t)nodeof(ap.x) * np1 + succ];
-        S.a4[s].w = dpw - ap.z - a.z;
-        S.b4[s].w = ap.z + a.z;
+        int4 a = gld(S.a4 + s);
+        if (s == gld(roffn + a.y)) continue;
+        const int4 ap = gld(S.a4 + s - 1);
+        const int succ = s + 1 < gld(roffn + a.y + 1) ? gld(nr + s + 1).x : 0;
+        const int dpw = gld(D + (size_t)nodeof(ap.x) * np1 + succ);
+        a.w = dpw - ap.z - a.z;
+        gst(S.a4 + s, a);
+        int4 b = gld(S.b4 + s);
+        b.w = ap.z + a.z;
+        gst(S.b4 + s, b);
     }
     __threadfence_block();
     __syncthreads();
 
     const int C = (Q + T - 1) / T;
     const int beg = min(Q, tid * C), end = min(Q, beg + C);
-    // forward scans (exclusive Hillis-Steele over the chunk aggregates)
+    // forward scans: prefix load, prefix distance, earliest service start A
     {
         FwdElem agg = fwd_identity();
-        for (int s = beg; s < end; ++s) agg = fwd_cat(agg, fwd_elem(S, s));
-        sh.f[tid] = agg;
-        __syncthreads();
-        for (int off = 1; off < T; off <<= 1) {
-            FwdElem x = tid >= off ? sh.f[tid - off] : fwd_identity();
-            __syncthreads();
-            if (tid >= off) sh.f[tid] = fwd_cat(x, sh.f[tid]);
-            __syncthreads();
-        }
-        FwdElem run = tid ? sh.f[tid - 1] : fwd_identity();
-        __syncthreads();
-        const int e0 = S.has_tw ? nd[0].y : 0;
+        for (int s = beg; s < end; ++s) agg = fwd_cat(agg, fwd_elem(S, roffn, s));
+        FwdElem run = block_prefix_fwd(agg, sh.fw);
+        const int e0 = tw ? gld(nd).y : 0;
         for (int s = beg; s < end; ++s) {
-            run = fwd_cat(run, fwd_elem(S, s));
-            S.b4[s].y = run.load;
-            S.pdist[s] = run.dist;
-            nr[s].x = S.has_tw ? fwd_apply(run, e0) : 0;  // A[s]
+            run = fwd_cat(run, fwd_elem(S, roffn, s));
+            int4 b = gld(S.b4 + s);
+            b.y = run.load;
+            gst(S.b4 + s, b);
+            gst(S.pdist + s, run.dist);
+            int2 z = gld(nr + s);
+            z.x = tw ? fwd_apply(run, e0) : 0;  // A[s]
+            gst(nr + s, z);
         }
     }
     __threadfence_block();
     __syncthreads();
-    // backward scan, in reversed thread order (position p = T-1-tid); CVRP
-    // needs no window attributes
-    if (!S.has_tw) {
-        for (int s = beg; s < end; ++s) nr[s].y = kTwOff;
+    // backward scan: latest feasible arrival Z (windows only)
+    if (!tw) {
+        for (int s = beg; s < end; ++s) {
+            int2 z = gld(nr + s);
+            z.y = kTwOff;
+            gst(nr + s, z);
+        }
     } else {
         BwdElem agg = bwd_identity();
-        for (int s = end - 1; s >= beg; --s) agg = bwd_cat(bwd_elem(S, s), agg);
-        const int p = T - 1 - tid;
-        sh.b[p] = agg;
-        __syncthreads();
-        for (int off = 1; off < T; off <<= 1) {
-            BwdElem x = p >= off ? sh.b[p - off] : bwd_identity();
-            __syncthreads();
-            if (p >= off) sh.b[p] = bwd_cat(sh.b[p], x);
-            __syncthreads();
-        }
-        BwdElem run = p ? sh.b[p - 1] : bwd_identity();
-        __syncthreads();
-        const int l0 = S.has_tw ? nd[0].z : kTwOff;
+        for (int s = end - 1; s >= beg; --s) agg = bwd_cat(bwd_elem(S, roffn, s), agg);
+        BwdElem run = block_suffix_bwd(agg, sh.bw);
+        const int l0 = gld(nd).z;
         for (int s = end - 1; s >= beg; --s) {
-            run = bwd_cat(bwd_elem(S, s), run);
-            nr[s].y = bwd_apply(run, l0);  // Z[s]
+            run = bwd_cat(bwd_elem(S, roffn, s), run);
+            int2 z = gld(nr + s);
+            z.y = bwd_apply(run, l0);  // Z[s]
+            gst(nr + s, z);
         }
     }
     __threadfence_block();
     __syncthreads();
     // pass 3: route totals (by the thread owning each route's last slot)
     for (int s = tid; s < Q; s += T) {
-        const int r = S.a4[s].y;
-        if (s == S.roff[r + 1] - 1) S.rdist[r] = S.pdist[s] + S.a4[s].z;
+        const int r = gld(S.a4 + s).y;
+        if (s == gld(roffn + r + 1) - 1) gst(S.rdist + r, gld(S.pdist + s) + gld(S.a4 + s).z);
     }
     // pass 4: derived per-slot values and flags
-    const int l0 = S.has_tw ? nd[0].z : kTwOff;
+    const int l0 = tw ? gld(nd).z : kTwOff;
     const int cap = S.cap;
     for (int s = tid; s < Q; s += T) {
-        int4 a = S.a4[s];
-        const int first = S.roff[a.y], last = S.roff[a.y + 1] - 1;
-        const int rload = S.b4[last].y;
-        const int4 w = S.w4[s];
-        const int A = nr[s].x;
+        int4 a = gld(S.a4 + s);
+        const int first = gld(roffn + a.y), last = gld(roffn + a.y + 1) - 1;
+        const int rload = gld(S.b4 + last).y;
+        const int4 w = gld(S.w4 + s);
+        const int2 az = gld(nr + s);
+        const int A = az.x;
         const int dep = A >= kInf ? kInf : A + w.z;
-        const int zn = s < last ? nr[s + 1].y : l0;
+        const int zn = s < last ? gld(nr + s + 1).y : l0;
         int adp = kInf;
         int flags = flagsof(a.x);
-        int4 b = S.b4[s];
+        int4 b = gld(S.b4 + s);
         if (s != first) {
-            const int Ap = nr[s - 1].x;
-            adp = Ap >= kInf ? kInf : Ap + S.w4[s - 1].z;
+            const int Ap = gld(nr + s - 1).x;
+            adp = Ap >= kInf ? kInf : Ap + gld(S.w4 + s - 1).z;
             if (rload - b.x <= cap) flags |= kFlagRemCap;
             // without this node: predecessor departure + c(pred, succ) <= Z(succ)
             const int dpw = a.w + b.w;  // removal delta + incident edges = c(pred, succ)
             if (adp < kInf && adp + dpw <= zn) flags |= kFlagRemTw;
         }
         a.x = nodeof(a.x) | (flags << 16);
-        S.a4[s] = a;
+        gst(S.a4 + s, a);
         b.z = rload;
-        S.b4[s] = b;
-        S.t4[s] = make_int4(dep, zn, adp, nr[s].y);
+        gst(S.b4 + s, b);
+        gst(S.t4 + s, make_int4(dep, zn, adp, az.y));
     }
     __threadfence_block();
     __syncthreads();
     // pass 5: cost and |N(S)| per operator
     long long v[5] = {0, 0, 0, 0, 0};
     for (int r = tid; r < R; r += T) {
-        const long long L = S.roff[r + 1] - S.roff[r] - 1;
-        v[0] += S.rdist[r];
+        const long long L = gld(roffn + r + 1) - gld(roffn + r) - 1;
+        v[0] += gld(S.rdist + r);
         v[1] += L * (Q - L - 1);
         v[2] += (L + 1) * (L + 1);
         v[3] += L * (L - 1) / 2;
@@ -428,10 +514,20 @@ __device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_u
 // lane i receives lane i-1 (lane 0 receives 0)
 __device__ __forceinline__ int from_prev_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
 
+// Column-side (lane) values of one chunk, kept in registers for a whole item.
+// Every feasibility condition below is written as a difference that must be
+// >= 0; "bad" values are 0 when a condition holds and negative otherwise, so
+// OR-ing them keeps the sign of "any condition fails".
 struct LaneCol {
     int4 ta, tb, tt, tw;
-    int node, fl, refT, routeLast;
-    bool own, cust;
+    int node;      // LDS gather index (node of slot t)
+    int refT;
+    int tyOwn;     // route(t) - 1 if the lane owns its column, else very negative
+    int tInval;    // t is a start depot (cannot move): negative
+    int tRemCap;   // t's route would exceed capacity without it... negative if not ok
+    int tRemTw;    // t's route is late without it: negative
+    int negTz, negTw;  // -edge(t), -(incident edges of t)
+    int zx, zy;        // route load - demand, route load - prefix load of t
 };
 
 // Stage rows [first, first + cnt) of S (clamped to the slot range) into LDS:
@@ -463,92 +559,133 @@ __device__ __forceinline__ void stage_rows(const SolDev &S, int first, int cnt, 
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// The four inter-route moves of row slot s against the lane's column slot t.
-// g = D[s][t], gp = D[pred(s)][t], gn = D[succ(s)][t]; gR = D[s][succ(t)],
-// gL = D[s][pred(t)].
+constexpr int kSign = (int)0x80000000;
+constexpr int kPenalty = 1 << 30;     // added to the delta of an inadmissible move
+constexpr int kAdmissible = 1 << 29;  // every admissible delta is below this
+
+// delta, plus kPenalty when viol < 0
+__device__ __forceinline__ int penalise(int d, int viol) {
+    return d + (int)(((uint32_t)viol >> 31) << 30);
+}
+
+// Row-side (scalar) values of one row slot s.
+struct RowVals {
+    int rs, refS;
+    int sInval, sRemCap, sRemTw;   // 0 or negative, as the lane's
+    int capA, capB, capC, capD, capE;
+    int rw_ra, rz;                 // removal delta of s, edge(s)
+    int rbw;                       // incident edges of s
+};
+
+__device__ __forceinline__ RowVals row_vals(const int4 &ra, const int4 &rb, int cap, int n) {
+    RowVals R;
+    const int fl = flagsof(ra.x);
+    const bool cust = fl & kFlagCustomer;
+    R.rs = ra.y;
+    R.refS = cust ? nodeof(ra.x) - 1 : n + ra.y;
+    R.sInval = cust ? 0 : kSign;
+    R.sRemCap = (fl & kFlagRemCap) ? 0 : kSign;
+    R.sRemTw = (fl & kFlagRemTw) ? 0 : kSign;
+    R.capA = cap - rb.x;          // relocate s->t: load(t) <= capA; swap: load(t) - dem(t) <= capA
+    R.capB = cap - rb.z;          // relocate t->s: dem(t) <= capB
+    R.capC = cap - rb.z + rb.x;   // swap: dem(t) <= capC
+    R.capD = cap - rb.y;          // 2-opt*: load(t) - prefix(t) <= capD
+    R.capE = cap - rb.z + rb.y;   // 2-opt*: prefix(t) <= capE
+    R.rw_ra = ra.w;
+    R.rz = ra.z;
+    R.rbw = rb.w;
+    return R;
+}
+
+// The four inter-route moves of row slot s against the lane's column slot t:
+// RELOCATE s -> after t, RELOCATE t -> after s, SWAP s <-> t, 2OPT*(s, t).
+// g = D[s][t], gp = D[pred(s)][t], gn = D[succ(s)][t], gR = D[s][succ(t)],
+// gL = D[s][pred(t)].  rt / rw: the row's time values and window (TW only).
 template <bool TW, bool DUMP>
-__device__ __forceinline__ void pair_moves(const LaneCol &L, const int4 &ra, const int4 &rb, const int4 &rt,
-                                           const int4 &rw, int gp, int g, int gn, int gR, int gL, int n,
-                                           int cap, uint32_t uQ, bool opRel, bool opSwap, bool op2s,
-                                           int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
-                                           int &bd, uint32_t &bid) {
+__device__ __forceinline__ void pair_moves(const LaneCol &L, const RowVals &R, const int4 &rt, const int4 &rw,
+                                           int gp, int g, int gn, int gR, int gL, uint32_t uQ, bool opRel,
+                                           bool opSwap, bool op2s, int32_t *__restrict__ dump_delta,
+                                           uint8_t *__restrict__ dump_feas, int &bd, uint32_t &bid) {
     const int4 ta = L.ta, tb = L.tb, tt = L.tt, tw = L.tw;
-    const int flT = L.fl;
-    const bool tCust = L.cust;
-    const uint32_t refT = (uint32_t)L.refT;
-    const bool pair = L.own && ta.y > ra.y;
-    const int flS = flagsof(ra.x);
-    const bool sCust = flS & kFlagCustomer;
-    const uint32_t refS = sCust ? nodeof(ra.x) - 1 : n + ra.y;
-    const uint32_t lo = min(refS, refT), hi = max(refS, refT);
+    const int pairViol = L.tyOwn - R.rs;  // >= 0 iff the lane owns t and route(t) > route(s)
 
     // RELOCATE s -> right after t
-    int d1 = kNoDelta;
-    bool v1 = false, c1 = false, w1 = true;
-    if (opRel && sCust) {
-        v1 = pair;
-        d1 = ra.w + g + gR - ta.z;
-        c1 = (flS & kFlagRemCap) && (tb.z + rb.x <= cap);
-        if (TW) w1 = (flS & kFlagRemTw) && tw_insert(tt.x, g, rw.x, rw.y, rw.z, gR, tt.y);
+    const int d1 = g + gR + L.negTz + R.rw_ra;
+    const int cap1 = R.capA - tb.z;
+    int tw1 = 0;
+    if (TW) {
+        const int arr = tt.x + g;
+        const int st = max(arr, rw.x);
+        tw1 = (rw.y - arr) | ((tt.y - rw.z) - (st + gR)) | R.sRemTw;
     }
+    const int v1 = pairViol | R.sInval;
+    const int e1 = penalise(d1, v1 | cap1 | R.sRemCap | tw1);
+
     // RELOCATE t -> right after s
-    int d2 = kNoDelta;
-    bool v2 = false, c2 = false, w2 = true;
-    if (opRel) {
-        v2 = pair && tCust;
-        d2 = ta.w + g + gn - ra.z;
-        c2 = (flT & kFlagRemCap) && (rb.z + tb.x <= cap);
-        if (TW) w2 = (flT & kFlagRemTw) && tw_insert(rt.x, g, tw.x, tw.y, tw.z, gn, rt.y);
+    const int d2 = g + gn + ta.w - R.rz;
+    const int cap2 = R.capB - tb.x;
+    int tw2 = 0;
+    if (TW) {
+        const int arr = rt.x + g;
+        const int st = max(arr, tw.x);
+        tw2 = (tw.y - arr) | (rt.y - (st + tw.z + gn)) | L.tRemTw;
     }
+    const int v2 = pairViol | L.tInval;
+    const int e2 = penalise(d2, v2 | cap2 | L.tRemCap | tw2);
+
     // SWAP s <-> t
-    int d3 = kNoDelta;
-    bool v3 = false, c3 = false, w3 = true;
-    if (opSwap && sCust) {
-        v3 = pair && tCust;
-        d3 = gp + gn + gL + gR - rb.w - tb.w;
-        c3 = (rb.z - rb.x + tb.x <= cap) && (tb.z - tb.x + rb.x <= cap);
-        if (TW)
-            w3 = tw_insert(rt.z, gp, tw.x, tw.y, tw.z, gn, rt.y) && tw_insert(tt.z, gL, rw.x, rw.y, rw.z, gR, tt.y);
+    const int d3 = gp + gn + gL + gR + L.negTw - R.rbw;
+    const int cap3 = (R.capC - tb.x) | (R.capA - L.zx);
+    int tw3 = 0;
+    if (TW) {
+        const int arrS = rt.z + gp;  // t placed where s was
+        const int stS = max(arrS, tw.x);
+        const int arrT = tt.z + gL;  // s placed where t was
+        const int stT = max(arrT, rw.x);
+        tw3 = (tw.y - arrS) | (rt.y - (stS + tw.z + gn)) | (rw.y - arrT) | (tt.y - (stT + rw.z + gR));
     }
+    const int v3 = pairViol | R.sInval | L.tInval;
+    const int e3 = penalise(d3, v3 | cap3 | tw3);
+
     // 2OPT*(s, t): heads keep their slots, tails are exchanged
-    int d4 = kNoDelta;
-    bool v4 = false, c4 = false, w4 = true;
-    if (op2s) {
-        v4 = pair;
-        d4 = gR + gn - ra.z - ta.z;
-        c4 = (rb.y + tb.z - tb.y <= cap) && (tb.y + rb.z - rb.y <= cap);
-        if (TW) w4 = (rt.x + gR <= tt.y) && (tt.x + gn <= rt.y);
-    }
+    const int d4 = gR + gn + L.negTz - R.rz;
+    const int cap4 = (R.capD - L.zy) | (R.capE - tb.y);
+    int tw4 = 0;
+    if (TW) tw4 = ((tt.y - gR) - rt.x) | ((rt.y - gn) - tt.x);
+    const int e4 = penalise(d4, pairViol | cap4 | tw4);
+
+    const uint32_t lo = min((uint32_t)R.refS, (uint32_t)L.refT), hi = max((uint32_t)R.refS, (uint32_t)L.refT);
     if (DUMP) {
-        if (v1) {
-            const uint32_t id = (uQ + refS) * uQ + refT;
+        // exact feasibility bits of every valid move
+        if (opRel && v1 >= 0) {
+            const uint32_t id = (uQ + R.refS) * uQ + L.refT;
             dump_delta[id] = d1;
-            dump_feas[id] = (uint8_t)(c1 | (w1 << 1));
+            dump_feas[id] = (uint8_t)(((cap1 | R.sRemCap) >= 0) | ((tw1 >= 0) << 1));
         }
-        if (v2) {
-            const uint32_t id = (uQ + refT) * uQ + refS;
+        if (opRel && v2 >= 0) {
+            const uint32_t id = (uQ + L.refT) * uQ + R.refS;
             dump_delta[id] = d2;
-            dump_feas[id] = (uint8_t)(c2 | (w2 << 1));
+            dump_feas[id] = (uint8_t)(((cap2 | L.tRemCap) >= 0) | ((tw2 >= 0) << 1));
         }
-        if (v3) {
+        if (opSwap && v3 >= 0) {
             const uint32_t id = (5u * uQ + lo) * uQ + hi;
             dump_delta[id] = d3;
-            dump_feas[id] = (uint8_t)(c3 | (w3 << 1));
+            dump_feas[id] = (uint8_t)((cap3 >= 0) | ((tw3 >= 0) << 1));
         }
-        if (v4) {
+        if (op2s && pairViol >= 0) {
             const uint32_t id = (8u * uQ + lo) * uQ + hi;
             dump_delta[id] = d4;
-            dump_feas[id] = (uint8_t)(c4 | (w4 << 1));
+            dump_feas[id] = (uint8_t)((cap4 >= 0) | ((tw4 >= 0) << 1));
         }
     }
-    const int m1 = (v1 && c1 && w1) ? d1 : kNoDelta;
-    const int m2 = (v2 && c2 && w2) ? d2 : kNoDelta;
-    const int m3 = (v3 && c3 && w3) ? d3 : kNoDelta;
-    const int m4 = (v4 && c4 && w4) ? d4 : kNoDelta;
+    const int m1 = opRel ? e1 : kNoDelta;
+    const int m2 = opRel ? e2 : kNoDelta;
+    const int m3 = opSwap ? e3 : kNoDelta;
+    const int m4 = op2s ? e4 : kNoDelta;
     const int m = min(min(m1, m2), min(m3, m4));
-    if (m != kNoDelta && m <= bd) {
-        consider(m1, (uQ + refS) * uQ + refT, bd, bid);
-        consider(m2, (uQ + refT) * uQ + refS, bd, bid);
+    if (m <= bd) {  // rare: only an admissible move can reach bd (< kAdmissible)
+        consider(m1, (uQ + R.refS) * uQ + L.refT, bd, bid);
+        consider(m2, (uQ + L.refT) * uQ + R.refS, bd, bid);
         consider(m3, (5u * uQ + lo) * uQ + hi, bd, bid);
         consider(m4, (8u * uQ + lo) * uQ + hi, bd, bid);
     }
@@ -576,7 +713,6 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         const int t = cb - 1 + lane;
         const int tc = min(max(t, 0), Q);
         LaneCol &L = col[c];
-        L.own = lane >= 1 && lane <= kColsPerWave && t < cend;
         L.ta = gld(S.a4 + tc);
         L.tb = gld(S.b4 + tc);
         if (TW) {
@@ -587,9 +723,18 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
             L.tw = make_int4(0, 0, 0, 0);
         }
         L.node = nodeof(L.ta.x);
-        L.fl = flagsof(L.ta.x);
-        L.cust = L.fl & kFlagCustomer;
-        L.refT = L.cust ? L.node - 1 : n + L.ta.y;
+        const int fl = flagsof(L.ta.x);
+        const bool cust = fl & kFlagCustomer;
+        const bool own = lane >= 1 && lane <= kColsPerWave && t < cend;
+        L.refT = cust ? L.node - 1 : n + L.ta.y;
+        L.tyOwn = own ? L.ta.y - 1 : -(1 << 30);
+        L.tInval = cust ? 0 : kSign;
+        L.tRemCap = (fl & kFlagRemCap) ? 0 : kSign;
+        L.tRemTw = (fl & kFlagRemTw) ? 0 : kSign;
+        L.negTz = -L.ta.z;
+        L.negTw = -L.tb.w;
+        L.zx = L.tb.z - L.tb.x;
+        L.zy = L.tb.z - L.tb.y;
         // route of the last owned column (-1: chunk empty); the same for every
         // lane of the wavefront, so keep it scalar
         const int lastLane = min(kColsPerWave, cend - cb);
@@ -598,7 +743,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         routeMax = max(routeMax, routeLast[c]);
     }
 
-    int bd = kNoDelta;
+    int bd = kAdmissibleBound;
     uint32_t bid = 0xFFFFFFFFu;
     int4 *rowa = smem4;
     int4 *rowb = rowa + (tr + 2);
@@ -627,6 +772,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 rt = rowt[k];
                 rw = roww[k];
             }
+            const RowVals R = row_vals(ra, rb, cap, n);
             const int *rowNext = rows + (k + 1) * np1;
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
@@ -634,8 +780,8 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 if (routeLast[c] > ra.y) {
                     const int gR = from_next_lane(g[c]);  // D[s][succ(t)]
                     const int gL = from_prev_lane(g[c]);  // D[s][pred(t)]
-                    pair_moves<TW, DUMP>(col[c], ra, rb, rt, rw, gp[c], g[c], gn, gR, gL, n, cap, uQ, opRel,
-                                         opSwap, op2s, dump_delta, dump_feas, bd, bid);
+                    pair_moves<TW, DUMP>(col[c], R, rt, rw, gp[c], g[c], gn, gR, gL, uQ, opRel, opSwap, op2s,
+                                         dump_delta, dump_feas, bd, bid);
                 }
                 gp[c] = g[c];
                 g[c] = gn;
@@ -673,7 +819,6 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 // the slot arrays and D directly.
 
 constexpr int kIntraRegionBytes = 8192;  // LDS per wavefront in the intra phase
-constexpr int kIntraMaxPos = 40;         // positions (L + 2) staged in a region
 
 // Staged view: seven per-position arrays and the distance sub-block.
 struct RouteLds {
@@ -703,19 +848,19 @@ struct RouteGlobal {
     __device__ int dd(int p, int q) const { return gld(S->D + (size_t)node(p) * S->np1 + node(q)); }
 };
 
+// Moves of route r (L customers, view V) whose first position is i, for
+// i = i0, i0 + di, ... <= L.
 template <bool TW, bool DUMP, class RV>
-__device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r, int L, uint32_t op_mask,
-                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas, int &bd,
-                            uint32_t &bid) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r, int L, int i0, int di,
+                                            bool capOK, uint32_t op_mask, int32_t *__restrict__ dump_delta,
+                                            uint8_t *__restrict__ dump_feas, int &bd, uint32_t &bid) {
     const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
     const int n = S.n;
     const uint32_t uQ = (uint32_t)S.Q;
-    const bool capOK = gld(S.b4 + gld(S.roff + r)).z <= S.cap;
     auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(V.node(p) - 1); };
     auto segAt = [&](int p) { return seg_node(V.e(p), V.l(p), V.s(p)); };
 #pragma unroll 1
-    for (int i = lane + 1; i <= L; i += 64) {
+    for (int i = i0; i <= L; i += di) {
         const int eP = V.edge(i - 1);  // c(c_{i-1}, c_i)
         const int depP = TW ? V.dep(i - 1) : 0;
         const uint32_t refI = ref(i);
@@ -829,71 +974,162 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
     }
 }
 
-// One wavefront evaluates every intra-route move of one route and commits
-// its best to the solution's key.  region: this wavefront's LDS bytes
-// (kIntraRegionBytes).
-template <bool TW, bool DUMP>
-__device__ __forceinline__ void intra_route(const SolDev &S, const IntraItem &item, uint32_t op_mask,
-                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
-                            int *region) {
+// Stage route r (P = L + 2 positions) at `base` in LDS: seven per-position
+// arrays followed by the P x P distance sub-block.  Returns the view.
+template <bool TW>
+__device__ __forceinline__ RouteLds stage_route(const SolDev &S, int off, int L, int l0, int *base) {
     const int lane = threadIdx.x & 63;
-    int bd = kNoDelta;
-    uint32_t bid = 0xFFFFFFFFu;
-    const int r = item.route;
-    const int off = gld(S.roff + r);
-    const int L = gld(S.roff + r + 1) - off - 1;
-    const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
     const int P = L + 2;
-    if (P <= kIntraMaxPos) {
-        int *pn = region, *pe = pn + P, *pdep = pe + P, *pz = pdep + P, *pe_ = pz + P, *pl = pe_ + P,
-            *ps = pl + P, *dm = ps + P;
-        for (int p = lane; p < P; p += 64) {
-            if (p <= L) {
-                const int4 a = gld(S.a4 + off + p);
-                pn[p] = nodeof(a.x);
-                pe[p] = a.z;
-                if (TW) {
-                    const int4 t = gld(S.t4 + off + p);
-                    const int4 w = gld(S.w4 + off + p);
-                    pdep[p] = t.x;
-                    pz[p] = t.w;
-                    pe_[p] = w.x;
-                    pl[p] = w.y;
-                    ps[p] = w.z;
-                }
-            } else {
-                pn[p] = 0;
-                pe[p] = 0;
-                pz[p] = l0;
+    int *pn = base, *pe = pn + P, *pdep = pe + P, *pz = pdep + P, *pe_ = pz + P, *pl = pe_ + P, *ps = pl + P,
+        *dm = ps + P;
+    for (int p = lane; p < P; p += 64) {
+        if (p <= L) {
+            const int4 a = gld(S.a4 + off + p);
+            pn[p] = nodeof(a.x);
+            pe[p] = a.z;
+            if (TW) {
+                const int4 t = gld(S.t4 + off + p);
+                const int4 w = gld(S.w4 + off + p);
+                pdep[p] = t.x;
+                pz[p] = t.w;
+                pe_[p] = w.x;
+                pl[p] = w.y;
+                ps[p] = w.z;
+            }
+        } else {
+            pn[p] = 0;
+            pe[p] = 0;
+            pz[p] = l0;
+        }
+    }
+    return RouteLds{pn, pe, pdep, pz, pe_, pl, ps, dm, P};
+}
+
+__device__ __forceinline__ void stage_dist_block(const SolDev &S, const RouteLds &V) {
+    const int lane = threadIdx.x & 63;
+    const int P = V.stride, np1 = S.np1;
+    int *dm = (int *)V.dm;
+    for (int x = lane; x < P * P; x += 64) {
+        const int p = x / P, q = x - p * P;
+        dm[x] = gld(S.D + (size_t)V.pn[p] * np1 + V.pn[q]);
+    }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kIntraMaxGroup = 8;  // routes per intra-route work item
+
+// One wavefront evaluates every intra-route move of routes [r0, r1) of one
+// solution and commits the best to the solution's key.  When all their
+// positions fit (sum of L <= 64 first positions, staged data within the
+// wavefront's LDS region), lane l takes one (route, first position) pair of
+// the whole group; otherwise routes are taken one at a time.
+template <bool TW, bool DUMP>
+__device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+                                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
+                                            int *region) {
+    const int lane = threadIdx.x & 63;
+    int bd = kAdmissibleBound;
+    uint32_t bid = 0xFFFFFFFFu;
+    const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
+    const int G = min(item.r1 - item.r0, kIntraMaxGroup);
+    int offs[kIntraMaxGroup + 1];
+    offs[0] = gld(S.roff + item.r0);
+    int sumL = 0, words = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if (k < G) {
+            offs[k + 1] = gld(S.roff + item.r0 + k + 1);
+            const int L = offs[k + 1] - offs[k] - 1, P = L + 2;
+            sumL += L;
+            words += 7 * P + P * P;
+        }
+    }
+    if (sumL <= 64 && words <= kIntraRegionBytes / 4) {
+        // stage every route of the group, then one lane per (route, first position)
+        int *base = region;
+#pragma unroll
+        for (int k = 0; k < kIntraMaxGroup; ++k) {
+            if (k < G) {
+                const int L = offs[k + 1] - offs[k] - 1;
+                stage_route<TW>(S, offs[k], L, l0, base);
+                base += 7 * (L + 2) + (L + 2) * (L + 2);
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        const int np1 = S.np1;
-        for (int x = lane; x < P * P; x += 64) {
-            const int p = x / P, q = x - p * P;
-            dm[x] = gld(S.D + (size_t)pn[p] * np1 + pn[q]);
+        wave_lds_sync();
+        base = region;
+#pragma unroll
+        for (int k = 0; k < kIntraMaxGroup; ++k) {
+            if (k < G) {
+                const int L = offs[k + 1] - offs[k] - 1, P = L + 2;
+                const int *pn = base;
+                int *dm = base + 7 * P;
+                for (int x = lane; x < P * P; x += 64) {
+                    const int p = x / P, q = x - p * P;
+                    dm[x] = gld(S.D + (size_t)pn[p] * S.np1 + pn[q]);
+                }
+                base += 7 * P + P * P;
+            }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const RouteLds V{pn, pe, pdep, pz, pe_, pl, ps, dm, P};
-        intra_moves<TW, DUMP>(S, V, r, L, op_mask, dump_delta, dump_feas, bd, bid);
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
+        // lane -> (route k, first position i) and that route's staged view
+        int myk = -1, myi = 0, myL = 0, myOff = 0, myBase = 0, cum = 0, words2 = 0;
+#pragma unroll
+        for (int k = 0; k < kIntraMaxGroup; ++k) {
+            if (k < G) {
+                const int L = offs[k + 1] - offs[k] - 1, P = L + 2;
+                if (myk < 0 && lane < cum + L) {
+                    myk = k;
+                    myi = lane - cum + 1;
+                    myL = L;
+                    myOff = offs[k];
+                    myBase = words2;
+                }
+                cum += L;
+                words2 += 7 * P + P * P;
+            }
+        }
+        if (myk >= 0) {
+            const int P = myL + 2;
+            int *b = region + myBase;
+            const RouteLds V{b, b + P, b + 2 * P, b + 3 * P, b + 4 * P, b + 5 * P, b + 6 * P, b + 7 * P, P};
+            const bool capOK = gld(S.b4 + myOff).z <= S.cap;
+            intra_moves<TW, DUMP>(S, V, item.r0 + myk, myL, myi, 1 << 30, capOK, op_mask, dump_delta, dump_feas,
+                                  bd, bid);
+        }
+        wave_lds_sync();
     } else {
-        const RouteGlobal V{&S, off, L, l0};
-        intra_moves<TW, DUMP>(S, V, r, L, op_mask, dump_delta, dump_feas, bd, bid);
+        for (int k = 0; k < G; ++k) {
+            const int r = item.r0 + k;
+            const int off = gld(S.roff + r);
+            const int L = gld(S.roff + r + 1) - off - 1;
+            const bool capOK = gld(S.b4 + off).z <= S.cap;
+            const int P = L + 2;
+            if (7 * P + P * P <= kIntraRegionBytes / 4) {
+                const RouteLds V = stage_route<TW>(S, off, L, l0, region);
+                wave_lds_sync();
+                stage_dist_block(S, V);
+                wave_lds_sync();
+                intra_moves<TW, DUMP>(S, V, r, L, lane + 1, 64, capOK, op_mask, dump_delta, dump_feas, bd, bid);
+                wave_lds_sync();
+            } else {
+                const RouteGlobal V{&S, off, L, l0};
+                intra_moves<TW, DUMP>(S, V, r, L, lane + 1, 64, capOK, op_mask, dump_delta, dump_feas, bd, bid);
+            }
+        }
     }
-    // per-wave commit (waves of one block may serve different solutions)
     wave_argmin(bd, bid);
-    if (lane == 0 && bd != kNoDelta) atomicMin(S.best_key, pack_key(bd, bid));
+    if (lane == 0 && bd < kAdmissibleBound) atomicMin(S.best_key, pack_key(bd, bid));
 }
 
 template <bool TW, bool DUMP>
-__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_intra(const SolDev *__restrict__ sols,
-                                                              const IntraItem *__restrict__ items,
-                                                              int nitems, uint32_t op_mask,
-                                                              int32_t *__restrict__ dump_delta,
-                                                              uint8_t *__restrict__ dump_feas) {
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_intra(
+    const SolDev *__restrict__ sols, const IntraItem *__restrict__ items, int nitems, uint32_t op_mask,
+    int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas) {
     extern __shared__ int4 smem4[];
     const int wave = threadIdx.x >> 6;
     int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
@@ -901,7 +1137,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         const IntraItem item = items[itx];
         const SolDev &S = sols[item.sol];
         if (S.state[kStDone]) continue;
-        intra_route<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
+        intra_group<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
     }
 }
 
@@ -973,9 +1209,9 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
             if (S.has_tw)
-                intra_route<true, false>(S, item, op_mask, nullptr, nullptr, region);
+                intra_group<true, false>(S, item, op_mask, nullptr, nullptr, region);
             else
-                intra_route<false, false>(S, item, op_mask, nullptr, nullptr, region);
+                intra_group<false, false>(S, item, op_mask, nullptr, nullptr, region);
         }
     }
     if (chunk == 0) return;

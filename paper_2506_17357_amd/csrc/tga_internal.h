@@ -8,10 +8,10 @@
 namespace tga {
 
 // Time sentinels (hard windows).  Every finite time on the path stays below
-// 2^28 (checked when an instance is loaded), so sums of a sentinel and a few
-// finite terms stay inside int32.
-constexpr int32_t kInf = 1 << 30;    // "cannot be reached in time"
-constexpr int32_t kNeg = -(1 << 30); // "no feasible arrival time"
+// 2^28 (checked when an instance is loaded), so a sentinel plus or minus a few
+// finite terms, and differences of two such sums, stay inside int32.
+constexpr int32_t kInf = 1 << 29;    // "cannot be reached in time"
+constexpr int32_t kNeg = -(1 << 29); // "no feasible arrival time"
 constexpr int32_t kNoDelta = 0x7FFFFFFF;
 
 // Slot flags (bits 16.. of a4.x; bits 0..15 hold the node, n < 2^14).
@@ -74,8 +74,9 @@ struct InterItem {
     int32_t sol, s0, s1, c0;
 };
 
+// Intra-route work item: routes [r0, r1) of one solution, one wavefront.
 struct IntraItem {
-    int32_t sol, route;
+    int32_t sol, r0, r1, pad;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

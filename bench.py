@@ -37,12 +37,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def eval_bytes(inst, R):
-    """Algorithmic HBM bytes of one evaluation: the distance matrix read once
-    plus the slot attributes the kernels need (two int4 per slot for CVRP,
-    four with time windows)."""
+def eval_bytes(inst, R, dist_bytes):
+    """Algorithmic HBM bytes of one evaluation: the distance matrix read once,
+    at the width the inter-route kernels stream it (2 bytes per entry when
+    every distance is below 2^16, else 4), plus the slot attributes the
+    kernels need (two int4 per slot for CVRP, four with time windows)."""
     Q = inst.n + R
-    return 4 * (inst.n + 1) ** 2 + (64 if inst.has_tw else 32) * (Q + 1)
+    return dist_bytes * (inst.n + 1) ** 2 + (64 if inst.has_tw else 32) * (Q + 1)
 
 
 def kernel_source_hash() -> str:
@@ -59,7 +60,7 @@ def committed_traffic(alg_bytes_per_launch):
     WRITE_SIZE (each scaled by the same counter on a copy of known size), as
     committed in profiles/; None when missing or taken on other kernel
     sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_eval_mixed_batched256.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_eval_batch_batched256.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -68,7 +69,7 @@ def committed_traffic(alg_bytes_per_launch):
         return None
     return {"bytes_per_launch": t["bytes_per_launch"],
             "vs_algorithmic": round(t["bytes_per_launch"] / alg_bytes_per_launch, 3),
-            "source": "profiles/traffic_k_eval_mixed_batched256.json"}
+            "source": "profiles/traffic_k_eval_batch_batched256.json"}
 
 
 def calibrate_copy():
@@ -151,8 +152,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--count", type=int, default=256)
     ap.add_argument("--served", action="store_true", help="benchmark the served form instead")
-    ap.add_argument("--requests", type=int, default=32)
-    ap.add_argument("--served-steps", type=int, default=100)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--served-steps", type=int, default=500)
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")
@@ -186,10 +187,11 @@ def main():
     log("workload generated in %.1f s: %d solutions, sum n = %d" % (time.time() - t, len(pairs), sum(sizes)))
     insts = [tga.Instance.from_workload(i) for i, _ in pairs]
     sols = [tga.Solution(I, s.offsets, s.customers) for I, (_, s) in zip(insts, pairs)]
-    ebytes = np.array([eval_bytes(i, s.R) for i, s in pairs], np.float64)
+    ebytes = np.array([eval_bytes(i, s.R, I.dist_bytes) for I, (i, s) in zip(insts, pairs)], np.float64)
     B = tga.Batch(sols)
     torch.cuda.synchronize()
-    log("uploaded: %.1f MB of distance matrices resident" % (sum(4 * (i.n + 1) ** 2 for i, _ in pairs) / 1e6))
+    log("uploaded: %.1f MB of distance matrices resident, %d of %d streamed at 16 bits" % (
+        sum(4 * (i.n + 1) ** 2 for i, _ in pairs) / 1e6, sum(I.dist_bytes == 2 for I in insts), len(insts)))
 
     def reload_all():
         for s, (_, sol) in zip(sols, pairs):
@@ -325,6 +327,7 @@ def main():
             "global_batch": len(pairs),
             "sum_customers": int(sum(sizes)),
             "dist_bytes_resident": int(sum(4 * (i.n + 1) ** 2 for i, _ in pairs)),
+            "dist_bytes_streamed_per_eval": int(sum(I.dist_bytes * (i.n + 1) ** 2 for I, (i, _) in zip(insts, pairs))),
             "moves_evaluated": moves_total,
             "accepted_moves": int(st_e.sum()),
             "form": "batched: one persistent evaluation launch + one finalize launch per step, "
@@ -332,7 +335,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_eval_mixed",
+            "kernel": "k_eval_batch<3>",
             "achieved": round(achieved_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -97,13 +97,19 @@ size_t tga_solution_workspace_bytes(int32_t n, int32_t R);
  *   node4  device, (n+1) x {demand, e, l, s} int32; node 0 is the depot with
  *          demand 0 and s = 0; 0 <= e <= l; s >= 0.
  *   capacity  vehicle capacity (>= 0).   has_tw  0 = CVRP, 1 = VRPTW.
- *   ws     device workspace of tga_instance_workspace_bytes(n) bytes.
+ *   ws     device workspace of tga_instance_workspace_bytes(n) bytes (it
+ *          also holds a 16-bit copy of D when every distance is below 2^16).
  * Values are checked on the device before the handle is returned
  * (TGA_EINVAL for asymmetry / negative values, TGA_ERANGE when sums along a
  * route could leave the exact int32 range).  Synchronises `stream`. */
 int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *node4, int32_t capacity,
                       int32_t has_tw, void *ws, size_t ws_bytes, void *stream,
                       tga_instance_t *out);
+
+/* Bytes per distance the inter-route kernels stream for this instance: 2
+ * when every distance is below 2^16 (tga_load_instance then keeps a 16-bit
+ * copy of D in the instance workspace), else 4.  0 for a null handle. */
+int32_t tga_instance_dist_bytes(tga_instance_t inst);
 
 /* Section 5.1 and Alg. A2 (initialise the solution tensor from S), Section
  * 5.2 and the positional tensors of Section 5.3.1 (route id and position of
@@ -192,7 +198,7 @@ int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes);
 /* Device workspace bytes for a batch of `count` solutions. */
 size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t count);
 
-/* rows_per_item: slot rows per inter-route work item (0 = about 32);
+/* rows_per_item: slot rows per inter-route work item (0 = one LDS sub-block);
  * sub_rows: rows staged in LDS at a time (0 = as many as the LDS budget of a
  * workgroup holds for the solution's n; larger values are clamped to it).
  * Both only change the schedule, never a result. */

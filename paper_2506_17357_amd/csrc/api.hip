@@ -72,7 +72,8 @@ int props(DevProps *out) {
         const int dyn = lds - 1024;
         const void *fns[] = {(const void *)k_eval_inter<false, false>, (const void *)k_eval_inter<true, false>,
                              (const void *)k_eval_inter<false, true>, (const void *)k_eval_inter<true, true>,
-                             (const void *)k_eval_mixed};
+                             (const void *)k_eval_batch<1>, (const void *)k_eval_batch<2>,
+                             (const void *)k_eval_batch<3>};
         bool ok = dyn > 65536;
         for (const void *f : fns)
             if (ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) ok = false;
@@ -96,26 +97,38 @@ size_t lds_budget() {
     return b;
 }
 
-size_t row_bytes(int np1) { return (size_t)np1 * 4 + 64; }
-
-int default_tile_rows(int np1) {
-    long t = (long)(lds_budget() / row_bytes(np1)) - 2;
-    return (int)std::max(1L, std::min(64L, t));
+// LDS of an inter-route workgroup with sub-blocks of h rows: the h rows and
+// one halo row on each side, 16- or 32-bit.
+size_t ring_lds(int np1, int h, bool w16) {
+    return (size_t)(h + 2) * (w16 ? 2 * (size_t)stride16_of(np1) : 4 * (size_t)np1);
 }
 
-size_t item_lds(int np1, int tile_rows) { return (size_t)(tile_rows + 2) * row_bytes(np1); }
+// Largest sub-block (at most 64 rows) that fits the LDS budget of one
+// workgroup; at least 1.
+int default_tile_rows(int np1, bool w16) {
+    int h = 1;
+    while (h < 64 && ring_lds(np1, h + 1, w16) <= lds_budget()) ++h;
+    return h;
+}
+
+// Rows per inter-route item of the single-solution form: thin enough that a
+// solution gives about 512 items (two per compute unit), at most what fits
+// the LDS budget.
+int plain_rows(int Q, int np1, bool w16) {
+    return std::max(1, std::min(default_tile_rows(np1, w16), (Q + 511) / 512));
+}
 
 // Inter-route items of one solution: row blocks of `rows` rows, each against
-// the column segments to its right.
+// every column slot to its right.
 template <class F>
 void for_each_item(int Q, int rows, F f) {
     for (int s0 = 0; s0 < Q; s0 += rows)
-        for (int c0 = s0 + 1; c0 < Q; c0 += kSegCols) f(s0, std::min(Q, s0 + rows), c0);
+        f(s0, std::min(Q, s0 + rows));
 }
 
 long long count_items(int Q, int rows) {
     long long c = 0;
-    for_each_item(Q, rows, [&](int, int, int) { ++c; });
+    for_each_item(Q, rows, [&](int, int) { ++c; });
     return c;
 }
 
@@ -149,7 +162,8 @@ SolLayout sol_layout(int n, int R) {
     L.rec = take(32);
     L.state = take(4 * 16);
     L.acc = take(8 * kAccCount);
-    L.max_items = (int)count_items((int)Q, default_tile_rows(n + 1));
+    // the 16-bit matrix only ever allows more rows per item, so size for int32
+    L.max_items = (int)count_items((int)Q, plain_rows((int)Q, n + 1, false));
     L.items = take(sizeof(InterItem) * L.max_items);
     L.intra = take(sizeof(IntraItem) * std::max(R, 1));  // at most one group per route
     L.total = off;
@@ -161,6 +175,8 @@ SolLayout sol_layout(int n, int R) {
 struct tga_instance {
     int32_t n, cap, has_tw;
     const int32_t *D;
+    const uint16_t *D16;  // in the instance workspace; null when some distance >= 2^16
+    int32_t stride16;
     const int4 *node4;
     int32_t maxD, maxE, maxL, maxS, maxDem;
 };
@@ -174,7 +190,8 @@ struct tga_solution {
     int nitems;
     IntraItem *intra;  // device
     int nintra;
-    int tile_rows;
+    int tile_rows;   // rows one workgroup's LDS budget holds (batched form)
+    int plain_rows;  // rows per item of the single-solution form
     size_t lds;
     uint32_t version;
     int in_batch;
@@ -190,7 +207,9 @@ struct tga_batch {
     int *queue;  // [0] inter queue head, [1] intra queue head, [2] finished workgroups
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
     size_t lds;
+    size_t lds_intra;
     int grid_inter, grid_intra;
+    int split;  // 1: the inter and intra phases as two launches; 0: one launch
     int chunk;  // 0: static schedule; > 0: dynamic, items per atomic
     hipGraphExec_t exec;
     hipGraph_t graph;
@@ -212,9 +231,12 @@ extern "C" int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes)
     return TGA_OK;
 }
 
+// Instance workspace: 256 bytes of check results, then room for the 16-bit
+// copy of D.
 extern "C" size_t tga_instance_workspace_bytes(int32_t n) {
     if (n < 1 || n > TGA_MAX_Q) return 0;
-    return 256;
+    const size_t np1 = (size_t)n + 1;
+    return 256 + 2 * np1 * (size_t)stride16_of((int)np1);
 }
 
 extern "C" size_t tga_solution_workspace_bytes(int32_t n, int32_t R) {
@@ -260,11 +282,21 @@ extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *
     if ((int64_t)n * maxDem >= (1 << 30)) return fail(TGA_ERANGE, "total demand may exceed 2^30");
     if (has_tw && (int64_t)np1 * (maxS + maxD) + maxL + maxE >= (1 << 28))
         return fail(TGA_ERANGE, "route durations may exceed 2^28");
+    const int stride16 = stride16_of(np1);
+    uint16_t *d16 = nullptr;
+    if (maxD < 65536) {  // every distance fits 16 bits: keep a packed copy for the inter-route kernels
+        d16 = (uint16_t *)((char *)ws + 256);
+        k_pack16<<<dim3((stride16 + 255) / 256, np1), 256, 0, st>>>(dist, np1, stride16, d16);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    }
     tga_instance *I = new tga_instance;
     I->n = n;
     I->cap = capacity;
     I->has_tw = has_tw;
     I->D = dist;
+    I->D16 = d16;
+    I->stride16 = stride16;
     I->node4 = (const int4 *)node4;
     I->maxD = (int32_t)maxD;
     I->maxE = (int32_t)maxE;
@@ -273,6 +305,11 @@ extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *
     I->maxDem = (int32_t)maxDem;
     *out = I;
     return TGA_OK;
+}
+
+extern "C" int32_t tga_instance_dist_bytes(tga_instance_t inst) {
+    if (!inst) return 0;
+    return inst->D16 ? 2 : 4;
 }
 
 extern "C" int tga_free_instance(tga_instance_t inst) {
@@ -295,8 +332,8 @@ static void push_intra_groups(int n, int R, int sol_index, std::vector<IntraItem
 
 static void build_plain_items(tga_solution *S, std::vector<InterItem> &items,
                               std::vector<IntraItem> &intra, int sol_index) {
-    for_each_item(S->Q, S->tile_rows,
-                  [&](int s0, int s1, int c0) { items.push_back(InterItem{sol_index, s0, s1, c0}); });
+    for_each_item(S->Q, S->plain_rows,
+                  [&](int s0, int s1) { items.push_back(InterItem{sol_index, s0, s1, 0}); });
     push_intra_groups(S->n, S->R, sol_index, intra);
 }
 
@@ -326,17 +363,21 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     S->n = n;
     S->R = R;
     S->Q = Q;
-    S->tile_rows = default_tile_rows(np1);
-    S->lds = item_lds(np1, S->tile_rows);
+    const bool w16 = inst->D16 != nullptr;
+    S->tile_rows = default_tile_rows(np1, w16);
+    S->plain_rows = plain_rows(Q, np1, w16);
+    S->lds = ring_lds(np1, S->plain_rows, w16);
     if (S->lds > (size_t)P.max_lds) {
         delete S;
         return fail(TGA_ERANGE, "n = %d needs %zu bytes of LDS per workgroup (device: %d)", n,
-                    item_lds(np1, 1), P.max_lds);
+                    ring_lds(np1, 1, w16), P.max_lds);
     }
     char *base = (char *)ws;
     SolDev &h = S->h;
     memset(&h, 0, sizeof h);
     h.D = inst->D;
+    h.D16 = inst->D16;
+    h.stride16 = inst->stride16;
     h.node4 = inst->node4;
     h.n = n;
     h.np1 = np1;
@@ -344,7 +385,7 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     h.has_tw = inst->has_tw;
     h.R = R;
     h.Q = Q;
-    h.tile_rows = S->tile_rows;
+    h.tile_rows = S->plain_rows;
     h.a4 = (int4 *)(base + L.a4);
     h.b4 = (int4 *)(base + L.b4);
     h.t4 = (int4 *)(base + L.t4);
@@ -694,6 +735,25 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     return off;
 }
 
+// Inter and intra phases of a batched step in one launch (default: the
+// intra-route groups fill the tail of the inter-route phase), or as two
+// launches with TGA_SPLIT=1 (tuning).
+static int batch_split() {
+    const char *e = getenv("TGA_SPLIT");
+    return (e && *e) ? (atoi(e) != 0) : 0;
+}
+
+// Workgroups of kInterThreads threads one compute unit holds at once for
+// kernel f with `lds` bytes of dynamic LDS (at least 1).
+static int resident_blocks(const void *f, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kInterThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return std::max(1, nb);
+}
+
 static int batch_max_items(const std::vector<tga_solution *> &sols, int rows_per_item) {
     long long m = 0;
     for (auto *s : sols) m += count_items(s->Q, rows_per_item > 0 ? rows_per_item : 1);
@@ -738,26 +798,34 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     std::vector<IntraItem> intra;
     std::vector<SolDev> descs(count);
     size_t lds = 0;
+    std::vector<int> trs(count);
     for (int i = 0; i < count; ++i) {
         tga_solution *s = v[i];
         descs[i] = s->h;
-        // LDS sub-block rows (bounded by the LDS budget of one workgroup) and
-        // rows per work item (a multiple of it, so column attributes loaded
-        // once per item serve about 32 rows)
+        // LDS sub-block rows (bounded by the LDS budget of one workgroup)
+        const bool w16 = s->h.D16 != nullptr;
         const int tr = sub_rows > 0 ? std::min(sub_rows, s->tile_rows) : s->tile_rows;
-        const int ri = rows_per_item > 0 ? rows_per_item : tr * std::max(1, 32 / tr);
+        trs[i] = tr;
         descs[i].tile_rows = tr;
-        lds = std::max(lds, item_lds(s->h.np1, tr));
-        for_each_item(s->Q, ri, [&](int s0, int s1, int c0) { items.push_back(InterItem{i, s0, s1, c0}); });
+        lds = std::max(lds, ring_lds(s->h.np1, tr, w16));
         push_intra_groups(s->n, s->R, i, intra);
     }
-    lds = std::max(lds, (size_t)kInterWaves * kIntraRegionBytes);  // the intra phase's regions
+    const int split = batch_split();
+    const size_t lds_intra = (size_t)kInterWaves * kIntraRegionBytes;  // the intra phase's regions
+    if (!split) lds = std::max(lds, lds_intra);
     if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);
-    // largest first (pairs of the item), ties in solution / row order so that
-    // the column segments of one row block run close together in time
+    // one resident wave of workgroups: as many as LDS and registers allow
+    const int grid_inter =
+        P.cus * resident_blocks(split ? (const void *)k_eval_batch<1> : (const void *)k_eval_batch<3>, lds);
+    // Inter-route items: strips of rows of one solution (one LDS sub-block
+    // each by default), largest first (rows times the columns to their
+    // right), ties in solution / row order
+    for (int i = 0; i < count; ++i)
+        for_each_item(v[i]->Q, rows_per_item > 0 ? rows_per_item : trs[i],
+                      [&](int s0, int s1) { items.push_back(InterItem{i, s0, s1, 0}); });
     auto work = [&](const InterItem &a) {
-        const long long cols = std::min<long long>(kSegCols, v[a.sol]->Q - a.c0);
-        return (long long)(a.s1 - a.s0) * cols;
+        const long long Q = v[a.sol]->Q, r = a.s1 - a.s0;
+        return r * (2 * Q - a.s0 - a.s1 + 1);
     };
     std::stable_sort(items.begin(), items.end(),
                      [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
@@ -774,10 +842,10 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->queue = (int *)(base + oqueue);
     B->done = B->queue + 16;
     B->lds = lds;
-    // one resident wave of workgroups: as many as LDS and registers allow
-    const int per_cu = std::max(1, std::min(2, (int)(P.max_lds / std::max<size_t>(lds, 1))));
-    B->grid_inter = std::max(1, P.cus * per_cu);
-    B->grid_intra = B->grid_inter;
+    B->lds_intra = lds_intra;
+    B->split = split;
+    B->grid_inter = grid_inter;
+    B->grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
     B->chunk = schedule_chunk();
     B->exec = nullptr;
     B->graph = nullptr;
@@ -804,9 +872,18 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
 }
 
 static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
-    if (op_mask & TGA_OP_ALL)
-        k_eval_mixed<<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
-                                                                   B->nintra, op_mask, B->queue, B->chunk);
+    if (!(op_mask & TGA_OP_ALL)) return;
+    if (!B->split) {
+        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
+                                                                     B->nintra, op_mask, B->queue, B->chunk);
+        return;
+    }
+    if (op_mask & 7)
+        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
+                                                                     B->nintra, op_mask, B->queue, B->chunk);
+    if (op_mask & (2 | 8 | 16))
+        k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
+            B->d, B->items, B->nitems, B->intra, B->nintra, op_mask, B->queue, B->chunk);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {

@@ -26,8 +26,6 @@ namespace tga {
 constexpr int kInterWaves = 8;      // wavefronts per inter-route workgroup
 constexpr int kInterThreads = kInterWaves * 64;
 constexpr int kColsPerWave = 62;    // lanes 1..62 own a column; 0 and 63 are halo
-constexpr int kChunks = 2;          // column chunks per wavefront
-constexpr int kSegCols = kInterWaves * kChunks * kColsPerWave;  // columns per work item
 constexpr int kIntraThreads = 256;
 constexpr int kApplyThreads = 1024;
 constexpr int kTwOff = 1 << 28;     // due time standing for "no window" (CVRP)
@@ -49,6 +47,15 @@ __device__ __forceinline__ int2 gld(const int2 *p) {
     typedef int v2i __attribute__((ext_vector_type(2)));
     const v2i v = *(const __attribute__((address_space(1))) v2i *)p;
     return make_int2(v.x, v.y);
+}
+
+// Load of a value every lane of the wavefront reads at the same address,
+// through the constant address space so that it becomes a scalar load into
+// SGPRs.  Only for data no kernel of the same launch writes.
+__device__ __forceinline__ int4 sld(const int4 *p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = *(const __attribute__((address_space(4))) v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
 }
 
 template <class T>
@@ -491,20 +498,20 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
 }
 
 // ------------------------------------------------------ inter-route eval ---
-// One work item = rows [s0, s1) (slots, route-major) against the column slots
-// [c0, c0 + kSegCols).  For each unordered pair of slots (s, t) in different
-// routes, route(s) < route(t), the fused pass evaluates RELOCATE s->after t,
-// RELOCATE t->after s, SWAP s<->t and 2OPT*(s, t) (the node-based extraction
-// of Section 5.3.1, eq. node_based1 and eq. node_based2, over the positional
-// attributes).
+// One work item = rows [s0, s1) (slots, route-major) against every column
+// slot of a later route.  For each unordered pair of slots (s, t) in
+// different routes, route(s) < route(t), the fused pass evaluates
+// RELOCATE s->after t, RELOCATE t->after s, SWAP s<->t and 2OPT*(s, t) (the
+// node-based extraction of Section 5.3.1, eq. node_based1 and
+// eq. node_based2, over the positional attributes).
 //
-// Each wavefront owns kChunks column chunks for the whole item and keeps their
-// attributes in registers.  Rows stream through LDS in sub-blocks of
-// S.tile_rows rows plus one halo row on each side, copied straight from HBM
-// into LDS (global_load_lds).  A lane gathers D[row][node(t)] from LDS once
-// per row and takes D[row][succ(t)] and D[row][pred(t)] from its neighbour
-// lanes (DPP wavefront shifts), D[pred(s)][t] and D[succ(s)][t] from the
-// previous and next row of a register window.
+// Rows stream through LDS in sub-blocks of S.tile_rows rows plus one halo row
+// on each side, copied straight from HBM into LDS (global_load_lds).  A lane
+// owns one column of a 62-column chunk and keeps its attributes in
+// registers; per row it gathers D[row][node(t)] from LDS once and takes
+// D[row][succ(t)] and D[row][pred(t)] from its neighbour lanes (DPP
+// wavefront shifts), D[pred(s)][t] and D[succ(s)][t] from the previous and
+// next row of a register window.
 
 typedef __attribute__((address_space(3))) void *lds_void_ptr;
 typedef __attribute__((address_space(1))) void *global_void_ptr;
@@ -514,10 +521,11 @@ __device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_u
 // lane i receives lane i-1 (lane 0 receives 0)
 __device__ __forceinline__ int from_prev_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
 
-// Column-side (lane) values of one chunk, kept in registers for a whole item.
-// Every feasibility condition below is written as a difference that must be
-// >= 0; "bad" values are 0 when a condition holds and negative otherwise, so
-// OR-ing them keeps the sign of "any condition fails".
+// Column-side (lane) values of one chunk, kept in registers while the
+// wavefront walks rows against it.  Every feasibility condition below is
+// written as a difference that must be >= 0; "bad" values are 0 when a
+// condition holds and negative otherwise, so OR-ing them keeps the sign of
+// "any condition fails".
 struct LaneCol {
     int4 ta, tb, tt, tw;
     int node;      // LDS gather index (node of slot t)
@@ -528,36 +536,99 @@ struct LaneCol {
     int tRemTw;    // t's route is late without it: negative
     int negTz, negTw;  // -edge(t), -(incident edges of t)
     int zx, zy;        // route load - demand, route load - prefix load of t
+    // delta terms of the four moves with kPenalty added for a disabled
+    // operator, for the delta-only pass
+    int cRel, cRel2, cSwap, c2s;
 };
 
-// Stage rows [first, first + cnt) of S (clamped to the slot range) into LDS:
-// their attributes, then their D rows.  Caller synchronises afterwards.
+// Raw column attributes of the chunk whose first owned column is slot cb
+// (lanes 1..kColsPerWave own cb..cb+61; lanes 0 and 63 hold the
+// neighbours), fetched ahead of their use.
+struct ColRaw {
+    int4 ta, tb, tt, tw;
+};
+
 template <bool TW>
-__device__ __forceinline__ void stage_rows(const SolDev &S, int first, int cnt, int4 *rowa, int4 *rowb,
-                                           int4 *rowt, int4 *roww, int *rows) {
-    const int Q = S.Q, np1 = S.np1;
-    for (int k = threadIdx.x; k < cnt; k += kInterThreads) {
-        const int s = min(max(first + k, 0), Q);
-        rowa[k] = gld(S.a4 + s);
-        rowb[k] = gld(S.b4 + s);
-        if (TW) {
-            rowt[k] = gld(S.t4 + s);
-            roww[k] = gld(S.w4 + s);
-        }
+__device__ __forceinline__ ColRaw col_fetch(const SolDev &S, int cb) {
+    const int lane = threadIdx.x & 63;
+    const int tc = min(max(cb - 1 + lane, 0), S.Q);
+    ColRaw c;
+    c.ta = gld(S.a4 + tc);
+    c.tb = gld(S.b4 + tc);
+    if (TW) {
+        c.tt = gld(S.t4 + tc);
+        c.tw = gld(S.w4 + tc);
+    } else {
+        c.tt = make_int4(0, 0, 0, 0);
+        c.tw = make_int4(0, 0, 0, 0);
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = wave; k < cnt; k += kInterWaves) {
-        const int s = min(max(first + k, 0), Q);
-        const int node = nodeof(gld(S.a4 + s).x);
-        const int *src = S.D + (size_t)node * np1;
-        int *dst = rows + k * np1;
-        for (int c = 0; c < np1; c += 64) {
-            if (c + lane < np1)
+    return c;
+}
+
+// Lane values of the chunk at cb from its raw attributes.  routeLast: route
+// of the last owned column (-1 if none), wave-uniform.
+__device__ __forceinline__ void col_setup(const SolDev &S, int cb, const ColRaw &c, uint32_t op_mask, LaneCol &L,
+                                          int &routeLast) {
+    const int lane = threadIdx.x & 63;
+    const int Q = S.Q, n = S.n;
+    const int t = cb - 1 + lane;
+    L.ta = c.ta;
+    L.tb = c.tb;
+    L.tt = c.tt;
+    L.tw = c.tw;
+    L.node = nodeof(L.ta.x);
+    const int fl = flagsof(L.ta.x);
+    const bool cust = fl & kFlagCustomer;
+    const bool own = lane >= 1 && lane <= kColsPerWave && t < Q;
+    L.refT = cust ? L.node - 1 : n + L.ta.y;
+    L.tyOwn = own ? L.ta.y - 1 : -(1 << 30);
+    L.tInval = cust ? 0 : (int)0x80000000;
+    L.tRemCap = (fl & kFlagRemCap) ? 0 : (int)0x80000000;
+    L.tRemTw = (fl & kFlagRemTw) ? 0 : (int)0x80000000;
+    L.negTz = -L.ta.z;
+    L.negTw = -L.tb.w;
+    L.zx = L.tb.z - L.tb.x;
+    L.zy = L.tb.z - L.tb.y;
+    const int offRel = (op_mask & 1) ? 0 : (1 << 30);
+    const int offSwap = (op_mask & 2) ? 0 : (1 << 30);
+    const int off2s = (op_mask & 4) ? 0 : (1 << 30);
+    L.cRel = L.negTz + offRel;
+    L.cRel2 = L.ta.w + offRel;
+    L.cSwap = L.negTw + offSwap;
+    L.c2s = L.negTz + off2s;
+    const int lastLane = min(kColsPerWave, Q - cb);
+    const int rl = __shfl(L.ta.y, max(lastLane, 0));
+    routeLast = __builtin_amdgcn_readfirstlane(lastLane >= 1 ? rl : -1);
+}
+
+// ---- LDS ring of distance rows of an inter-route item.  Slot x of the item
+// starting at row s0 (x >= s0 - 1) sits at ring position (x - s0 + 1) mod NB;
+// slots outside [0, Q] are read clamped.
+
+__device__ __forceinline__ int ring_pos(int x, int s0, int N) { return (x - s0 + 1) % N; }
+
+// Distance rows of slots [x0, x0 + cnt) copied straight from HBM into the
+// ring (global_load_lds, one dword per lane), from the 16-bit copy of D when
+// W16.  The issuing wavefront must wait (vmcnt) before a barrier publishes
+// them.  `wave` is the wavefront index (uniform).
+template <bool W16>
+__device__ __forceinline__ void drow_issue(const SolDev &S, void *ring, int NB, int s0, int x0, int cnt, int wave) {
+    const int lane = threadIdx.x & 63;
+    const int words = W16 ? S.stride16 / 2 : S.np1;  // dwords per row
+    for (int r = wave; r < cnt; r += kInterWaves) {
+        const int x = x0 + r;
+        const int node = nodeof(sld(S.a4 + min(max(x, 0), S.Q)).x);
+        const int *src = W16 ? (const int *)(S.D16 + (size_t)node * S.stride16) : S.D + (size_t)node * S.np1;
+        int *dst = (int *)ring + ring_pos(x, s0, NB) * words;
+        for (int c = 0; c < words; c += 64) {
+            if (c + lane < words)
                 __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);
 }
+
+template <bool W16> struct DistElem { typedef int type; };
+template <> struct DistElem<true> { typedef uint16_t type; };
 
 constexpr int kSign = (int)0x80000000;
 constexpr int kPenalty = 1 << 30;     // added to the delta of an inadmissible move
@@ -691,100 +762,172 @@ __device__ __forceinline__ void pair_moves(const LaneCol &L, const RowVals &R, c
     }
 }
 
-// Whole-workgroup evaluation of one inter-route item.  smem4 is the dynamic
-// LDS area; red holds kInterWaves keys.
-template <bool TW, bool DUMP>
+// Delta of the best admissible move committed so far for S (kAdmissibleBound
+// if none): every workgroup working on S may skip moves that cannot beat it.
+__device__ __forceinline__ int committed_delta(const SolDev &S) {
+    const unsigned long long k = __hip_atomic_load(S.best_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return k == ~0ull ? kAdmissibleBound : (int)((uint32_t)(k >> 32) ^ 0x80000000u);
+}
+
+// The (column chunk, row) pairs of the sub-block of nr rows starting at slot
+// sb, chunk-major, with chunks of kColsPerWave columns from slot sb + 1:
+// [lo, hi) is the equal share of wavefront `wave`.
+__device__ __forceinline__ void wave_share(int Q, int sb, int nr, int wave, int &lo, int &hi) {
+    const int k = (Q - sb - 1 + kColsPerWave - 1) / kColsPerWave;
+    const long long T = (long long)k * nr;
+    lo = (int)(T * wave / kInterWaves);
+    hi = (int)(T * (wave + 1) / kInterWaves);
+}
+
+// Whole-workgroup evaluation of one inter-route item: the row slots
+// [s0, s1) against every column slot after the row.  The distance rows
+// (16-bit when W16) are staged in LDS in sub-blocks of h = S.tile_rows rows
+// plus a halo row on each side (one sub-block per item by default); row
+// attributes are wave-uniform and come through the scalar cache, one row
+// ahead of their use.  The (column chunk, row) pairs of a
+// sub-block are split into kInterWaves equal contiguous runs, chunk-major, so
+// every wavefront gets the same work whatever the shape of the triangle; the
+// column attributes of a wavefront's next run are fetched while the current
+// one is evaluated.
+//
+// Each pair first gets the deltas of its four moves only; the feasibility
+// conditions and move ids are evaluated only where some delta is <= the
+// lane's threshold: the smaller of its own best admissible delta and the
+// best any wavefront of the workgroup has published in LDS (thr_sh, read at
+// the start of a run, published at its end) or the solution has committed.
+// Every threshold is the delta of an admissible move of this neighbourhood,
+// so no move that could be the minimum (or tie with it) is ever skipped.
+// With dump arrays every move is evaluated.  smem4 is the dynamic LDS area;
+// red holds kInterWaves keys.
+template <bool TW, bool DUMP, bool W16>
 __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_mask,
                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
-                           int4 *smem4, unsigned long long *red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                           int4 *smem4, unsigned long long *red, int *thr_sh) {
+    typedef typename DistElem<W16>::type DT;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const bool opRel = op_mask & 1, opSwap = op_mask & 2, op2s = op_mask & 4;
-    const int Q = S.Q, np1 = S.np1, n = S.n, cap = S.cap, tr = S.tile_rows;
+    const int Q = S.Q, np1 = S.np1, n = S.n, cap = S.cap, h = S.tile_rows;
     const uint32_t uQ = (uint32_t)Q;
-    const int cend = min(Q, item.c0 + kSegCols);
-
-    // column chunks of this wavefront: attributes stay in registers
-    LaneCol col[kChunks];
-    int routeLast[kChunks];
-    int routeMax = -1;
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-        const int cb = item.c0 + (c * kInterWaves + wave) * kColsPerWave;
-        const int t = cb - 1 + lane;
-        const int tc = min(max(t, 0), Q);
-        LaneCol &L = col[c];
-        L.ta = gld(S.a4 + tc);
-        L.tb = gld(S.b4 + tc);
-        if (TW) {
-            L.tt = gld(S.t4 + tc);
-            L.tw = gld(S.w4 + tc);
-        } else {
-            L.tt = make_int4(0, 0, 0, 0);
-            L.tw = make_int4(0, 0, 0, 0);
-        }
-        L.node = nodeof(L.ta.x);
-        const int fl = flagsof(L.ta.x);
-        const bool cust = fl & kFlagCustomer;
-        const bool own = lane >= 1 && lane <= kColsPerWave && t < cend;
-        L.refT = cust ? L.node - 1 : n + L.ta.y;
-        L.tyOwn = own ? L.ta.y - 1 : -(1 << 30);
-        L.tInval = cust ? 0 : kSign;
-        L.tRemCap = (fl & kFlagRemCap) ? 0 : kSign;
-        L.tRemTw = (fl & kFlagRemTw) ? 0 : kSign;
-        L.negTz = -L.ta.z;
-        L.negTw = -L.tb.w;
-        L.zx = L.tb.z - L.tb.x;
-        L.zy = L.tb.z - L.tb.y;
-        // route of the last owned column (-1: chunk empty); the same for every
-        // lane of the wavefront, so keep it scalar
-        const int lastLane = min(kColsPerWave, cend - cb);
-        const int rl = __shfl(L.ta.y, max(lastLane, 0));
-        routeLast[c] = __builtin_amdgcn_readfirstlane(lastLane >= 1 ? rl : -1);
-        routeMax = max(routeMax, routeLast[c]);
-    }
+    const int s0 = item.s0, s1 = item.s1;
+    const int nsb = (s1 - s0 + h - 1) / h;
+    const int NB = h + 2;
+    const int rs = W16 ? S.stride16 : np1;  // ring row stride (elements)
+    DT *ring = (DT *)smem4;
+    const DT *ringEnd = ring + NB * rs;
 
     int bd = kAdmissibleBound;
     uint32_t bid = 0xFFFFFFFFu;
-    int4 *rowa = smem4;
-    int4 *rowb = rowa + (tr + 2);
-    int4 *rowt = rowb + (tr + 2);
-    int4 *roww = rowt + (tr + 2);
-    int *rows = (int *)(roww + (tr + 2));
 
-    for (int sb = item.s0; sb < item.s1; sb += tr) {
-        const int nr = min(tr, item.s1 - sb);  // rows of this sub-block
-        __syncthreads();                       // previous sub-block fully consumed
-        stage_rows<TW>(S, sb - 1, nr + 2, rowa, rowb, rowt, roww, rows);
-        __syncthreads();
-        if (routeMax <= rowa[1].y) continue;  // nothing to the right of this sub-block
-        int gp[kChunks], g[kChunks];
-#pragma unroll
-        for (int c = 0; c < kChunks; ++c) {
-            gp[c] = rows[col[c].node];
-            g[c] = rows[np1 + col[c].node];
+    // prologue: the distance rows of sub-block 0 (with its halo rows)
+    __syncthreads();  // the previous item is done with LDS
+    if (!DUMP && threadIdx.x == 0) *thr_sh = committed_delta(S);
+    drow_issue<W16>(S, ring, NB, s0, s0 - 1, min(h, s1 - s0) + 2, wave);
+    __builtin_amdgcn_s_waitcnt(0);
+
+    ColRaw nxt;  // column attributes fetched ahead for the chunk at nxt_cb
+    int nxt_cb = -1;
+    for (int i = 0; i < nsb; ++i) {
+        const int sb = s0 + i * h;
+        const int nr = min(h, s1 - sb);  // rows of this sub-block
+        __syncthreads();                 // rows of sub-block i resident (i = 0), or i - 1 consumed
+        if (i > 0) {                     // rows sb - 1 and sb are already there
+            drow_issue<W16>(S, ring, NB, s0, sb + 1, nr, wave);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
         }
-        for (int k = 1; k <= nr; ++k) {
-            const int4 ra = rowa[k];
-            if (routeMax <= ra.y) break;
-            const int4 rb = rowb[k];
-            int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
-            if (TW) {
-                rt = rowt[k];
-                rw = roww[k];
-            }
-            const RowVals R = row_vals(ra, rb, cap, n);
-            const int *rowNext = rows + (k + 1) * np1;
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int gn = rowNext[col[c].node];
-                if (routeLast[c] > ra.y) {
-                    const int gR = from_next_lane(g[c]);  // D[s][succ(t)]
-                    const int gL = from_prev_lane(g[c]);  // D[s][pred(t)]
-                    pair_moves<TW, DUMP>(col[c], R, rt, rw, gp[c], g[c], gn, gR, gL, uQ, opRel, opSwap, op2s,
-                                         dump_delta, dump_feas, bd, bid);
+        // columns: every slot after the sub-block's first row (pairs in the
+        // same route are skipped per pair)
+        if (sb + 1 < Q) {
+            int idx, hi;
+            wave_share(Q, sb, nr, wave, idx, hi);
+            while (idx < hi) {
+                const int j = idx / nr, r0 = idx - j * nr;
+                const int r1 = min(nr, r0 + (hi - idx));
+                idx += r1 - r0;
+                const int cb = sb + 1 + j * kColsPerWave;
+                const ColRaw cur = nxt_cb == cb ? nxt : col_fetch<TW>(S, cb);
+                // fetch the chunk of this wavefront's next run (here or in a
+                // later sub-block) while this one is evaluated
+                int cb2 = -1;
+                if (idx < hi) {
+                    cb2 = sb + 1 + (idx / nr) * kColsPerWave;
+                } else {
+                    for (int i2 = i + 1; i2 < nsb && cb2 < 0; ++i2) {
+                        const int sb2 = s0 + i2 * h, nr2 = min(h, s1 - sb2);
+                        int lo2, hi2;
+                        if (sb2 + 1 >= Q) break;
+                        wave_share(Q, sb2, nr2, wave, lo2, hi2);
+                        if (lo2 < hi2) cb2 = sb2 + 1 + (lo2 / nr2) * kColsPerWave;
+                    }
                 }
-                gp[c] = g[c];
-                g[c] = gn;
+                if (cb2 >= 0 && cb2 != cb) nxt = col_fetch<TW>(S, cb2);
+                else if (cb2 == cb) nxt = cur;
+                nxt_cb = cb2;
+                LaneCol L;
+                int routeLast;
+                col_setup(S, cb, cur, op_mask, L, routeLast);
+                int x = sb + r0;  // row slot
+                const int xend = sb + r1;
+                // register window over the distance ring: rows x - 1, x, x + 1
+                const DT *pp = ring + ring_pos(x - 1, s0, NB) * rs;
+                int gp = pp[L.node];
+                pp += rs;
+                if (pp == ringEnd) pp = ring;
+                int g = pp[L.node];
+                pp += rs;
+                if (pp == ringEnd) pp = ring;
+                int gn = pp[L.node];
+                int4 ra = sld(S.a4 + x), rb = sld(S.b4 + x);
+                const int thrRun = DUMP ? 0 : __hip_atomic_load(thr_sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // Each pass first consumes what the previous one fetched, then
+                // fetches row x + 1 (attributes) and the gather of row x + 2,
+                // then evaluates row x from registers (the rare full
+                // evaluation also reads the row's time attributes).
+                while (routeLast > ra.y) {
+                    pp += rs;
+                    if (pp == ringEnd) pp = ring;
+                    const int gnn = pp[L.node];  // row x + 2 (past the halo on the last row: unused)
+                    const int xn = min(x + 1, Q);
+                    const int4 ran = sld(S.a4 + xn), rbn = sld(S.b4 + xn);
+                    const int gR = from_next_lane(g);  // D[s][succ(t)]
+                    const int gL = from_prev_lane(g);  // D[s][pred(t)]
+                    bool full = true;
+                    int thr = 0;
+                    if (!DUMP) {
+                        thr = min(bd, thrRun);
+                        const int d1 = g + gR + (L.cRel + ra.w);
+                        const int d2 = g + gn + (L.cRel2 - ra.z);
+                        const int d3 = (gp + gn) + (gL + gR) + (L.cSwap - rb.w);
+                        const int d4 = gR + gn + (L.c2s - ra.z);
+                        const int m = min(min(d1, d2), min(d3, d4));
+                        full = m <= thr && L.tyOwn >= ra.y;
+                    }
+                    if (full) {
+                        int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
+                        if (TW) {
+                            rt = sld(S.t4 + x);
+                            rw = sld(S.w4 + x);
+                        }
+                        const RowVals R = row_vals(ra, rb, cap, n);
+                        pair_moves<TW, DUMP>(L, R, rt, rw, gp, g, gn, gR, gL, uQ, opRel, opSwap, op2s, dump_delta,
+                                             dump_feas, bd, bid);
+                    }
+                    if (++x >= xend) break;
+                    ra = ran;
+                    rb = rbn;
+                    gp = g;
+                    g = gn;
+                    gn = gnn;
+                }
+                // publish this wavefront's best to the workgroup (one lane, one
+                // LDS atomic, only when some lane improved on the shared value)
+                if (!DUMP && __builtin_amdgcn_ballot_w64(bd < thrRun)) {
+                    int wmin = bd;
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) wmin = min(wmin, __shfl_xor(wmin, off));
+                    if (lane == 0) atomicMin(thr_sh, wmin);
+                }
             }
         }
     }
@@ -799,11 +942,15 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
                                                               uint8_t *__restrict__ dump_feas) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
+    __shared__ int thr_sh;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const InterItem item = items[it];
         const SolDev &S = sols[item.sol];
         if (S.state[kStDone]) continue;
-        inter_item<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, smem4, red);
+        if (S.D16)
+            inter_item<TW, DUMP, true>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
+        else
+            inter_item<TW, DUMP, false>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
     }
 }
 
@@ -1141,24 +1288,31 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
-// Batched form: one persistent launch evaluates every solution of the batch.
-// Phase 1: inter-route items (whole workgroup per item, largest first);
-// phase 2: single routes (one wavefront per route).  Solutions of both
-// problem types share the launch; each item takes the window-aware or the
-// capacity-only path of its own solution.
-// chunk == 0: static schedule, workgroup b takes items b, b + G, b + 2G, ...
-// (round-robin over the largest-first list).  chunk > 0: dynamic schedule,
-// workgroups take `chunk` consecutive items per atomic on queue[0] / queue[1];
-// the last workgroup to finish resets the queue heads, so consecutive
-// launches (also inside a captured graph) need no reset in between.
-__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_mixed(
+// Batched form: persistent launches evaluate every solution of the batch.
+// PH bit 0: inter-route items (whole workgroup per item, largest first);
+// PH bit 1: intra-route groups (one wavefront per group of routes).  PH = 3
+// runs both phases in one launch; PH = 1 and PH = 2 are the two halves as
+// separate launches, each compiled alone so that it gets its own register
+// budget and occupancy.  Solutions of both problem types share a launch;
+// each item takes the window-aware or the capacity-only path of its own
+// solution.
+// chunk == 0: static schedule, workgroup (or wavefront) b takes items b,
+// b + G, b + 2G, ... (round-robin over the largest-first list).  chunk > 0:
+// dynamic schedule, workgroups take `chunk` consecutive items per atomic on
+// queue[0] (inter) / queue[1] (intra); the last workgroup to finish (counted
+// in queue[2], or queue[3] for PH = 2) resets the heads it used, so
+// consecutive launches (also inside a captured graph) need no reset in
+// between.
+template <int PH>
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
     const SolDev *__restrict__ sols, const InterItem *__restrict__ items, int nitems,
     const IntraItem *__restrict__ intra, int nintra, uint32_t op_mask, int *__restrict__ queue, int chunk) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int cur;
+    __shared__ int thr_sh;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (op_mask & 7) {
+    if ((PH & 1) && (op_mask & 7)) {
         int base = blockIdx.x, step = gridDim.x, left = 0;
         for (;;) {
             int it;
@@ -1180,13 +1334,20 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
-            if (S.has_tw)
-                inter_item<true, false>(S, item, op_mask, nullptr, nullptr, smem4, red);
-            else
-                inter_item<false, false>(S, item, op_mask, nullptr, nullptr, smem4, red);
+            if (S.has_tw) {
+                if (S.D16)
+                    inter_item<true, false, true>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                else
+                    inter_item<true, false, false>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+            } else {
+                if (S.D16)
+                    inter_item<false, false, true>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                else
+                    inter_item<false, false, false>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+            }
         }
     }
-    if (op_mask & (2 | 8 | 16)) {
+    if ((PH & 2) && (op_mask & (2 | 8 | 16))) {
         int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
         int base = blockIdx.x * kInterWaves + wave, step = gridDim.x * kInterWaves, left = 0;
         for (;;) {
@@ -1215,15 +1376,16 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         }
     }
     if (chunk == 0) return;
-    // every workgroup has taken its last items from both queues before it
-    // counts itself finished; the last one resets the queue for the next launch
+    // every workgroup has taken its last items from its queues before it
+    // counts itself finished; the last one resets them for the next launch
     __syncthreads();
     if (threadIdx.x == 0) {
+        int *fin = &queue[PH == 2 ? 3 : 2];
         __threadfence();
-        if (atomicAdd(&queue[2], 1) == (int)gridDim.x - 1) {
-            atomicExch(&queue[0], 0);
-            atomicExch(&queue[1], 0);
-            atomicExch(&queue[2], 0);
+        if (atomicAdd(fin, 1) == (int)gridDim.x - 1) {
+            if (PH & 1) atomicExch(&queue[0], 0);
+            if (PH & 2) atomicExch(&queue[1], 0);
+            atomicExch(fin, 0);
             __threadfence();
         }
     }
@@ -1442,6 +1604,14 @@ __global__ __launch_bounds__(256) void k_check_dist(const int32_t *__restrict__ 
     }
     if (bad) atomicOr(&out[0], bad);
     atomicMax(&out[1], mx);
+}
+
+// 16-bit copy of D (every value < 2^16), rows padded to `stride` with zeros.
+__global__ __launch_bounds__(256) void k_pack16(const int32_t *__restrict__ D, int np1, int stride,
+                                                uint16_t *__restrict__ out) {
+    const int u = blockIdx.y;
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < stride; v += gridDim.x * 256)
+        out[(size_t)u * stride + v] = v < np1 ? (uint16_t)D[(size_t)u * np1 + v] : (uint16_t)0;
 }
 
 __global__ __launch_bounds__(256) void k_check_nodes(const int4 *__restrict__ nd, int np1, int has_tw,

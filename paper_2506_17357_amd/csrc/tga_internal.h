@@ -25,6 +25,9 @@ constexpr int32_t kFlagRemTw = 4;   // route stays window-feasible without this 
 struct SolDev {
     // instance (borrowed)
     const int32_t *D;     // (n+1)^2 row-major
+    const uint16_t *D16;  // the same values as uint16, rows of stride16 (null when some d >= 2^16)
+    int32_t stride16;
+    int32_t pad16;
     const int4 *node4;    // {demand, e, l, s}
     int32_t n, np1, cap, has_tw;
     int32_t R, Q;
@@ -70,8 +73,12 @@ enum {
 
 // Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the
 // item's column span); only pairs whose column lies in a later route count.
-struct InterItem {
-    int32_t sol, s0, s1, c0;
+// Row stride (elements) of the 16-bit copy of D: a multiple of 8 keeps every
+// row 16-byte aligned.
+constexpr int stride16_of(int np1) { return (np1 + 7) & ~7; }
+
+struct InterItem {  // row slots [s0, s1) of solution `sol`
+    int32_t sol, s0, s1, pad;
 };
 
 // Intra-route work item: routes [r0, r1) of one solution, one wavefront.

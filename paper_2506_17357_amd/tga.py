@@ -50,6 +50,7 @@ EXPORTS = [
     "tga_batch_ls_run", "tga_batch_eval", "tga_batch_reset", "tga_batch_free",
     "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
     "tga_solution_reload", "tga_solution_begin", "tga_batch_poll", "tga_solution_stats",
+    "tga_instance_dist_bytes",
 ]
 
 
@@ -92,6 +93,7 @@ def lib():
         "tga_solution_begin": (i32, [P, i32, P]),
         "tga_batch_poll": (i32, [P, P, P]),
         "tga_solution_stats": (i32, [P, P, P, P, P, P]),
+        "tga_instance_dist_bytes": (i32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -141,6 +143,11 @@ class Instance:
                                    self.has_tw, _dev_ptr(self.ws), nbytes, _stream(stream),
                                    ctypes.byref(h)))
         self.h = h
+
+    @property
+    def dist_bytes(self) -> int:
+        """Bytes per distance the inter-route kernels stream (2 or 4)."""
+        return int(lib().tga_instance_dist_bytes(self.h))
 
     @staticmethod
     def from_workload(inst, device="cuda", stream=None) -> "Instance":

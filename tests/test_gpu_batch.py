@@ -56,6 +56,22 @@ def test_batch_ls_equals_oracle(tga, use_graph):
         assert off.tolist() == ref.offsets.tolist() and cust.tolist() == ref.customers.tolist()
 
 
+def test_batch_mixed_distance_widths(tga):
+    """Solutions whose matrices stream at 16 and at 32 bits share a launch."""
+    pairs = small_mix(6, seed=5)
+    for k in range(3):
+        inst = W.tiny_instance(150 + 40 * k, 930 + k, bool(k % 2), span=100000)
+        pairs.append((inst, W.random_solution(inst, 6 + k, 940 + k)))
+    insts, sols = make_solutions(tga, pairs)
+    assert sorted({I.dist_bytes for I in insts}) == [2, 4]
+    B = tga.Batch(sols)
+    steps, moves, cost = B.ls_run(25)
+    B.close()
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=25)
+        assert (steps[b], moves[b], cost[b]) == (len(ids), mv, oracle.cost(inst, final)[0]), b
+
+
 def test_batch_graph_replay_and_reset(tga):
     """A captured graph replayed twice from fresh solutions gives the same
     result; begin/step_part/collect gives the same result too."""

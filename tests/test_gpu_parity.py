@@ -105,6 +105,29 @@ def test_dump_medium_random(tga, has_tw):
     check_dump(tga, inst, sol, tag="medium")
 
 
+@pytest.mark.parametrize("has_tw", [0, 1])
+def test_dump_wide_distances(tga, has_tw):
+    """Distances above 2^16: the inter-route kernels stream the int32 matrix
+    (the generators' instances all fit the 16-bit copy)."""
+    inst = W.tiny_instance(333, 91 + has_tw, bool(has_tw), span=100000)
+    assert int(inst.dist.max()) >= 1 << 16
+    sol = W.random_solution(inst, 17, 92)
+    S = check_dump(tga, inst, sol, tag="wide")
+    assert S.inst.dist_bytes == 4
+
+
+@pytest.mark.parametrize("dmax,width", [(65535, 2), (65536, 4)])
+def test_distance_width_boundary(tga, dmax, width):
+    """The largest distance decides the streamed width; 65535 must survive
+    the 16-bit copy exactly."""
+    inst = W.tiny_instance(60, 97, True, span=300)
+    inst.dist[0, 7] = inst.dist[7, 0] = dmax
+    inst.dist[3, 9] = inst.dist[9, 3] = dmax - 1
+    sol = W.random_solution(inst, 5, 98)
+    S = check_dump(tga, inst, sol, tag="width%d" % width)
+    assert S.inst.dist_bytes == width
+
+
 def test_dump_c1(tga):
     inst, sol = W.c1()
     check_dump(tga, inst, sol, tag="C1")

@@ -204,13 +204,14 @@ struct tga_batch {
     int nitems;
     IntraItem *intra;
     int nintra;
-    int *queue;  // [0] inter queue head, [1] intra queue head, [2] finished workgroups
+    int *xoff;      // device: inter item list of XCD x = items[xoff[x] .. xoff[x+1])
+    int *ixoff;     // device: the same for intra-route groups
+    int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
     size_t lds;
     size_t lds_intra;
     int grid_inter, grid_intra;
     int split;  // 1: the inter and intra phases as two launches; 0: one launch
-    int chunk;  // 0: static schedule; > 0: dynamic, items per atomic
     hipGraphExec_t exec;
     hipGraph_t graph;
     int graph_steps;
@@ -712,16 +713,8 @@ extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stre
 
 // ---------------------------------------------------------------- batch ----
 
-// Work-item schedule of the batched evaluation: 0 = static round-robin,
-// k > 0 = dynamic, k items per atomic.  TGA_SCHEDULE overrides the default.
-static int schedule_chunk() {
-    const char *e = getenv("TGA_SCHEDULE");
-    if (e && *e) return std::max(0, std::min(64, atoi(e)));
-    return 0;
-}
-
 static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc, size_t *items,
-                           size_t *intra, size_t *queue, int max_items, int nintra) {
+                           size_t *intra, size_t *sched, int max_items, int nintra) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -731,7 +724,7 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     *desc = take(sizeof(SolDev) * sols.size());
     *items = take(sizeof(InterItem) * std::max(max_items, 1));
     *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    *queue = take(64 + 4 * sols.size());
+    *sched = take(4 * 2 * (kMaxXcds + 1) + 4 * sols.size());  // item list offsets, then done flags
     return off;
 }
 
@@ -808,7 +801,6 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         trs[i] = tr;
         descs[i].tile_rows = tr;
         lds = std::max(lds, ring_lds(s->h.np1, tr, w16));
-        push_intra_groups(s->n, s->R, i, intra);
     }
     const int split = batch_split();
     const size_t lds_intra = (size_t)kInterWaves * kIntraRegionBytes;  // the intra phase's regions
@@ -817,20 +809,45 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     // one resident wave of workgroups: as many as LDS and registers allow
     const int grid_inter =
         P.cus * resident_blocks(split ? (const void *)k_eval_batch<1> : (const void *)k_eval_batch<3>, lds);
-    // Inter-route items: strips of rows of one solution (one LDS sub-block
-    // each by default), largest first (rows times the columns to their
-    // right), ties in solution / row order
-    for (int i = 0; i < count; ++i)
-        for_each_item(v[i]->Q, rows_per_item > 0 ? rows_per_item : trs[i],
-                      [&](int s0, int s1) { items.push_back(InterItem{i, s0, s1, 0}); });
+    // Workgroups of a resident grid are dispatched round-robin over the XCDs
+    // (each with its own L2), so workgroup b works on the item list of XCD
+    // b mod nx.  Every solution is placed on one XCD (largest first, onto the
+    // least loaded one): its attributes and halo rows then stay in one L2.
+    // Inter-route items are strips of rows of one solution (one LDS sub-block
+    // each by default); each list is sorted largest first (rows times the
+    // columns to their right), ties in solution / row order.
+    const int grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
+    const int nx = (grid_inter % kMaxXcds == 0 && grid_intra % kMaxXcds == 0) ? kMaxXcds : 1;
+    std::vector<int> order(count), xcd(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto sol_work = [&](int i) { return 0.5 * (double)v[i]->Q * v[i]->Q; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sol_work(a) > sol_work(b); });
+    std::vector<double> load(nx, 0.0);
+    for (int i : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        xcd[i] = x;
+        load[x] += sol_work(i);
+    }
     auto work = [&](const InterItem &a) {
         const long long Q = v[a.sol]->Q, r = a.s1 - a.s0;
         return r * (2 * Q - a.s0 - a.s1 + 1);
     };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
-    size_t odesc, oitems, ointra, oqueue;
-    batch_layout(v, &odesc, &oitems, &ointra, &oqueue, (int)items.size(), (int)intra.size());
+    std::vector<int> xoff(nx + 1, 0), ixoff(nx + 1, 0);
+    for (int x = 0; x < nx; ++x) {
+        const size_t first = items.size();
+        for (int i = 0; i < count; ++i) {
+            if (xcd[i] != x) continue;
+            for_each_item(v[i]->Q, rows_per_item > 0 ? rows_per_item : trs[i],
+                          [&](int s0, int s1) { items.push_back(InterItem{i, s0, s1, 0}); });
+            push_intra_groups(v[i]->n, v[i]->R, i, intra);
+        }
+        std::stable_sort(items.begin() + first, items.end(),
+                         [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
+        xoff[x + 1] = (int)items.size();
+        ixoff[x + 1] = (int)intra.size();
+    }
+    size_t odesc, oitems, ointra, osched;
+    batch_layout(v, &odesc, &oitems, &ointra, &osched, (int)items.size(), (int)intra.size());
     char *base = (char *)ws;
     tga_batch *B = new tga_batch();
     B->sols = v;
@@ -839,14 +856,15 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->nitems = (int)items.size();
     B->intra = (IntraItem *)(base + ointra);
     B->nintra = (int)intra.size();
-    B->queue = (int *)(base + oqueue);
-    B->done = B->queue + 16;
+    B->xoff = (int *)(base + osched);
+    B->ixoff = B->xoff + (kMaxXcds + 1);
+    B->nx = nx;
+    B->done = B->xoff + 2 * (kMaxXcds + 1);
     B->lds = lds;
     B->lds_intra = lds_intra;
     B->split = split;
     B->grid_inter = grid_inter;
-    B->grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
-    B->chunk = schedule_chunk();
+    B->grid_intra = grid_intra;
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
@@ -857,10 +875,9 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         e = hipMemcpyAsync(B->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-        k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = hipMemcpyAsync(B->xoff, xoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->ixoff, ixoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         delete B;
@@ -874,16 +891,16 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
 static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
     if (!(op_mask & TGA_OP_ALL)) return;
     if (!B->split) {
-        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
-                                                                     B->nintra, op_mask, B->queue, B->chunk);
+        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
+                                                                     B->ixoff, B->nx, op_mask);
         return;
     }
     if (op_mask & 7)
-        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->nitems, B->intra,
-                                                                     B->nintra, op_mask, B->queue, B->chunk);
+        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
+                                                                     B->ixoff, B->nx, op_mask);
     if (op_mask & (2 | 8 | 16))
         k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
-            B->d, B->items, B->nitems, B->intra, B->nintra, op_mask, B->queue, B->chunk);
+            B->d, B->items, B->xoff, B->intra, B->ixoff, B->nx, op_mask);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
@@ -900,7 +917,6 @@ extern "C" int tga_batch_reset(tga_batch_t B, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, 0);
-    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return TGA_OK;
@@ -932,7 +948,6 @@ extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, 
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, steps);
-    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     HIPCHK(hipGetLastError());
     // `steps` evaluations per solution suffice (see tga_ls_run)
     const int evals = steps;
@@ -970,7 +985,6 @@ extern "C" int tga_batch_begin(tga_batch_t B, int32_t max_steps, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, max_steps);
-    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     HIPCHK(hipGetLastError());
     return TGA_OK;
 }
@@ -1011,7 +1025,6 @@ extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best,
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
     k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, 0);
-    k_zero_i32<<<1, 64, 0, st>>>(B->queue, 16);
     batch_step(B, op_mask, kModeRecord, st);
     HIPCHK(hipGetLastError());
     std::vector<int32_t> rec(8 * n), state(16 * n);

@@ -321,19 +321,24 @@ __device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, const int32_t *roff
     return e;
 }
 
-// Rebuild every attribute of S from the layout nr[] = {node, route} and
-// roffn[].  nr doubles as scratch for {A, Z} after the first two passes.
+// Attributes of the slots [lo, hi) of the layout (nr, roffn), a union of
+// whole routes, from their nodes (nr[s] = {node, route}; nr is then reused
+// as scratch for the scans' A and Z).  `full`: the whole layout (also the
+// route offsets and the sentinel slot Q); otherwise the other slots are
+// already right.  Route distances, cost and |N(S)| are refreshed either way.
 // Requires blockDim.x == kApplyThreads.
-__device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
+__device__ __forceinline__ void rebuild_range(const SolDev &S, int2 *nr, const int32_t *roffn, int lo, int hi,
+                                              bool full, ApplyShared &sh) {
     const int Q = S.Q, R = S.R, n = S.n, np1 = S.np1;
     const int tid = threadIdx.x, T = blockDim.x;
     const int32_t *D = S.D;
     const int4 *nd = S.node4;
     const bool tw = S.has_tw;
 
-    for (int r = tid; r <= R; r += T) gst(S.roff + r, gld(roffn + r));
+    if (full)
+        for (int r = tid; r <= R; r += T) gst(S.roff + r, gld(roffn + r));
     // pass 1: node, route, edge, per-node data, ref map
-    for (int s = tid; s < Q; s += T) {
+    for (int s = lo + tid; s < hi; s += T) {
         const int2 x = gld(nr + s);
         const int node = x.x, r = x.y;
         const int first = gld(roffn + r), last = gld(roffn + r + 1) - 1;
@@ -347,7 +352,7 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
         gst(S.b4 + s, make_int4(cust ? q.x : 0, 0, 0, 0));
         gst(S.ref2slot + (cust ? node - 1 : n + r), s);
     }
-    if (tid == 0) {
+    if (full && tid == 0) {
         gst(S.a4 + Q, make_int4(0, R, 0, 0));
         gst(S.b4 + Q, make_int4(0, 0, 0, 0));
         gst(S.w4 + Q, make_int4(tw ? gld(nd).y : 0, tw ? gld(nd).z : kTwOff, 0, 0));
@@ -357,7 +362,7 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     __threadfence_block();
     __syncthreads();
     // pass 2: removal delta and incident-edge sums (customers)
-    for (int s = tid; s < Q; s += T) {
+    for (int s = lo + tid; s < hi; s += T) {
         int4 a = gld(S.a4 + s);
         if (s == gld(roffn + a.y)) continue;
         const int4 ap = gld(S.a4 + s - 1);
@@ -372,8 +377,8 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     __threadfence_block();
     __syncthreads();
 
-    const int C = (Q + T - 1) / T;
-    const int beg = min(Q, tid * C), end = min(Q, beg + C);
+    const int C = (hi - lo + T - 1) / T;
+    const int beg = min(hi, lo + tid * C), end = min(hi, beg + C);
     // forward scans: prefix load, prefix distance, earliest service start A
     {
         FwdElem agg = fwd_identity();
@@ -415,14 +420,14 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     __threadfence_block();
     __syncthreads();
     // pass 3: route totals (by the thread owning each route's last slot)
-    for (int s = tid; s < Q; s += T) {
+    for (int s = lo + tid; s < hi; s += T) {
         const int r = gld(S.a4 + s).y;
         if (s == gld(roffn + r + 1) - 1) gst(S.rdist + r, gld(S.pdist + s) + gld(S.a4 + s).z);
     }
     // pass 4: derived per-slot values and flags
     const int l0 = tw ? gld(nd).z : kTwOff;
     const int cap = S.cap;
-    for (int s = tid; s < Q; s += T) {
+    for (int s = lo + tid; s < hi; s += T) {
         int4 a = gld(S.a4 + s);
         const int first = gld(roffn + a.y), last = gld(roffn + a.y + 1) - 1;
         const int rload = gld(S.b4 + last).y;
@@ -483,6 +488,10 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     }
     __threadfence_block();
     __syncthreads();
+}
+
+__device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
+    rebuild_range(S, nr, roffn, 0, S.Q, true, sh);
 }
 
 // Build the attributes of a freshly uploaded layout (nr_alt, roff_alt).
@@ -1291,46 +1300,26 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 // Batched form: persistent launches evaluate every solution of the batch.
 // PH bit 0: inter-route items (whole workgroup per item, largest first);
 // PH bit 1: intra-route groups (one wavefront per group of routes).  PH = 3
-// runs both phases in one launch; PH = 1 and PH = 2 are the two halves as
-// separate launches, each compiled alone so that it gets its own register
-// budget and occupancy.  Solutions of both problem types share a launch;
-// each item takes the window-aware or the capacity-only path of its own
-// solution.
-// chunk == 0: static schedule, workgroup (or wavefront) b takes items b,
-// b + G, b + 2G, ... (round-robin over the largest-first list).  chunk > 0:
-// dynamic schedule, workgroups take `chunk` consecutive items per atomic on
-// queue[0] (inter) / queue[1] (intra); the last workgroup to finish (counted
-// in queue[2], or queue[3] for PH = 2) resets the heads it used, so
-// consecutive launches (also inside a captured graph) need no reset in
-// between.
+// runs both phases in one launch (the groups fill the tail of the inter-route
+// phase); PH = 1 and PH = 2 are the two halves as separate launches.
+// Solutions of both problem types and both distance widths share a launch;
+// each item takes the path of its own solution.  Static schedule: the items
+// are split into nx lists, one per XCD, and workgroup b (dispatched to XCD
+// b mod nx) takes items j, j + G', j + 2G', ... of list b mod nx, where
+// j = b / nx and G' = gridDim.x / nx; its wavefronts do the same with the
+// intra-route groups.
 template <int PH>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
-    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, int nitems,
-    const IntraItem *__restrict__ intra, int nintra, uint32_t op_mask, int *__restrict__ queue, int chunk) {
+    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ xoff,
+    const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx, uint32_t op_mask) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
-    __shared__ int cur;
     __shared__ int thr_sh;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int x = blockIdx.x % nx, j = blockIdx.x / nx, step = gridDim.x / nx;
     if ((PH & 1) && (op_mask & 7)) {
-        int base = blockIdx.x, step = gridDim.x, left = 0;
-        for (;;) {
-            int it;
-            if (chunk == 0) {
-                it = base;
-                base += step;
-            } else {
-                if (left == 0) {
-                    if (threadIdx.x == 0) cur = atomicAdd(&queue[0], chunk);
-                    __syncthreads();
-                    base = cur;
-                    left = chunk;
-                    __syncthreads();
-                }
-                it = base++;
-                --left;
-            }
-            if (it >= nitems) break;
+        const int end = xoff[x + 1];
+        for (int it = xoff[x] + j; it < end; it += step) {
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
@@ -1349,23 +1338,8 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
     if ((PH & 2) && (op_mask & (2 | 8 | 16))) {
         int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
-        int base = blockIdx.x * kInterWaves + wave, step = gridDim.x * kInterWaves, left = 0;
-        for (;;) {
-            int it;
-            if (chunk == 0) {
-                it = base;
-                base += step;
-            } else {
-                if (left == 0) {
-                    int b0 = 0;
-                    if (lane == 0) b0 = atomicAdd(&queue[1], chunk);
-                    base = __shfl(b0, 0);
-                    left = chunk;
-                }
-                it = base++;
-                --left;
-            }
-            if (it >= nintra) break;
+        const int end = ixoff[x + 1];
+        for (int it = ixoff[x] + j * kInterWaves + wave; it < end; it += step * kInterWaves) {
             const IntraItem item = intra[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
@@ -1373,20 +1347,6 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
                 intra_group<true, false>(S, item, op_mask, nullptr, nullptr, region);
             else
                 intra_group<false, false>(S, item, op_mask, nullptr, nullptr, region);
-        }
-    }
-    if (chunk == 0) return;
-    // every workgroup has taken its last items from its queues before it
-    // counts itself finished; the last one resets them for the next launch
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int *fin = &queue[PH == 2 ? 3 : 2];
-        __threadfence();
-        if (atomicAdd(fin, 1) == (int)gridDim.x - 1) {
-            if (PH & 1) atomicExch(&queue[0], 0);
-            if (PH & 2) atomicExch(&queue[1], 0);
-            atomicExch(fin, 0);
-            __threadfence();
         }
     }
 }
@@ -1481,30 +1441,70 @@ __device__ __forceinline__ void decode_move(const SolDev &S, uint32_t id, MoveIn
     m.valid = ok;
 }
 
-// Apply m (valid) and rebuild.  All threads of the block participate.
+// Apply m (valid).  All threads of the block participate.  Every slot
+// attribute is route-local, so only the touched routes are rebuilt; the
+// routes strictly between two touched routes of different lengths move as a
+// block by the first one's length change (a plain copy of their records).
 __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo &m, ApplyShared &sh) {
-    const int R = S.R, Q = S.Q, T = blockDim.x, tid = threadIdx.x;
+    const int R = S.R, T = blockDim.x, tid = threadIdx.x;
     const bool inter = m.ra != m.rb;
     const int dA = m.nLa - m.La, dB = inter ? m.nLb - m.Lb : 0;
     auto shift = [&](int r) { return (r > m.ra ? dA : 0) + (inter && r > m.rb ? dB : 0); };
+    // 1. new offsets, and the touched routes' nodes (read from the old layout)
     for (int r = tid; r <= R; r += T) S.roff_alt[r] = S.roff[r] + shift(r);
-    // untouched routes keep their nodes, shifted
-    for (int s = tid; s < Q; s += T) {
-        const int4 a = S.a4[s];
-        const int r = a.y;
-        if (r == m.ra || r == m.rb) continue;
-        S.nr_alt[s + shift(r)] = make_int2(nodeof(a.x), r);
-    }
-    // touched routes
     const int baseA = S.roff[m.ra] + shift(m.ra);
     for (int p = tid; p <= m.nLa; p += T) S.nr_alt[baseA + p] = make_int2(new_node(S, m, m.ra, p), m.ra);
+    int baseB = 0;
     if (inter) {
-        const int baseB = S.roff[m.rb] + shift(m.rb);
+        baseB = S.roff[m.rb] + shift(m.rb);
         for (int p = tid; p <= m.nLb; p += T) S.nr_alt[baseB + p] = make_int2(new_node(S, m, m.rb, p), m.rb);
     }
     __threadfence_block();
     __syncthreads();
-    rebuild(S, S.nr_alt, S.roff_alt, sh);
+    // 2. routes strictly between the touched ones move by d; rounds of T
+    //    slots, each read completely before it is written, taken in the
+    //    direction of the move so no round overwrites a later one's source
+    if (inter) {
+        const int r1 = min(m.ra, m.rb), r2 = max(m.ra, m.rb);
+        const int d = r1 == m.ra ? dA : dB;
+        const int lo = S.roff[r1 + 1], hi = S.roff[r2];  // old slots of the routes between
+        if (d != 0 && hi > lo) {
+            const int rounds = (hi - lo + T - 1) / T;
+            for (int k = 0; k < rounds; ++k) {
+                const int rk = d < 0 ? k : rounds - 1 - k;
+                const int src = lo + rk * T + tid;
+                const bool on = src < hi;
+                int4 a = make_int4(0, 0, 0, 0), b = a, t = a, w = a;
+                int pd = 0;
+                if (on) {
+                    a = S.a4[src];
+                    b = S.b4[src];
+                    t = S.t4[src];
+                    w = S.w4[src];
+                    pd = S.pdist[src];
+                }
+                __syncthreads();
+                if (on) {
+                    const int dst = src + d;
+                    S.a4[dst] = a;
+                    S.b4[dst] = b;
+                    S.t4[dst] = t;
+                    S.w4[dst] = w;
+                    S.pdist[dst] = pd;
+                    const int node = nodeof(a.x);
+                    S.ref2slot[(flagsof(a.x) & kFlagCustomer) ? node - 1 : S.n + a.y] = dst;
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
+        }
+    }
+    for (int r = tid; r <= R; r += T) S.roff[r] = S.roff_alt[r];
+    __threadfence_block();
+    __syncthreads();
+    // 3. rebuild the touched routes in place
+    rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
+    if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
 }
 
 // One block per solution.  kModeRecord: publish the best move (status 1 if

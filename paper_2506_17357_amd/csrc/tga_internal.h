@@ -77,6 +77,8 @@ enum {
 // row 16-byte aligned.
 constexpr int stride16_of(int np1) { return (np1 + 7) & ~7; }
 
+constexpr int kMaxXcds = 8;  // accelerator dies (each with its own L2) the batched items are spread over
+
 struct InterItem {  // row slots [s0, s1) of solution `sol`
     int32_t sol, s0, s1, pad;
 };

@@ -190,6 +190,9 @@ def main():
     ebytes = np.array([eval_bytes(i, s.R, I.dist_bytes) for I, (i, s) in zip(insts, pairs)], np.float64)
     B = tga.Batch(sols)
     torch.cuda.synchronize()
+    t = time.time()
+    schedule = B.autotune(launches=5)  # untimed: picks tile shapes and launch split
+    log("autotuned schedule in %.2f s: %s" % (time.time() - t, schedule))
     log("uploaded: %.1f MB of distance matrices resident, %d of %d streamed at 16 bits" % (
         sum(4 * (i.n + 1) ** 2 for i, _ in pairs) / 1e6, sum(I.dist_bytes == 2 for I in insts), len(insts)))
 
@@ -330,8 +333,9 @@ def main():
             "dist_bytes_streamed_per_eval": int(sum(I.dist_bytes * (i.n + 1) ** 2 for I, (i, _) in zip(insts, pairs))),
             "moves_evaluated": moves_total,
             "accepted_moves": int(st_e.sum()),
-            "form": "batched: one persistent evaluation launch + one finalize launch per step, "
+            "form": "batched: persistent evaluation launch(es) + one finalize launch per step, "
                     "step loop captured in a HIP graph",
+            "schedule": schedule,
         },
         "roofline": {
             "bound": "hbm",

@@ -195,13 +195,29 @@ int tga_device_limits(int32_t *compute_units, int32_t *max_lds_bytes);
  * most one batch and must not be used through the single-solution calls
  * while the batch exists. */
 
-/* Device workspace bytes for a batch of `count` solutions. */
+/* Device workspace bytes for a batch of `count` solutions (enough for every
+ * schedule a batch can be given). */
 size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t count);
+
+/* Schedule of a batch; none of it changes a result.
+ *   lds_kb         LDS budget of an inter-route workgroup, KiB (8..160): it
+ *                  sets how many distance-matrix rows one strip stages (at
+ *                  most 64), per solution.
+ *   split          0: inter- and intra-route phases in one launch (the
+ *                  intra-route groups fill the tail); 1: two launches.
+ *   rows_per_item, sub_rows  as for tga_batch_create.
+ *   us_per_eval    written by tga_batch_autotune: measured microseconds per
+ *                  evaluation step of the chosen schedule; ignored on input. */
+typedef struct {
+    int32_t lds_kb, split, rows_per_item, sub_rows;
+    float us_per_eval;
+} tga_batch_config_t;
 
 /* rows_per_item: slot rows per inter-route work item (0 = one LDS sub-block);
  * sub_rows: rows staged in LDS at a time (0 = as many as the LDS budget of a
  * workgroup holds for the solution's n; larger values are clamped to it).
- * Both only change the schedule, never a result. */
+ * Both only change the schedule, never a result.  The batch starts with
+ * lds_kb = 64 (or TGA_LDS_KB) and split = 0. */
 int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
                      int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
                      tga_batch_t *out);
@@ -238,6 +254,23 @@ int tga_batch_eval(tga_batch_t b, uint32_t op_mask, tga_move_t *best, int32_t *s
 
 /* Clear the per-solution "converged" flags and step counters. */
 int tga_batch_reset(tga_batch_t b, void *stream);
+
+/* The batch's current schedule. */
+int tga_batch_get_config(tga_batch_t b, tga_batch_config_t *out);
+
+/* Re-plan the batch for `cfg` (TGA_ERANGE if it does not fit the device;
+ * the batch keeps its schedule then).  Drops a captured step loop.
+ * Synchronises `stream`. */
+int tga_batch_set_config(tga_batch_t b, const tga_batch_config_t *cfg, void *stream);
+
+/* The project's autotuner for the batched form: times `launches` evaluation
+ * steps (each followed by a finalize that only records the best move, so no
+ * solution changes) of the batch's current state under each candidate
+ * schedule (lds_kb in {40, 52, 64, 78} x split in {0, 1}, keeping
+ * rows_per_item and sub_rows), keeps the fastest and writes it to `best`
+ * (nullable).  Drops a captured step loop.  Synchronises `stream`. */
+int tga_batch_autotune(tga_batch_t b, uint32_t op_mask, int32_t launches, tga_batch_config_t *best,
+                       void *stream);
 
 int tga_batch_free(tga_batch_t b);
 

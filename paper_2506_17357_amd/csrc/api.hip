@@ -211,7 +211,8 @@ struct tga_batch {
     size_t lds;
     size_t lds_intra;
     int grid_inter, grid_intra;
-    int split;  // 1: the inter and intra phases as two launches; 0: one launch
+    tga_batch_config_t cfg;  // the schedule the plan was made for
+    int max_items, max_intra;  // workspace capacity of the item lists
     hipGraphExec_t exec;
     hipGraph_t graph;
     int graph_steps;
@@ -728,14 +729,6 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     return off;
 }
 
-// Inter and intra phases of a batched step in one launch (default: the
-// intra-route groups fill the tail of the inter-route phase), or as two
-// launches with TGA_SPLIT=1 (tuning).
-static int batch_split() {
-    const char *e = getenv("TGA_SPLIT");
-    return (e && *e) ? (atoi(e) != 0) : 0;
-}
-
 // Workgroups of kInterThreads threads one compute unit holds at once for
 // kernel f with `lds` bytes of dynamic LDS (at least 1).
 static int resident_blocks(const void *f, size_t lds) {
@@ -766,27 +759,20 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
     return batch_layout(v, &a, &b, &c, &d, batch_max_items(v, 1), nintra);
 }
 
-extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
-                                int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
-                                tga_batch_t *out) {
-    if (!out) return fail(TGA_EINVAL, "out is null");
-    *out = nullptr;
-    if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
-    if (rows_per_item < 0 || rows_per_item > 256 || sub_rows < 0 || sub_rows > 64)
-        return fail(TGA_ERANGE, "rows_per_item in [0, 256], sub_rows in [0, 64]");
-    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
-    std::vector<tga_solution *> v(sols, sols + count);
-    for (auto *s : v) {
-        if (!s) return fail(TGA_EINVAL, "null solution in batch");
-        if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
-    }
-    for (size_t i = 0; i < v.size(); ++i)
-        for (size_t j = i + 1; j < v.size(); ++j)
-            if (v[i] == v[j]) return fail(TGA_EINVAL, "solution listed twice");
-    DevProps P;
-    int rc = props(&P);
-    if (rc) return rc;
-    if (ws_bytes < tga_batch_workspace_bytes(sols, count)) return fail(TGA_ENOMEM, "batch workspace too small");
+// Rows per LDS sub-block for an LDS budget of `budget` bytes.
+static int tile_rows_for(int np1, bool w16, size_t budget) {
+    int h = 1;
+    while (h < 64 && ring_lds(np1, h + 1, w16) <= budget) ++h;
+    return h;
+}
+
+// Plan the batch's schedule for its configuration and upload it: the
+// descriptors (with their rows per sub-block) and the per-XCD item lists.
+// The workspace regions hold the worst case of every configuration.
+static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
+    const std::vector<tga_solution *> &v = B->sols;
+    const int count = (int)v.size();
+    const tga_batch_config_t &c = B->cfg;
     std::vector<InterItem> items;
     std::vector<IntraItem> intra;
     std::vector<SolDev> descs(count);
@@ -797,18 +783,19 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         descs[i] = s->h;
         // LDS sub-block rows (bounded by the LDS budget of one workgroup)
         const bool w16 = s->h.D16 != nullptr;
-        const int tr = sub_rows > 0 ? std::min(sub_rows, s->tile_rows) : s->tile_rows;
+        const int cap_rows = tile_rows_for(s->h.np1, w16, (size_t)c.lds_kb * 1024);
+        const int tr = c.sub_rows > 0 ? std::min(c.sub_rows, cap_rows) : cap_rows;
         trs[i] = tr;
         descs[i].tile_rows = tr;
         lds = std::max(lds, ring_lds(s->h.np1, tr, w16));
     }
-    const int split = batch_split();
     const size_t lds_intra = (size_t)kInterWaves * kIntraRegionBytes;  // the intra phase's regions
-    if (!split) lds = std::max(lds, lds_intra);
+    if (!c.split) lds = std::max(lds, lds_intra);
     if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);
     // one resident wave of workgroups: as many as LDS and registers allow
     const int grid_inter =
-        P.cus * resident_blocks(split ? (const void *)k_eval_batch<1> : (const void *)k_eval_batch<3>, lds);
+        P.cus * resident_blocks(c.split ? (const void *)k_eval_batch<1> : (const void *)k_eval_batch<3>, lds);
+    const int grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
     // Workgroups of a resident grid are dispatched round-robin over the XCDs
     // (each with its own L2), so workgroup b works on the item list of XCD
     // b mod nx.  Every solution is placed on one XCD (largest first, onto the
@@ -816,7 +803,6 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     // Inter-route items are strips of rows of one solution (one LDS sub-block
     // each by default); each list is sorted largest first (rows times the
     // columns to their right), ties in solution / row order.
-    const int grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
     const int nx = (grid_inter % kMaxXcds == 0 && grid_intra % kMaxXcds == 0) ? kMaxXcds : 1;
     std::vector<int> order(count), xcd(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -837,7 +823,7 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         const size_t first = items.size();
         for (int i = 0; i < count; ++i) {
             if (xcd[i] != x) continue;
-            for_each_item(v[i]->Q, rows_per_item > 0 ? rows_per_item : trs[i],
+            for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : trs[i],
                           [&](int s0, int s1) { items.push_back(InterItem{i, s0, s1, 0}); });
             push_intra_groups(v[i]->n, v[i]->R, i, intra);
         }
@@ -846,42 +832,96 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
         xoff[x + 1] = (int)items.size();
         ixoff[x + 1] = (int)intra.size();
     }
-    size_t odesc, oitems, ointra, osched;
-    batch_layout(v, &odesc, &oitems, &ointra, &osched, (int)items.size(), (int)intra.size());
-    char *base = (char *)ws;
-    tga_batch *B = new tga_batch();
-    B->sols = v;
-    B->d = (SolDev *)(base + odesc);
-    B->items = (InterItem *)(base + oitems);
+    if ((int)items.size() > B->max_items || (int)intra.size() > B->max_intra)
+        return fail(TGA_ERANGE, "batch schedule exceeds its workspace");
     B->nitems = (int)items.size();
-    B->intra = (IntraItem *)(base + ointra);
     B->nintra = (int)intra.size();
-    B->xoff = (int *)(base + osched);
-    B->ixoff = B->xoff + (kMaxXcds + 1);
     B->nx = nx;
-    B->done = B->xoff + 2 * (kMaxXcds + 1);
     B->lds = lds;
     B->lds_intra = lds_intra;
-    B->split = split;
     B->grid_inter = grid_inter;
     B->grid_intra = grid_intra;
-    B->exec = nullptr;
-    B->graph = nullptr;
+    // a captured step loop holds the old launch shapes
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
     B->graph_steps = -1;
-    B->cap_stream = nullptr;
-    hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(B->d, descs.data(), sizeof(SolDev) * count, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !intra.empty())
         e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(B->xoff, xoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->ixoff, ixoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
+    if (e != hipSuccess) return fail(TGA_EDEVICE, "batch plan: %s", hipGetErrorString(e));
+    return TGA_OK;
+}
+
+static int check_config(const tga_batch_config_t &c) {
+    if (c.rows_per_item < 0 || c.rows_per_item > 256 || c.sub_rows < 0 || c.sub_rows > 64)
+        return fail(TGA_ERANGE, "rows_per_item in [0, 256], sub_rows in [0, 64]");
+    if (c.lds_kb < 8 || c.lds_kb > 160) return fail(TGA_ERANGE, "lds_kb in [8, 160]");
+    if (c.split != 0 && c.split != 1) return fail(TGA_EINVAL, "split must be 0 or 1");
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
+                                int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
+                                tga_batch_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
+    tga_batch_config_t cfg;
+    cfg.lds_kb = (int32_t)(lds_budget() / 1024);
+    cfg.split = 0;
+    cfg.rows_per_item = rows_per_item;
+    cfg.sub_rows = sub_rows;
+    cfg.us_per_eval = 0.f;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<tga_solution *> v(sols, sols + count);
+    for (auto *s : v) {
+        if (!s) return fail(TGA_EINVAL, "null solution in batch");
+        if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
+    }
+    for (size_t i = 0; i < v.size(); ++i)
+        for (size_t j = i + 1; j < v.size(); ++j)
+            if (v[i] == v[j]) return fail(TGA_EINVAL, "solution listed twice");
+    DevProps P;
+    if ((rc = props(&P))) return rc;
+    if (ws_bytes < tga_batch_workspace_bytes(sols, count)) return fail(TGA_ENOMEM, "batch workspace too small");
+    int nintra = 0;
+    for (auto *s : v) nintra += s->R;
+    const int max_items = batch_max_items(v, 1);
+    size_t odesc, oitems, ointra, osched;
+    batch_layout(v, &odesc, &oitems, &ointra, &osched, max_items, nintra);
+    char *base = (char *)ws;
+    tga_batch *B = new tga_batch();
+    B->sols = v;
+    B->cfg = cfg;
+    B->d = (SolDev *)(base + odesc);
+    B->items = (InterItem *)(base + oitems);
+    B->max_items = max_items;
+    B->intra = (IntraItem *)(base + ointra);
+    B->max_intra = nintra;
+    B->xoff = (int *)(base + osched);
+    B->ixoff = B->xoff + (kMaxXcds + 1);
+    B->done = B->xoff + 2 * (kMaxXcds + 1);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_steps = -1;
+    B->cap_stream = nullptr;
+    if ((rc = batch_plan(B, P, (hipStream_t)stream))) {
         delete B;
-        return fail(TGA_EDEVICE, "batch_create: %s", hipGetErrorString(e));
+        return rc;
     }
     for (auto *s : v) s->in_batch = 1;
     *out = B;
@@ -890,7 +930,7 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
 
 static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
     if (!(op_mask & TGA_OP_ALL)) return;
-    if (!B->split) {
+    if (!B->cfg.split) {
         k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
                                                                      B->ixoff, B->nx, op_mask);
         return;
@@ -910,6 +950,94 @@ static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipS
 static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
     batch_eval_launch(B, op_mask, st);
     batch_finalize_launch(B, op_mask, mode, st);
+}
+
+extern "C" int tga_batch_get_config(tga_batch_t B, tga_batch_config_t *out) {
+    if (!B || !out) return fail(TGA_EINVAL, "null argument");
+    *out = B->cfg;
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_set_config(tga_batch_t B, const tga_batch_config_t *cfg, void *stream) {
+    if (!B || !cfg) return fail(TGA_EINVAL, "null argument");
+    int rc = check_config(*cfg);
+    if (rc) return rc;
+    DevProps P;
+    if ((rc = props(&P))) return rc;
+    const tga_batch_config_t old = B->cfg;
+    B->cfg = *cfg;
+    B->cfg.us_per_eval = 0.f;
+    if ((rc = batch_plan(B, P, (hipStream_t)stream))) {
+        B->cfg = old;  // keep (and re-upload) the previous schedule
+        const std::string msg = tga_last_error();
+        if (batch_plan(B, P, (hipStream_t)stream) != TGA_OK) return rc;
+        return fail(rc, "%s", msg.c_str());
+    }
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launches, tga_batch_config_t *best,
+                                  void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (launches < 1 || launches > 1000) return fail(TGA_ERANGE, "launches in [1, 1000]");
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(TGA_EDEVICE, "hipEventCreate failed");
+    }
+    const tga_batch_config_t base = B->cfg;
+    static const int kLdsKb[] = {40, 52, 64, 78};
+    tga_batch_config_t chosen = base;
+    float best_us = 0.f;
+    bool any = false;
+    hipError_t e = hipSuccess;
+    for (int split = 0; split <= 1 && e == hipSuccess; ++split) {
+        for (int kb : kLdsKb) {
+            tga_batch_config_t c = base;
+            c.lds_kb = kb;
+            c.split = split;
+            c.us_per_eval = 0.f;
+            B->cfg = c;
+            if (batch_plan(B, P, st) != TGA_OK) continue;  // does not fit this device
+            batch_step(B, op_mask, kModeRecord, st);     // untimed
+            e = hipEventRecord(e0, st);
+            for (int i = 0; i < launches && e == hipSuccess; ++i) batch_step(B, op_mask, kModeRecord, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            const float us = ms * 1000.f / launches;
+            if (!any || us < best_us) {
+                any = true;
+                best_us = us;
+                chosen = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        B->cfg = base;
+        (void)batch_plan(B, P, st);
+        return fail(TGA_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    }
+    if (!any) {
+        B->cfg = base;
+        (void)batch_plan(B, P, st);
+        return fail(TGA_ERANGE, "no candidate schedule fits the device");
+    }
+    chosen.us_per_eval = best_us;
+    B->cfg = chosen;
+    if ((rc = batch_plan(B, P, st))) return rc;
+    if (best) *best = chosen;
+    return TGA_OK;
 }
 
 extern "C" int tga_batch_reset(tga_batch_t B, void *stream) {

@@ -42,6 +42,16 @@ class Move(ctypes.Structure):
                 % (self.op, self.k, self.a, self.b, self.delta, self.feas, self.id, self.version))
 
 
+class BatchConfig(ctypes.Structure):
+    """Schedule of a batch (tga_batch_config_t); never changes a result."""
+    _fields_ = [("lds_kb", ctypes.c_int32), ("split", ctypes.c_int32), ("rows_per_item", ctypes.c_int32),
+                ("sub_rows", ctypes.c_int32), ("us_per_eval", ctypes.c_float)]
+
+    def as_dict(self):
+        return {"lds_kb": self.lds_kb, "split": self.split, "rows_per_item": self.rows_per_item,
+                "sub_rows": self.sub_rows, "us_per_eval": round(float(self.us_per_eval), 2)}
+
+
 EXPORTS = [
     "tga_instance_workspace_bytes", "tga_solution_workspace_bytes", "tga_load_instance",
     "tga_set_solution", "tga_eval_neighborhood", "tga_apply_move", "tga_ls_run",
@@ -50,7 +60,7 @@ EXPORTS = [
     "tga_batch_ls_run", "tga_batch_eval", "tga_batch_reset", "tga_batch_free",
     "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
     "tga_solution_reload", "tga_solution_begin", "tga_batch_poll", "tga_solution_stats",
-    "tga_instance_dist_bytes",
+    "tga_instance_dist_bytes", "tga_batch_get_config", "tga_batch_set_config", "tga_batch_autotune",
 ]
 
 
@@ -94,6 +104,9 @@ def lib():
         "tga_batch_poll": (i32, [P, P, P]),
         "tga_solution_stats": (i32, [P, P, P, P, P, P]),
         "tga_instance_dist_bytes": (i32, [P]),
+        "tga_batch_get_config": (i32, [P, ctypes.POINTER(BatchConfig)]),
+        "tga_batch_set_config": (i32, [P, ctypes.POINTER(BatchConfig), P]),
+        "tga_batch_autotune": (i32, [P, u32, i32, ctypes.POINTER(BatchConfig), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -283,6 +296,22 @@ class Batch:
 
     def begin(self, max_steps: int, stream=None):
         _check(lib().tga_batch_begin(self.h, max_steps, _stream(stream)))
+
+    def config(self) -> dict:
+        c = BatchConfig()
+        _check(lib().tga_batch_get_config(self.h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, lds_kb: int, split: int, rows_per_item: int = 0, sub_rows: int = 0, stream=None):
+        c = BatchConfig(lds_kb, split, rows_per_item, sub_rows, 0.0)
+        _check(lib().tga_batch_set_config(self.h, ctypes.byref(c), _stream(stream)))
+
+    def autotune(self, op_mask: int = OPS_ALL, launches: int = 5, stream=None) -> dict:
+        """Pick the fastest schedule for the batch's current state (see
+        tga_batch_autotune); returns it."""
+        c = BatchConfig()
+        _check(lib().tga_batch_autotune(self.h, op_mask, launches, ctypes.byref(c), _stream(stream)))
+        return c.as_dict()
 
     def step_part(self, part: int, op_mask: int = OPS_ALL, stream=None):
         _check(lib().tga_batch_step_part(self.h, op_mask, part, _stream(stream)))

@@ -116,6 +116,38 @@ def test_schedule_does_not_change_results(tga, rows_per_item, sub_rows):
         assert steps[b] == len(ids) and cost[b] == oracle.cost(inst, final)[0]
 
 
+@pytest.mark.parametrize("lds_kb,split", [(40, 0), (52, 1), (78, 0), (24, 1)])
+def test_config_does_not_change_results(tga, lds_kb, split):
+    pairs = small_mix(6, seed=4)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    B.set_config(lds_kb, split)
+    c = B.config()
+    assert (c["lds_kb"], c["split"]) == (lds_kb, split)
+    steps, moves, cost = B.ls_run(25, use_graph=True)
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=25)
+        assert (steps[b], moves[b], cost[b]) == (len(ids), mv, oracle.cost(inst, final)[0]), b
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(tga):
+    pairs = small_mix(8, seed=6)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    cfg = B.autotune(launches=2)
+    print("autotuned", cfg, flush=True)
+    assert cfg["lds_kb"] in (40, 52, 64, 78) and cfg["split"] in (0, 1) and cfg["us_per_eval"] > 0
+    assert B.config() == cfg
+    steps, moves, cost = B.ls_run(30)
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=30)
+        assert (steps[b], moves[b], cost[b]) == (len(ids), mv, oracle.cost(inst, final)[0]), b
+    with pytest.raises(tga.TGAError) as e:
+        B.set_config(200, 0)
+    assert e.value.code == tga.TGA_ERANGE
+    assert B.config() == cfg
+
+
 def test_full_batched_workload_sampled(tga):
     """The 256-solution mix (100..2000 customers) for 200 steps: every
     solution equals its plain form; a sample equals the oracle."""

@@ -321,6 +321,46 @@ __device__ __forceinline__ BwdElem bwd_elem(const SolDev &S, const int32_t *roff
     return e;
 }
 
+// Cost (sum of route distances) and |N(S)| per operator from the route
+// offsets and distances.  Every thread of the block calls it.
+__device__ __forceinline__ void solution_totals(const SolDev &S, const int32_t *roffn, ApplyShared &sh) {
+    const int Q = S.Q, R = S.R, n = S.n;
+    const int tid = threadIdx.x, T = blockDim.x;
+    // cost and |N(S)| per operator
+    long long v[5] = {0, 0, 0, 0, 0};
+    for (int r = tid; r < R; r += T) {
+        const long long L = gld(roffn + r + 1) - gld(roffn + r) - 1;
+        v[0] += gld(S.rdist + r);
+        v[1] += L * (Q - L - 1);
+        v[2] += (L + 1) * (L + 1);
+        v[3] += L * (L - 1) / 2;
+        for (int k = 1; k <= 3; ++k)
+            if (k <= L) v[4] += (L - k + 1) * (L - k);
+    }
+    for (int i = 0; i < 5; ++i) {
+        long long x = v[i];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+        v[i] = x;
+    }
+    if ((tid & 63) == 0)
+        for (int i = 0; i < 5; ++i) sh.red[tid >> 6][i] = v[i];
+    __syncthreads();
+    if (tid == 0) {
+        long long t[5] = {0, 0, 0, 0, 0};
+        for (int w = 0; w < T / 64; ++w)
+            for (int i = 0; i < 5; ++i) t[i] += sh.red[w][i];
+        const long long qq = (long long)Q * Q;
+        S.acc[kAccCost] = t[0];
+        S.acc[kAccCnt0 + 0] = t[1];
+        S.acc[kAccCnt0 + 1] = (long long)n * (n - 1) / 2;
+        S.acc[kAccCnt0 + 2] = (qq - t[2]) / 2;
+        S.acc[kAccCnt0 + 3] = t[3];
+        S.acc[kAccCnt0 + 4] = t[4];
+    }
+    __threadfence_block();
+    __syncthreads();
+}
+
 // Attributes of the slots [lo, hi) of the layout (nr, roffn), a union of
 // whole routes, from their nodes (nr[s] = {node, route}; nr is then reused
 // as scratch for the scans' A and Z).  `full`: the whole layout (also the
@@ -455,39 +495,92 @@ __device__ __forceinline__ void rebuild_range(const SolDev &S, int2 *nr, const i
     }
     __threadfence_block();
     __syncthreads();
-    // pass 5: cost and |N(S)| per operator
-    long long v[5] = {0, 0, 0, 0, 0};
-    for (int r = tid; r < R; r += T) {
-        const long long L = gld(roffn + r + 1) - gld(roffn + r) - 1;
-        v[0] += gld(S.rdist + r);
-        v[1] += L * (Q - L - 1);
-        v[2] += (L + 1) * (L + 1);
-        v[3] += L * (L - 1) / 2;
-        for (int k = 1; k <= 3; ++k)
-            if (k <= L) v[4] += (L - k + 1) * (L - k);
+    solution_totals(S, roffn, sh);
+}
+
+// The same attributes for one route of at most 64 slots, by one wavefront
+// entirely in registers: lane p holds position p (slot base + p; p = 0 is
+// the start depot, L customers follow; nr[slot].x is the node).  The
+// prefix load and distance and the two window maps are wavefront shuffle
+// scans of the same elements the block scans use.  Writes the slot
+// attributes, the reverse map and the route distance; no barrier.
+__device__ __forceinline__ void rebuild_route_wave(const SolDev &S, const int2 *nr, int r, int base, int L) {
+    const int lane = threadIdx.x & 63, np1 = S.np1;
+    const int32_t *D = S.D;
+    const bool tw = S.has_tw;
+    const bool on = lane <= L;
+    const int s = base + lane;
+    const int node = on ? nr[s].x : 0;
+    const int succ = __shfl(node, min(lane + 1, 63));
+    const int nsucc = lane < L ? succ : 0;  // the route ends at the depot
+    const int pred = __shfl(node, max(lane - 1, 0));
+    int4 q = gld(S.node4 + node);
+    if (!tw) q = make_int4(q.x, 0, kTwOff, 0);
+    const int edge = on ? gld(D + (size_t)node * np1 + nsucc) : 0;
+    const bool cust = lane >= 1 && on;
+    const int demand = cust ? q.x : 0;
+    const int epred = __shfl(edge, max(lane - 1, 0));
+    const int spred = __shfl(q.w, max(lane - 1, 0));
+    const int dpw = cust ? gld(D + (size_t)pred * np1 + nsucc) : 0;  // c(pred, succ)
+    // forward elements (as fwd_elem): reset at the start depot
+    FwdElem f;
+    if (lane == 0 || !on) {
+        f = fwd_identity();
+        f.rs = lane == 0;
+    } else {
+        f.rs = 0;
+        f.load = demand;
+        f.dist = epred;
+        f.al = spred + epred;
+        f.th = q.z - f.al;
+        f.be = q.y;
     }
-    for (int i = 0; i < 5; ++i) {
-        long long x = v[i];
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-        v[i] = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const FwdElem y = shfl_f(f, lane - d < 0 ? lane : lane - d);
+        if (lane >= d) f = fwd_cat(y, f);
     }
-    if ((tid & 63) == 0)
-        for (int i = 0; i < 5; ++i) sh.red[tid >> 6][i] = v[i];
-    __syncthreads();
-    if (tid == 0) {
-        long long t[5] = {0, 0, 0, 0, 0};
-        for (int w = 0; w < T / 64; ++w)
-            for (int i = 0; i < 5; ++i) t[i] += sh.red[w][i];
-        const long long qq = (long long)Q * Q;
-        S.acc[kAccCost] = t[0];
-        S.acc[kAccCnt0 + 0] = t[1];
-        S.acc[kAccCnt0 + 1] = (long long)n * (n - 1) / 2;
-        S.acc[kAccCnt0 + 2] = (qq - t[2]) / 2;
-        S.acc[kAccCnt0 + 3] = t[3];
-        S.acc[kAccCnt0 + 4] = t[4];
+    // backward elements (as bwd_elem): reset at the last slot
+    BwdElem g;
+    if (on) {
+        const int b = q.w + edge;
+        g.rs = lane == L;
+        g.th = q.y + b;
+        g.al = -b;
+        g.be = q.z;
+    } else {
+        g = bwd_identity();
     }
-    __threadfence_block();
-    __syncthreads();
+    for (int d = 1; d < 64; d <<= 1) {
+        const BwdElem y = shfl_b(g, lane + d > 63 ? lane : lane + d);
+        if (lane + d < 64) g = bwd_cat(g, y);
+    }
+    const int e0 = tw ? gld(S.node4).y : 0;
+    const int l0 = tw ? gld(S.node4).z : kTwOff;
+    const int A = tw ? fwd_apply(f, e0) : 0;
+    const int Z = tw ? bwd_apply(g, l0) : kTwOff;
+    const int rload = __shfl(f.load, L);
+    const int Zn = __shfl(Z, min(lane + 1, 63));
+    const int Ap = __shfl(A, max(lane - 1, 0));
+    const int dep = A >= kInf ? kInf : A + q.w;
+    const int zn = lane < L ? Zn : l0;
+    int adp = kInf;
+    int flags = cust ? kFlagCustomer : 0;
+    if (cust) {
+        adp = Ap >= kInf ? kInf : Ap + spred;
+        if (rload - demand <= S.cap) flags |= kFlagRemCap;
+        if (adp < kInf && adp + dpw <= zn) flags |= kFlagRemTw;
+    }
+    if (on) {
+        const int rem = cust ? dpw - epred - edge : 0;
+        const int inc = cust ? epred + edge : 0;
+        gst(S.a4 + s, make_int4(node | (flags << 16), r, edge, rem));
+        gst(S.b4 + s, make_int4(demand, f.load, rload, inc));
+        gst(S.w4 + s, make_int4(q.y, q.z, q.w, 0));
+        gst(S.t4 + s, make_int4(dep, zn, adp, Z));
+        gst(S.pdist + s, f.dist);
+        gst(S.ref2slot + (cust ? node - 1 : S.n + r), s);
+        if (lane == L) gst(S.rdist + r, f.dist + edge);
+    }
 }
 
 __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t *roffn, ApplyShared &sh) {
@@ -1502,9 +1595,19 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
     for (int r = tid; r <= R; r += T) S.roff[r] = S.roff_alt[r];
     __threadfence_block();
     __syncthreads();
-    // 3. rebuild the touched routes in place
-    rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
-    if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
+    // 3. rebuild the touched routes in place: one wavefront each when they
+    //    fit one (the usual case), else the block scans
+    if (m.nLa < 64 && (!inter || m.nLb < 64)) {
+        const int wave = threadIdx.x >> 6;
+        if (wave == 0) rebuild_route_wave(S, S.nr_alt, m.ra, baseA, m.nLa);
+        if (wave == 1 && inter) rebuild_route_wave(S, S.nr_alt, m.rb, baseB, m.nLb);
+        __threadfence_block();
+        __syncthreads();
+        solution_totals(S, S.roff_alt, sh);
+    } else {
+        rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
+        if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
+    }
 }
 
 // One block per solution.  kModeRecord: publish the best move (status 1 if

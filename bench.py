@@ -84,6 +84,48 @@ def calibrate_copy():
     del a, b
 
 
+def n1000_comparison(steps):
+    """Batched against plain at n = 1000: 256 CVRP solutions of exactly 1000
+    customers (seeds 4500 + b), sweep start, `steps` local-search steps, both
+    forms timed from the same initial solutions and compared bit for bit."""
+    import torch
+    from paper_2506_17357_amd import tga, workload as W
+    t = time.time()
+    pairs = W.c4_uniform()
+    insts = [tga.Instance.from_workload(i) for i, _ in pairs]
+    sols = [tga.Solution(I, s.offsets, s.customers) for I, (_, s) in zip(insts, pairs)]
+
+    def reload_all():
+        for s, (_, sol) in zip(sols, pairs):
+            s.reload(sol.offsets, sol.customers)
+        torch.cuda.synchronize()
+
+    B = tga.Batch(sols)
+    B.autotune(launches=3)
+    B.ls_run(steps, use_graph=True)  # capture + first replay, untimed
+    reload_all()
+    t0 = time.perf_counter()
+    st_b, mv_b, cost_b = B.ls_run(steps, use_graph=True)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    B.close()
+    reload_all()
+    t0 = time.perf_counter()
+    res = [s.ls_run(steps) for s in sols]
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    same = (np.array_equal([r[0] for r in res], st_b) and np.array_equal([r[1] for r in res], mv_b) and
+            np.array_equal([r[2] for r in res], cost_b))
+    out = {"workload": "256 CVRP solutions of n = 1000 (seeds 4500+b), sweep start, %d steps" % steps,
+           "batched_gmoves_s": round(int(mv_b.sum()) / t_b / 1e9, 3),
+           "plain_gmoves_s": round(int(sum(r[1] for r in res)) / t_p / 1e9, 3),
+           "bit_exact": bool(same)}
+    out["batched_over_plain"] = round(out["batched_gmoves_s"] / out["plain_gmoves_s"], 2)
+    log("n = 1000: batched %.1f GMoves/s, plain %.2f GMoves/s, bit-exact %s (%.1f s)" % (
+        out["batched_gmoves_s"], out["plain_gmoves_s"], same, time.time() - t))
+    return out
+
+
 def served(args):
     """Served form: a Poisson stream of local-search requests (200..10000
     customers, CVRP / VRPTW alternating, seeds 5000 + k, arrivals seed 5999)
@@ -107,7 +149,8 @@ def served(args):
     t_closed = time.perf_counter() - t0
     cap_qps = len(reqs) / t_closed
     qps = 0.7 * cap_qps
-    log("closed loop: %.2f s, capacity %.2f requests/s -> offered %.2f requests/s" % (t_closed, cap_qps, qps))
+    log("closed loop: %.2f s, capacity %.2f requests/s -> offered %.2f requests/s (%d batch rebuilds, %.2f s)"
+        % (t_closed, cap_qps, qps, srv.rebuilds, srv.rebuild_s))
     arrivals = W.request_stream(args.requests, qps=qps, max_steps=args.served_steps)
     for q, a in zip(reqs, arrivals):
         q.arrival_s = a.arrival_s
@@ -135,6 +178,9 @@ def served(args):
                        "p99": round(float(np.percentile(lat, 99)), 2),
                        "max": round(float(lat.max()), 2)},
         "makespan_s": round(t_open, 3),
+        "steps_per_tick": srv.steps_per_tick,
+        "batch_rebuilds": srv.rebuilds,
+        "batch_rebuild_s": round(srv.rebuild_s, 3),
         "peak_active_requests": srv.peak_active,
         "peak_resident_bytes": srv.peak_used,
         "ticks": srv.ticks,
@@ -287,6 +333,7 @@ def main():
                                      "p99": round(float(np.percentile(lat, 99)), 1),
                                      "n": pairs[b1k][0].n, "kind": pairs[b1k][0].kind,
                                      "evals": int(lat.size)},
+            "n1000": n1000_comparison(min(K, 50)),
         }
 
     cpu = None

@@ -798,37 +798,67 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     const int grid_intra = P.cus * resident_blocks((const void *)k_eval_batch<2>, lds_intra);
     // Workgroups of a resident grid are dispatched round-robin over the XCDs
     // (each with its own L2), so workgroup b works on the item list of XCD
-    // b mod nx.  Every solution is placed on one XCD (largest first, onto the
-    // least loaded one): its attributes and halo rows then stay in one L2.
+    // b mod nx.  A solution is placed on one XCD (largest first, onto the
+    // least loaded one), so that its attributes and halo rows stay in one L2,
+    // unless it holds more than half of an XCD's fair share of the work: then
+    // its strips are split into contiguous ranges of about a quarter of that
+    // share, each placed the same way, and its intra-route groups are dealt
+    // round-robin (one large request must not be confined to one XCD).
     // Inter-route items are strips of rows of one solution (one LDS sub-block
     // each by default); each list is sorted largest first (rows times the
     // columns to their right), ties in solution / row order.
     const int nx = (grid_inter % kMaxXcds == 0 && grid_intra % kMaxXcds == 0) ? kMaxXcds : 1;
-    std::vector<int> order(count), xcd(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    auto sol_work = [&](int i) { return 0.5 * (double)v[i]->Q * v[i]->Q; };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sol_work(a) > sol_work(b); });
-    std::vector<double> load(nx, 0.0);
-    for (int i : order) {
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        xcd[i] = x;
-        load[x] += sol_work(i);
-    }
     auto work = [&](const InterItem &a) {
         const long long Q = v[a.sol]->Q, r = a.s1 - a.s0;
         return r * (2 * Q - a.s0 - a.s1 + 1);
     };
+    std::vector<std::vector<InterItem>> own(count);
+    std::vector<double> sol_work(count, 0.0);
+    double total = 0.0;
+    for (int i = 0; i < count; ++i) {
+        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : trs[i],
+                      [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
+        for (const auto &it : own[i]) sol_work[i] += (double)work(it);
+        total += sol_work[i];
+    }
+    const double share = total / nx;
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sol_work[a] > sol_work[b]; });
+    std::vector<double> load(nx, 0.0);
+    std::vector<std::vector<InterItem>> xitems(nx);
+    std::vector<std::vector<IntraItem>> xintra(nx);
+    auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
+    int rr = 0;
+    for (int i : order) {
+        std::vector<IntraItem> groups;
+        push_intra_groups(v[i]->n, v[i]->R, i, groups);
+        if (nx == 1 || sol_work[i] <= 0.5 * share) {
+            const int x = least();
+            load[x] += sol_work[i];
+            xitems[x].insert(xitems[x].end(), own[i].begin(), own[i].end());
+            xintra[x].insert(xintra[x].end(), groups.begin(), groups.end());
+            continue;
+        }
+        const double piece = 0.25 * share;
+        size_t k = 0;
+        while (k < own[i].size()) {
+            const int x = least();
+            double w = 0.0;
+            do {
+                w += (double)work(own[i][k]);
+                xitems[x].push_back(own[i][k++]);
+            } while (k < own[i].size() && w < piece);
+            load[x] += w;
+        }
+        for (const auto &g : groups) xintra[rr++ % nx].push_back(g);
+    }
     std::vector<int> xoff(nx + 1, 0), ixoff(nx + 1, 0);
     for (int x = 0; x < nx; ++x) {
-        const size_t first = items.size();
-        for (int i = 0; i < count; ++i) {
-            if (xcd[i] != x) continue;
-            for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : trs[i],
-                          [&](int s0, int s1) { items.push_back(InterItem{i, s0, s1, 0}); });
-            push_intra_groups(v[i]->n, v[i]->R, i, intra);
-        }
-        std::stable_sort(items.begin() + first, items.end(),
+        std::stable_sort(xitems[x].begin(), xitems[x].end(),
                          [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
+        items.insert(items.end(), xitems[x].begin(), xitems[x].end());
+        intra.insert(intra.end(), xintra[x].begin(), xintra[x].end());
         xoff[x + 1] = (int)items.size();
         ixoff[x + 1] = (int)intra.size();
     }

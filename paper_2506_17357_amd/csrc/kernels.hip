@@ -1391,10 +1391,12 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // Batched form: persistent launches evaluate every solution of the batch.
-// PH bit 0: inter-route items (whole workgroup per item, largest first);
-// PH bit 1: intra-route groups (one wavefront per group of routes).  PH = 3
-// runs both phases in one launch (the groups fill the tail of the inter-route
-// phase); PH = 1 and PH = 2 are the two halves as separate launches.
+// PH bit 1: intra-route groups (one wavefront per group of routes); PH bit 0:
+// inter-route items (whole workgroup per item, largest first).  PH = 3 runs
+// both phases in one launch, the latency-bound intra-route walks first so
+// that they overlap other workgroups' inter-route work and the small
+// inter-route items fill the tail; PH = 1 and PH = 2 are the two halves as
+// separate launches.
 // Solutions of both problem types and both distance widths share a launch;
 // each item takes the path of its own solution.  Static schedule: the items
 // are split into nx lists, one per XCD, and workgroup b (dispatched to XCD
@@ -1410,6 +1412,20 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     __shared__ int thr_sh;
     const int wave = threadIdx.x >> 6;
     const int x = blockIdx.x % nx, j = blockIdx.x / nx, step = gridDim.x / nx;
+    if ((PH & 2) && (op_mask & (2 | 8 | 16))) {
+        int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+        const int end = ixoff[x + 1];
+        for (int it = ixoff[x] + j * kInterWaves + wave; it < end; it += step * kInterWaves) {
+            const IntraItem item = intra[it];
+            const SolDev &S = sols[item.sol];
+            if (S.state[kStDone]) continue;
+            if (S.has_tw)
+                intra_group<true, false>(S, item, op_mask, nullptr, nullptr, region);
+            else
+                intra_group<false, false>(S, item, op_mask, nullptr, nullptr, region);
+        }
+    }
+    __syncthreads();  // the intra-route regions and the inter-route rows share LDS
     if ((PH & 1) && (op_mask & 7)) {
         const int end = xoff[x + 1];
         for (int it = xoff[x] + j; it < end; it += step) {
@@ -1427,19 +1443,6 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
                 else
                     inter_item<false, false, false>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
             }
-        }
-    }
-    if ((PH & 2) && (op_mask & (2 | 8 | 16))) {
-        int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
-        const int end = ixoff[x + 1];
-        for (int it = ixoff[x] + j * kInterWaves + wave; it < end; it += step * kInterWaves) {
-            const IntraItem item = intra[it];
-            const SolDev &S = sols[item.sol];
-            if (S.state[kStDone]) continue;
-            if (S.has_tw)
-                intra_group<true, false>(S, item, op_mask, nullptr, nullptr, region);
-            else
-                intra_group<false, false>(S, item, op_mask, nullptr, nullptr, region);
         }
     }
 }

@@ -5,8 +5,8 @@ A request is admitted when its device bytes (distance matrix, node data,
 instance and solution workspaces) fit in the HBM budget still free; its data
 are uploaded on a copy stream while the compute stream keeps stepping the
 requests already on the device.  Every engine tick runs one batched step
-(one persistent evaluation launch + one finalize launch) over all admitted
-requests; a request leaves when it reaches a local optimum or its cap, its
+(one persistent evaluation launch + one finalize launch; `steps_per_tick`
+of them if asked) over all admitted requests; a request leaves when it reaches a local optimum or its cap, its
 memory is returned, and queued requests are admitted.  Results do not depend
 on what else is in the batch: each solution's step only reads its own data.
 """
@@ -59,9 +59,10 @@ def device_bytes(inst, R: int) -> int:
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
-                 device: str = "cuda"):
+                 device: str = "cuda", steps_per_tick: int = 1):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
+        self.steps_per_tick = int(steps_per_tick)
         self.op_mask = op_mask
         self.device = device
         self.compute = torch.cuda.Stream(device=device)
@@ -70,6 +71,8 @@ class Server:
         self.peak_used = 0
         self.peak_active = 0
         self.ticks = 0
+        self.rebuilds = 0
+        self.rebuild_s = 0.0
 
     def _admit(self, req: ServeRequest, t0: float):
         with torch.cuda.stream(self.copy):
@@ -111,13 +114,17 @@ class Server:
                     time.sleep(max(0.0, min(0.001, pending[0].arrival_s - (time.perf_counter() - t0))))
                 continue
             if dirty:
+                tb = time.perf_counter()
                 if batch is not None:
                     batch.close()
                 with torch.cuda.stream(self.compute):
                     batch = tga.Batch([a["sol"] for a in active], stream=self.compute)
                 dirty = False
-            batch.step_part(0, self.op_mask, stream=self.compute)
-            batch.step_part(1, self.op_mask, stream=self.compute)
+                self.rebuilds += 1
+                self.rebuild_s += time.perf_counter() - tb
+            for _ in range(self.steps_per_tick):  # a finished solution skips the rest of a tick
+                batch.step_part(0, self.op_mask, stream=self.compute)
+                batch.step_part(1, self.op_mask, stream=self.compute)
             self.ticks += 1
             done = batch.poll(stream=self.compute)
             if done.any():

@@ -55,6 +55,17 @@ def test_mix_equals_alone_and_oracle(env):
         assert r.latency_s >= 0 and r.admitted_s >= req.arrival_s - 1e-3
 
 
+@pytest.mark.parametrize("steps_per_tick", [1, 7])
+def test_tick_length_does_not_change_results(env, steps_per_tick):
+    tga, serve = env
+    reqs = make_requests(serve, count=6, seed=4, max_steps=30)
+    res = serve.Server(hbm_budget_bytes=1 << 32, steps_per_tick=steps_per_tick).run(reqs)
+    for r, req in zip(res, reqs):
+        steps, moves, cost, off, cust = alone(tga, req)
+        assert (r.steps, r.moves, r.cost) == (steps, moves, cost), (steps_per_tick, r.rid)
+        assert r.customers.tolist() == cust.tolist()
+
+
 def test_admission_respects_budget(env):
     tga, serve = env
     reqs = make_requests(serve, count=8, seed=1, gap_s=0.0, max_steps=40)

@@ -639,8 +639,8 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
     while (launched < max_steps) {
         const int todo = std::min(chunk, max_steps - launched);
         for (int i = 0; i < todo; ++i) {
-            launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
-                        sol->lds, sol->nitems, nullptr, nullptr, st);
+            launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw,
+                        op_mask | kImprovingOnly, sol->lds, sol->nitems, nullptr, nullptr, st);
             k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask);
         }
         HIPCHK(hipGetLastError());
@@ -958,8 +958,11 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     return TGA_OK;
 }
 
-static void batch_eval_launch(tga_batch *B, uint32_t op_mask, hipStream_t st) {
+// `ls`: the evaluation feeds a local-search step (only an improving move can
+// be applied), see kImprovingOnly.
+static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream_t st) {
     if (!(op_mask & TGA_OP_ALL)) return;
+    if (ls) op_mask |= kImprovingOnly;
     if (!B->cfg.split) {
         k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
                                                                      B->ixoff, B->nx, op_mask);
@@ -978,7 +981,7 @@ static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipS
 }
 
 static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
-    batch_eval_launch(B, op_mask, st);
+    batch_eval_launch(B, op_mask, mode == kModeLS, st);
     batch_finalize_launch(B, op_mask, mode, st);
 }
 
@@ -1035,9 +1038,15 @@ extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launc
             c.us_per_eval = 0.f;
             B->cfg = c;
             if (batch_plan(B, P, st) != TGA_OK) continue;  // does not fit this device
-            batch_step(B, op_mask, kModeRecord, st);     // untimed
+            // local-search evaluations, each followed by a finalize that only
+            // records (and clears) the best move
+            auto step = [&]() {
+                batch_eval_launch(B, op_mask, true, st);
+                batch_finalize_launch(B, op_mask, kModeRecord, st);
+            };
+            step();  // untimed
             e = hipEventRecord(e0, st);
-            for (int i = 0; i < launches && e == hipSuccess; ++i) batch_step(B, op_mask, kModeRecord, st);
+            for (int i = 0; i < launches && e == hipSuccess; ++i) step();
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1164,7 +1173,7 @@ extern "C" int tga_batch_step_part(tga_batch_t B, uint32_t op_mask, int32_t part
     if (part != 0 && part != 1) return fail(TGA_EINVAL, "part must be 0 (evaluate) or 1 (finalize)");
     hipStream_t st = (hipStream_t)stream;
     if (part == 0)
-        batch_eval_launch(B, op_mask, st);
+        batch_eval_launch(B, op_mask, true, st);
     else
         batch_finalize_launch(B, op_mask, kModeLS, st);
     HIPCHK(hipGetLastError());

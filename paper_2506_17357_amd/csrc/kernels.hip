@@ -82,6 +82,17 @@ __device__ __forceinline__ int flagsof(int x) { return x >> 16; }
 // penalty of 2^30; every admissible delta is far below 2^29).
 constexpr int kAdmissibleBound = 1 << 29;
 
+// Internal operator-mask bit: the evaluation feeds a local-search step, which
+// applies the best move only when its delta is negative.  Lanes then start
+// from the bound (delta 0, no id): moves with a positive delta are never
+// evaluated in full, and the best improving move — the only one the step can
+// apply — is found exactly as before.
+constexpr uint32_t kImprovingOnly = 1u << 31;
+
+__device__ __forceinline__ int initial_bound(uint32_t op_mask) {
+    return (op_mask & kImprovingOnly) ? 0 : kAdmissibleBound;
+}
+
 __device__ __forceinline__ unsigned long long pack_key(int delta, uint32_t id) {
     return ((unsigned long long)((uint32_t)delta ^ 0x80000000u) << 32) | id;
 }
@@ -115,7 +126,7 @@ __device__ __forceinline__ void block_argmin_commit(int bd, uint32_t bid, unsign
                                     unsigned long long *red) {
     wave_argmin(bd, bid);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = bd >= kAdmissibleBound ? ~0ull : pack_key(bd, bid);
+    if (lane == 0) red[wave] = (bd >= kAdmissibleBound || bid == 0xFFFFFFFFu) ? ~0ull : pack_key(bd, bid);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = ~0ull;
@@ -918,7 +929,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
     DT *ring = (DT *)smem4;
     const DT *ringEnd = ring + NB * rs;
 
-    int bd = kAdmissibleBound;
+    int bd = initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
 
     // prologue: the distance rows of sub-block 0 (with its halo rows)
@@ -1282,7 +1293,7 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
                                             int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
                                             int *region) {
     const int lane = threadIdx.x & 63;
-    int bd = kAdmissibleBound;
+    int bd = initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
     const int l0 = S.has_tw ? S.node4[0].z : kTwOff;
     const int G = min(item.r1 - item.r0, kIntraMaxGroup);
@@ -1372,7 +1383,7 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
         }
     }
     wave_argmin(bd, bid);
-    if (lane == 0 && bd < kAdmissibleBound) atomicMin(S.best_key, pack_key(bd, bid));
+    if (lane == 0 && bd < kAdmissibleBound && bid != 0xFFFFFFFFu) atomicMin(S.best_key, pack_key(bd, bid));
 }
 
 template <bool TW, bool DUMP>

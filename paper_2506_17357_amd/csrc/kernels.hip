@@ -1015,6 +1015,17 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                         const int d4 = gR + gn + (L.c2s - ra.z);
                         const int m = min(min(d1, d2), min(d3, d4));
                         full = m <= thr && L.tyOwn >= ra.y;
+                        if (full) {
+                            // capacity screen: a move whose capacity condition
+                            // fails is inadmissible whatever its delta (most
+                            // screened-in moves late in a search are such)
+                            const int capA = cap - rb.x, capB = cap - rb.z;
+                            const int e1 = (capA - L.tb.z) >= 0 ? d1 : kNoDelta;
+                            const int e2 = (capB - L.tb.x) >= 0 ? d2 : kNoDelta;
+                            const int e3 = ((capB + rb.x - L.tb.x) | (capA - L.zx)) >= 0 ? d3 : kNoDelta;
+                            const int e4 = ((cap - rb.y - L.zy) | (capB + rb.y - L.tb.y)) >= 0 ? d4 : kNoDelta;
+                            full = min(min(e1, e2), min(e3, e4)) <= thr;
+                        }
                     }
                     if (full) {
                         int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);

@@ -133,7 +133,7 @@ long long count_items(int Q, int rows) {
 }
 
 struct SolLayout {
-    size_t desc, a4, b4, t4, w4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, best_key, rec,
+    size_t desc, a4, b4, t4, w4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, rblk, best_key, rec,
         state, acc, items, intra, total;
     int max_items;
 };
@@ -158,6 +158,7 @@ SolLayout sol_layout(int n, int R) {
     L.rdist = take(4 * std::max(R, 1));
     L.nr_alt = take(8 * S);
     L.roff_alt = take(4 * (R + 1));
+    L.rblk = take(4 * (size_t)kRouteBlockWords * std::max(R, 1));
     L.best_key = take(8);
     L.rec = take(32);
     L.state = take(4 * 16);
@@ -398,6 +399,7 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     h.rdist = (int32_t *)(base + L.rdist);
     h.nr_alt = (int2 *)(base + L.nr_alt);
     h.roff_alt = (int32_t *)(base + L.roff_alt);
+    h.rblk = (int32_t *)(base + L.rblk);
     h.best_key = (unsigned long long *)(base + L.best_key);
     h.rec = (int32_t *)(base + L.rec);
     h.state = (int32_t *)(base + L.state);
@@ -441,6 +443,7 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     if (e == hipSuccess) e = up(S->items, items.data(), sizeof(InterItem) * items.size());
     if (e == hipSuccess) e = up(S->intra, intra.data(), sizeof(IntraItem) * intra.size());
     if (e == hipSuccess) {
+        k_route_blocks_clear<<<(R + 255) / 256, 256, 0, st>>>(h.rblk, R);
         k_build<<<1, kApplyThreads, 0, st>>>(S->d);
         e = hipGetLastError();
     }
@@ -486,6 +489,7 @@ extern "C" int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, c
     HIPCHK(hipMemcpyAsync(sol->h.nr_alt, nr.data(), sizeof(int2) * (Q + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(sol->h.roff_alt, roff.data(), sizeof(int32_t) * (R + 1), hipMemcpyHostToDevice, st));
     k_reset_state<<<1, 64, 0, st>>>(sol->d, 1, 0);
+    k_route_blocks_clear<<<(R + 255) / 256, 256, 0, st>>>(sol->h.rblk, R);  // start cold, as a new solution
     k_build<<<1, kApplyThreads, 0, st>>>(sol->d);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));

@@ -1133,8 +1133,12 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
 #pragma unroll 1
     for (int i = i0; i <= L; i += di) {
         const int eP = V.edge(i - 1);  // c(c_{i-1}, c_i)
+        const int eI = V.edge(i);      // c(c_i, c_{i+1})
         const int depP = TW ? V.dep(i - 1) : 0;
         const uint32_t refI = ref(i);
+        // Every step computes the deltas (and carries the segment summaries
+        // along); feasibility, ids and the running minimum are evaluated
+        // only where a delta can still reach the lane's best.
         // ---- 2OPT(i, j) and SWAP(i, j), j > i
         if (op2o || opSwap) {
             Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};
@@ -1145,16 +1149,17 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
                 if (TW) rev = seg_cat(segAt(j), ejm, rev);
                 const int d1 = V.dd(i - 1, j), d2 = V.dd(i, j + 1);
                 const int dlt2 = d1 + d2 - eP - ej;
-                bool tw2 = true;
-                if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
-                const uint32_t refJ = ref(j);
-                const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
-                int dS = dlt2;
-                bool twS = tw2;
+                int dS = dlt2, dA = 0, dB = 0;
                 if (j > i + 1) {
-                    const int dA = V.dd(j, i + 1), dB = V.dd(j - 1, i);
-                    dS = d1 + dA + dB + d2 - eP - V.edge(i) - ejm - ej;
-                    if (TW) {
+                    dA = V.dd(j, i + 1);
+                    dB = V.dd(j - 1, i);
+                    dS = d1 + dA + dB + d2 - eP - eI - ejm - ej;
+                }
+                if (DUMP || (capOK && min(op2o ? dlt2 : kNoDelta, opSwap ? dS : kNoDelta) <= bd)) {
+                    bool tw2 = true;
+                    if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
+                    bool twS = tw2;
+                    if (TW && j > i + 1) {
                         const int arr0 = depP + d1;
                         bool ok = arr0 <= V.l(j);
                         const int t0 = max(arr0, V.e(j)) + V.s(j);
@@ -1164,22 +1169,24 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
                         const int t2 = max(arrI, V.e(i)) + V.s(i);
                         twS = ok && (t2 + d2 <= V.z(j + 1));
                     }
-                }
-                if (op2o) {
-                    const uint32_t id = (12u * uQ + lo) * uQ + hi;
-                    if (DUMP) {
-                        dump_delta[id] = dlt2;
-                        dump_feas[id] = (uint8_t)(capOK | (tw2 << 1));
+                    const uint32_t refJ = ref(j);
+                    const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
+                    if (op2o) {
+                        const uint32_t id = (12u * uQ + lo) * uQ + hi;
+                        if (DUMP) {
+                            dump_delta[id] = dlt2;
+                            dump_feas[id] = (uint8_t)(capOK | (tw2 << 1));
+                        }
+                        if (capOK && tw2) consider(dlt2, id, bd, bid);
                     }
-                    if (capOK && tw2) consider(dlt2, id, bd, bid);
-                }
-                if (opSwap) {
-                    const uint32_t id = (5u * uQ + lo) * uQ + hi;
-                    if (DUMP) {
-                        dump_delta[id] = dS;
-                        dump_feas[id] = (uint8_t)(capOK | (twS << 1));
+                    if (opSwap) {
+                        const uint32_t id = (5u * uQ + lo) * uQ + hi;
+                        if (DUMP) {
+                            dump_delta[id] = dS;
+                            dump_feas[id] = (uint8_t)(capOK | (twS << 1));
+                        }
+                        if (capOK && twS) consider(dS, id, bd, bid);
                     }
-                    if (capOK && twS) consider(dS, id, bd, bid);
                 }
                 // middle c_{i+1} .. c_j for the next j
                 if (TW) mid = (j == i + 1) ? segAt(j) : seg_cat(mid, ejm, segAt(j));
@@ -1207,18 +1214,20 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
                 if (TW) mid = (j == w) ? segAt(j) : seg_cat(mid, V.edge(j - 1), segAt(j));
                 const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
                 const int dlt = base + dVF + dGV - V.edge(j);
-                bool tw = true;
-                if (TW) {
-                    const int dm = seg_pass(mid, depP + dPW);
-                    const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
-                    tw = ds < kInf && ds + dGV <= V.z(j + 1);
+                if (DUMP || (capOK && dlt <= bd)) {
+                    bool tw = true;
+                    if (TW) {
+                        const int dm = seg_pass(mid, depP + dPW);
+                        const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
+                        tw = ds < kInf && ds + dGV <= V.z(j + 1);
+                    }
+                    const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
+                    if (DUMP) {
+                        dump_delta[id] = dlt;
+                        dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                    }
+                    if (capOK && tw) consider(dlt, id, bd, bid);
                 }
-                const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
-                if (DUMP) {
-                    dump_delta[id] = dlt;
-                    dump_feas[id] = (uint8_t)(capOK | (tw << 1));
-                }
-                if (capOK && tw) consider(dlt, id, bd, bid);
             }
             // ---- backward: right after c_j, j <= i-2 (middle c_{j+1} .. c_{i-1})
             const int zW = TW ? V.z(w) : 0;
@@ -1228,18 +1237,20 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
                 if (TW) mid = (j == i - 2) ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
                 const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
                 const int dlt = base + dVF + dGV - V.edge(j);
-                bool tw = true;
-                if (TW) {
-                    const int ds = seg_pass(sig, V.dep(j) + dVF);
-                    const int dmm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
-                    tw = dmm < kInf && dmm + dPW <= zW;
+                if (DUMP || (capOK && dlt <= bd)) {
+                    bool tw = true;
+                    if (TW) {
+                        const int ds = seg_pass(sig, V.dep(j) + dVF);
+                        const int dmm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
+                        tw = dmm < kInf && dmm + dPW <= zW;
+                    }
+                    const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
+                    if (DUMP) {
+                        dump_delta[id] = dlt;
+                        dump_feas[id] = (uint8_t)(capOK | (tw << 1));
+                    }
+                    if (capOK && tw) consider(dlt, id, bd, bid);
                 }
-                const uint32_t id = ((16u + k) * uQ + refI) * uQ + ref(j);
-                if (DUMP) {
-                    dump_delta[id] = dlt;
-                    dump_feas[id] = (uint8_t)(capOK | (tw << 1));
-                }
-                if (capOK && tw) consider(dlt, id, bd, bid);
             }
         }
     }
@@ -1276,13 +1287,83 @@ __device__ __forceinline__ RouteLds stage_route(const SolDev &S, int off, int L,
     return RouteLds{pn, pe, pdep, pz, pe_, pl, ps, dm, P};
 }
 
-__device__ __forceinline__ void stage_dist_block(const SolDev &S, const RouteLds &V) {
+constexpr int kIntraMaxGroup = 8;  // routes per intra-route work item
+constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while staging
+
+// The P x P distance sub-blocks of G staged routes (route k = r0 + k: P[k]
+// positions, staged at word offset at[k] of the region, nodes first):
+// element y of route k's block is D[node(y / P)][node(y % P)].  A route whose
+// cache entry holds the same P and nodes copies its block from there
+// (contiguous loads); any other route gathers it from D and, when
+// P <= kRouteBlockMaxP, rewrites its entry.  Each lane keeps up to
+// kGatherBatch loads in flight before it stores them, so a group costs a
+// couple of memory round trips.
+__device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],
+                                                  const int (&at)[kIntraMaxGroup], int G, int r0) {
     const int lane = threadIdx.x & 63;
-    const int P = V.stride, np1 = S.np1;
-    int *dm = (int *)V.dm;
-    for (int x = lane; x < P * P; x += 64) {
-        const int p = x / P, q = x - p * P;
-        dm[x] = gld(S.D + (size_t)V.pn[p] * np1 + V.pn[q]);
+    int cum[kIntraMaxGroup + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) cum[k + 1] = cum[k] + (k < G ? P[k] * P[k] : 0);
+    const int E = cum[kIntraMaxGroup];
+    // which routes' cached blocks are current (bit k), and which entries to rewrite
+    uint32_t hit = 0, fill = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if (k < G && P[k] <= kRouteBlockMaxP) {
+            const int *c = S.rblk + (size_t)(r0 + k) * kRouteBlockWords;
+            const bool same = lane >= P[k] || gld(c + kRouteBlockNodes + lane) == region[at[k] + lane];
+            const bool ok = __builtin_amdgcn_readfirstlane(gld(c)) == P[k] && __builtin_amdgcn_ballot_w64(!same) == 0;
+            hit |= (ok ? 1u : 0u) << k;
+            fill |= (ok ? 0u : 1u) << k;
+        }
+    }
+    for (int x0 = 0; x0 < E; x0 += 64 * kGatherBatch) {
+        int val[kGatherBatch], dst[kGatherBatch], cst[kGatherBatch];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) {
+            const int x = x0 + u * 64 + lane;
+            dst[u] = -1;
+            cst[u] = -1;
+            val[u] = 0;
+            if (x < E) {
+                int k = 0, c = 0, pk = P[0], ak = at[0];
+#pragma unroll
+                for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
+                    if (kk < G && x >= cum[kk]) {
+                        k = kk;
+                        c = cum[kk];
+                        pk = P[kk];
+                        ak = at[kk];
+                    }
+                }
+                const int y = x - c;
+                const int ce = (r0 + k) * kRouteBlockWords + kRouteBlockData + y;  // cache word of element y
+                if ((hit >> k) & 1) {
+                    val[u] = gld(S.rblk + ce);
+                } else {
+                    const int pp = y / pk, qq = y - pp * pk;
+                    const int *pn = region + ak;
+                    val[u] = gld(S.D + (size_t)pn[pp] * S.np1 + pn[qq]);
+                    if ((fill >> k) & 1) cst[u] = ce;
+                }
+                dst[u] = ak + 7 * pk + y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) {
+            if (dst[u] >= 0) region[dst[u]] = val[u];
+            if (cst[u] >= 0) S.rblk[cst[u]] = val[u];
+        }
+    }
+    // entries rewritten above: their nodes, then P
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if ((fill >> k) & 1) {
+            int *c = S.rblk + (size_t)(r0 + k) * kRouteBlockWords;
+            if (lane < P[k]) c[kRouteBlockNodes + lane] = region[at[k] + lane];
+            if (lane == 0) c[0] = P[k];
+        }
     }
 }
 
@@ -1291,8 +1372,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-constexpr int kIntraMaxGroup = 8;  // routes per intra-route work item
 
 // One wavefront evaluates every intra-route move of routes [r0, r1) of one
 // solution and commits the best to the solution's key.  When all their
@@ -1332,19 +1411,15 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
             }
         }
         wave_lds_sync();
-        base = region;
+        {
+            int Pk[kIntraMaxGroup], at[kIntraMaxGroup], w = 0;
 #pragma unroll
-        for (int k = 0; k < kIntraMaxGroup; ++k) {
-            if (k < G) {
-                const int L = offs[k + 1] - offs[k] - 1, P = L + 2;
-                const int *pn = base;
-                int *dm = base + 7 * P;
-                for (int x = lane; x < P * P; x += 64) {
-                    const int p = x / P, q = x - p * P;
-                    dm[x] = gld(S.D + (size_t)pn[p] * S.np1 + pn[q]);
-                }
-                base += 7 * P + P * P;
+            for (int k = 0; k < kIntraMaxGroup; ++k) {
+                Pk[k] = k < G ? offs[k + 1] - offs[k] + 1 : 0;
+                at[k] = w;
+                w += 7 * Pk[k] + Pk[k] * Pk[k];
             }
+            stage_dist_blocks(S, region, Pk, at, G, item.r0);
         }
         wave_lds_sync();
         // lane -> (route k, first position i) and that route's staged view
@@ -1383,7 +1458,15 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
             if (7 * P + P * P <= kIntraRegionBytes / 4) {
                 const RouteLds V = stage_route<TW>(S, off, L, l0, region);
                 wave_lds_sync();
-                stage_dist_block(S, V);
+                {
+                    int Pk[kIntraMaxGroup], at[kIntraMaxGroup];
+#pragma unroll
+                    for (int k = 0; k < kIntraMaxGroup; ++k) {
+                        Pk[k] = k == 0 ? P : 0;
+                        at[k] = 0;
+                    }
+                    stage_dist_blocks(S, region, Pk, at, 1, r);
+                }
                 wave_lds_sync();
                 intra_moves<TW, DUMP>(S, V, r, L, lane + 1, 64, capOK, op_mask, dump_delta, dump_feas, bd, bid);
                 wave_lds_sync();
@@ -1757,6 +1840,12 @@ __global__ __launch_bounds__(256) void k_check_nodes(const int4 *__restrict__ nd
     }
     if (bad) atomicOr(&out[0], 8);
     atomicMax(&out[5], q.x);
+}
+
+// Marks every route's distance-block cache entry empty.
+__global__ void k_route_blocks_clear(int32_t *rblk, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) rblk[(size_t)r * kRouteBlockWords] = -1;
 }
 
 __global__ void k_zero_i32(int32_t *p, int count) {

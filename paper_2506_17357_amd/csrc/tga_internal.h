@@ -47,6 +47,8 @@ struct SolDev {
     // apply / build staging
     int2 *nr_alt;     // Q+1 {node, route} of the next layout
     int32_t *roff_alt;// R+1
+    // per route: the route's distance sub-block as last staged (see kRouteBlock*)
+    int32_t *rblk;
     // per-solution state
     unsigned long long *best_key;  // running minimum of (delta, id) keys
     int32_t *rec;     // 8 ints: the tga_move_t of the last finalize
@@ -77,7 +79,19 @@ enum {
 // row 16-byte aligned.
 constexpr int stride16_of(int np1) { return (np1 + 7) & ~7; }
 
-constexpr int kMaxXcds = 8;  // accelerator dies (each with its own L2) the batched items are spread over
+constexpr int kMaxXcds = 8;
+
+// Route distance-block cache, one entry of kRouteBlockWords ints per route:
+// {P, unused, node of positions 0..P-1 (kRouteBlockMaxP slots), the P x P
+// block D[node(p)][node(q)] row-major}.  An entry is used only when P and
+// every node equal the route's current ones, so it never needs to be
+// invalidated; P = -1 marks an empty entry.  Routes with more than
+// kRouteBlockMaxP positions are not cached.
+constexpr int kRouteBlockMaxP = 40;
+constexpr int kRouteBlockNodes = 2;
+constexpr int kRouteBlockData = kRouteBlockNodes + kRouteBlockMaxP;
+constexpr int kRouteBlockWords = 1664;  // >= kRouteBlockData + kRouteBlockMaxP^2, a multiple of 64
+static_assert(kRouteBlockData + kRouteBlockMaxP * kRouteBlockMaxP <= kRouteBlockWords, "route block entry");  // accelerator dies (each with its own L2) the batched items are spread over
 
 struct InterItem {  // row slots [s0, s1) of solution `sol`
     int32_t sol, s0, s1, pad;

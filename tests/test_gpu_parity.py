@@ -156,6 +156,47 @@ def test_dump_long_routes(tga):
     check_dump(tga, inst, sol, tag="long")
 
 
+@pytest.mark.parametrize("has_tw", [0, 1])
+def test_route_block_cache_follows_route_changes(tga, has_tw):
+    """Intra-route distance blocks cached per route are reused only for the
+    same nodes in the same order.  Routes are reordered in place and
+    customers exchanged between routes of equal length, by applied moves
+    (the cache then holds the old routes) and by reloads; every state is
+    compared with the oracle."""
+    inst = W.tiny_instance(240, 77 + has_tw, bool(has_tw), capacity=10 ** 6, span=1000)
+    if has_tw:
+        inst.node4[:, 2] = np.maximum(inst.node4[:, 2], 1 << 20)
+        inst.node4[0, 2] = 1 << 22
+    off = np.arange(0, 241, 20, dtype=np.int32)  # 12 routes of 20 customers (22 positions, cached)
+    rng = np.random.Generator(np.random.PCG64(5))
+    cust_a = rng.permutation(np.arange(1, 241)).astype(np.int32)
+    cust_b = cust_a.copy()
+    cust_b[0:20] = cust_b[0:20][::-1]                  # route 0 reversed
+    cust_b[40:60], cust_b[80:100] = cust_a[80:100], cust_a[40:60]  # routes 2 and 4 exchanged
+    cust_b[120:140] = np.roll(cust_b[120:140], 3)      # route 6 rotated
+    A, B = W.Solution(off, cust_a), W.Solution(off, cust_b)
+    I, S = gpu_solution(tga, inst, A)
+
+    def same_as_oracle(sol, tag):
+        ob, odd, odf = oracle.eval_neighbourhood(inst, sol, 0x1F, dump=True, threads=0)
+        gb, gdd, gdf = S.eval(0x1F, dump=True)
+        assert np.array_equal(gdf.cpu().numpy(), odf), tag
+        assert np.array_equal(gdd.cpu().numpy(), odd), tag
+        assert (gb.delta, gb.id) == (ob.delta, ob.id), tag
+        m = S.eval()  # the non-dump path skips moves that cannot win
+        assert (m.delta, m.id) == (ob.delta, ob.id), tag
+        return m
+
+    for tag, sol in [("a", A), ("b", B), ("a again", A)]:
+        S.reload(sol.offsets, sol.customers)
+        cur = sol
+        for step in range(4):  # applied moves rewrite one or two routes each
+            m = same_as_oracle(cur, "%s step %d" % (tag, step))
+            S.apply(m)
+            cur = oracle.apply_move(inst, cur, m.id)
+        same_as_oracle(cur, tag + " end")
+
+
 def test_c1_trajectory_step_by_step(tga):
     inst, sol = W.c1()
     _, ids, deltas, _ = oracle.local_search(inst, sol, max_steps=100)

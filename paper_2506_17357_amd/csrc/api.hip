@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <queue>
 #include <vector>
 
 #include "tga.h"
@@ -205,8 +206,8 @@ struct tga_batch {
     int nitems;
     IntraItem *intra;
     int nintra;
-    int *xoff;      // device: inter item list of XCD x = items[xoff[x] .. xoff[x+1])
-    int *ixoff;     // device: the same for intra-route groups
+    int *woff;      // device: inter items of workgroup b = items[woff[b] .. woff[b+1])
+    int *ixoff;     // device: intra-route groups of XCD x = intra[ixoff[x] .. ixoff[x+1])
     int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
     size_t lds;
@@ -729,7 +730,7 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     *desc = take(sizeof(SolDev) * sols.size());
     *items = take(sizeof(InterItem) * std::max(max_items, 1));
     *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    *sched = take(4 * 2 * (kMaxXcds + 1) + 4 * sols.size());  // item list offsets, then done flags
+    *sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * sols.size());  // item list offsets, then done flags
     return off;
 }
 
@@ -857,14 +858,34 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         }
         for (const auto &g : groups) xintra[rr++ % nx].push_back(g);
     }
-    std::vector<int> xoff(nx + 1, 0), ixoff(nx + 1, 0);
+    // Within an XCD, items go to its workgroups longest first, each to the
+    // workgroup with the least estimated work so far (pairs, TW items
+    // weighted 1.1, plus a fixed cost per item for staging its rows).
+    if (grid_inter > kMaxBatchGrid) return fail(TGA_ERANGE, "batch grid of %d workgroups", grid_inter);
+    auto cost = [&](const InterItem &a) {
+        return (double)work(a) * (v[a.sol]->h.has_tw ? 1.1 : 1.0) + 3000.0;
+    };
+    const int per_x = grid_inter / nx;
+    std::vector<std::vector<InterItem>> wl(grid_inter);
+    std::vector<int> woff(grid_inter + 1, 0), ixoff(nx + 1, 0);
     for (int x = 0; x < nx; ++x) {
         std::stable_sort(xitems[x].begin(), xitems[x].end(),
                          [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
-        items.insert(items.end(), xitems[x].begin(), xitems[x].end());
+        std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>,
+                            std::greater<std::pair<double, int>>> heap;
+        for (int j = 0; j < per_x; ++j) heap.push({0.0, j});
+        for (const auto &it : xitems[x]) {
+            auto top = heap.top();
+            heap.pop();
+            wl[x + top.second * nx].push_back(it);
+            heap.push({top.first + cost(it), top.second});
+        }
         intra.insert(intra.end(), xintra[x].begin(), xintra[x].end());
-        xoff[x + 1] = (int)items.size();
         ixoff[x + 1] = (int)intra.size();
+    }
+    for (int b = 0; b < grid_inter; ++b) {
+        items.insert(items.end(), wl[b].begin(), wl[b].end());
+        woff[b + 1] = (int)items.size();
     }
     if ((int)items.size() > B->max_items || (int)intra.size() > B->max_intra)
         return fail(TGA_ERANGE, "batch schedule exceeds its workspace");
@@ -890,7 +911,8 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         e = hipMemcpyAsync(B->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !intra.empty())
         e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->xoff, xoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->woff, woff.data(), sizeof(int) * (grid_inter + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->ixoff, ixoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -946,9 +968,9 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->max_items = max_items;
     B->intra = (IntraItem *)(base + ointra);
     B->max_intra = nintra;
-    B->xoff = (int *)(base + osched);
-    B->ixoff = B->xoff + (kMaxXcds + 1);
-    B->done = B->xoff + 2 * (kMaxXcds + 1);
+    B->woff = (int *)(base + osched);
+    B->ixoff = B->woff + (kMaxBatchGrid + 1);
+    B->done = B->ixoff + (kMaxXcds + 1);
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
@@ -968,16 +990,16 @@ static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream
     if (!(op_mask & TGA_OP_ALL)) return;
     if (ls) op_mask |= kImprovingOnly;
     if (!B->cfg.split) {
-        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
+        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
                                                                      B->ixoff, B->nx, op_mask);
         return;
     }
     if (op_mask & 7)
-        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->xoff, B->intra,
+        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
                                                                      B->ixoff, B->nx, op_mask);
     if (op_mask & (2 | 8 | 16))
         k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
-            B->d, B->items, B->xoff, B->intra, B->ixoff, B->nx, op_mask);
+            B->d, B->items, B->woff, B->intra, B->ixoff, B->nx, op_mask);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {

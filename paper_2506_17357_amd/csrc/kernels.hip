@@ -1503,14 +1503,15 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 // inter-route items fill the tail; PH = 1 and PH = 2 are the two halves as
 // separate launches.
 // Solutions of both problem types and both distance widths share a launch;
-// each item takes the path of its own solution.  Static schedule: the items
-// are split into nx lists, one per XCD, and workgroup b (dispatched to XCD
-// b mod nx) takes items j, j + G', j + 2G', ... of list b mod nx, where
-// j = b / nx and G' = gridDim.x / nx; its wavefronts do the same with the
-// intra-route groups.
+// each item takes the path of its own solution.  Static schedule planned on
+// the host: workgroup b (dispatched to XCD b mod nx) takes the inter-route
+// items items[woff[b] .. woff[b + 1]) (all of solutions placed on that XCD);
+// its wavefronts take the intra-route groups j * 8 + wave, then every
+// (G' * 8)-th after it, of the XCD's group list, where j = b / nx and
+// G' = gridDim.x / nx.
 template <int PH>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
-    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ xoff,
+    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ woff,
     const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx, uint32_t op_mask) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
@@ -1532,8 +1533,8 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
     __syncthreads();  // the intra-route regions and the inter-route rows share LDS
     if ((PH & 1) && (op_mask & 7)) {
-        const int end = xoff[x + 1];
-        for (int it = xoff[x] + j; it < end; it += step) {
+        const int end = woff[blockIdx.x + 1];
+        for (int it = woff[blockIdx.x]; it < end; ++it) {
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;

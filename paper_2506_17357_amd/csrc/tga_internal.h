@@ -79,7 +79,8 @@ enum {
 // row 16-byte aligned.
 constexpr int stride16_of(int np1) { return (np1 + 7) & ~7; }
 
-constexpr int kMaxXcds = 8;
+constexpr int kMaxXcds = 8;  // accelerator dies (each with its own L2) the batched items are spread over
+constexpr int kMaxBatchGrid = 4096;  // workgroups of one batched evaluation launch
 
 // Route distance-block cache, one entry of kRouteBlockWords ints per route:
 // {P, unused, node of positions 0..P-1 (kRouteBlockMaxP slots), the P x P

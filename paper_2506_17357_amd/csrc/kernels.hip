@@ -58,6 +58,14 @@ __device__ __forceinline__ int4 sld(const int4 *p) {
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
+// The same at a byte offset from p (one scalar load with an offset register).
+__device__ __forceinline__ int4 sld_at(const int4 *p, uint32_t byte_off) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(4))) char *b = (const __attribute__((address_space(4))) char *)p;
+    const v4i v = *(const __attribute__((address_space(4))) v4i *)(b + byte_off);
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 template <class T>
 __device__ __forceinline__ void gst(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
@@ -991,58 +999,71 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 pp += rs;
                 if (pp == ringEnd) pp = ring;
                 int gn = pp[L.node];
-                int4 ra = sld(S.a4 + x), rb = sld(S.b4 + x);
+                uint32_t ro = (uint32_t)x * 16u;  // byte offset of row x's slot attributes
+                int4 ra = sld_at(S.a4, ro), rb = sld_at(S.b4, ro);
                 const int thrRun = DUMP ? 0 : __hip_atomic_load(thr_sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 // Each pass first consumes what the previous one fetched, then
                 // fetches row x + 1 (attributes) and the gather of row x + 2,
                 // then evaluates row x from registers (the rare full
-                // evaluation also reads the row's time attributes).
-                while (routeLast > ra.y) {
+                // evaluation also reads the row's time attributes).  Passes
+                // go in pairs so that the two sets of row attributes take
+                // turns without copies.
+                auto pass = [&](const int4 &rA, const int4 &rB, int4 &rAn, int4 &rBn, int wp, int w0, int wn,
+                                int &wnn) {
                     pp += rs;
                     if (pp == ringEnd) pp = ring;
-                    const int gnn = pp[L.node];  // row x + 2 (past the halo on the last row: unused)
-                    const int xn = min(x + 1, Q);
-                    const int4 ran = sld(S.a4 + xn), rbn = sld(S.b4 + xn);
-                    const int gR = from_next_lane(g);  // D[s][succ(t)]
-                    const int gL = from_prev_lane(g);  // D[s][pred(t)]
+                    wnn = pp[L.node];  // row x + 2 (past the halo on the last row: unused)
+                    rAn = sld_at(S.a4, ro + 16u);  // x + 1 <= Q
+                    rBn = sld_at(S.b4, ro + 16u);
+                    const int gR = from_next_lane(w0);  // D[s][succ(t)]
+                    const int gL = from_prev_lane(w0);  // D[s][pred(t)]
                     bool full = true;
-                    int thr = 0;
                     if (!DUMP) {
-                        thr = min(bd, thrRun);
-                        const int d1 = g + gR + (L.cRel + ra.w);
-                        const int d2 = g + gn + (L.cRel2 - ra.z);
-                        const int d3 = (gp + gn) + (gL + gR) + (L.cSwap - rb.w);
-                        const int d4 = gR + gn + (L.c2s - ra.z);
+                        const int thr = min(bd, thrRun);
+                        const int d1 = w0 + gR + (L.cRel + rA.w);
+                        const int d2 = w0 + wn + (L.cRel2 - rA.z);
+                        const int d3 = (wp + wn) + (gL + gR) + (L.cSwap - rB.w);
+                        const int d4 = gR + wn + (L.c2s - rA.z);
                         const int m = min(min(d1, d2), min(d3, d4));
-                        full = m <= thr && L.tyOwn >= ra.y;
+                        full = m <= thr && L.tyOwn >= rA.y;
                         if (full) {
                             // capacity screen: a move whose capacity condition
                             // fails is inadmissible whatever its delta (most
                             // screened-in moves late in a search are such)
-                            const int capA = cap - rb.x, capB = cap - rb.z;
+                            const int capA = cap - rB.x, capB = cap - rB.z;
                             const int e1 = (capA - L.tb.z) >= 0 ? d1 : kNoDelta;
                             const int e2 = (capB - L.tb.x) >= 0 ? d2 : kNoDelta;
-                            const int e3 = ((capB + rb.x - L.tb.x) | (capA - L.zx)) >= 0 ? d3 : kNoDelta;
-                            const int e4 = ((cap - rb.y - L.zy) | (capB + rb.y - L.tb.y)) >= 0 ? d4 : kNoDelta;
+                            const int e3 = ((capB + rB.x - L.tb.x) | (capA - L.zx)) >= 0 ? d3 : kNoDelta;
+                            const int e4 = ((cap - rB.y - L.zy) | (capB + rB.y - L.tb.y)) >= 0 ? d4 : kNoDelta;
                             full = min(min(e1, e2), min(e3, e4)) <= thr;
                         }
                     }
                     if (full) {
                         int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
                         if (TW) {
-                            rt = sld(S.t4 + x);
-                            rw = sld(S.w4 + x);
+                            rt = sld_at(S.t4, ro);
+                            rw = sld_at(S.w4, ro);
                         }
-                        const RowVals R = row_vals(ra, rb, cap, n);
-                        pair_moves<TW, DUMP>(L, R, rt, rw, gp, g, gn, gR, gL, uQ, opRel, opSwap, op2s, dump_delta,
+                        const RowVals R = row_vals(rA, rB, cap, n);
+                        pair_moves<TW, DUMP>(L, R, rt, rw, wp, w0, wn, gR, gL, uQ, opRel, opSwap, op2s, dump_delta,
                                              dump_feas, bd, bid);
                     }
-                    if (++x >= xend) break;
-                    ra = ran;
-                    rb = rbn;
-                    gp = g;
-                    g = gn;
-                    gn = gnn;
+                    ++x;
+                    ro += 16u;
+                };
+                int4 ra2, rb2;
+                int g3 = 0;
+                bool more = routeLast > ra.y;
+                while (more) {
+                    pass(ra, rb, ra2, rb2, gp, g, gn, g3);
+                    more = x < xend && routeLast > ra2.y;
+                    if (!more) break;
+                    pass(ra2, rb2, ra, rb, g, gn, g3, gp);
+                    const int w1 = gn;  // window (rows x - 1, x, x + 1) back in gp, g, gn
+                    gn = gp;
+                    gp = w1;
+                    g = g3;
+                    more = x < xend && routeLast > ra.y;
                 }
                 // publish this wavefront's best to the workgroup (one lane, one
                 // LDS atomic, only when some lane improved on the shared value)

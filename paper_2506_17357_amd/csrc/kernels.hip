@@ -638,9 +638,9 @@ typedef __attribute__((address_space(3))) void *lds_void_ptr;
 typedef __attribute__((address_space(1))) void *global_void_ptr;
 
 // lane i receives lane i+1 (lane 63 receives 0)
-__device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
 // lane i receives lane i-1 (lane 0 receives 0)
-__device__ __forceinline__ int from_prev_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int from_prev_lane(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
 
 // Column-side (lane) values of one chunk, kept in registers while the
 // wavefront walks rows against it.  Every feasibility condition below is

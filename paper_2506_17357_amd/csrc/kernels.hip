@@ -722,25 +722,25 @@ __device__ __forceinline__ void col_setup(const SolDev &S, int cb, const ColRaw 
     routeLast = __builtin_amdgcn_readfirstlane(lastLane >= 1 ? rl : -1);
 }
 
-// ---- LDS ring of distance rows of an inter-route item.  Slot x of the item
-// starting at row s0 (x >= s0 - 1) sits at ring position (x - s0 + 1) mod NB;
-// slots outside [0, Q] are read clamped.
-
-__device__ __forceinline__ int ring_pos(int x, int s0, int N) { return (x - s0 + 1) % N; }
+// ---- LDS block of distance rows of an inter-route item.  While the rows of
+// a sub-block starting at row sb are evaluated, slot x (sb - 1 <= x <= the
+// sub-block's last row + 1) sits at row position x - sb + 1; slots outside
+// [0, Q] are read clamped.
 
 // Distance rows of slots [x0, x0 + cnt) copied straight from HBM into the
-// ring (global_load_lds, one dword per lane), from the 16-bit copy of D when
-// W16.  The issuing wavefront must wait (vmcnt) before a barrier publishes
-// them.  `wave` is the wavefront index (uniform).
+// block (global_load_lds, one dword per lane), slot `base` at position 0,
+// from the 16-bit copy of D when W16.  The issuing wavefront must wait
+// (vmcnt) before a barrier publishes them.  `wave` is the wavefront index
+// (uniform).
 template <bool W16>
-__device__ __forceinline__ void drow_issue(const SolDev &S, void *ring, int NB, int s0, int x0, int cnt, int wave) {
+__device__ __forceinline__ void drow_issue(const SolDev &S, void *ring, int base, int x0, int cnt, int wave) {
     const int lane = threadIdx.x & 63;
     const int words = W16 ? S.stride16 / 2 : S.np1;  // dwords per row
     for (int r = wave; r < cnt; r += kInterWaves) {
         const int x = x0 + r;
         const int node = nodeof(sld(S.a4 + min(max(x, 0), S.Q)).x);
         const int *src = W16 ? (const int *)(S.D16 + (size_t)node * S.stride16) : S.D + (size_t)node * S.np1;
-        int *dst = (int *)ring + ring_pos(x, s0, NB) * words;
+        int *dst = (int *)ring + (x - base) * words;
         for (int c = 0; c < words; c += 64) {
             if (c + lane < words)
                 __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
@@ -935,7 +935,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
     const int NB = h + 2;
     const int rs = W16 ? S.stride16 : np1;  // ring row stride (elements)
     DT *ring = (DT *)smem4;
-    const DT *ringEnd = ring + NB * rs;
+    const DT *ringLast = ring + (NB - 1) * rs;  // the last row position
 
     int bd = initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
@@ -943,7 +943,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
     // prologue: the distance rows of sub-block 0 (with its halo rows)
     __syncthreads();  // the previous item is done with LDS
     if (!DUMP && threadIdx.x == 0) *thr_sh = committed_delta(S);
-    drow_issue<W16>(S, ring, NB, s0, s0 - 1, min(h, s1 - s0) + 2, wave);
+    drow_issue<W16>(S, ring, s0 - 1, s0 - 1, min(h, s1 - s0) + 2, wave);
     __builtin_amdgcn_s_waitcnt(0);
 
     ColRaw nxt;  // column attributes fetched ahead for the chunk at nxt_cb
@@ -952,8 +952,8 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         const int sb = s0 + i * h;
         const int nr = min(h, s1 - sb);  // rows of this sub-block
         __syncthreads();                 // rows of sub-block i resident (i = 0), or i - 1 consumed
-        if (i > 0) {                     // rows sb - 1 and sb are already there
-            drow_issue<W16>(S, ring, NB, s0, sb + 1, nr, wave);
+        if (i > 0) {                     // the rows of sub-block i with its halo rows
+            drow_issue<W16>(S, ring, sb - 1, sb - 1, nr + 2, wave);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
@@ -990,14 +990,12 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 col_setup(S, cb, cur, op_mask, L, routeLast);
                 int x = sb + r0;  // row slot
                 const int xend = sb + r1;
-                // register window over the distance ring: rows x - 1, x, x + 1
-                const DT *pp = ring + ring_pos(x - 1, s0, NB) * rs;
+                // register window over the distance rows: x - 1, x, x + 1
+                const DT *pp = ring + (x - sb) * rs;
                 int gp = pp[L.node];
                 pp += rs;
-                if (pp == ringEnd) pp = ring;
                 int g = pp[L.node];
                 pp += rs;
-                if (pp == ringEnd) pp = ring;
                 int gn = pp[L.node];
                 uint32_t ro = (uint32_t)x * 16u;  // byte offset of row x's slot attributes
                 int4 ra = sld_at(S.a4, ro), rb = sld_at(S.b4, ro);
@@ -1010,8 +1008,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 // turns without copies.
                 auto pass = [&](const int4 &rA, const int4 &rB, int4 &rAn, int4 &rBn, int wp, int w0, int wn,
                                 int &wnn) {
-                    pp += rs;
-                    if (pp == ringEnd) pp = ring;
+                    pp = min(pp + rs, ringLast);
                     wnn = pp[L.node];  // row x + 2 (past the halo on the last row: unused)
                     rAn = sld_at(S.a4, ro + 16u);  // x + 1 <= Q
                     rBn = sld_at(S.b4, ro + 16u);

@@ -1017,10 +1017,11 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                     bool full = true;
                     if (!DUMP) {
                         const int thr = min(bd, thrRun);
+                        const int wz = wn - rA.z;  // shared by RELOCATE t -> s and 2OPT*
                         const int d1 = w0 + gR + (L.cRel + rA.w);
-                        const int d2 = w0 + wn + (L.cRel2 - rA.z);
-                        const int d3 = (wp + wn) + (gL + gR) + (L.cSwap - rB.w);
-                        const int d4 = gR + wn + (L.c2s - rA.z);
+                        const int d2 = w0 + wz + L.cRel2;
+                        const int d3 = (wp + wn) + gL + (gR + (L.cSwap - rB.w));
+                        const int d4 = gR + wz + L.c2s;
                         const int m = min(min(d1, d2), min(d3, d4));
                         full = m <= thr && L.tyOwn >= rA.y;
                         if (full) {

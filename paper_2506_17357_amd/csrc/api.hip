@@ -210,6 +210,7 @@ struct tga_batch {
     int *ixoff;     // device: intra-route groups of XCD x = intra[ixoff[x] .. ixoff[x+1])
     int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
+    int32_t *steps; // device: evaluation steps run (the inter-route lists alternate direction)
     size_t lds;
     size_t lds_intra;
     int grid_inter, grid_intra;
@@ -574,7 +575,7 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
     if ((rc = pinned(&pin))) return rc;
     launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
                 sol->lds, sol->nitems, dump_delta, dump_feas, st);
-    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask);
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(pin, sol->h.rec, 32, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char *)pin + 32, sol->h.state, 16, hipMemcpyDeviceToHost, st));
@@ -612,7 +613,7 @@ extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_
     p[6] = (int32_t)move->id;
     p[7] = (int32_t)move->version;
     HIPCHK(hipMemcpyAsync(sol->h.rec, p, 32, hipMemcpyHostToDevice, st));
-    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeApplyRec, TGA_OP_ALL);
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeApplyRec, TGA_OP_ALL, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(p + 8, sol->h.state, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8, hipMemcpyDeviceToHost, st));
@@ -646,7 +647,7 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
         for (int i = 0; i < todo; ++i) {
             launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw,
                         op_mask | kImprovingOnly, sol->lds, sol->nitems, nullptr, nullptr, st);
-            k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask);
+            k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask, nullptr);
         }
         HIPCHK(hipGetLastError());
         launched += todo;
@@ -730,7 +731,7 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     *desc = take(sizeof(SolDev) * sols.size());
     *items = take(sizeof(InterItem) * std::max(max_items, 1));
     *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    *sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * sols.size());  // item list offsets, then done flags
+    *sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (sols.size() + 1));  // item list offsets, done flags, step counter
     return off;
 }
 
@@ -913,6 +914,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->woff, woff.data(), sizeof(int) * (grid_inter + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(B->steps, 0, sizeof(int32_t), st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->ixoff, ixoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -971,6 +973,7 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->woff = (int *)(base + osched);
     B->ixoff = B->woff + (kMaxBatchGrid + 1);
     B->done = B->ixoff + (kMaxXcds + 1);
+    B->steps = B->done + v.size();
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
@@ -991,19 +994,19 @@ static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream
     if (ls) op_mask |= kImprovingOnly;
     if (!B->cfg.split) {
         k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                     B->ixoff, B->nx, op_mask);
+                                                                     B->ixoff, B->nx, op_mask, B->steps);
         return;
     }
     if (op_mask & 7)
         k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                     B->ixoff, B->nx, op_mask);
+                                                                     B->ixoff, B->nx, op_mask, B->steps);
     if (op_mask & (2 | 8 | 16))
         k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
-            B->d, B->items, B->woff, B->intra, B->ixoff, B->nx, op_mask);
+            B->d, B->items, B->woff, B->intra, B->ixoff, B->nx, op_mask, B->steps);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {
-    k_finalize<<<(int)B->sols.size(), kApplyThreads, 0, st>>>(B->d, mode, op_mask);
+    k_finalize<<<(int)B->sols.size(), kApplyThreads, 0, st>>>(B->d, mode, op_mask, B->steps);
 }
 
 static void batch_step(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {

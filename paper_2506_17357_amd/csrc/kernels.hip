@@ -1531,7 +1531,8 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 template <int PH>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
     const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ woff,
-    const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx, uint32_t op_mask) {
+    const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx, uint32_t op_mask,
+    const int *__restrict__ steps) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int thr_sh;
@@ -1552,8 +1553,12 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
     __syncthreads();  // the intra-route regions and the inter-route rows share LDS
     if ((PH & 1) && (op_mask & 7)) {
-        const int end = woff[blockIdx.x + 1];
-        for (int it = woff[blockIdx.x]; it < end; ++it) {
+        // every other step walks the list backwards, so that a step starts on
+        // the distance rows the previous one read last (still in cache)
+        const int first = woff[blockIdx.x], cnt = woff[blockIdx.x + 1] - first;
+        const bool back = __builtin_amdgcn_readfirstlane(*steps) & 1;
+        for (int k = 0; k < cnt; ++k) {
+            const int it = back ? first + cnt - 1 - k : first + k;
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
@@ -1801,9 +1806,11 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
     }
 }
 
+// `steps` (nullable): a batch's step counter, advanced once per launch.
 __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__restrict__ sols, int mode,
-                                                            uint32_t op_mask) {
+                                                            uint32_t op_mask, int *__restrict__ steps) {
     finalize_block(sols[blockIdx.x], mode, op_mask);
+    if (steps && blockIdx.x == 0 && threadIdx.x == 0) *steps += 1;
 }
 
 

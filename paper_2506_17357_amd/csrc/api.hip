@@ -211,6 +211,8 @@ struct tga_batch {
     int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
     int32_t *steps; // device: evaluation steps run (the inter-route lists alternate direction)
+    long long *coll = nullptr;    // device: {steps, version, moves, cost} per solution (k_collect)
+    long long *coll_h = nullptr;  // pinned host copy of coll
     size_t lds;
     size_t lds_intra;
     int grid_inter, grid_intra;
@@ -732,6 +734,7 @@ static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc
     *items = take(sizeof(InterItem) * std::max(max_items, 1));
     *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
     *sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (sols.size() + 1));  // item list offsets, done flags, step counter
+    take(32 * sols.size());  // collected results
     return off;
 }
 
@@ -974,11 +977,18 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     B->ixoff = B->woff + (kMaxBatchGrid + 1);
     B->done = B->ixoff + (kMaxXcds + 1);
     B->steps = B->done + v.size();
+    B->coll = (long long *)(base + align_up(osched + 4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (v.size() + 1), 256));
+    if (hipHostMalloc((void **)&B->coll_h, 32 * v.size(), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete B;
+        return fail(TGA_ENOMEM, "pinned host buffer of %zu bytes", 32 * v.size());
+    }
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_steps = -1;
     B->cap_stream = nullptr;
     if ((rc = batch_plan(B, P, (hipStream_t)stream))) {
+        (void)hipHostFree(B->coll_h);
         delete B;
         return rc;
     }
@@ -1118,20 +1128,19 @@ extern "C" int tga_batch_reset(tga_batch_t B, void *stream) {
     return TGA_OK;
 }
 
+// One kernel gathers every solution's results, one copy brings them over.
 static int batch_collect(tga_batch *B, int32_t *steps_done, int64_t *moves, int64_t *cost, hipStream_t st) {
     const int n = (int)B->sols.size();
-    std::vector<int32_t> state(16 * n);
-    std::vector<long long> acc(kAccCount * n);
-    for (int i = 0; i < n; ++i) {
-        HIPCHK(hipMemcpyAsync(&state[16 * i], B->sols[i]->h.state, 64, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(&acc[kAccCount * i], B->sols[i]->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
-    }
+    k_collect<<<(n + 255) / 256, 256, 0, st>>>(B->d, n, B->coll);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(B->coll_h, B->coll, 32 * (size_t)n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) {
-        B->sols[i]->version = (uint32_t)state[16 * i + kStVersion];
-        if (steps_done) steps_done[i] = state[16 * i + kStSteps];
-        if (moves) moves[i] = acc[kAccCount * i + kAccMoves];
-        if (cost) cost[i] = acc[kAccCount * i + kAccCost];
+        const long long *r = B->coll_h + 4 * i;
+        B->sols[i]->version = (uint32_t)r[1];
+        if (steps_done) steps_done[i] = (int32_t)r[0];
+        if (moves) moves[i] = r[2];
+        if (cost) cost[i] = r[3];
     }
     return TGA_OK;
 }
@@ -1242,6 +1251,7 @@ extern "C" int tga_batch_free(tga_batch_t B) {
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    if (B->coll_h) (void)hipHostFree(B->coll_h);
     for (auto *s : B->sols) s->in_batch = 0;
     delete B;
     return TGA_OK;

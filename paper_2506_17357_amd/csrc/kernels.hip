@@ -1886,6 +1886,19 @@ __global__ void k_poll_done(const SolDev *__restrict__ sols, int nsols, int32_t 
     if (i < nsols) out[i] = sols[i].state[kStDone];
 }
 
+// Per-solution results of a batch in one array: {steps, version, moves
+// evaluated, cost} per solution, for a single copy to the host.
+__global__ void k_collect(const SolDev *__restrict__ sols, int nsols, long long *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsols) {
+        const SolDev &S = sols[i];
+        out[4 * i] = S.state[kStSteps];
+        out[4 * i + 1] = S.state[kStVersion];
+        out[4 * i + 2] = S.acc[kAccMoves];
+        out[4 * i + 3] = S.acc[kAccCost];
+    }
+}
+
 // Reset per-solution state for a new run (no memset, so it can sit in a
 // captured graph).
 __global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int max_steps) {

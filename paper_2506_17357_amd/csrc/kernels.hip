@@ -728,7 +728,8 @@ __device__ __forceinline__ void col_setup(const SolDev &S, int cb, const ColRaw 
 // [0, Q] are read clamped.
 
 // Distance rows of slots [x0, x0 + cnt) copied straight from HBM into the
-// block (global_load_lds, one dword per lane), slot `base` at position 0,
+// block (global_load_lds, four dwords per lane for 16-bit rows, else one),
+// slot `base` at position 0,
 // from the 16-bit copy of D when W16.  The issuing wavefront must wait
 // (vmcnt) before a barrier publishes them.  `wave` is the wavefront index
 // (uniform).
@@ -741,9 +742,18 @@ __device__ __forceinline__ void drow_issue(const SolDev &S, void *ring, int base
         const int node = nodeof(sld(S.a4 + min(max(x, 0), S.Q)).x);
         const int *src = W16 ? (const int *)(S.D16 + (size_t)node * S.stride16) : S.D + (size_t)node * S.np1;
         int *dst = (int *)ring + (x - base) * words;
-        for (int c = 0; c < words; c += 64) {
-            if (c + lane < words)
-                __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
+        if (W16) {  // rows are 16-byte aligned multiples of 16 bytes: four dwords per lane
+            for (int c = 0; c < words; c += 256) {
+                if (c + 4 * lane < words)
+                    __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + 4 * lane), (lds_void_ptr)(dst + c), 16,
+                                                     0, 0);
+            }
+        } else {
+            for (int c = 0; c < words; c += 64) {
+                if (c + lane < words)
+                    __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0,
+                                                     0);
+            }
         }
     }
 }

@@ -1323,7 +1323,7 @@ constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while 
 // positions, staged at word offset at[k] of the region, nodes first):
 // element y of route k's block is D[node(y / P)][node(y % P)].  A route whose
 // cache entry holds the same P and nodes copies its block from there
-// (contiguous loads); any other route gathers it from D and, when
+// (LDS DMA); any other route gathers it from D and, when
 // P <= kRouteBlockMaxP, rewrites its entry.  Each lane keeps up to
 // kGatherBatch loads in flight before it stores them, so a group costs a
 // couple of memory round trips.
@@ -1347,44 +1347,58 @@ __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, 
             fill |= (ok ? 0u : 1u) << k;
         }
     }
-    for (int x0 = 0; x0 < E; x0 += 64 * kGatherBatch) {
-        int val[kGatherBatch], dst[kGatherBatch], cst[kGatherBatch];
+    // current cached blocks: straight from the cache into LDS (LDS DMA, no
+    // register round trip)
 #pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) {
-            const int x = x0 + u * 64 + lane;
-            dst[u] = -1;
-            cst[u] = -1;
-            val[u] = 0;
-            if (x < E) {
-                int k = 0, c = 0, pk = P[0], ak = at[0];
-#pragma unroll
-                for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
-                    if (kk < G && x >= cum[kk]) {
-                        k = kk;
-                        c = cum[kk];
-                        pk = P[kk];
-                        ak = at[kk];
-                    }
-                }
-                const int y = x - c;
-                const int ce = (r0 + k) * kRouteBlockWords + kRouteBlockData + y;  // cache word of element y
-                if ((hit >> k) & 1) {
-                    val[u] = gld(S.rblk + ce);
-                } else {
-                    const int pp = y / pk, qq = y - pp * pk;
-                    const int *pn = region + ak;
-                    val[u] = gld(S.D + (size_t)pn[pp] * S.np1 + pn[qq]);
-                    if ((fill >> k) & 1) cst[u] = ce;
-                }
-                dst[u] = ak + 7 * pk + y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) {
-            if (dst[u] >= 0) region[dst[u]] = val[u];
-            if (cst[u] >= 0) S.rblk[cst[u]] = val[u];
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if ((hit >> k) & 1) {
+            const int *src = S.rblk + (size_t)(r0 + k) * kRouteBlockWords + kRouteBlockData;
+            int *dst = region + at[k] + 7 * P[k];
+            const int PP = P[k] * P[k];
+            for (int c = 0; c < PP; c += 64)
+                if (c + lane < PP)
+                    __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
         }
     }
+    // the other routes: gathered from D
+    if (hit != (1u << G) - 1u) {
+        for (int x0 = 0; x0 < E; x0 += 64 * kGatherBatch) {
+            int val[kGatherBatch], dst[kGatherBatch], cst[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                const int x = x0 + u * 64 + lane;
+                dst[u] = -1;
+                cst[u] = -1;
+                val[u] = 0;
+                if (x < E) {
+                    int k = 0, c = 0, pk = P[0], ak = at[0];
+#pragma unroll
+                    for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
+                        if (kk < G && x >= cum[kk]) {
+                            k = kk;
+                            c = cum[kk];
+                            pk = P[kk];
+                            ak = at[kk];
+                        }
+                    }
+                    if (!((hit >> k) & 1)) {
+                        const int y = x - c;
+                        const int pp = y / pk, qq = y - pp * pk;
+                        const int *pn = region + ak;
+                        val[u] = gld(S.D + (size_t)pn[pp] * S.np1 + pn[qq]);
+                        if ((fill >> k) & 1) cst[u] = (r0 + k) * kRouteBlockWords + kRouteBlockData + y;
+                        dst[u] = ak + 7 * pk + y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                if (dst[u] >= 0) region[dst[u]] = val[u];
+                if (cst[u] >= 0) S.rblk[cst[u]] = val[u];
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the LDS DMA above has landed (the caller then syncs the wavefront)
     // entries rewritten above: their nodes, then P
 #pragma unroll
     for (int k = 0; k < kIntraMaxGroup; ++k) {

@@ -86,7 +86,11 @@ typedef struct {
 } tga_move_t;
 
 /* Device workspace sizes (bytes) for an instance of n customers and for a
- * solution with R route slots.  Returns 0 when n or R is out of range. */
+ * solution with R route slots.  Returns 0 when n or R is out of range.  A
+ * solution workspace holds the slot attributes, the work lists of the
+ * single-solution form and, per route, the route's distance sub-block as
+ * last staged by the intra-route evaluation (6.5 KB per route; an entry is
+ * used only while the route's node sequence is unchanged). */
 size_t tga_instance_workspace_bytes(int32_t n);
 size_t tga_solution_workspace_bytes(int32_t n, int32_t R);
 
@@ -97,8 +101,9 @@ size_t tga_solution_workspace_bytes(int32_t n, int32_t R);
  *   node4  device, (n+1) x {demand, e, l, s} int32; node 0 is the depot with
  *          demand 0 and s = 0; 0 <= e <= l; s >= 0.
  *   capacity  vehicle capacity (>= 0).   has_tw  0 = CVRP, 1 = VRPTW.
- *   ws     device workspace of tga_instance_workspace_bytes(n) bytes (it
- *          also holds a 16-bit copy of D when every distance is below 2^16).
+ *   ws     device workspace of tga_instance_workspace_bytes(n) bytes,
+ *          256-byte aligned (it also holds a 16-bit copy of D, rows 16-byte
+ *          aligned, when every distance is below 2^16).
  * Values are checked on the device before the handle is returned
  * (TGA_EINVAL for asymmetry / negative values, TGA_ERANGE when sums along a
  * route could leave the exact int32 range).  Synchronises `stream`. */
@@ -125,8 +130,9 @@ int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
 
 /* Replace the routes of an existing solution (same instance, same R) and
  * rebuild its attributes in place: the workspace, and every batch or captured
- * graph that refers to the solution, stay valid.  Resets the version to 0.
- * Same argument rules as tga_set_solution.  Synchronises `stream`. */
+ * graph that refers to the solution, stay valid.  Resets the version to 0
+ * and empties the per-route distance-block cache.  Same argument rules as
+ * tga_set_solution.  Synchronises `stream`. */
 int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, const int32_t *customers,
                         void *stream);
 

@@ -264,6 +264,7 @@ extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *
     if (has_tw != 0 && has_tw != 1) return fail(TGA_EINVAL, "has_tw must be 0 or 1");
     if (ws_bytes < tga_instance_workspace_bytes(n)) return fail(TGA_ENOMEM, "instance workspace too small");
     if (((uintptr_t)node4) & 15) return fail(TGA_EINVAL, "node4 must be 16-byte aligned");
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
     DevProps P;
     int rc = props(&P);
     if (rc) return rc;

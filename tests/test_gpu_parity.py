@@ -312,6 +312,18 @@ def test_errors(tga):
     with pytest.raises(T.TGAError) as e:
         T.Instance(inst.n, inst.dist, tw, inst.capacity, 1)
     assert e.value.code == T.TGA_EINVAL
+    # an instance workspace that is not 256-byte aligned is refused
+    import ctypes
+    import torch
+    L = T.lib()
+    dd = torch.from_numpy(inst.dist).cuda()
+    nd = torch.from_numpy(inst.node4).cuda()
+    nb = L.tga_instance_workspace_bytes(inst.n)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    rc = L.tga_load_instance(inst.n, dd.data_ptr(), nd.data_ptr(), inst.capacity, 0, ws.data_ptr() + 16, nb,
+                             T._stream(None), ctypes.byref(h))
+    assert rc == T.TGA_EINVAL and h.value is None
     assert S.eval() is not None  # still usable after the errors
 
 

@@ -272,7 +272,7 @@ int tga_batch_set_config(tga_batch_t b, const tga_batch_config_t *cfg, void *str
 /* The project's autotuner for the batched form: times `launches` evaluation
  * steps (each followed by a finalize that only records the best move, so no
  * solution changes) of the batch's current state under each candidate
- * schedule (lds_kb in {40, 52, 64, 78} x split in {0, 1}, keeping
+ * schedule (lds_kb in {40, 52, 64, 78, 79} x split in {0, 1}, keeping
  * rows_per_item and sub_rows), keeps the fastest and writes it to `best`
  * (nullable).  Drops a captured step loop.  Synchronises `stream`. */
 int tga_batch_autotune(tga_batch_t b, uint32_t op_mask, int32_t launches, tga_batch_config_t *best,

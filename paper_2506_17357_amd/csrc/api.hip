@@ -1065,7 +1065,7 @@ extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launc
         return fail(TGA_EDEVICE, "hipEventCreate failed");
     }
     const tga_batch_config_t base = B->cfg;
-    static const int kLdsKb[] = {40, 52, 64, 78};
+    static const int kLdsKb[] = {40, 52, 64, 78, 79};
     tga_batch_config_t chosen = base;
     float best_us = 0.f;
     bool any = false;

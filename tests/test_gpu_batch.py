@@ -116,7 +116,7 @@ def test_schedule_does_not_change_results(tga, rows_per_item, sub_rows):
         assert steps[b] == len(ids) and cost[b] == oracle.cost(inst, final)[0]
 
 
-@pytest.mark.parametrize("lds_kb,split", [(40, 0), (52, 1), (78, 0), (24, 1)])
+@pytest.mark.parametrize("lds_kb,split", [(40, 0), (52, 1), (78, 0), (79, 0), (24, 1)])
 def test_config_does_not_change_results(tga, lds_kb, split):
     pairs = small_mix(6, seed=4)
     insts, sols = make_solutions(tga, pairs)
@@ -136,7 +136,7 @@ def test_autotune_picks_a_candidate_and_keeps_results(tga):
     B = tga.Batch(sols)
     cfg = B.autotune(launches=2)
     print("autotuned", cfg, flush=True)
-    assert cfg["lds_kb"] in (40, 52, 64, 78) and cfg["split"] in (0, 1) and cfg["us_per_eval"] > 0
+    assert cfg["lds_kb"] in (40, 52, 64, 78, 79) and cfg["split"] in (0, 1) and cfg["us_per_eval"] > 0
     assert B.config() == cfg
     steps, moves, cost = B.ls_run(30)
     for b, (inst, sol) in enumerate(pairs):

@@ -100,7 +100,7 @@ size_t lds_budget() {
 
 // LDS of an inter-route workgroup with sub-blocks of h rows: the h rows and
 // one halo row on each side, 16- or 32-bit.
-size_t ring_lds(int np1, int h, bool w16) {
+size_t rows_lds(int np1, int h, bool w16) {
     return (size_t)(h + 2) * (w16 ? 2 * (size_t)stride16_of(np1) : 4 * (size_t)np1);
 }
 
@@ -108,7 +108,7 @@ size_t ring_lds(int np1, int h, bool w16) {
 // workgroup; at least 1.
 int default_tile_rows(int np1, bool w16) {
     int h = 1;
-    while (h < 64 && ring_lds(np1, h + 1, w16) <= lds_budget()) ++h;
+    while (h < 64 && rows_lds(np1, h + 1, w16) <= lds_budget()) ++h;
     return h;
 }
 
@@ -374,11 +374,11 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     const bool w16 = inst->D16 != nullptr;
     S->tile_rows = default_tile_rows(np1, w16);
     S->plain_rows = plain_rows(Q, np1, w16);
-    S->lds = ring_lds(np1, S->plain_rows, w16);
+    S->lds = rows_lds(np1, S->plain_rows, w16);
     if (S->lds > (size_t)P.max_lds) {
         delete S;
         return fail(TGA_ERANGE, "n = %d needs %zu bytes of LDS per workgroup (device: %d)", n,
-                    ring_lds(np1, 1, w16), P.max_lds);
+                    rows_lds(np1, 1, w16), P.max_lds);
     }
     char *base = (char *)ws;
     SolDev &h = S->h;
@@ -772,7 +772,7 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
 // Rows per LDS sub-block for an LDS budget of `budget` bytes.
 static int tile_rows_for(int np1, bool w16, size_t budget) {
     int h = 1;
-    while (h < 64 && ring_lds(np1, h + 1, w16) <= budget) ++h;
+    while (h < 64 && rows_lds(np1, h + 1, w16) <= budget) ++h;
     return h;
 }
 
@@ -797,7 +797,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         const int tr = c.sub_rows > 0 ? std::min(c.sub_rows, cap_rows) : cap_rows;
         trs[i] = tr;
         descs[i].tile_rows = tr;
-        lds = std::max(lds, ring_lds(s->h.np1, tr, w16));
+        lds = std::max(lds, rows_lds(s->h.np1, tr, w16));
     }
     const size_t lds_intra = (size_t)kInterWaves * kIntraRegionBytes;  // the intra phase's regions
     if (!c.split) lds = std::max(lds, lds_intra);

@@ -734,14 +734,14 @@ __device__ __forceinline__ void col_setup(const SolDev &S, int cb, const ColRaw 
 // (vmcnt) before a barrier publishes them.  `wave` is the wavefront index
 // (uniform).
 template <bool W16>
-__device__ __forceinline__ void drow_issue(const SolDev &S, void *ring, int base, int x0, int cnt, int wave) {
+__device__ __forceinline__ void drow_issue(const SolDev &S, void *rows, int base, int x0, int cnt, int wave) {
     const int lane = threadIdx.x & 63;
     const int words = W16 ? S.stride16 / 2 : S.np1;  // dwords per row
     for (int r = wave; r < cnt; r += kInterWaves) {
         const int x = x0 + r;
         const int node = nodeof(sld(S.a4 + min(max(x, 0), S.Q)).x);
         const int *src = W16 ? (const int *)(S.D16 + (size_t)node * S.stride16) : S.D + (size_t)node * S.np1;
-        int *dst = (int *)ring + (x - base) * words;
+        int *dst = (int *)rows + (x - base) * words;
         if (W16) {  // rows are 16-byte aligned multiples of 16 bytes: four dwords per lane
             for (int c = 0; c < words; c += 256) {
                 if (c + 4 * lane < words)
@@ -943,9 +943,9 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
     const int s0 = item.s0, s1 = item.s1;
     const int nsb = (s1 - s0 + h - 1) / h;
     const int NB = h + 2;
-    const int rs = W16 ? S.stride16 : np1;  // ring row stride (elements)
-    DT *ring = (DT *)smem4;
-    const DT *ringLast = ring + (NB - 1) * rs;  // the last row position
+    const int rs = W16 ? S.stride16 : np1;  // row stride in LDS (elements)
+    DT *rows = (DT *)smem4;
+    const DT *rowsLast = rows + (NB - 1) * rs;  // the last row position
 
     int bd = initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
@@ -953,7 +953,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
     // prologue: the distance rows of sub-block 0 (with its halo rows)
     __syncthreads();  // the previous item is done with LDS
     if (!DUMP && threadIdx.x == 0) *thr_sh = committed_delta(S);
-    drow_issue<W16>(S, ring, s0 - 1, s0 - 1, min(h, s1 - s0) + 2, wave);
+    drow_issue<W16>(S, rows, s0 - 1, s0 - 1, min(h, s1 - s0) + 2, wave);
     __builtin_amdgcn_s_waitcnt(0);
 
     ColRaw nxt;  // column attributes fetched ahead for the chunk at nxt_cb
@@ -963,7 +963,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         const int nr = min(h, s1 - sb);  // rows of this sub-block
         __syncthreads();                 // rows of sub-block i resident (i = 0), or i - 1 consumed
         if (i > 0) {                     // the rows of sub-block i with its halo rows
-            drow_issue<W16>(S, ring, sb - 1, sb - 1, nr + 2, wave);
+            drow_issue<W16>(S, rows, sb - 1, sb - 1, nr + 2, wave);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
@@ -1001,7 +1001,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 int x = sb + r0;  // row slot
                 const int xend = sb + r1;
                 // register window over the distance rows: x - 1, x, x + 1
-                const DT *pp = ring + (x - sb) * rs;
+                const DT *pp = rows + (x - sb) * rs;
                 int gp = pp[L.node];
                 pp += rs;
                 int g = pp[L.node];
@@ -1018,7 +1018,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 // turns without copies.
                 auto pass = [&](const int4 &rA, const int4 &rB, int4 &rAn, int4 &rBn, int wp, int w0, int wn,
                                 int &wnn) {
-                    pp = min(pp + rs, ringLast);
+                    pp = min(pp + rs, rowsLast);
                     wnn = pp[L.node];  // row x + 2 (past the halo on the last row: unused)
                     rAn = sld_at(S.a4, ro + 16u);  // x + 1 <= Q
                     rBn = sld_at(S.b4, ro + 16u);

@@ -98,17 +98,19 @@ size_t lds_budget() {
     return b;
 }
 
+constexpr int kMaxTileRows = 64;  // rows per inter-route sub-block (128 was slower on the mix)
+
 // LDS of an inter-route workgroup with sub-blocks of h rows: the h rows and
 // one halo row on each side, 16- or 32-bit.
 size_t rows_lds(int np1, int h, bool w16) {
     return (size_t)(h + 2) * (w16 ? 2 * (size_t)stride16_of(np1) : 4 * (size_t)np1);
 }
 
-// Largest sub-block (at most 64 rows) that fits the LDS budget of one
+// Largest sub-block (at most kMaxTileRows rows) that fits the LDS budget of one
 // workgroup; at least 1.
 int default_tile_rows(int np1, bool w16) {
     int h = 1;
-    while (h < 64 && rows_lds(np1, h + 1, w16) <= lds_budget()) ++h;
+    while (h < kMaxTileRows && rows_lds(np1, h + 1, w16) <= lds_budget()) ++h;
     return h;
 }
 
@@ -772,7 +774,7 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
 // Rows per LDS sub-block for an LDS budget of `budget` bytes.
 static int tile_rows_for(int np1, bool w16, size_t budget) {
     int h = 1;
-    while (h < 64 && rows_lds(np1, h + 1, w16) <= budget) ++h;
+    while (h < kMaxTileRows && rows_lds(np1, h + 1, w16) <= budget) ++h;
     return h;
 }
 

@@ -74,7 +74,9 @@ int props(DevProps *out) {
         const void *fns[] = {(const void *)k_eval_inter<false, false>, (const void *)k_eval_inter<true, false>,
                              (const void *)k_eval_inter<false, true>, (const void *)k_eval_inter<true, true>,
                              (const void *)k_eval_batch<1>, (const void *)k_eval_batch<2>,
-                             (const void *)k_eval_batch<3>};
+                             (const void *)k_eval_batch<3>,
+                             (const void *)k_eval_solution<false, false>, (const void *)k_eval_solution<true, false>,
+                             (const void *)k_eval_solution<false, true>, (const void *)k_eval_solution<true, true>};
         bool ok = dyn > 65536;
         for (const void *f : fns)
             if (ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) ok = false;
@@ -523,6 +525,29 @@ static void launch_eval(const SolDev *d, const InterItem *items, int nitems, con
                         int nintra, int has_tw, uint32_t op_mask, size_t lds, int grid_inter,
                         int32_t *dd, uint8_t *df, hipStream_t st) {
     const bool dump = dd != nullptr;
+    if ((op_mask & 7) && nitems > 0 && (op_mask & (2 | 8 | 16)) && nintra > 0) {
+        // both kinds in one launch: inter-route workgroups first, then one
+        // workgroup per kInterWaves intra-route groups
+        const int ninter = std::max(1, std::min(nitems, grid_inter));
+        const int grid = ninter + (nintra + kInterWaves - 1) / kInterWaves;
+        const size_t l = std::max(lds, (size_t)kInterWaves * kIntraRegionBytes);
+        if (has_tw) {
+            if (dump)
+                k_eval_solution<true, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                                                                            op_mask, dd, df);
+            else
+                k_eval_solution<true, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                                                                             op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_solution<false, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                                                                             op_mask, dd, df);
+            else
+                k_eval_solution<false, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                                                                              op_mask, dd, df);
+        }
+        return;
+    }
     if ((op_mask & 7) && nitems > 0) {
         const int grid = std::max(1, std::min(nitems, grid_inter));
         if (has_tw) {

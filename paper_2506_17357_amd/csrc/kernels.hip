@@ -1538,6 +1538,40 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+// Single-solution form with both operator kinds: workgroups below
+// ninter take the inter-route items (as k_eval_inter), the others the
+// intra-route groups (as k_eval_intra), so both run at once in one launch.
+// The dynamic LDS is the larger of the two needs.
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_solution(
+    const SolDev *__restrict__ sols, const InterItem *__restrict__ items, int nitems,
+    const IntraItem *__restrict__ intra, int nintra, int ninter, uint32_t op_mask, int32_t *__restrict__ dump_delta,
+    uint8_t *__restrict__ dump_feas) {
+    extern __shared__ int4 smem4[];
+    __shared__ unsigned long long red[kInterWaves];
+    __shared__ int thr_sh;
+    if ((int)blockIdx.x < ninter) {
+        for (int it = blockIdx.x; it < nitems; it += ninter) {
+            const InterItem item = items[it];
+            const SolDev &S = sols[item.sol];
+            if (S.state[kStDone]) continue;
+            if (S.D16)
+                inter_item<TW, DUMP, true>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
+            else
+                inter_item<TW, DUMP, false>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
+        }
+    } else {
+        const int wave = threadIdx.x >> 6, b = blockIdx.x - ninter, nb = gridDim.x - ninter;
+        int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+        for (int itx = b * kInterWaves + wave; itx < nintra; itx += nb * kInterWaves) {
+            const IntraItem item = intra[itx];
+            const SolDev &S = sols[item.sol];
+            if (S.state[kStDone]) continue;
+            intra_group<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
+        }
+    }
+}
+
 // Batched form: persistent launches evaluate every solution of the batch.
 // PH bit 1: intra-route groups (one wavefront per group of routes); PH bit 0:
 // inter-route items (whole workgroup per item, largest first).  PH = 3 runs

@@ -972,8 +972,10 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         if (sb + 1 < Q) {
             int idx, hi;
             wave_share(Q, sb, nr, wave, idx, hi);
-            while (idx < hi) {
-                const int j = idx / nr, r0 = idx - j * nr;
+            // run = (chunk j, rows [r0, r1)); every run after the first of a
+            // share starts the next chunk at row 0
+            int j = idx / nr, r0 = idx - j * nr;
+            for (; idx < hi; ++j, r0 = 0) {
                 const int r1 = min(nr, r0 + (hi - idx));
                 idx += r1 - r0;
                 const int cb = sb + 1 + j * kColsPerWave;
@@ -982,7 +984,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 // later sub-block) while this one is evaluated
                 int cb2 = -1;
                 if (idx < hi) {
-                    cb2 = sb + 1 + (idx / nr) * kColsPerWave;
+                    cb2 = cb + kColsPerWave;
                 } else {
                     for (int i2 = i + 1; i2 < nsb && cb2 < 0; ++i2) {
                         const int sb2 = s0 + i2 * h, nr2 = min(h, s1 - sb2);

@@ -58,6 +58,8 @@ __device__ __forceinline__ int4 sld(const int4 *p) {
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ int sld1(const int *p) { return *(const __attribute__((address_space(4))) int *)p; }
+
 // The same at a byte offset from p (one scalar load with an offset register).
 __device__ __forceinline__ int4 sld_at(const int4 *p, uint32_t byte_off) {
     typedef int v4i __attribute__((ext_vector_type(4)));
@@ -1001,7 +1003,10 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 int routeLast;
                 col_setup(S, cb, cur, op_mask, L, routeLast);
                 int x = sb + r0;  // row slot
-                const int xend = sb + r1;
+                // rows whose route precedes the chunk's last route (slots are
+                // route-major, so those before that route's first slot), at
+                // most up to the end of the run
+                const int xlim = routeLast >= 0 ? min(sb + r1, sld1(S.roff + routeLast)) : x;
                 // register window over the distance rows: x - 1, x, x + 1
                 const DT *pp = rows + (x - sb) * rs;
                 int gp = pp[L.node];
@@ -1063,17 +1068,14 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 };
                 int4 ra2, rb2;
                 int g3 = 0;
-                bool more = routeLast > ra.y;
-                while (more) {
+                while (x < xlim) {
                     pass(ra, rb, ra2, rb2, gp, g, gn, g3);
-                    more = x < xend && routeLast > ra2.y;
-                    if (!more) break;
+                    if (x >= xlim) break;
                     pass(ra2, rb2, ra, rb, g, gn, g3, gp);
                     const int w1 = gn;  // window (rows x - 1, x, x + 1) back in gp, g, gn
                     gn = gp;
                     gp = w1;
                     g = g3;
-                    more = x < xend && routeLast > ra.y;
                 }
                 // publish this wavefront's best to the workgroup (one lane, one
                 // LDS atomic, only when some lane improved on the shared value)

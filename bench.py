@@ -205,8 +205,8 @@ def main():
                     help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py: this build measures one GPU only (the batched solutions are independent; "
-            "see DESIGN.md for how the path would shard); run with --gpus 1")
+        log("bench.py: measures one GPU only (the batched solutions are independent, so more GPUs "
+            "would each take a share of the solutions); run with --gpus 1")
         sys.exit(2)
     K, Wm = args.steps, args.warmup
     from paper_2506_17357_amd import build_lib

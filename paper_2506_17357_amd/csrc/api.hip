@@ -165,9 +165,11 @@ SolLayout sol_layout(int n, int R) {
     L.roff_alt = take(4 * (R + 1));
     L.rblk = take(4 * (size_t)kRouteBlockWords * std::max(R, 1));
     L.best_key = take(8);
-    L.rec = take(32);
-    L.state = take(4 * 16);
-    L.acc = take(8 * kAccCount);
+    // last record, state and accumulators back to back, so that every host
+    // call reads what it needs with one copy
+    L.rec = take(32 + 4 * 16 + 8 * kAccCount);
+    L.state = L.rec + 32;
+    L.acc = L.state + 4 * 16;
     // the 16-bit matrix only ever allows more rows per item, so size for int32
     L.max_items = (int)count_items((int)Q, plain_rows((int)Q, n + 1, false));
     L.items = take(sizeof(InterItem) * L.max_items);
@@ -607,8 +609,7 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
                 sol->lds, sol->nitems, dump_delta, dump_feas, st);
     k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(pin, sol->h.rec, 32, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char *)pin + 32, sol->h.state, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin, sol->h.rec, 32 + 16, hipMemcpyDeviceToHost, st));  // record, state[0..3]
     HIPCHK(hipStreamSynchronize(st));
     const int32_t *rec = (const int32_t *)pin;
     const int32_t status = ((const int32_t *)pin)[8 + kStStatus];
@@ -645,12 +646,11 @@ extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_
     HIPCHK(hipMemcpyAsync(sol->h.rec, p, 32, hipMemcpyHostToDevice, st));
     k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeApplyRec, TGA_OP_ALL, nullptr);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(p + 8, sol->h.state, 16, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p + 8, sol->h.state, 4 * 16 + 8, hipMemcpyDeviceToHost, st));  // state, acc[0]
     HIPCHK(hipStreamSynchronize(st));
     if (p[8 + kStStatus] != 0) return fail(TGA_EINVAL, "move id %u is not a move of N(S)", move->id);
     sol->version++;
-    if (new_cost) *new_cost = *(long long *)(p + 16);
+    if (new_cost) *new_cost = *(long long *)(p + 8 + 16);
     return TGA_OK;
 }
 
@@ -685,8 +685,7 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
         HIPCHK(hipStreamSynchronize(st));
         if (p[kStDone]) break;
     }
-    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64 + 8 * kAccCount, hipMemcpyDeviceToHost, st));  // state, acc
     HIPCHK(hipStreamSynchronize(st));
     const long long *acc = (const long long *)(p + 16);
     sol->version = (uint32_t)p[kStVersion];
@@ -726,8 +725,7 @@ extern "C" int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32
     int rc = pinned(&pin);
     if (rc) return rc;
     int32_t *p = (int32_t *)pin;
-    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(p + 16, sol->h.acc, 8 * kAccCount, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(p, sol->h.state, 64 + 8 * kAccCount, hipMemcpyDeviceToHost, st));  // state, acc
     HIPCHK(hipStreamSynchronize(st));
     const long long *acc = (const long long *)(p + 16);
     sol->version = (uint32_t)p[kStVersion];

@@ -528,24 +528,26 @@ static void launch_eval(const SolDev *d, const InterItem *items, int nitems, con
                         int32_t *dd, uint8_t *df, hipStream_t st) {
     const bool dump = dd != nullptr;
     if ((op_mask & 7) && nitems > 0 && (op_mask & (2 | 8 | 16)) && nintra > 0) {
-        // both kinds in one launch: inter-route workgroups first, then one
-        // workgroup per kInterWaves intra-route groups
+        // both kinds in one launch: one workgroup per intra-route group first
+        // (their walks are the launch's longest chains), then the inter-route
+        // workgroups
         const int ninter = std::max(1, std::min(nitems, grid_inter));
-        const int grid = ninter + (nintra + kInterWaves - 1) / kInterWaves;
+        const int nbintra = nintra;
+        const int grid = nbintra + ninter;
         const size_t l = std::max(lds, (size_t)kInterWaves * kIntraRegionBytes);
         if (has_tw) {
             if (dump)
-                k_eval_solution<true, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                k_eval_solution<true, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, nbintra,
                                                                             op_mask, dd, df);
             else
-                k_eval_solution<true, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                k_eval_solution<true, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, nbintra,
                                                                              op_mask, dd, df);
         } else {
             if (dump)
-                k_eval_solution<false, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                k_eval_solution<false, true><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, nbintra,
                                                                              op_mask, dd, df);
             else
-                k_eval_solution<false, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, ninter,
+                k_eval_solution<false, false><<<grid, kInterThreads, l, st>>>(d, items, nitems, intra, nintra, nbintra,
                                                                               op_mask, dd, df);
         }
         return;
@@ -565,7 +567,7 @@ static void launch_eval(const SolDev *d, const InterItem *items, int nitems, con
         }
     }
     if ((op_mask & (2 | 8 | 16)) && nintra > 0) {
-        const int grid = (nintra + kInterWaves - 1) / kInterWaves;
+        const int grid = nintra;  // one workgroup per group: every walk has a compute unit to itself
         const size_t ilds = (size_t)kInterWaves * kIntraRegionBytes;
         if (has_tw) {
             if (dump)

@@ -1534,7 +1534,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     extern __shared__ int4 smem4[];
     const int wave = threadIdx.x >> 6;
     int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
-    for (int itx = blockIdx.x * kInterWaves + wave; itx < nitems; itx += gridDim.x * kInterWaves) {
+    for (int itx = wave * gridDim.x + blockIdx.x; itx < nitems; itx += gridDim.x * kInterWaves) {
         const IntraItem item = items[itx];
         const SolDev &S = sols[item.sol];
         if (S.state[kStDone]) continue;
@@ -1542,20 +1542,23 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
-// Single-solution form with both operator kinds: workgroups below
-// ninter take the inter-route items (as k_eval_inter), the others the
-// intra-route groups (as k_eval_intra), so both run at once in one launch.
-// The dynamic LDS is the larger of the two needs.
+// Single-solution form with both operator kinds: workgroups below nbintra
+// take the intra-route groups (as k_eval_intra; with one workgroup per group
+// every walk has a compute unit to itself), the others the inter-route items
+// (as k_eval_inter), so both run at once in one launch and the long
+// intra-route chains are dispatched first.  The dynamic LDS is the larger of
+// the two needs.
 template <bool TW, bool DUMP>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_solution(
     const SolDev *__restrict__ sols, const InterItem *__restrict__ items, int nitems,
-    const IntraItem *__restrict__ intra, int nintra, int ninter, uint32_t op_mask, int32_t *__restrict__ dump_delta,
+    const IntraItem *__restrict__ intra, int nintra, int nbintra, uint32_t op_mask, int32_t *__restrict__ dump_delta,
     uint8_t *__restrict__ dump_feas) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int thr_sh;
-    if ((int)blockIdx.x < ninter) {
-        for (int it = blockIdx.x; it < nitems; it += ninter) {
+    if ((int)blockIdx.x >= nbintra) {
+        const int ninter = gridDim.x - nbintra;
+        for (int it = blockIdx.x - nbintra; it < nitems; it += ninter) {
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
@@ -1565,9 +1568,9 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
                 inter_item<TW, DUMP, false>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
         }
     } else {
-        const int wave = threadIdx.x >> 6, b = blockIdx.x - ninter, nb = gridDim.x - ninter;
+        const int wave = threadIdx.x >> 6, b = blockIdx.x;
         int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
-        for (int itx = b * kInterWaves + wave; itx < nintra; itx += nb * kInterWaves) {
+        for (int itx = wave * nbintra + b; itx < nintra; itx += nbintra * kInterWaves) {
             const IntraItem item = intra[itx];
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;

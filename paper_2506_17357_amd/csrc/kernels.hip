@@ -1153,11 +1153,16 @@ struct RouteGlobal {
 };
 
 // Moves of route r (L customers, view V) whose first position is i, for
-// i = i0, i0 + di, ... <= L.
-template <bool TW, bool DUMP, class RV>
+// i = i0, i0 + di, ... <= L.  Without SPLIT: all of them; with it only walk per
+// first position: 0 the 2-opt / same-route swap walk, 1..3 the forward and
+// 4..6 the backward or-opt walk of segment length 1..3 (the seven walks
+// cover each move exactly once).
+template <bool TW, bool DUMP, bool SPLIT, class RV>
 __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r, int L, int i0, int di,
-                                            bool capOK, uint32_t op_mask, int32_t *__restrict__ dump_delta,
-                                            uint8_t *__restrict__ dump_feas, int &bd, uint32_t &bid) {
+                                            bool capOK, uint32_t op_mask, int walk_arg,
+                                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas, int &bd,
+                                            uint32_t &bid) {
+    const int walk = SPLIT ? walk_arg : -1;  // a compile-time -1 without the split
     const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
     const int n = S.n;
     const uint32_t uQ = (uint32_t)S.Q;
@@ -1173,7 +1178,7 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
         // along); feasibility, ids and the running minimum are evaluated
         // only where a delta can still reach the lane's best.
         // ---- 2OPT(i, j) and SWAP(i, j), j > i
-        if (op2o || opSwap) {
+        if ((op2o || opSwap) && walk <= 0) {
             Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};
             Seg mid = Seg{0, 0, 0, true};
 #pragma unroll 1
@@ -1225,9 +1230,10 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
                 if (TW) mid = (j == i + 1) ? segAt(j) : seg_cat(mid, ejm, segAt(j));
             }
         }
-        if (!opOr) continue;
+        if (!opOr || walk == 0) continue;
 #pragma unroll 1
         for (int k = 1; k <= 3; ++k) {
+            if (walk > 0 && k != (walk <= 3 ? walk : walk - 3)) continue;
             if (i + k - 1 > L) break;
             // segment c_i..c_{i+k-1} (first f = i, last g = i+k-1), followed by w = i+k
             const int g = i + k - 1, w = i + k;
@@ -1243,7 +1249,7 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
             // ---- forward: right after c_j, j >= i+k (middle c_{i+k} .. c_j)
             Seg mid = Seg{0, 0, 0, true};
 #pragma unroll 1
-            for (int j = w; j <= L; ++j) {
+            for (int j = w; j <= (walk <= 3 ? L : w - 1); ++j) {
                 if (TW) mid = (j == w) ? segAt(j) : seg_cat(mid, V.edge(j - 1), segAt(j));
                 const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
                 const int dlt = base + dVF + dGV - V.edge(j);
@@ -1266,7 +1272,7 @@ __device__ __forceinline__ void intra_moves(const SolDev &S, const RV &V, int r,
             const int zW = TW ? V.z(w) : 0;
             mid = Seg{0, 0, 0, true};
 #pragma unroll 1
-            for (int j = i - 2; j >= 0; --j) {
+            for (int j = i - 2; j >= (walk < 0 || walk >= 4 ? 0 : i - 1); --j) {
                 if (TW) mid = (j == i - 2) ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
                 const int dVF = V.dd(j, i), dGV = V.dd(g, j + 1);
                 const int dlt = base + dVF + dGV - V.edge(j);
@@ -1321,6 +1327,7 @@ __device__ __forceinline__ RouteLds stage_route(const SolDev &S, int off, int L,
 }
 
 constexpr int kIntraMaxGroup = 8;  // routes per intra-route work item
+constexpr int kIntraWalks = 7;     // walks per first position (2-opt / swap, 3 forward and 3 backward or-opt)
 constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while staging
 
 // The P x P distance sub-blocks of G staged routes (route k = r0 + k: P[k]
@@ -1332,7 +1339,7 @@ constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while 
 // kGatherBatch loads in flight before it stores them, so a group costs a
 // couple of memory round trips.
 __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],
-                                                  const int (&at)[kIntraMaxGroup], int G, int r0) {
+                                                  const int (&at)[kIntraMaxGroup], int G, int r0, bool cache) {
     const int lane = threadIdx.x & 63;
     int cum[kIntraMaxGroup + 1];
     cum[0] = 0;
@@ -1343,7 +1350,7 @@ __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, 
     uint32_t hit = 0, fill = 0;
 #pragma unroll
     for (int k = 0; k < kIntraMaxGroup; ++k) {
-        if (k < G && P[k] <= kRouteBlockMaxP) {
+        if (cache && k < G && P[k] <= kRouteBlockMaxP) {
             const int *c = S.rblk + (size_t)(r0 + k) * kRouteBlockWords;
             const bool same = lane >= P[k] || gld(c + kRouteBlockNodes + lane) == region[at[k] + lane];
             const bool ok = __builtin_amdgcn_readfirstlane(gld(c)) == P[k] && __builtin_amdgcn_ballot_w64(!same) == 0;
@@ -1421,12 +1428,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // One wavefront evaluates every intra-route move of routes [r0, r1) of one
-// solution and commits the best to the solution's key.  When all their
-// positions fit (sum of L <= 64 first positions, staged data within the
-// wavefront's LDS region), lane l takes one (route, first position) pair of
-// the whole group; otherwise routes are taken one at a time.
-template <bool TW, bool DUMP>
-__device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+// solution (with SPLIT, only the moves of walk `walk`, so that seven
+// wavefronts share a group) and commits the best to the solution's key.
+// When all their positions fit (sum of L <= 64 first positions, staged data
+// within the wavefront's LDS region), lane l takes one (route, first
+// position) pair of the whole group; otherwise routes are taken one at a
+// time.  Only a wavefront that evaluates every walk of its routes (no SPLIT,
+// or walk 0) reads or rewrites the route distance-block cache, so no two
+// wavefronts of a launch ever touch the same entry.
+template <bool TW, bool DUMP, bool SPLIT = false>
+__device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &item, uint32_t op_mask, int walk,
                                             int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
                                             int *region) {
     const int lane = threadIdx.x & 63;
@@ -1466,7 +1477,7 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
                 at[k] = w;
                 w += 7 * Pk[k] + Pk[k] * Pk[k];
             }
-            stage_dist_blocks(S, region, Pk, at, G, item.r0);
+            stage_dist_blocks(S, region, Pk, at, G, item.r0, !SPLIT || walk == 0);
         }
         wave_lds_sync();
         // lane -> (route k, first position i) and that route's staged view
@@ -1491,7 +1502,7 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
             int *b = region + myBase;
             const RouteLds V{b, b + P, b + 2 * P, b + 3 * P, b + 4 * P, b + 5 * P, b + 6 * P, b + 7 * P, P};
             const bool capOK = gld(S.b4 + myOff).z <= S.cap;
-            intra_moves<TW, DUMP>(S, V, item.r0 + myk, myL, myi, 1 << 30, capOK, op_mask, dump_delta, dump_feas,
+            intra_moves<TW, DUMP, SPLIT>(S, V, item.r0 + myk, myL, myi, 1 << 30, capOK, op_mask, walk, dump_delta, dump_feas,
                                   bd, bid);
         }
         wave_lds_sync();
@@ -1512,14 +1523,14 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
                         Pk[k] = k == 0 ? P : 0;
                         at[k] = 0;
                     }
-                    stage_dist_blocks(S, region, Pk, at, 1, r);
+                    stage_dist_blocks(S, region, Pk, at, 1, r, !SPLIT || walk == 0);
                 }
                 wave_lds_sync();
-                intra_moves<TW, DUMP>(S, V, r, L, lane + 1, 64, capOK, op_mask, dump_delta, dump_feas, bd, bid);
+                intra_moves<TW, DUMP, SPLIT>(S, V, r, L, lane + 1, 64, capOK, op_mask, walk, dump_delta, dump_feas, bd, bid);
                 wave_lds_sync();
             } else {
                 const RouteGlobal V{&S, off, L, l0};
-                intra_moves<TW, DUMP>(S, V, r, L, lane + 1, 64, capOK, op_mask, dump_delta, dump_feas, bd, bid);
+                intra_moves<TW, DUMP, SPLIT>(S, V, r, L, lane + 1, 64, capOK, op_mask, walk, dump_delta, dump_feas, bd, bid);
             }
         }
     }
@@ -1534,11 +1545,18 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     extern __shared__ int4 smem4[];
     const int wave = threadIdx.x >> 6;
     int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+    if ((int)gridDim.x >= nitems) {  // one workgroup per group: wavefront w < 7 takes walk w
+        const IntraItem item = items[blockIdx.x];
+        const SolDev &S = sols[item.sol];
+        if (wave < kIntraWalks && !S.state[kStDone])
+            intra_group<TW, DUMP, true>(S, item, op_mask, wave, dump_delta, dump_feas, region);
+        return;
+    }
     for (int itx = wave * gridDim.x + blockIdx.x; itx < nitems; itx += gridDim.x * kInterWaves) {
         const IntraItem item = items[itx];
         const SolDev &S = sols[item.sol];
         if (S.state[kStDone]) continue;
-        intra_group<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
+        intra_group<TW, DUMP>(S, item, op_mask, -1, dump_delta, dump_feas, region);
     }
 }
 
@@ -1570,11 +1588,18 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     } else {
         const int wave = threadIdx.x >> 6, b = blockIdx.x;
         int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
-        for (int itx = wave * nbintra + b; itx < nintra; itx += nbintra * kInterWaves) {
-            const IntraItem item = intra[itx];
+        if (nbintra >= nintra) {  // one workgroup per group: wavefront w < 7 takes walk w
+            const IntraItem item = intra[b];
             const SolDev &S = sols[item.sol];
-            if (S.state[kStDone]) continue;
-            intra_group<TW, DUMP>(S, item, op_mask, dump_delta, dump_feas, region);
+            if (wave < kIntraWalks && !S.state[kStDone])
+                intra_group<TW, DUMP, true>(S, item, op_mask, wave, dump_delta, dump_feas, region);
+        } else {
+            for (int itx = wave * nbintra + b; itx < nintra; itx += nbintra * kInterWaves) {
+                const IntraItem item = intra[itx];
+                const SolDev &S = sols[item.sol];
+                if (S.state[kStDone]) continue;
+                intra_group<TW, DUMP>(S, item, op_mask, -1, dump_delta, dump_feas, region);
+            }
         }
     }
 }
@@ -1611,9 +1636,9 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const SolDev &S = sols[item.sol];
             if (S.state[kStDone]) continue;
             if (S.has_tw)
-                intra_group<true, false>(S, item, op_mask, nullptr, nullptr, region);
+                intra_group<true, false>(S, item, op_mask, -1, nullptr, nullptr, region);
             else
-                intra_group<false, false>(S, item, op_mask, nullptr, nullptr, region);
+                intra_group<false, false>(S, item, op_mask, -1, nullptr, nullptr, region);
         }
     }
     __syncthreads();  // the intra-route regions and the inter-route rows share LDS

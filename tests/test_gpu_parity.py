@@ -147,13 +147,16 @@ def test_dump_2000_vrptw(tga):
     check_dump(tga, inst, sol, tag="vrptw2000")
 
 
-def test_dump_long_routes(tga):
-    """Routes longer than a wavefront (intra-route lanes wrap)."""
+@pytest.mark.parametrize("op_mask", [0x1F, 8 | 16])
+def test_dump_long_routes(tga, op_mask):
+    """Routes longer than a wavefront (intra-route lanes wrap, and a route
+    too long for LDS is read from global memory), with all operators and
+    with the intra-route ones alone (their own launch)."""
     inst = W.tiny_instance(300, 31, True, capacity=10 ** 6, span=1000)
     inst.node4[:, 2] = np.maximum(inst.node4[:, 2], 1 << 20)  # loose windows
     inst.node4[0, 2] = 1 << 22
     sol = W.random_solution(inst, 2, 32)
-    check_dump(tga, inst, sol, tag="long")
+    check_dump(tga, inst, sol, op_mask, tag="long")
 
 
 @pytest.mark.parametrize("has_tw", [0, 1])

@@ -1332,10 +1332,11 @@ constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while 
 
 // The P x P distance sub-blocks of G staged routes (route k = r0 + k: P[k]
 // positions, staged at word offset at[k] of the region, nodes first):
-// element y of route k's block is D[node(y / P)][node(y % P)].  A route whose
-// cache entry holds the same P and nodes copies its block from there
-// (LDS DMA); any other route gathers it from D and, when
-// P <= kRouteBlockMaxP, rewrites its entry.  Each lane keeps up to
+// element y of route k's block is D[node(y / P)][node(y % P)].  With cache,
+// a route whose cache entry holds the same P and nodes copies its block from
+// there (LDS DMA) and any other route gathers it from D and, when
+// P <= kRouteBlockMaxP, rewrites its entry; without it every block is
+// gathered and no entry is read or written.  Each lane keeps up to
 // kGatherBatch loads in flight before it stores them, so a group costs a
 // couple of memory round trips.
 __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],

@@ -1547,6 +1547,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     const int wave = threadIdx.x >> 6;
     int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
     if ((int)gridDim.x >= nitems) {  // one workgroup per group: wavefront w < 7 takes walk w
+        if ((int)blockIdx.x >= nitems) return;
         const IntraItem item = items[blockIdx.x];
         const SolDev &S = sols[item.sol];
         if (wave < kIntraWalks && !S.state[kStDone])
@@ -1590,6 +1591,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         const int wave = threadIdx.x >> 6, b = blockIdx.x;
         int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
         if (nbintra >= nintra) {  // one workgroup per group: wavefront w < 7 takes walk w
+            if (b >= nintra) return;
             const IntraItem item = intra[b];
             const SolDev &S = sols[item.sol];
             if (wave < kIntraWalks && !S.state[kStDone])

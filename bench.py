@@ -143,7 +143,7 @@ def served(args):
     log("requests generated in %.1f s" % (time.time() - t))
     budget = int(args.hbm_budget_gb * (1 << 30))
     # closed loop (everything queued at t = 0) measures the capacity
-    srv = serve.Server(budget)
+    srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
     t0 = time.perf_counter()
     res0 = srv.run(reqs)
     t_closed = time.perf_counter() - t0
@@ -154,7 +154,7 @@ def served(args):
     arrivals = W.request_stream(args.requests, qps=qps, max_steps=args.served_steps)
     for q, a in zip(reqs, arrivals):
         q.arrival_s = a.arrival_s
-    srv = serve.Server(budget)
+    srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
     t0 = time.perf_counter()
     res = srv.run(reqs, log=log)
     t_open = time.perf_counter() - t0
@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--served", action="store_true", help="benchmark the served form instead")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--served-steps", type=int, default=500)
+    ap.add_argument("--steps-per-tick", type=int, default=2,
+                    help="served form: local-search steps per scheduling tick (one poll per tick)")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")

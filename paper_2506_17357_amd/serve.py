@@ -4,9 +4,10 @@ Requests (an instance, a starting solution, a step cap) arrive over time.
 A request is admitted when its device bytes (distance matrix, node data,
 instance and solution workspaces) fit in the HBM budget still free; its data
 are uploaded on a copy stream while the compute stream keeps stepping the
-requests already on the device.  Every engine tick runs one batched step
-(one persistent evaluation launch + one finalize launch; `steps_per_tick`
-of them if asked) over all admitted requests; a request leaves when it reaches a local optimum or its cap, its
+requests already on the device.  Every engine tick runs `steps_per_tick`
+batched steps (each one persistent evaluation launch + one finalize launch;
+two by default, which halves the host polls at the cost of at most one
+step of latency) over all admitted requests; a request leaves when it reaches a local optimum or its cap, its
 memory is returned, and queued requests are admitted.  Results do not depend
 on what else is in the batch: each solution's step only reads its own data.
 """
@@ -59,7 +60,7 @@ def device_bytes(inst, R: int) -> int:
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
-                 device: str = "cuda", steps_per_tick: int = 1):
+                 device: str = "cuda", steps_per_tick: int = 2):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.steps_per_tick = int(steps_per_tick)

@@ -212,8 +212,7 @@ def main():
         sys.exit(2)
     K, Wm = args.steps, args.warmup
     from paper_2506_17357_amd import build_lib
-    if not os.path.exists(build_lib.LIB):
-        build_lib.build(verbose=True)
+    build_lib.ensure_built(verbose=True)
     if args.served:
         served(args)
         return

@@ -19,7 +19,9 @@
  * - Return value: TGA_OK (0) on success, TGA_ENOMOVE (1) when no move is
  *   admissible (not an error), a negative TGA_E* code on failure.  On failure
  *   tga_last_error() returns a message (thread-local, valid until the next
- *   call on the same thread).  Validation happens before any device work.
+ *   call on the same thread).  Arguments are validated before any device
+ *   work; the exceptions are stated per call (instance values checked on the
+ *   device by tga_load_instance, move ids by tga_apply_move).
  * - Device memory is owned by the caller (typically PyTorch tensors).  The
  *   library borrows the buffers for the lifetime of the handle that received
  *   them and never frees them.  Host arrays are read during the call only.
@@ -150,9 +152,12 @@ int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best
 /* Section 5.3.5 and Alg. A2: apply a move to the solution on the device and
  * rebuild every attribute.  The move need not be improving or admissible.
  * Returns TGA_ESTALE if move->version is not the solution's current version
- * and TGA_EINVAL if move->id is not a move of N(S).  On success the version
- * increases by one and *new_cost (nullable) receives the total distance.
- * Synchronises `stream`. */
+ * (checked on the host) and TGA_EINVAL if move->id is not a move of N(S):
+ * ids of 20*Q*Q or more are refused on the host; whether a smaller id names
+ * a move of the current routes is decided on the device by the launch that
+ * would apply it, which then leaves the solution unchanged.  On success the
+ * version increases by one and *new_cost (nullable) receives the total
+ * distance.  Synchronises `stream`. */
 int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream);
 
 /* Alg. A2 run on the device: repeat {evaluate, apply the best move if its
@@ -253,8 +258,10 @@ int tga_batch_collect(tga_batch_t b, int32_t *steps_done, int64_t *moves_evaluat
  * gathered on the device and copied in one transfer.  Synchronises. */
 int tga_batch_poll(tga_batch_t b, int32_t *done, void *stream);
 
-/* One evaluation of every solution in the batch (no apply); best moves to a
- * host array of `count` records; per-solution status to status (nullable). */
+/* One evaluation of every solution in the batch (no apply), converged ones
+ * included; best moves to a host array of `count` records; per-solution
+ * status to status (nullable).  Converged flags and step counters are left
+ * as they are. */
 int tga_batch_eval(tga_batch_t b, uint32_t op_mask, tga_move_t *best, int32_t *status,
                    void *stream);
 

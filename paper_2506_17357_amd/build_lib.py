@@ -14,7 +14,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",
-    # keep hipcc from emitting packed fp32 instructions
+    # keep the device code free of packed fp32 instructions (the device pass
+    # honours the feature; only hipcc's host pass warns that it does not know it)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
@@ -28,6 +29,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    return LIB
+
+
+def ensure_built(verbose: bool = False) -> str:
+    """Build when the library is missing or older than any of its sources."""
+    if is_stale():
+        build(verbose=verbose)
     return LIB
 
 

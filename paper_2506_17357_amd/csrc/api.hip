@@ -351,28 +351,28 @@ static void build_plain_items(tga_solution *S, std::vector<InterItem> &items,
     push_intra_groups(S->n, S->R, sol_index, intra);
 }
 
-extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
-                                const int32_t *customers, void *ws, size_t ws_bytes, void *stream,
-                                tga_solution_t *out) {
-    if (!out) return fail(TGA_EINVAL, "out is null");
-    *out = nullptr;
-    if (!inst || !offsets || !customers || !ws) return fail(TGA_EINVAL, "null argument");
+// Argument checks shared by every way of setting up a solution.
+static int check_solution_args(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                               const int32_t *customers) {
+    if (!inst || !offsets || !customers) return fail(TGA_EINVAL, "null argument");
     const int n = inst->n;
     if (R < 1) return fail(TGA_ERANGE, "R = %d < 1", R);
     if ((int64_t)n + R > TGA_MAX_Q) return fail(TGA_ERANGE, "n + R = %lld > %d", (long long)n + R, TGA_MAX_Q);
     if ((int64_t)(n + R + 1) * inst->maxD >= (1 << 30)) return fail(TGA_ERANGE, "total distance may exceed 2^30");
-    {
-        int rc0 = check_partition(n, R, offsets, customers);
-        if (rc0) return rc0;
-    }
+    return check_partition(n, R, offsets, customers);
+}
+
+// Lay a solution out in the workspace at `ws` (checked by the caller: large
+// enough, 256-byte aligned), upload its routes and build its attributes.
+// Fills *S; synchronises `st`.  Allocates no device or pinned memory.
+static int solution_init(tga_solution *S, tga_instance_t inst, int32_t R, const int32_t *offsets,
+                         const int32_t *customers, void *ws, hipStream_t st) {
+    const int n = inst->n;
     const SolLayout L = sol_layout(n, R);
-    if (ws_bytes < L.total) return fail(TGA_ENOMEM, "solution workspace %zu < %zu", ws_bytes, L.total);
-    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
     DevProps P;
     int rc = props(&P);
     if (rc) return rc;
     const int Q = n + R, np1 = n + 1;
-    tga_solution *S = new tga_solution();
     S->inst = inst;
     S->n = n;
     S->R = R;
@@ -381,11 +381,9 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     S->tile_rows = default_tile_rows(np1, w16);
     S->plain_rows = plain_rows(Q, np1, w16);
     S->lds = rows_lds(np1, S->plain_rows, w16);
-    if (S->lds > (size_t)P.max_lds) {
-        delete S;
+    if (S->lds > (size_t)P.max_lds)
         return fail(TGA_ERANGE, "n = %d needs %zu bytes of LDS per workgroup (device: %d)", n,
                     rows_lds(np1, 1, w16), P.max_lds);
-    }
     char *base = (char *)ws;
     SolDev &h = S->h;
     memset(&h, 0, sizeof h);
@@ -435,11 +433,7 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
     build_plain_items(S, items, intra, 0);
     S->nitems = (int)items.size();
     S->nintra = (int)intra.size();
-    if (S->nitems > L.max_items) {
-        delete S;
-        return fail(TGA_ERANGE, "too many work items");
-    }
-    hipStream_t st = (hipStream_t)stream;
+    if (S->nitems > L.max_items) return fail(TGA_ERANGE, "too many work items");
     std::vector<int32_t> state(16, 0);
     std::vector<long long> acc(kAccCount, 0);
     auto up = [&](void *dst, const void *src, size_t bytes) {
@@ -459,9 +453,25 @@ extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *o
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
+    if (e != hipSuccess) return fail(TGA_EDEVICE, "set_solution: %s", hipGetErrorString(e));
+    return TGA_OK;
+}
+
+extern "C" int tga_set_solution(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                                const int32_t *customers, void *ws, size_t ws_bytes, void *stream,
+                                tga_solution_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!ws) return fail(TGA_EINVAL, "null argument");
+    int rc = check_solution_args(inst, R, offsets, customers);
+    if (rc) return rc;
+    const SolLayout L = sol_layout(inst->n, R);
+    if (ws_bytes < L.total) return fail(TGA_ENOMEM, "solution workspace %zu < %zu", ws_bytes, L.total);
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    tga_solution *S = new tga_solution();
+    if ((rc = solution_init(S, inst, R, offsets, customers, ws, (hipStream_t)stream))) {
         delete S;
-        return fail(TGA_EDEVICE, "set_solution: %s", hipGetErrorString(e));
+        return rc;
     }
     *out = S;
     return TGA_OK;
@@ -594,6 +604,27 @@ static void to_move(const int32_t *rec, tga_move_t *m) {
     m->version = (uint32_t)rec[7];
 }
 
+// One evaluation of a solution whose workspace is set up: evaluation launch,
+// record-mode finalize, and one copy of the record and state[0..3] into
+// `host` (48 bytes; pinned or pageable).
+static int eval_record(tga_solution *sol, uint32_t op_mask, tga_move_t *best, int32_t *dump_delta,
+                       uint8_t *dump_feas, hipStream_t st, int32_t *host) {
+    launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
+                sol->lds, sol->nitems, dump_delta, dump_feas, st);
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, sol->h.rec, 32 + 16, hipMemcpyDeviceToHost, st));  // record, state[0..3]
+    HIPCHK(hipStreamSynchronize(st));
+    if (host[8 + kStStatus] == 1) {
+        memset(best, 0, sizeof *best);
+        best->version = sol->version;
+        return TGA_ENOMOVE;
+    }
+    to_move(host, best);
+    best->version = sol->version;
+    return TGA_OK;
+}
+
 extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best,
                                      int32_t *dump_delta, uint8_t *dump_feas, void *stream) {
     if (!sol || !best) return fail(TGA_EINVAL, "null argument");
@@ -601,28 +632,12 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
         return fail(TGA_EINVAL, "dump_delta and dump_feas must both be set or both be null");
     if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
-    hipStream_t st = (hipStream_t)stream;
     DevProps P;
     int rc = props(&P);
     if (rc) return rc;
     void *pin;
     if ((rc = pinned(&pin))) return rc;
-    launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
-                sol->lds, sol->nitems, dump_delta, dump_feas, st);
-    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(pin, sol->h.rec, 32 + 16, hipMemcpyDeviceToHost, st));  // record, state[0..3]
-    HIPCHK(hipStreamSynchronize(st));
-    const int32_t *rec = (const int32_t *)pin;
-    const int32_t status = ((const int32_t *)pin)[8 + kStStatus];
-    if (status == 1) {
-        memset(best, 0, sizeof *best);
-        best->version = sol->version;
-        return TGA_ENOMOVE;
-    }
-    to_move(rec, best);
-    best->version = sol->version;
-    return TGA_OK;
+    return eval_record(sol, op_mask, best, dump_delta, dump_feas, (hipStream_t)stream, (int32_t *)pin);
 }
 
 extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream) {
@@ -1257,7 +1272,8 @@ extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best,
     if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
-    k_reset_state<<<(n + 63) / 64, 64, 0, st>>>(B->d, n, 0);
+    // a record evaluation covers converged solutions too, so their flags and
+    // counters stay as they are
     batch_step(B, op_mask, kModeRecord, st);
     HIPCHK(hipGetLastError());
     std::vector<int32_t> rec(8 * n), state(16 * n);

@@ -103,6 +103,12 @@ __device__ __forceinline__ int initial_bound(uint32_t op_mask) {
     return (op_mask & kImprovingOnly) ? 0 : kAdmissibleBound;
 }
 
+// A local-search evaluation skips a solution that has converged (or reached
+// its step cap); any other evaluation covers every solution, converged or not.
+__device__ __forceinline__ bool skip_solution(const SolDev &S, uint32_t op_mask) {
+    return (op_mask & kImprovingOnly) && S.state[kStDone];
+}
+
 __device__ __forceinline__ unsigned long long pack_key(int delta, uint32_t id) {
     return ((unsigned long long)((uint32_t)delta ^ 0x80000000u) << 32) | id;
 }
@@ -1103,7 +1109,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const InterItem item = items[it];
         const SolDev &S = sols[item.sol];
-        if (S.state[kStDone]) continue;
+        if (skip_solution(S, op_mask)) continue;
         if (S.D16)
             inter_item<TW, DUMP, true>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
         else
@@ -1550,14 +1556,14 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         if ((int)blockIdx.x >= nitems) return;
         const IntraItem item = items[blockIdx.x];
         const SolDev &S = sols[item.sol];
-        if (wave < kIntraWalks && !S.state[kStDone])
+        if (wave < kIntraWalks && !skip_solution(S, op_mask))
             intra_group<TW, DUMP, true>(S, item, op_mask, wave, dump_delta, dump_feas, region);
         return;
     }
     for (int itx = wave * gridDim.x + blockIdx.x; itx < nitems; itx += gridDim.x * kInterWaves) {
         const IntraItem item = items[itx];
         const SolDev &S = sols[item.sol];
-        if (S.state[kStDone]) continue;
+        if (skip_solution(S, op_mask)) continue;
         intra_group<TW, DUMP>(S, item, op_mask, -1, dump_delta, dump_feas, region);
     }
 }
@@ -1581,7 +1587,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         for (int it = blockIdx.x - nbintra; it < nitems; it += ninter) {
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
-            if (S.state[kStDone]) continue;
+            if (skip_solution(S, op_mask)) continue;
             if (S.D16)
                 inter_item<TW, DUMP, true>(S, item, op_mask, dump_delta, dump_feas, smem4, red, &thr_sh);
             else
@@ -1594,13 +1600,13 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             if (b >= nintra) return;
             const IntraItem item = intra[b];
             const SolDev &S = sols[item.sol];
-            if (wave < kIntraWalks && !S.state[kStDone])
+            if (wave < kIntraWalks && !skip_solution(S, op_mask))
                 intra_group<TW, DUMP, true>(S, item, op_mask, wave, dump_delta, dump_feas, region);
         } else {
             for (int itx = wave * nbintra + b; itx < nintra; itx += nbintra * kInterWaves) {
                 const IntraItem item = intra[itx];
                 const SolDev &S = sols[item.sol];
-                if (S.state[kStDone]) continue;
+                if (skip_solution(S, op_mask)) continue;
                 intra_group<TW, DUMP>(S, item, op_mask, -1, dump_delta, dump_feas, region);
             }
         }
@@ -1637,7 +1643,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
         for (int it = ixoff[x] + j * kInterWaves + wave; it < end; it += step * kInterWaves) {
             const IntraItem item = intra[it];
             const SolDev &S = sols[item.sol];
-            if (S.state[kStDone]) continue;
+            if (skip_solution(S, op_mask)) continue;
             if (S.has_tw)
                 intra_group<true, false>(S, item, op_mask, -1, nullptr, nullptr, region);
             else
@@ -1654,7 +1660,7 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const int it = back ? first + cnt - 1 - k : first + k;
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
-            if (S.state[kStDone]) continue;
+            if (skip_solution(S, op_mask)) continue;
             if (S.has_tw) {
                 if (S.D16)
                     inter_item<true, false, true>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);

@@ -356,9 +356,3 @@ def device_limits():
     _check(lib().tga_device_limits(ctypes.byref(cu), ctypes.byref(lds)))
     return int(cu.value), int(lds.value)
 
-
-def decode(Q: int, move_id: int):
-    """(op, k, a, b) of a move id."""
-    qq = Q * Q
-    opk, rem = divmod(int(move_id), qq)
-    return opk // 4, opk % 4, rem // Q, rem % Q

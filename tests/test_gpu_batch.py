@@ -105,6 +105,27 @@ def test_batch_eval_equals_single(tga):
             assert (best[b].delta, best[b].id) == (ob.delta, ob.id), b
 
 
+def test_batch_eval_after_ls_run(tga):
+    """A record evaluation after a batched local search covers the converged
+    solutions too and leaves their flags and counters as they were."""
+    pairs = small_mix(8, seed=6)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    steps, moves, cost = B.ls_run(600, use_graph=False)
+    done = B.poll()
+    assert done.all()
+    best, status = B.eval()
+    assert (B.poll() == done).all()
+    assert B.collect()[0].tolist() == steps.tolist()
+    for b, s in enumerate(sols):
+        off, cust, _ = s.get()
+        ob = oracle.eval_neighbourhood(pairs[b][0], W.Solution(off, cust))
+        assert status[b] == (0 if ob.found else 1), b
+        if ob.found:
+            assert (best[b].delta, best[b].id) == (ob.delta, ob.id), b
+            assert best[b].delta >= 0, b
+
+
 @pytest.mark.parametrize("rows_per_item,sub_rows", [(1, 1), (2, 3), (5, 1), (0, 2), (7, 3), (0, 0), (100, 8)])
 def test_schedule_does_not_change_results(tga, rows_per_item, sub_rows):
     pairs = small_mix(6, seed=3)

@@ -346,3 +346,26 @@ def test_single_customer(tga):
     for R in (1, 3):
         sol = W.random_solution(inst, R, 82)
         check_dump(tga, inst, sol, tag="n1")
+
+
+@pytest.mark.parametrize("has_tw", [0, 1])
+@pytest.mark.parametrize("cap", [7, 100000])
+def test_eval_after_ls_run(tga, has_tw, cap):
+    """An evaluation after a device local search (stopped at the step cap or
+    at the local optimum) still covers every move of the current routes."""
+    inst = W.make_vrptw(150, 33) if has_tw else W.make_cvrp(150, 33)
+    sol = W.sweep(inst)
+    I, S = gpu_solution(tga, inst, sol)
+    steps, _, cost = S.ls_run(cap)
+    assert (steps == cap) == (cap == 7)
+    off, cust, _ = S.get()
+    cur = W.Solution(off, cust)
+    ob, odd, odf = oracle.eval_neighbourhood(inst, cur, 0x1F, dump=True, threads=0)
+    gb, gdd, gdf = S.eval(0x1F, dump=True)
+    assert np.array_equal(gdf.cpu().numpy(), odf) and np.array_equal(gdd.cpu().numpy(), odd)
+    assert ob.found and (gb.delta, gb.id) == (ob.delta, ob.id)
+    if cap > steps:
+        assert gb.delta >= 0  # a local optimum
+    m = S.eval()
+    assert (m.delta, m.id) == (ob.delta, ob.id)
+    assert S.stats()[0] == steps  # the evaluation leaves the run's counters alone

@@ -149,6 +149,27 @@ int tga_solution_reload(tga_solution_t sol, const int32_t *offsets, const int32_
 int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best,
                           int32_t *dump_delta, uint8_t *dump_feas, void *stream);
 
+/* For callers that cannot allocate device memory (code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the
+ * result of tga_set_solution followed by tga_eval_neighborhood(op_mask, no
+ * dump) on the routes given, without a caller workspace.  The solution's
+ * attribute arrays and work lists go into a library-owned static device
+ * buffer of TGA_STATIC_SCRATCH_BYTES per GPU (held from the library's load
+ * until the process ends); the call allocates no device or pinned memory.
+ *   inst      a loaded instance (its buffers as for tga_load_instance).
+ *   R, offsets, customers   as for tga_set_solution (host arrays).
+ *   best      host; the best admissible move, version 0.
+ * Returns TGA_ENOMOVE as tga_eval_neighborhood does, and TGA_ERANGE when
+ * the solution needs more than TGA_STATIC_SCRATCH_BYTES (the workspace size
+ * tga_solution_workspace_bytes reports; 8 MiB holds n = 10^4 customers with
+ * up to about 1000 routes).  Every call on one GPU uses that
+ * GPU's one buffer and overwrites what the previous call left there: calls
+ * that overlap on one GPU (other host threads, or other streams before the
+ * previous call returned) race.  Synchronises `stream`. */
+#define TGA_STATIC_SCRATCH_BYTES (8u << 20)
+int tga_eval_routes_static(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                           const int32_t *customers, uint32_t op_mask, tga_move_t *best, void *stream);
+
 /* Section 5.3.5 and Alg. A2: apply a move to the solution on the device and
  * rebuild every attribute.  The move need not be improving or admissible.
  * Returns TGA_ESTALE if move->version is not the solution's current version

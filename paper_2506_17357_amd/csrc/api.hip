@@ -640,6 +640,58 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
     return eval_record(sol, op_mask, best, dump_delta, dump_feas, (hipStream_t)stream, (int32_t *)pin);
 }
 
+// ------------------------------------------------- no-allocation variant ----
+
+// Per-device scratch of tga_eval_routes_static: the solution workspace
+// (descriptor, slot attributes, work lists) of the call.  Each GPU the
+// library runs on holds one copy until the process ends.  In host code the
+// name stands for the host-side shadow, not a device address: kernels and
+// copies take the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[TGA_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_ptr(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TGA_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return fail(TGA_EDEVICE, "scratch symbol address %p", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TGA_OK;
+}
+}  // namespace
+
+extern "C" int tga_eval_routes_static(tga_instance_t inst, int32_t R, const int32_t *offsets,
+                                      const int32_t *customers, uint32_t op_mask, tga_move_t *best,
+                                      void *stream) {
+    if (!best) return fail(TGA_EINVAL, "null argument");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    int rc = check_solution_args(inst, R, offsets, customers);
+    if (rc) return rc;
+    const size_t need = sol_layout(inst->n, R).total;
+    if (need > (size_t)TGA_STATIC_SCRATCH_BYTES)
+        return fail(TGA_ERANGE, "n = %d, R = %d needs %zu bytes of scratch (maximum %zu)", inst->n, R, need,
+                    (size_t)TGA_STATIC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    tga_solution S{};  // lives for this call only; its arrays are in the scratch
+    if ((rc = solution_init(&S, inst, R, offsets, customers, ws, st))) return rc;
+    int32_t host[12];  // record and state[0..3]: pageable, so nothing is allocated
+    return eval_record(&S, op_mask, best, nullptr, nullptr, st, host);
+}
+
 extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream) {
     if (!sol || !move) return fail(TGA_EINVAL, "null argument");
     if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");

@@ -61,6 +61,7 @@ EXPORTS = [
     "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
     "tga_solution_reload", "tga_solution_begin", "tga_batch_poll", "tga_solution_stats",
     "tga_instance_dist_bytes", "tga_batch_get_config", "tga_batch_set_config", "tga_batch_autotune",
+    "tga_eval_routes_static",
 ]
 
 
@@ -81,6 +82,7 @@ def lib():
         "tga_load_instance": (i32, [i32, P, P, i32, i32, P, sz, P, pp]),
         "tga_set_solution": (i32, [P, i32, P, P, P, sz, P, pp]),
         "tga_eval_neighborhood": (i32, [P, u32, ctypes.POINTER(Move), P, P, P]),
+        "tga_eval_routes_static": (i32, [P, i32, P, P, u32, ctypes.POINTER(Move), P]),
         "tga_apply_move": (i32, [P, ctypes.POINTER(Move), P, P]),
         "tga_ls_run": (i32, [P, u32, i32, P, P, P, P]),
         "tga_get_solution": (i32, [P, P, P, P, P]),
@@ -356,3 +358,18 @@ def device_limits():
     _check(lib().tga_device_limits(ctypes.byref(cu), ctypes.byref(lds)))
     return int(cu.value), int(lds.value)
 
+
+STATIC_SCRATCH_BYTES = 8 << 20  # TGA_STATIC_SCRATCH_BYTES
+
+
+def eval_routes_static(inst: "Instance", offsets, customers, op_mask: int = OPS_ALL, stream=None):
+    """Best admissible move (or None) of the given routes, evaluated in the
+    library's static per-GPU scratch (tga_eval_routes_static: no workspace,
+    nothing allocated)."""
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(customers, dtype=np.int32)
+    m = Move()
+    rc = _check(lib().tga_eval_routes_static(inst.h, int(off.shape[0] - 1), _np_ptr(off), _np_ptr(cust),
+                                            op_mask, ctypes.byref(m), _stream(stream)),
+                allow=(TGA_OK, TGA_ENOMOVE))
+    return None if rc == TGA_ENOMOVE else m

@@ -46,3 +46,11 @@ def test_workspace_size_queries_need_no_device():
     assert lib.tga_solution_workspace_bytes(14000, 655) == 0  # n + R > 14654
     assert lib.tga_solution_workspace_bytes(10, 0) == 0
     assert lib.tga_instance_workspace_bytes(0) == 0
+
+
+def test_static_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define TGA_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m
+    from paper_2506_17357_amd import tga
+    assert tga.STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))

@@ -306,6 +306,53 @@ int tga_batch_set_config(tga_batch_t b, const tga_batch_config_t *cfg, void *str
 int tga_batch_autotune(tga_batch_t b, uint32_t op_mask, int32_t launches, tga_batch_config_t *best,
                        void *stream);
 
+/* ------------------------------------------------------- slot batches --
+ * Served form (continuous batching): a batch with a fixed number of slots
+ * whose members change while it runs.  Each member steps on its own until a
+ * local optimum or the step cap set by tga_solution_begin; a converged
+ * member costs nothing and can be replaced.  Membership changes and ticks
+ * are asynchronous: nothing here waits for the device, except that the host
+ * never runs more than two ticks (and two plan uploads) ahead of it.  The
+ * launch shapes, and so a captured tick, stay valid across membership
+ * changes.  Every batch call above also accepts a slot batch (empty slots
+ * are skipped: converged, no move, zero counters). */
+
+/* Device workspace bytes for `slots` slots whose members together hold at
+ * most max_sum_q refs (sum of n + R) and max_sum_r routes.  0 if out of
+ * range (1 <= slots <= 1024). */
+size_t tga_batch_slots_workspace_bytes(int32_t slots, int32_t max_sum_q, int32_t max_sum_r);
+
+/* An empty slot batch; allocates two pinned staging buffers and two pinned
+ * result buffers (host).  Same ownership rules as tga_batch_create. */
+int tga_batch_create_slots(int32_t slots, int32_t max_sum_q, int32_t max_sum_r, void *ws,
+                           size_t ws_bytes, void *stream, tga_batch_t *out);
+
+/* Replace the membership: sols holds one entry per slot (NULL = empty).  A
+ * solution keeps its slot for as long as it is a member; a new member needs
+ * tga_solution_begin (on the same stream, before its first tick) and must
+ * not belong to another batch.  The new plan is uploaded on `stream` and
+ * takes effect for the ticks enqueued after this call; ticks already
+ * enqueued still use the old members, so a removed solution's memory may be
+ * reused only once those have finished (e.g. after an event recorded on
+ * `stream` after this call).  TGA_ERANGE when the members exceed the sizes
+ * the batch was created for. */
+int tga_batch_set_members(tga_batch_t b, const tga_solution_t *sols, void *stream);
+
+/* Enqueue one tick: `steps` (1..64) local-search steps of every member (the
+ * step loop captured once per (steps, op_mask) and replayed), then the
+ * per-slot results are copied into a pinned buffer.  *tick (nullable) = the
+ * tick's number (0, 1, ...).  Blocks only while two earlier ticks are still
+ * running. */
+int tga_batch_tick(tga_batch_t b, uint32_t op_mask, int32_t steps, int32_t *tick, void *stream);
+
+/* Per-slot results of the newest finished tick, without waiting: *tick = its
+ * number, or -1 when none has finished (the arrays are then untouched).
+ * Host arrays of `slots` entries (nullable): converged flag, accepted moves,
+ * moves evaluated, cost.  A slot's entry describes the member it had when
+ * that tick was enqueued. */
+int tga_batch_tick_status(tga_batch_t b, int32_t *tick, int32_t *converged, int32_t *steps_done,
+                          int64_t *moves_evaluated, int64_t *cost);
+
 int tga_batch_free(tga_batch_t b);
 
 #ifdef __cplusplus

@@ -100,6 +100,7 @@ size_t lds_budget() {
     return b;
 }
 
+constexpr int kMaxSlots = 1024;   // slots of a slot batch (served form)
 constexpr int kMaxTileRows = 64;  // rows per inter-route sub-block (128 was slower on the mix)
 
 // LDS of an inter-route workgroup with sub-blocks of h rows: the h rows and
@@ -229,6 +230,22 @@ struct tga_batch {
     int graph_steps;
     uint32_t graph_mask;
     hipStream_t cap_stream;  // library-owned stream used only for graph capture
+    // slot batches (served form): a fixed number of slots whose members
+    // change while the batch runs; sols[i] == nullptr marks an empty slot
+    int slotted = 0;
+    int max_sum_q = 0, max_sum_r = 0;
+    char *stage_h[2] = {nullptr, nullptr};  // pinned staging of plan uploads, used in turn
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    size_t stage_bytes = 0;
+    int stage_k = 0;
+    long long *tick_h[2] = {nullptr, nullptr};  // pinned per-slot results of the last two ticks
+    hipEvent_t tick_ev[2] = {nullptr, nullptr};
+    int tick_seq[2] = {-1, -1};  // tick number whose results each buffer receives
+    int ticks = 0;               // ticks launched
+    hipGraphExec_t tick_exec = nullptr;
+    hipGraph_t tick_graph = nullptr;
+    int tick_steps = -1;
+    uint32_t tick_mask = 0;
 };
 
 // ----------------------------------------------------------------- misc ----
@@ -817,20 +834,27 @@ extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stre
 
 // ---------------------------------------------------------------- batch ----
 
-static size_t batch_layout(const std::vector<tga_solution *> &sols, size_t *desc, size_t *items,
-                           size_t *intra, size_t *sched, int max_items, int nintra) {
+struct BatchLayout {
+    size_t desc, items, intra, sched, coll, total;
+};
+
+// Workspace of a batch of `count` solution slots with room for `max_items`
+// inter-route items and `nintra` intra-route groups.
+static BatchLayout batch_layout(size_t count, int max_items, int nintra) {
+    BatchLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off = align_up(off + bytes, 256);
         return o;
     };
-    *desc = take(sizeof(SolDev) * sols.size());
-    *items = take(sizeof(InterItem) * std::max(max_items, 1));
-    *intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    *sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (sols.size() + 1));  // item list offsets, done flags, step counter
-    take(32 * sols.size());  // collected results
-    return off;
+    L.desc = take(sizeof(SolDev) * count);
+    L.items = take(sizeof(InterItem) * std::max(max_items, 1));
+    L.intra = take(sizeof(IntraItem) * std::max(nintra, 1));
+    L.sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (count + 1));  // item list offsets, done flags, step counter
+    L.coll = take(32 * count);  // collected results
+    L.total = off;
+    return L;
 }
 
 // Workgroups of kInterThreads threads one compute unit holds at once for
@@ -846,7 +870,8 @@ static int resident_blocks(const void *f, size_t lds) {
 
 static int batch_max_items(const std::vector<tga_solution *> &sols, int rows_per_item) {
     long long m = 0;
-    for (auto *s : sols) m += count_items(s->Q, rows_per_item > 0 ? rows_per_item : 1);
+    for (auto *s : sols)
+        if (s) m += count_items(s->Q, rows_per_item > 0 ? rows_per_item : 1);
     return (int)std::min<long long>(m, 1 << 30);
 }
 
@@ -858,9 +883,8 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
         if (!s) return 0;
         nintra += s->R;
     }
-    size_t a, b, c, d;
     // worst case over the schedules tga_batch_create accepts: one row per item
-    return batch_layout(v, &a, &b, &c, &d, batch_max_items(v, 1), nintra);
+    return batch_layout(v.size(), batch_max_items(v, 1), nintra).total;
 }
 
 // Rows per LDS sub-block for an LDS budget of `budget` bytes.
@@ -868,6 +892,45 @@ static int tile_rows_for(int np1, bool w16, size_t budget) {
     int h = 1;
     while (h < kMaxTileRows && rows_lds(np1, h + 1, w16) <= budget) ++h;
     return h;
+}
+
+static void drop_tick_graph(tga_batch *B) {
+    if (B->tick_exec) (void)hipGraphExecDestroy(B->tick_exec);
+    if (B->tick_graph) (void)hipGraphDestroy(B->tick_graph);
+    B->tick_exec = nullptr;
+    B->tick_graph = nullptr;
+    B->tick_steps = -1;
+}
+
+// Upload a slot batch's plan without synchronising the host: the plan is
+// written into one of two pinned staging buffers (taken in turn; the host
+// waits only if that buffer's previous upload has not run yet) and copied on
+// `st`, so it takes effect for the launches enqueued after it.
+static int stage_upload(tga_batch *B, const std::vector<SolDev> &descs, const std::vector<InterItem> &items,
+                        const std::vector<IntraItem> &intra, const std::vector<int> &woff,
+                        const std::vector<int> &ixoff, hipStream_t st) {
+    const size_t nd = sizeof(SolDev) * descs.size(), ni = sizeof(InterItem) * items.size(),
+                 ng = sizeof(IntraItem) * intra.size(), nw = sizeof(int) * woff.size(),
+                 nx = sizeof(int) * ixoff.size();
+    const size_t od = 0, oi = align_up(od + nd, 64), og = align_up(oi + ni, 64), ow = align_up(og + ng, 64),
+                 ox = align_up(ow + nw, 64), total = ox + nx;
+    if (total > B->stage_bytes) return fail(TGA_ERANGE, "plan of %zu bytes exceeds the staging buffer", total);
+    const int k = B->stage_k;
+    B->stage_k ^= 1;
+    HIPCHK(hipEventSynchronize(B->stage_ev[k]));
+    char *h = B->stage_h[k];
+    memcpy(h + od, descs.data(), nd);
+    if (ni) memcpy(h + oi, items.data(), ni);
+    if (ng) memcpy(h + og, intra.data(), ng);
+    memcpy(h + ow, woff.data(), nw);
+    memcpy(h + ox, ixoff.data(), nx);
+    HIPCHK(hipMemcpyAsync(B->d, h + od, nd, hipMemcpyHostToDevice, st));
+    if (ni) HIPCHK(hipMemcpyAsync(B->items, h + oi, ni, hipMemcpyHostToDevice, st));
+    if (ng) HIPCHK(hipMemcpyAsync(B->intra, h + og, ng, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B->woff, h + ow, nw, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B->ixoff, h + ox, nx, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(B->stage_ev[k], st));
+    return TGA_OK;
 }
 
 // Plan the batch's schedule for its configuration and upload it: the
@@ -881,9 +944,13 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     std::vector<IntraItem> intra;
     std::vector<SolDev> descs(count);
     size_t lds = 0;
-    std::vector<int> trs(count);
+    std::vector<int> trs(count, 0);
     for (int i = 0; i < count; ++i) {
         tga_solution *s = v[i];
+        if (!s) {  // empty slot: Q = 0, no items; the per-solution kernels skip it
+            memset(&descs[i], 0, sizeof(SolDev));
+            continue;
+        }
         descs[i] = s->h;
         // LDS sub-block rows (bounded by the LDS budget of one workgroup)
         const bool w16 = s->h.D16 != nullptr;
@@ -895,6 +962,10 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     }
     const size_t lds_intra = (size_t)kInterWaves * kIntraRegionBytes;  // the intra phase's regions
     if (!c.split) lds = std::max(lds, lds_intra);
+    // A slot batch keeps its launch shapes while members come and go (so a
+    // captured tick stays valid): LDS at least the configured budget, and
+    // never below what earlier members needed.
+    if (B->slotted) lds = std::max(lds, std::max((size_t)c.lds_kb * 1024, B->lds));
     if (lds > (size_t)P.max_lds) return fail(TGA_ERANGE, "batch needs %zu bytes of LDS", lds);
     // one resident wave of workgroups: as many as LDS and registers allow
     const int grid_inter =
@@ -920,6 +991,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     std::vector<double> sol_work(count, 0.0);
     double total = 0.0;
     for (int i = 0; i < count; ++i) {
+        if (!v[i]) continue;
         for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : trs[i],
                       [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
         for (const auto &it : own[i]) sol_work[i] += (double)work(it);
@@ -935,6 +1007,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
     int rr = 0;
     for (int i : order) {
+        if (!v[i]) continue;
         std::vector<IntraItem> groups;
         push_intra_groups(v[i]->n, v[i]->R, i, groups);
         if (nx == 1 || sol_work[i] <= 0.5 * share) {
@@ -988,6 +1061,8 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     }
     if ((int)items.size() > B->max_items || (int)intra.size() > B->max_intra)
         return fail(TGA_ERANGE, "batch schedule exceeds its workspace");
+    const bool shapes_same = B->nx == nx && B->lds == lds && B->lds_intra == lds_intra &&
+                             B->grid_inter == grid_inter && B->grid_intra == grid_intra;
     B->nitems = (int)items.size();
     B->nintra = (int)intra.size();
     B->nx = nx;
@@ -995,7 +1070,9 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     B->lds_intra = lds_intra;
     B->grid_inter = grid_inter;
     B->grid_intra = grid_intra;
-    // a captured step loop holds the old launch shapes
+    // A captured step loop holds the old launch shapes and the old
+    // membership; a captured tick of a slot batch reads the membership from
+    // the workspace and stays valid while the shapes do.
     if (B->exec) {
         (void)hipGraphExecDestroy(B->exec);
         B->exec = nullptr;
@@ -1005,6 +1082,8 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         B->graph = nullptr;
     }
     B->graph_steps = -1;
+    if (!shapes_same) drop_tick_graph(B);
+    if (B->slotted) return stage_upload(B, descs, items, intra, woff, ixoff, st);
     hipError_t e = hipMemcpyAsync(B->d, descs.data(), sizeof(SolDev) * count, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st);
@@ -1028,18 +1107,89 @@ static int check_config(const tga_batch_config_t &c) {
     return TGA_OK;
 }
 
-extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
-                                int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
-                                tga_batch_t *out) {
-    if (!out) return fail(TGA_EINVAL, "out is null");
-    *out = nullptr;
-    if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
+// Release what a batch owns on the host side (pinned buffers, events,
+// graphs, the capture stream) and the batch itself.
+static void batch_destroy(tga_batch *B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    drop_tick_graph(B);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    if (B->coll_h) (void)hipHostFree(B->coll_h);
+    for (int k = 0; k < 2; ++k) {
+        if (B->stage_ev[k]) (void)hipEventDestroy(B->stage_ev[k]);
+        if (B->tick_ev[k]) (void)hipEventDestroy(B->tick_ev[k]);
+        if (B->stage_h[k]) (void)hipHostFree(B->stage_h[k]);
+        if (B->tick_h[k]) (void)hipHostFree(B->tick_h[k]);
+    }
+    for (auto *s : B->sols)
+        if (s) s->in_batch = 0;
+    delete B;
+}
+
+// Common set-up of both kinds of batch: workspace layout for `count` slots,
+// the pinned result buffer, and (slot batches) the staging buffers and
+// events; then the first plan.
+static int batch_init(tga_batch *B, int max_items, int nintra, void *ws, hipStream_t st) {
+    const size_t count = B->sols.size();
+    const BatchLayout L = batch_layout(count, max_items, nintra);
+    char *base = (char *)ws;
+    B->d = (SolDev *)(base + L.desc);
+    B->items = (InterItem *)(base + L.items);
+    B->max_items = max_items;
+    B->intra = (IntraItem *)(base + L.intra);
+    B->max_intra = nintra;
+    B->woff = (int *)(base + L.sched);
+    B->ixoff = B->woff + (kMaxBatchGrid + 1);
+    B->done = B->ixoff + (kMaxXcds + 1);
+    B->steps = B->done + count;
+    B->coll = (long long *)(base + L.coll);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_steps = -1;
+    B->cap_stream = nullptr;
+    if (hipHostMalloc((void **)&B->coll_h, 32 * count, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        B->coll_h = nullptr;
+        return fail(TGA_ENOMEM, "pinned host buffer of %zu bytes", 32 * count);
+    }
+    if (B->slotted) {
+        B->stage_bytes = sizeof(SolDev) * count + sizeof(InterItem) * max_items + sizeof(IntraItem) * nintra +
+                         4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 5 * 64;
+        for (int k = 0; k < 2; ++k) {
+            if (hipHostMalloc((void **)&B->stage_h[k], B->stage_bytes, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&B->tick_h[k], 32 * count, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(TGA_ENOMEM, "pinned staging buffers");
+            }
+            HIPCHK(hipEventCreateWithFlags(&B->stage_ev[k], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&B->tick_ev[k], hipEventDisableTiming));
+        }
+        k_zero_i32<<<1, 64, 0, st>>>(B->steps, 1);
+        HIPCHK(hipGetLastError());
+    }
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    return batch_plan(B, P, st);
+}
+
+static tga_batch_config_t default_config(int32_t rows_per_item, int32_t sub_rows) {
     tga_batch_config_t cfg;
     cfg.lds_kb = (int32_t)(lds_budget() / 1024);
     cfg.split = 0;
     cfg.rows_per_item = rows_per_item;
     cfg.sub_rows = sub_rows;
     cfg.us_per_eval = 0.f;
+    return cfg;
+}
+
+extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per_item,
+                                int32_t sub_rows, void *ws, size_t ws_bytes, void *stream,
+                                tga_batch_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!sols || count < 1 || !ws) return fail(TGA_EINVAL, "bad batch arguments");
+    const tga_batch_config_t cfg = default_config(rows_per_item, sub_rows);
     int rc = check_config(cfg);
     if (rc) return rc;
     if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
@@ -1051,44 +1201,86 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     for (size_t i = 0; i < v.size(); ++i)
         for (size_t j = i + 1; j < v.size(); ++j)
             if (v[i] == v[j]) return fail(TGA_EINVAL, "solution listed twice");
-    DevProps P;
-    if ((rc = props(&P))) return rc;
     if (ws_bytes < tga_batch_workspace_bytes(sols, count)) return fail(TGA_ENOMEM, "batch workspace too small");
     int nintra = 0;
     for (auto *s : v) nintra += s->R;
-    const int max_items = batch_max_items(v, 1);
-    size_t odesc, oitems, ointra, osched;
-    batch_layout(v, &odesc, &oitems, &ointra, &osched, max_items, nintra);
-    char *base = (char *)ws;
     tga_batch *B = new tga_batch();
     B->sols = v;
     B->cfg = cfg;
-    B->d = (SolDev *)(base + odesc);
-    B->items = (InterItem *)(base + oitems);
-    B->max_items = max_items;
-    B->intra = (IntraItem *)(base + ointra);
-    B->max_intra = nintra;
-    B->woff = (int *)(base + osched);
-    B->ixoff = B->woff + (kMaxBatchGrid + 1);
-    B->done = B->ixoff + (kMaxXcds + 1);
-    B->steps = B->done + v.size();
-    B->coll = (long long *)(base + align_up(osched + 4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (v.size() + 1), 256));
-    if (hipHostMalloc((void **)&B->coll_h, 32 * v.size(), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        delete B;
-        return fail(TGA_ENOMEM, "pinned host buffer of %zu bytes", 32 * v.size());
-    }
-    B->exec = nullptr;
-    B->graph = nullptr;
-    B->graph_steps = -1;
-    B->cap_stream = nullptr;
-    if ((rc = batch_plan(B, P, (hipStream_t)stream))) {
-        (void)hipHostFree(B->coll_h);
-        delete B;
+    if ((rc = batch_init(B, batch_max_items(v, 1), nintra, ws, (hipStream_t)stream))) {
+        B->sols.assign(v.size(), nullptr);  // not members yet
+        batch_destroy(B);
         return rc;
     }
     for (auto *s : v) s->in_batch = 1;
     *out = B;
+    return TGA_OK;
+}
+
+extern "C" size_t tga_batch_slots_workspace_bytes(int32_t slots, int32_t max_sum_q, int32_t max_sum_r) {
+    if (slots < 1 || slots > kMaxSlots || max_sum_q < 1 || max_sum_r < 1) return 0;
+    return batch_layout((size_t)slots, max_sum_q, max_sum_r).total;
+}
+
+extern "C" int tga_batch_create_slots(int32_t slots, int32_t max_sum_q, int32_t max_sum_r, void *ws,
+                                      size_t ws_bytes, void *stream, tga_batch_t *out) {
+    if (!out) return fail(TGA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!ws) return fail(TGA_EINVAL, "null workspace");
+    if (slots < 1 || slots > kMaxSlots) return fail(TGA_ERANGE, "slots = %d outside [1, %d]", slots, kMaxSlots);
+    if (max_sum_q < 1 || max_sum_r < 1) return fail(TGA_ERANGE, "max_sum_q and max_sum_r must be positive");
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < tga_batch_slots_workspace_bytes(slots, max_sum_q, max_sum_r))
+        return fail(TGA_ENOMEM, "batch workspace too small");
+    tga_batch *B = new tga_batch();
+    B->sols.assign(slots, nullptr);
+    B->cfg = default_config(0, 0);
+    B->slotted = 1;
+    B->max_sum_q = max_sum_q;
+    B->max_sum_r = max_sum_r;
+    int rc = batch_init(B, max_sum_q, max_sum_r, ws, (hipStream_t)stream);
+    if (rc) {
+        batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return TGA_OK;
+}
+
+extern "C" int tga_batch_set_members(tga_batch_t B, const tga_solution_t *sols, void *stream) {
+    if (!B || !sols) return fail(TGA_EINVAL, "null argument");
+    if (!B->slotted) return fail(TGA_EINVAL, "not a slot batch");
+    const int slots = (int)B->sols.size();
+    long long sq = 0, sr = 0;
+    for (int i = 0; i < slots; ++i) {
+        tga_solution *s = sols[i];
+        if (!s) continue;
+        bool ours = false;
+        for (auto *o : B->sols) ours = ours || o == s;
+        if (s->in_batch && !ours) return fail(TGA_EINVAL, "solution in slot %d belongs to another batch", i);
+        for (int j = 0; j < i; ++j)
+            if (sols[j] == s) return fail(TGA_EINVAL, "solution listed in slots %d and %d", j, i);
+        sq += s->Q;
+        sr += s->R;
+    }
+    if (sq > B->max_sum_q || sr > B->max_sum_r)
+        return fail(TGA_ERANGE, "members hold Q = %lld, R = %lld (room for %d, %d)", sq, sr, B->max_sum_q,
+                    B->max_sum_r);
+    std::vector<tga_solution *> old = B->sols;
+    for (auto *o : old)
+        if (o) o->in_batch = 0;
+    B->sols.assign(sols, sols + slots);
+    DevProps P;
+    int rc = props(&P);
+    if (!rc) rc = batch_plan(B, P, (hipStream_t)stream);
+    if (rc) {
+        B->sols = old;
+        for (auto *o : old)
+            if (o) o->in_batch = 1;
+        return rc;
+    }
+    for (auto *s : B->sols)
+        if (s) s->in_batch = 1;
     return TGA_OK;
 }
 
@@ -1134,6 +1326,7 @@ extern "C" int tga_batch_set_config(tga_batch_t B, const tga_batch_config_t *cfg
     const tga_batch_config_t old = B->cfg;
     B->cfg = *cfg;
     B->cfg.us_per_eval = 0.f;
+    B->lds = 0;  // a new schedule sets the LDS of a slot batch afresh
     if ((rc = batch_plan(B, P, (hipStream_t)stream))) {
         B->cfg = old;  // keep (and re-upload) the previous schedule
         const std::string msg = tga_last_error();
@@ -1171,6 +1364,7 @@ extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launc
             c.split = split;
             c.us_per_eval = 0.f;
             B->cfg = c;
+            B->lds = 0;
             if (batch_plan(B, P, st) != TGA_OK) continue;  // does not fit this device
             // local-search evaluations, each followed by a finalize that only
             // records (and clears) the best move
@@ -1198,16 +1392,19 @@ extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launc
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) {
         B->cfg = base;
+        B->lds = 0;
         (void)batch_plan(B, P, st);
         return fail(TGA_EDEVICE, "autotune: %s", hipGetErrorString(e));
     }
     if (!any) {
         B->cfg = base;
+        B->lds = 0;
         (void)batch_plan(B, P, st);
         return fail(TGA_ERANGE, "no candidate schedule fits the device");
     }
     chosen.us_per_eval = best_us;
     B->cfg = chosen;
+    B->lds = 0;
     if ((rc = batch_plan(B, P, st))) return rc;
     if (best) *best = chosen;
     return TGA_OK;
@@ -1232,7 +1429,7 @@ static int batch_collect(tga_batch *B, int32_t *steps_done, int64_t *moves, int6
     HIPCHK(hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) {
         const long long *r = B->coll_h + 4 * i;
-        B->sols[i]->version = (uint32_t)r[1];
+        if (B->sols[i]) B->sols[i]->version = (uint32_t)r[1];  // low half; converged flag above
         if (steps_done) steps_done[i] = (int32_t)r[0];
         if (moves) moves[i] = r[2];
         if (cost) cost[i] = r[3];
@@ -1328,27 +1525,89 @@ extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best,
     // counters stay as they are
     batch_step(B, op_mask, kModeRecord, st);
     HIPCHK(hipGetLastError());
-    std::vector<int32_t> rec(8 * n), state(16 * n);
+    std::vector<int32_t> rec(8 * n, 0), state(16 * n, 0);
     for (int i = 0; i < n; ++i) {
+        if (!B->sols[i]) continue;
         HIPCHK(hipMemcpyAsync(&rec[8 * i], B->sols[i]->h.rec, 32, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(&state[16 * i], B->sols[i]->h.state, 64, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) {
         to_move(&rec[8 * i], &best[i]);
+        if (!B->sols[i]) {  // empty slot
+            if (status) status[i] = 1;
+            continue;
+        }
         best[i].version = B->sols[i]->version;
         if (status) status[i] = state[16 * i + kStStatus];
     }
     return TGA_OK;
 }
 
+// One tick of a slot batch: `steps` local-search steps of every member (one
+// captured graph, replayed), then the per-slot results gathered and copied
+// into the pinned buffer of this tick, with an event behind the copy.
+extern "C" int tga_batch_tick(tga_batch_t B, uint32_t op_mask, int32_t steps, int32_t *tick, void *stream) {
+    if (!B) return fail(TGA_EINVAL, "null batch");
+    if (!B->slotted) return fail(TGA_EINVAL, "not a slot batch");
+    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (steps < 1 || steps > 64) return fail(TGA_ERANGE, "steps per tick in [1, 64]");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)B->sols.size();
+    if (!B->tick_exec || B->tick_steps != steps || B->tick_mask != op_mask) {
+        drop_tick_graph(B);
+        if (!B->cap_stream) HIPCHK(hipStreamCreate(&B->cap_stream));
+        HIPCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < steps; ++i) batch_step(B, op_mask, kModeLS, B->cap_stream);
+        k_collect<<<(n + 255) / 256, 256, 0, B->cap_stream>>>(B->d, n, B->coll);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(B->cap_stream, &g));
+        B->tick_graph = g;
+        HIPCHK(hipGraphInstantiate(&B->tick_exec, g, nullptr, nullptr, 0));
+        B->tick_steps = steps;
+        B->tick_mask = op_mask;
+    }
+    const int k = B->ticks & 1;
+    HIPCHK(hipEventSynchronize(B->tick_ev[k]));  // the buffer's previous tick has been read back
+    HIPCHK(hipGraphLaunch(B->tick_exec, st));
+    HIPCHK(hipMemcpyAsync(B->tick_h[k], B->coll, 32 * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(B->tick_ev[k], st));
+    B->tick_seq[k] = B->ticks;
+    if (tick) *tick = B->ticks;
+    B->ticks++;
+    return TGA_OK;
+}
+
+// Results of the newest finished tick, without waiting: *tick = its number
+// (-1 when none has finished yet; the arrays are then untouched).
+extern "C" int tga_batch_tick_status(tga_batch_t B, int32_t *tick, int32_t *converged, int32_t *steps_done,
+                                     int64_t *moves_evaluated, int64_t *cost) {
+    if (!B || !tick) return fail(TGA_EINVAL, "null argument");
+    if (!B->slotted) return fail(TGA_EINVAL, "not a slot batch");
+    *tick = -1;
+    const int n = (int)B->sols.size();
+    for (int back = 1; back <= 2; ++back) {
+        const int t = B->ticks - back;
+        if (t < 0) break;
+        const int k = t & 1;
+        const hipError_t q = hipEventQuery(B->tick_ev[k]);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(TGA_EDEVICE, "tick event: %s", hipGetErrorString(q));
+        const long long *r = B->tick_h[k];
+        for (int i = 0; i < n; ++i) {
+            if (converged) converged[i] = (int32_t)(r[4 * i + 1] >> 32);
+            if (steps_done) steps_done[i] = (int32_t)r[4 * i];
+            if (moves_evaluated) moves_evaluated[i] = r[4 * i + 2];
+            if (cost) cost[i] = r[4 * i + 3];
+        }
+        *tick = B->tick_seq[k];
+        return TGA_OK;
+    }
+    return TGA_OK;
+}
+
 extern "C" int tga_batch_free(tga_batch_t B) {
     if (!B) return TGA_OK;
-    if (B->exec) (void)hipGraphExecDestroy(B->exec);
-    if (B->graph) (void)hipGraphDestroy(B->graph);
-    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
-    if (B->coll_h) (void)hipHostFree(B->coll_h);
-    for (auto *s : B->sols) s->in_batch = 0;
-    delete B;
+    batch_destroy(B);
     return TGA_OK;
 }

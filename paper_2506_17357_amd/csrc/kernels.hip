@@ -1906,10 +1906,12 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
 }
 
 // `steps` (nullable): a batch's step counter, advanced once per launch.
+// Empty slots of a slot batch (Q = 0) are skipped.
 __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__restrict__ sols, int mode,
                                                             uint32_t op_mask, int *__restrict__ steps) {
-    finalize_block(sols[blockIdx.x], mode, op_mask);
     if (steps && blockIdx.x == 0 && threadIdx.x == 0) *steps += 1;
+    if (sols[blockIdx.x].Q == 0) return;
+    finalize_block(sols[blockIdx.x], mode, op_mask);
 }
 
 
@@ -1979,20 +1981,29 @@ __global__ void k_zero_i32(int32_t *p, int count) {
     if (i < count) p[i] = 0;
 }
 
-// Gather the converged flags of a batch into one array (one copy to the host).
+// Gather the converged flags of a batch into one array (one copy to the
+// host); an empty slot reads as converged.
 __global__ void k_poll_done(const SolDev *__restrict__ sols, int nsols, int32_t *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nsols) out[i] = sols[i].state[kStDone];
+    if (i < nsols) out[i] = sols[i].Q == 0 ? 1 : sols[i].state[kStDone];
 }
 
-// Per-solution results of a batch in one array: {steps, version, moves
-// evaluated, cost} per solution, for a single copy to the host.
+// Per-solution results of a batch in one array: {steps, version | converged
+// << 32, moves evaluated, cost} per solution, for a single copy to the host
+// (an empty slot: zeros, converged).
 __global__ void k_collect(const SolDev *__restrict__ sols, int nsols, long long *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nsols) {
         const SolDev &S = sols[i];
+        if (S.Q == 0) {
+            out[4 * i] = 0;
+            out[4 * i + 1] = 1ll << 32;
+            out[4 * i + 2] = 0;
+            out[4 * i + 3] = 0;
+            return;
+        }
         out[4 * i] = S.state[kStSteps];
-        out[4 * i + 1] = S.state[kStVersion];
+        out[4 * i + 1] = (long long)(uint32_t)S.state[kStVersion] | ((long long)(S.state[kStDone] != 0) << 32);
         out[4 * i + 2] = S.acc[kAccMoves];
         out[4 * i + 3] = S.acc[kAccCost];
     }
@@ -2002,7 +2013,7 @@ __global__ void k_collect(const SolDev *__restrict__ sols, int nsols, long long 
 // captured graph).
 __global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int max_steps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsols) return;
+    if (i >= nsols || sols[i].Q == 0) return;
     const SolDev &S = sols[i];
     S.state[kStDone] = 0;
     S.state[kStSteps] = 0;

@@ -1,19 +1,29 @@
 """Served form: continuous batching of local-search requests on one GPU.
 
 Requests (an instance, a starting solution, a step cap) arrive over time.
-A request is admitted when its device bytes (distance matrix, node data,
-instance and solution workspaces) fit in the HBM budget still free; its data
-are uploaded on a copy stream while the compute stream keeps stepping the
-requests already on the device.  Every engine tick runs `steps_per_tick`
-batched steps (each one persistent evaluation launch + one finalize launch;
-two by default, which halves the host polls at the cost of at most one
-step of latency) over all admitted requests; a request leaves when it reaches a local optimum or its cap, its
-memory is returned, and queued requests are admitted.  Results do not depend
-on what else is in the batch: each solution's step only reads its own data.
+A request is admitted, first come first served, when its device bytes
+(distance matrix, node data, instance and solution workspaces) fit in the
+HBM budget still free and a slot of the engine is free.  An upload thread
+copies its data to the device on a copy stream while the compute stream
+keeps stepping the requests already there.
+
+The engine is one slot batch (tga_batch_create_slots): a fixed number of
+slots whose members change while it runs.  Every tick enqueues
+`steps_per_tick` batched local-search steps of all members (one captured
+graph, replayed) plus a copy of the per-slot results into pinned memory;
+the host keeps up to two ticks in flight and reads the newest finished
+tick's results without waiting.  A member that reached its local optimum or
+step cap is skipped by the kernels; the host reads its routes back on a
+separate stream (nothing writes a converged solution), frees its slot with
+an asynchronous plan update, and returns its memory once the device is past
+the last tick that could read it.  Results do not depend on what else is in
+the batch: each solution's step reads only its own data.
 """
 from __future__ import annotations
 
 import collections
+import queue as queue_mod
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -60,94 +70,165 @@ def device_bytes(inst, R: int) -> int:
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
-                 device: str = "cuda", steps_per_tick: int = 2):
+                 device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
+                 max_sum_r: int = 1 << 17, autotune: bool = True, ticks_ahead: int = 2):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.steps_per_tick = int(steps_per_tick)
         self.op_mask = op_mask
         self.device = device
+        self.max_sum_q = int(max_sum_q)
+        self.max_sum_r = int(max_sum_r)
+        self.autotune = autotune
+        self.ticks_ahead = int(ticks_ahead)
         self.compute = torch.cuda.Stream(device=device)
         self.copy = torch.cuda.Stream(device=device)
+        self.readback = torch.cuda.Stream(device=device)
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
         self.ticks = 0
-        self.rebuilds = 0
-        self.rebuild_s = 0.0
+        self.rebuilds = 0       # plan updates (membership changes)
+        self.rebuild_s = 0.0    # host time spent in them
+        self.config = None
 
-    def _admit(self, req: ServeRequest, t0: float):
-        with torch.cuda.stream(self.copy):
-            I = tga.Instance.from_workload(req.inst, device=self.device, stream=self.copy)
-            S = tga.Solution(I, req.sol.offsets, req.sol.customers, stream=self.copy)
-            S.begin(req.max_steps, stream=self.copy)
-        self.copy.synchronize()
-        return {"req": req, "inst": I, "sol": S, "bytes": device_bytes(req.inst, req.sol.R),
-                "admitted": time.perf_counter() - t0}
+    # ---------------------------------------------------------------- upload
+    def _upload_loop(self, todo: queue_mod.Queue, ready: queue_mod.Queue, t0: float):
+        while True:
+            req = todo.get()
+            if req is None:
+                return
+            try:
+                with torch.cuda.stream(self.copy):
+                    I = tga.Instance.from_workload(req.inst, device=self.device, stream=self.copy)
+                    S = tga.Solution(I, req.sol.offsets, req.sol.customers, stream=self.copy)
+                ready.put((req, I, S, time.perf_counter() - t0, None))
+            except Exception as e:  # handed to the serving loop, which raises it
+                ready.put((req, None, None, 0.0, e))
 
+    # ------------------------------------------------------------------ run
     def run(self, requests: list[ServeRequest], log=None) -> list[ServeResult]:
         """Serve every request in real time (arrival_s relative to the start)."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
-        queue: collections.deque = collections.deque()
-        active: list[dict] = []
+        waiting: collections.deque = collections.deque()
+        todo: queue_mod.Queue = queue_mod.Queue()
+        ready: queue_mod.Queue = queue_mod.Queue()
+        slots = [None] * self.max_slots   # per slot: dict of the member, or None
+        retiring: list = []               # (event, entry): memory kept until the event has passed
         results: list[ServeResult] = []
-        batch = None
-        dirty = False
+        uploading = 0
+        q_used = r_used = 0
+        tuned = not self.autotune
+        B = tga.SlotBatch(self.max_slots, self.max_sum_q, self.max_sum_r, device=self.device, stream=self.compute)
         t0 = time.perf_counter()
-        while pending or queue or active:
-            now = time.perf_counter() - t0
-            while pending and pending[0].arrival_s <= now:
-                queue.append(pending.popleft())
-            while queue and len(active) < self.max_slots:
-                need = device_bytes(queue[0].inst, queue[0].sol.R)
-                if need > self.budget:
-                    raise ValueError("request %d needs %d bytes, more than the whole budget"
-                                     % (queue[0].rid, need))
-                if self.used + need > self.budget:
-                    break
-                req = queue.popleft()
-                active.append(self._admit(req, t0))
-                self.used += need
-                dirty = True
-            self.peak_used = max(self.peak_used, self.used)
-            self.peak_active = max(self.peak_active, len(active))
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, min(0.001, pending[0].arrival_s - (time.perf_counter() - t0))))
-                continue
-            if dirty:
-                tb = time.perf_counter()
-                if batch is not None:
-                    batch.close()
-                with torch.cuda.stream(self.compute):
-                    batch = tga.Batch([a["sol"] for a in active], stream=self.compute)
-                dirty = False
-                self.rebuilds += 1
-                self.rebuild_s += time.perf_counter() - tb
-            for _ in range(self.steps_per_tick):  # a finished solution skips the rest of a tick
-                batch.step_part(0, self.op_mask, stream=self.compute)
-                batch.step_part(1, self.op_mask, stream=self.compute)
-            self.ticks += 1
-            done = batch.poll(stream=self.compute)
-            if done.any():
-                t_done = time.perf_counter() - t0
+        worker = threading.Thread(target=self._upload_loop, args=(todo, ready, t0), daemon=True)
+        worker.start()
+        in_flight = 0      # ticks enqueued and not yet seen finished
+        last_seen = -1     # newest tick whose status was processed
+        next_tick = 0      # number the next tick will get
+        changed = False
+        try:
+            while pending or waiting or uploading or any(slots) or retiring:
+                now = time.perf_counter() - t0
+                while pending and pending[0].arrival_s <= now:
+                    waiting.append(pending.popleft())
+                # release the memory of retired members the device is done with
                 keep = []
-                for a, d in zip(active, done):
-                    if not d:
-                        keep.append(a)
-                        continue
-                    S, req = a["sol"], a["req"]
-                    steps, _, moves, cost = S.stats(stream=self.compute)
-                    off, cust, _ = S.get(stream=self.compute)
-                    results.append(ServeResult(req.rid, req.inst.n, req.inst.kind, req.arrival_s,
-                                               a["admitted"], t_done, steps, moves, cost, off, cust))
-                    self.used -= a["bytes"]
-                    if log:
-                        log("request %d (n=%d) done: %d steps, latency %.3f s"
-                            % (req.rid, req.inst.n, steps, t_done - req.arrival_s))
-                batch.close()
-                batch = None
-                active = keep
-                dirty = bool(active)
-        if batch is not None:
-            batch.close()
+                for ev, ent in retiring:
+                    if ev.query():
+                        self.used -= ent["bytes"]
+                    else:
+                        keep.append((ev, ent))
+                retiring = keep
+                # admission, first come first served: budget, slots, batch capacity
+                free_slots = sum(s is None for s in slots) - uploading
+                while waiting and free_slots > 0:
+                    req = waiting[0]
+                    need = device_bytes(req.inst, req.sol.R)
+                    if need > self.budget:
+                        raise ValueError("request %d needs %d bytes, more than the whole budget" % (req.rid, need))
+                    Q, R = req.inst.n + req.sol.R, req.sol.R
+                    if Q > self.max_sum_q or R > self.max_sum_r:
+                        raise ValueError("request %d (Q = %d, R = %d) exceeds the engine's size" % (req.rid, Q, R))
+                    if self.used + need > self.budget or q_used + Q > self.max_sum_q or r_used + R > self.max_sum_r:
+                        break
+                    waiting.popleft()
+                    self.used += need
+                    q_used += Q
+                    r_used += R
+                    uploading += 1
+                    free_slots -= 1
+                    todo.put(req)
+                self.peak_used = max(self.peak_used, self.used)
+                # uploaded requests join free slots
+                while True:
+                    try:
+                        req, I, S, t_adm, err = ready.get_nowait()
+                    except queue_mod.Empty:
+                        break
+                    uploading -= 1
+                    if err is not None:
+                        raise err
+                    k = slots.index(None)
+                    S.begin(req.max_steps, stream=self.compute)
+                    slots[k] = {"req": req, "inst": I, "sol": S, "bytes": device_bytes(req.inst, req.sol.R),
+                                "admitted": t_adm, "joined": next_tick, "Q": req.inst.n + req.sol.R,
+                                "R": req.sol.R}
+                    changed = True
+                active = sum(s is not None for s in slots)
+                self.peak_active = max(self.peak_active, active)
+                if changed:
+                    tb = time.perf_counter()
+                    B.set_members([s["sol"] if s else None for s in slots], stream=self.compute)
+                    changed = False
+                    self.rebuilds += 1
+                    self.rebuild_s += time.perf_counter() - tb
+                    if not tuned and (active >= 8 or (not pending and not waiting and not uploading)):
+                        self.config = B.autotune(self.op_mask, launches=2, stream=self.compute)
+                        tuned = True
+                if active and in_flight < self.ticks_ahead:
+                    B.tick(self.steps_per_tick, self.op_mask, stream=self.compute)
+                    next_tick += 1
+                    in_flight += 1
+                    self.ticks += 1
+                tick, conv, steps, moves, cost = B.status()
+                if tick > last_seen:
+                    in_flight -= tick - last_seen
+                    last_seen = tick
+                    for k, ent in enumerate(slots):
+                        if ent is None or ent["joined"] > tick or not conv[k]:
+                            continue
+                        S, req = ent["sol"], ent["req"]
+                        off, cust, _ = S.get(stream=self.readback)
+                        t_done = time.perf_counter() - t0
+                        results.append(ServeResult(req.rid, req.inst.n, req.inst.kind, req.arrival_s,
+                                                   ent["admitted"], t_done, int(steps[k]), int(moves[k]),
+                                                   int(cost[k]), off, cust))
+                        if log:
+                            log("request %d (n=%d) done: %d steps, latency %.3f s"
+                                % (req.rid, req.inst.n, int(steps[k]), t_done - req.arrival_s))
+                        slots[k] = None
+                        q_used -= ent["Q"]
+                        r_used -= ent["R"]
+                        changed = True
+                        ent["retired"] = True
+                        retiring.append((None, ent))
+                    if changed:
+                        tb = time.perf_counter()
+                        B.set_members([s["sol"] if s else None for s in slots], stream=self.compute)
+                        changed = False
+                        self.rebuilds += 1
+                        self.rebuild_s += time.perf_counter() - tb
+                        ev = torch.cuda.Event()
+                        ev.record(self.compute)
+                        retiring = [(ev if e is None else e, ent) for e, ent in retiring]
+                elif in_flight >= self.ticks_ahead or (not active and (uploading or retiring)):
+                    time.sleep(5e-5)
+                elif not active and pending and not waiting and not uploading:
+                    time.sleep(max(0.0, min(0.001, pending[0].arrival_s - (time.perf_counter() - t0))))
+        finally:
+            todo.put(None)
+            worker.join()
+            torch.cuda.synchronize()
+            B.close()
         return sorted(results, key=lambda r: r.rid)

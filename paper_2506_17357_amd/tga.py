@@ -61,7 +61,8 @@ EXPORTS = [
     "tga_device_limits", "tga_batch_begin", "tga_batch_step_part", "tga_batch_collect",
     "tga_solution_reload", "tga_solution_begin", "tga_batch_poll", "tga_solution_stats",
     "tga_instance_dist_bytes", "tga_batch_get_config", "tga_batch_set_config", "tga_batch_autotune",
-    "tga_eval_routes_static",
+    "tga_eval_routes_static", "tga_batch_slots_workspace_bytes", "tga_batch_create_slots",
+    "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
 ]
 
 
@@ -83,6 +84,11 @@ def lib():
         "tga_set_solution": (i32, [P, i32, P, P, P, sz, P, pp]),
         "tga_eval_neighborhood": (i32, [P, u32, ctypes.POINTER(Move), P, P, P]),
         "tga_eval_routes_static": (i32, [P, i32, P, P, u32, ctypes.POINTER(Move), P]),
+        "tga_batch_slots_workspace_bytes": (sz, [i32, i32, i32]),
+        "tga_batch_create_slots": (i32, [i32, i32, i32, P, sz, P, pp]),
+        "tga_batch_set_members": (i32, [P, P, P]),
+        "tga_batch_tick": (i32, [P, u32, i32, P, P]),
+        "tga_batch_tick_status": (i32, [P, P, P, P, P, P]),
         "tga_apply_move": (i32, [P, ctypes.POINTER(Move), P, P]),
         "tga_ls_run": (i32, [P, u32, i32, P, P, P, P]),
         "tga_get_solution": (i32, [P, P, P, P, P]),
@@ -349,6 +355,51 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+class SlotBatch(Batch):
+    """A batch of fixed slots whose members change while it runs (served
+    form): asynchronous membership updates and ticks, non-blocking status."""
+
+    def __init__(self, slots: int, max_sum_q: int, max_sum_r: int, device="cuda", stream=None):
+        L = lib()
+        self.slots = int(slots)
+        self.sols = [None] * self.slots
+        nbytes = L.tga_batch_slots_workspace_bytes(self.slots, int(max_sum_q), int(max_sum_r))
+        if nbytes == 0:
+            raise TGAError(TGA_ERANGE, "bad slot batch sizes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(L.tga_batch_create_slots(self.slots, int(max_sum_q), int(max_sum_r), _dev_ptr(self.ws), nbytes,
+                                        _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self._st = np.zeros(self.slots, np.int32)
+        self._cv = np.zeros(self.slots, np.int32)
+        self._mv = np.zeros(self.slots, np.int64)
+        self._cost = np.zeros(self.slots, np.int64)
+
+    def set_members(self, sols, stream=None):
+        """sols: one Solution or None per slot."""
+        if len(sols) != self.slots:
+            raise ValueError("need %d entries" % self.slots)
+        arr = (ctypes.c_void_p * self.slots)(*[s.h.value if s is not None else None for s in sols])
+        _check(lib().tga_batch_set_members(self.h, arr, _stream(stream)))
+        self.sols = list(sols)
+
+    def tick(self, steps: int, op_mask: int = OPS_ALL, stream=None) -> int:
+        t = ctypes.c_int32()
+        _check(lib().tga_batch_tick(self.h, op_mask, steps, ctypes.byref(t), _stream(stream)))
+        return int(t.value)
+
+    def status(self):
+        """(tick, converged, steps, moves, cost) of the newest finished tick
+        (tick = -1 and no arrays when none has finished)."""
+        t = ctypes.c_int32()
+        _check(lib().tga_batch_tick_status(self.h, ctypes.byref(t), _np_ptr(self._cv), _np_ptr(self._st),
+                                           _np_ptr(self._mv), _np_ptr(self._cost)))
+        if t.value < 0:
+            return -1, None, None, None, None
+        return int(t.value), self._cv.copy(), self._st.copy(), self._mv.copy(), self._cost.copy()
 
 
 def device_limits():

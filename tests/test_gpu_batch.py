@@ -192,3 +192,71 @@ def test_full_batched_workload_sampled(tga):
         assert steps[b] == len(ids) and moves[b] == mv
         assert finals[b][0].tolist() == final.offsets.tolist()
         assert finals[b][1].tolist() == final.customers.tolist()
+
+
+def test_slot_batch_members_come_and_go(tga):
+    """A slot batch whose members are replaced while it runs (served form):
+    every solution ends exactly where the oracle's local search ends, with
+    the same counters, whatever slot it had and whoever it shared the
+    launches with; empty slots are skipped."""
+    import torch
+    pairs = small_mix(9, seed=7)
+    insts, sols = make_solutions(tga, pairs)
+    caps = [15, 40, 7, 25, 60, 3, 33, 18, 50]
+    B = tga.SlotBatch(4, 1 << 14, 1 << 10)
+    members = [None] * 4
+    queue = list(range(len(sols)))
+    result = {}
+    st = torch.cuda.current_stream()
+    joined = {}
+    ticks = 0
+    while queue or any(m is not None for m in members):
+        changed = False
+        for k in range(4):
+            if members[k] is None and queue and k != 2:  # slot 2 stays empty
+                b = queue.pop(0)
+                sols[b].begin(caps[b])
+                members[k] = b
+                joined[b] = ticks
+                changed = True
+        if changed:
+            B.set_members([sols[b] if b is not None else None for b in members])
+        t = B.tick(3)
+        ticks += 1
+        st.synchronize()
+        tick, conv, steps, moves, cost = B.status()
+        assert tick == t
+        assert conv[2] == 1 and steps[2] == 0
+        for k, b in enumerate(members):
+            if b is not None and conv[k]:
+                result[b] = (int(steps[k]), int(moves[k]), int(cost[k]))
+                members[k] = None
+                changed = True
+        if changed:
+            B.set_members([sols[b] if b is not None else None for b in members])
+    st.synchronize()
+    B.close()
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=caps[b])
+        assert result[b] == (len(ids), mv, oracle.cost(inst, final)[0]), b
+        off, cust, c = sols[b].get()
+        assert off.tolist() == final.offsets.tolist() and cust.tolist() == final.customers.tolist(), b
+
+
+def test_slot_batch_other_calls_skip_empty_slots(tga):
+    pairs = small_mix(3, seed=8)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.SlotBatch(5, 1 << 12, 1 << 8)
+    B.set_members([None, sols[0], None, sols[1], sols[2]])
+    best, status = B.eval()
+    assert status[0] == 1 and status[2] == 1
+    for k, b in ((1, 0), (3, 1), (4, 2)):
+        ob = oracle.eval_neighbourhood(*pairs[b])
+        assert (best[k].delta, best[k].id) == (ob.delta, ob.id)
+    steps, moves, cost = B.ls_run(12, use_graph=False)
+    assert steps[0] == steps[2] == 0 and cost[0] == 0
+    for k, b in ((1, 0), (3, 1), (4, 2)):
+        final, ids, _, mv = oracle.local_search(*pairs[b], max_steps=12)
+        assert (steps[k], moves[k], cost[k]) == (len(ids), mv, oracle.cost(pairs[b][0], final)[0])
+    assert B.poll().tolist()[0] == 1
+    B.close()

@@ -102,3 +102,41 @@ def test_large_request_in_the_mix(env):
         steps, moves, cost, off, cust = alone(tga, req)
         r = res[req.rid]
         assert (r.steps, r.moves, r.cost) == (steps, moves, cost), req.rid
+
+
+def test_largest_requests_served_equal_oracle_goldens(env):
+    """The four largest served cases (about 10^4 customers, Q about 10.5k)
+    admitted next to small requests: each result equals the oracle's stored
+    trajectory (tests/golden/traj_c5_large.json)."""
+    import hashlib
+    import json
+    import os
+    from tests import large_requests
+    tga, serve = env
+    path = os.path.join(os.path.dirname(__file__), "golden", "traj_c5_large.json")
+    if not os.path.exists(path):
+        pytest.skip("golden traj_c5_large.json not written")
+    with open(path) as f:
+        g = json.load(f)["entries"]
+    reqs = make_requests(serve, count=6, seed=9, max_steps=20)
+    labels = {}
+    for j, (label, _) in enumerate(large_requests.cases()):
+        inst, sol, req = large_requests.instance(label)
+        assert inst.sha256() == g[label]["instance_sha256"]
+        rid = 100 + j
+        labels[rid] = label
+        reqs.insert(2 * j, serve.ServeRequest(rid, 0.001 * j, inst, sol, req.max_steps))
+    srv = serve.Server(hbm_budget_bytes=1 << 34)
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert srv.peak_active > 1
+    for rid, label in labels.items():
+        r, e = res[rid], g[label]
+        assert (r.steps, r.moves, r.cost) == (e["steps"], e["moves_evaluated"], e["final_cost"]), label
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(r.offsets, dtype="<i4").tobytes())
+        h.update(np.ascontiguousarray(r.customers, dtype="<i4").tobytes())
+        assert h.hexdigest() == e["final_routes_sha256"], label
+    for req in reqs:
+        if req.rid < 100:
+            steps, moves, cost, off, cust = alone(tga, req)
+            assert (res[req.rid].steps, res[req.rid].moves, res[req.rid].cost) == (steps, moves, cost)

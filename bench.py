@@ -37,13 +37,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def eval_bytes(inst, R, dist_bytes):
-    """Algorithmic HBM bytes of one evaluation: the distance matrix read once,
-    at the width the inter-route kernels stream it (2 bytes per entry when
-    every distance is below 2^16, else 4), plus the slot attributes the
-    kernels need (two int4 per slot for CVRP, four with time windows)."""
+def eval_bytes(inst, R):
+    """Algorithmic HBM bytes of one full-neighbourhood evaluation: the int32
+    distance matrix read once, 4(n+1)^2, plus 36 bytes of slot attributes per
+    ref (Q = n + R), 16 bytes of node data per node and 16 bytes per route."""
+    Q = inst.n + R
+    return 4 * (inst.n + 1) ** 2 + 36 * Q + 16 * (inst.n + 1) + 16 * R
+
+
+def streamed_bytes(inst, R, dist_bytes):
+    """The bytes the kernels actually stream per evaluation: the matrix at the
+    width the inter-route kernels read it (2 bytes per entry when every
+    distance is below 2^16, else 4) plus the slot attribute records (two int4
+    per slot for CVRP, four with time windows)."""
     Q = inst.n + R
     return dist_bytes * (inst.n + 1) ** 2 + (64 if inst.has_tw else 32) * (Q + 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def kernel_source_hash() -> str:
@@ -55,21 +74,43 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def committed_traffic(alg_bytes_per_launch):
-    """HBM bytes per evaluation launch measured with rocprofv3 FETCH_SIZE and
-    WRITE_SIZE (each scaled by the same counter on a copy of known size), as
-    committed in profiles/; None when missing or taken on other kernel
-    sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_eval_batch_batched256.json")
+def committed_counters(name):
+    """A counter summary committed under profiles/ (rocprofv3 runs of the
+    default benchmark's evaluation launch); None when missing or taken on
+    other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    return t
+
+
+def traffic_entry(alg_bytes_per_launch):
+    """HBM bytes per evaluation launch from FETCH_SIZE and WRITE_SIZE (each
+    scaled by the same counter on a plain copy of known size)."""
+    t = committed_counters("traffic_k_eval_batch_batched256.json")
+    if t is None:
+        return None
     return {"bytes_per_launch": t["bytes_per_launch"],
             "vs_algorithmic": round(t["bytes_per_launch"] / alg_bytes_per_launch, 3),
             "source": "profiles/traffic_k_eval_batch_batched256.json"}
+
+
+def valu_entry(avg_launch_us):
+    """VALU issue fraction of the evaluation launch: wavefront VALU
+    instructions per launch (SQ_INSTS_VALU) over what the chip issues in the
+    launch time (256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+    cycles at 2.4 GHz)."""
+    t = committed_counters("valu_k_eval_batch_batched256.json")
+    if t is None:
+        return None
+    peak_per_us = 256 * 4 * 2400.0 / 4
+    return {"valu_insts_per_launch": t["valu_insts_per_launch"],
+            "frac": round(t["valu_insts_per_launch"] / (avg_launch_us * peak_per_us), 4),
+            "source": "profiles/valu_k_eval_batch_batched256.json"}
 
 
 def calibrate_copy():
@@ -82,6 +123,113 @@ def calibrate_copy():
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+
+
+def eager_pass(B, K, ebytes, sbytes):
+    """K local-search steps of batch B from its current state, launched one
+    by one with HIP events (on the launching stream) around every evaluation
+    launch.  ebytes / sbytes: algorithmic / streamed bytes of one evaluation
+    of each solution; a launch is charged for the solutions still active in
+    it."""
+    import torch
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.begin(K)
+    for k in range(K):
+        ev0[k].record()
+        B.step_part(0)
+        ev1[k].record()
+        B.step_part(1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st, mv, cost = B.collect()
+    dur_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    evals = np.where(st < K, st + 1, K)
+    active = np.arange(K)[:, None] < evals[None, :]
+    return {"seconds": t, "steps": st, "moves": mv, "cost": cost, "dur_ms": dur_ms,
+            "alg_bytes": (active * ebytes[None, :]).sum(axis=1),
+            "str_bytes": (active * sbytes[None, :]).sum(axis=1)}
+
+
+def roofline_entry(ev, kernel="k_eval_batch<3>"):
+    secs = ev["dur_ms"].sum() * 1e-3
+    alg = ev["alg_bytes"].sum() / secs / 1e9
+    streamed = ev["str_bytes"].sum() / secs / 1e9
+    return {
+        "bound": "hbm", "kernel": kernel,
+        "achieved": round(alg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / HBM_PEAK_GBS, 4),
+        "bytes_model": "per active solution per launch: 4(n+1)^2 + 36Q + 16(n+1) + 16R",
+        "avg_launch_us": round(float(ev["dur_ms"].mean() * 1e3), 2),
+        "avg_bytes_per_launch": int(ev["alg_bytes"].mean()),
+        "streamed": {"achieved": round(streamed, 1), "frac": round(streamed / HBM_PEAK_GBS, 4),
+                     "avg_bytes_per_launch": int(ev["str_bytes"].mean()),
+                     "bytes_model": "w(n+1)^2 at the streamed width w (2 B below 2^16, else 4) "
+                                    "+ 32 (CVRP) or 64 (VRPTW) bytes per slot"},
+    }
+
+
+def plain_configs(log_lat=True):
+    """The single-solution configurations on the plain form: moves per
+    second of the device-resident loop to the local optimum (100 steps for
+    the 100-customer case), and the best-move latency of a host call
+    (evaluation + record copy) at every step of the same trajectory."""
+    import torch
+    from paper_2506_17357_amd import tga, workload as W
+    out = {}
+    for name, caps in (("c1", 100), ("c2", 100000), ("c3", 100000)):
+        inst, sol = getattr(W, name)()
+        I = tga.Instance.from_workload(inst)
+        S = tga.Solution(I, sol.offsets, sol.customers)
+        S.ls_run(5)  # warm the code paths
+        S.reload(sol.offsets, sol.customers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, moves, cost = S.ls_run(caps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        S.reload(sol.offsets, sol.customers)
+        lat = []
+        for _ in range(steps + 1):
+            t1 = time.perf_counter()
+            m = S.eval()
+            lat.append((time.perf_counter() - t1) * 1e6)
+            if m is None or m.delta >= 0:
+                break
+            S.apply(m)
+        lat = np.array(lat)
+        out[name] = {"workload": "%s: n = %d %s, seed %d, sweep start, R = %d" % (
+                         name, inst.n, inst.kind, inst.seed, sol.R),
+                     "steps": int(steps), "moves_evaluated": int(moves), "final_cost": int(cost),
+                     "seconds": round(t, 5), "gmoves_s": round(moves / t / 1e9, 3),
+                     "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
+                                              "p99": round(float(np.percentile(lat, 99)), 1),
+                                              "evals": int(lat.size)}}
+        log("%s: %d steps to the local optimum in %.4f s, %.2f GMoves/s, best-move latency p50 %.1f us "
+            "p99 %.1f us" % (name, steps, t, out[name]["gmoves_s"], out[name]["best_move_latency_us"]["p50"],
+                             out[name]["best_move_latency_us"]["p99"]))
+    return out
+
+
+def oracle_configs(threads):
+    """The oracle on one full-neighbourhood evaluation of each
+    single-solution configuration's starting state, at `threads` threads and
+    at one thread."""
+    import oracle
+    from paper_2506_17357_amd import workload as W
+    out = {}
+    for name in ("c1", "c2", "c3"):
+        inst, sol = getattr(W, name)()
+        row = {}
+        for T in (threads, 1):
+            t0 = time.perf_counter()
+            r = oracle.eval_neighbourhood(inst, sol, threads=T)
+            t = time.perf_counter() - t0
+            row["t%d" % T] = {"gmoves_s": round(r.moves / t / 1e9, 5), "seconds": round(t, 4)}
+        row["moves"] = int(r.moves)
+        out[name] = row
+    return out
 
 
 def n1000_comparison(steps):
@@ -102,6 +250,11 @@ def n1000_comparison(steps):
 
     B = tga.Batch(sols)
     B.autotune(launches=3)
+    reload_all()
+    ebytes = np.array([eval_bytes(i, s.R) for i, s in pairs], np.float64)
+    sbytes = np.array([streamed_bytes(i, s.R, I.dist_bytes) for I, (i, s) in zip(insts, pairs)], np.float64)
+    ev = eager_pass(B, steps, ebytes, sbytes)
+    reload_all()
     B.ls_run(steps, use_graph=True)  # capture + first replay, untimed
     reload_all()
     t0 = time.perf_counter()
@@ -109,6 +262,7 @@ def n1000_comparison(steps):
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     B.close()
+    assert np.array_equal(st_b, ev["steps"]) and np.array_equal(cost_b, ev["cost"])
     reload_all()
     t0 = time.perf_counter()
     res = [s.ls_run(steps) for s in sols]
@@ -121,72 +275,79 @@ def n1000_comparison(steps):
            "plain_gmoves_s": round(int(sum(r[1] for r in res)) / t_p / 1e9, 3),
            "bit_exact": bool(same)}
     out["batched_over_plain"] = round(out["batched_gmoves_s"] / out["plain_gmoves_s"], 2)
+    out["roofline"] = roofline_entry(ev)
     log("n = 1000: batched %.1f GMoves/s, plain %.2f GMoves/s, bit-exact %s (%.1f s)" % (
         out["batched_gmoves_s"], out["plain_gmoves_s"], same, time.time() - t))
     return out
 
 
-def served(args):
-    """Served form: a Poisson stream of local-search requests (200..10000
-    customers, CVRP / VRPTW alternating, seeds 5000 + k, arrivals seed 5999)
-    served by continuous batching under an HBM budget."""
+def served_run(args, count):
+    """Served form: a Poisson stream of `count` local-search requests
+    (200..10000 customers log-uniform, CVRP / VRPTW alternating, seeds
+    5000 + k, arrivals seed 5999, <= --served-steps steps each) served by
+    continuous batching under an HBM budget.  A closed loop (every request
+    queued at t = 0) measures the capacity; the open loop offers 0.7 x that
+    rate and must give every request the closed loop's result."""
     import torch
-    from paper_2506_17357_amd import serve, tga, workload as W
+    from paper_2506_17357_amd import serve, workload as W
     torch.cuda.set_device(0)
     t = time.time()
-    base = W.request_stream(args.requests, qps=1.0, max_steps=args.served_steps)
+    base = W.request_stream(count, qps=1.0, max_steps=args.served_steps)
     reqs = []
     for r in base:
         inst = W.request_instance(r)
         reqs.append(serve.ServeRequest(r.k, 0.0, inst, W.sweep(inst), r.max_steps))
-        log("request %d: n=%d %s" % (r.k, inst.n, inst.kind))
-    log("requests generated in %.1f s" % (time.time() - t))
+    log("served: %d requests generated in %.1f s (sum n = %d)" % (len(reqs), time.time() - t,
+                                                                  sum(q.inst.n for q in reqs)))
     budget = int(args.hbm_budget_gb * (1 << 30))
-    # closed loop (everything queued at t = 0) measures the capacity
+    srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
+    srv.run(reqs[: min(8, len(reqs))])  # warm: code paths, autotuned schedule
     srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
     t0 = time.perf_counter()
     res0 = srv.run(reqs)
     t_closed = time.perf_counter() - t0
+    moves0 = sum(r.moves for r in res0)
     cap_qps = len(reqs) / t_closed
     qps = 0.7 * cap_qps
-    log("closed loop: %.2f s, capacity %.2f requests/s -> offered %.2f requests/s (%d batch rebuilds, %.2f s)"
-        % (t_closed, cap_qps, qps, srv.rebuilds, srv.rebuild_s))
-    arrivals = W.request_stream(args.requests, qps=qps, max_steps=args.served_steps)
+    log("served closed loop: %.2f s, %.1f GMoves/s, capacity %.2f requests/s -> offered %.2f requests/s "
+        "(%d plan updates, %.3f s)" % (t_closed, moves0 / t_closed / 1e9, cap_qps, qps, srv.rebuilds,
+                                       srv.rebuild_s))
+    arrivals = W.request_stream(count, qps=qps, max_steps=args.served_steps)
     for q, a in zip(reqs, arrivals):
         q.arrival_s = a.arrival_s
     srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
     t0 = time.perf_counter()
-    res = srv.run(reqs, log=log)
+    res = srv.run(reqs)
     t_open = time.perf_counter() - t0
     same = all((a.steps, a.moves, a.cost) == (b.steps, b.moves, b.cost) and
                a.customers.tolist() == b.customers.tolist() for a, b in zip(res0, res))
     lat = np.array([r.latency_s for r in res]) * 1e3
     moves = sum(r.moves for r in res)
-    line = {
+    out = {
         "metric": "served: aggregate GMoves/s + p50/p99 request latency (continuous batching)",
         "value": round(moves / t_open / 1e9, 4),
         "unit": "GMoves/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "served: %d requests, 200..10000 customers log-uniform, CVRP/VRPTW "
-                               "alternating, <= %d steps each, Poisson arrivals" % (len(reqs), args.served_steps),
-                   "qps": round(qps, 3), "capacity_qps": round(cap_qps, 3),
-                   "hbm_budget_bytes": budget, "moves_evaluated": moves},
+        "closed_loop_gmoves_s": round(moves0 / t_closed / 1e9, 4),
+        "workload": "served: %d requests, 200..10000 customers log-uniform, CVRP/VRPTW alternating, "
+                    "<= %d steps each, Poisson arrivals at 0.7 x the closed-loop capacity" % (
+                        len(reqs), args.served_steps),
+        "qps": round(qps, 3), "capacity_qps": round(cap_qps, 3),
+        "hbm_budget_bytes": budget, "moves_evaluated": moves,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                        "p99": round(float(np.percentile(lat, 99)), 2),
                        "max": round(float(lat.max()), 2)},
         "makespan_s": round(t_open, 3),
         "steps_per_tick": srv.steps_per_tick,
-        "batch_rebuilds": srv.rebuilds,
-        "batch_rebuild_s": round(srv.rebuild_s, 3),
+        "plan_updates": srv.rebuilds,
+        "plan_update_s": round(srv.rebuild_s, 3),
         "peak_active_requests": srv.peak_active,
         "peak_resident_bytes": srv.peak_used,
         "ticks": srv.ticks,
         "same_results_as_closed_loop": bool(same),
     }
-    print(json.dumps(line), flush=True)
+    log("served open loop: %.1f GMoves/s, p50 %.1f ms, p99 %.1f ms, same results %s" % (
+        out["value"], out["latency_ms"]["p50"], out["latency_ms"]["p99"], same))
+    return out
 
 
 def main():
@@ -203,6 +364,9 @@ def main():
     ap.add_argument("--steps-per-tick", type=int, default=2,
                     help="served form: local-search steps per scheduling tick (one poll per tick)")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-leg-requests", type=int, default=100,
+                    help="requests of the served leg of the default run (0 = none)")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -214,7 +378,9 @@ def main():
     from paper_2506_17357_amd import build_lib
     build_lib.ensure_built(verbose=True)
     if args.served:
-        served(args)
+        line = served_run(args, args.requests)
+        line.update({"n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic"})
+        print(json.dumps(line), flush=True)
         return
     import torch
     from paper_2506_17357_amd import tga, workload as W
@@ -234,7 +400,8 @@ def main():
     log("workload generated in %.1f s: %d solutions, sum n = %d" % (time.time() - t, len(pairs), sum(sizes)))
     insts = [tga.Instance.from_workload(i) for i, _ in pairs]
     sols = [tga.Solution(I, s.offsets, s.customers) for I, (_, s) in zip(insts, pairs)]
-    ebytes = np.array([eval_bytes(i, s.R, I.dist_bytes) for I, (i, s) in zip(insts, pairs)], np.float64)
+    ebytes = np.array([eval_bytes(i, s.R) for i, s in pairs], np.float64)
+    sbytes = np.array([streamed_bytes(i, s.R, I.dist_bytes) for I, (i, s) in zip(insts, pairs)], np.float64)
     B = tga.Batch(sols)
     torch.cuda.synchronize()
     t = time.time()
@@ -257,30 +424,16 @@ def main():
     B.collect()
     log("warmup: %d steps" % Wm)
 
-    # ---- timed eager pass with events around every evaluation launch
+    # ---- eager pass with events around every evaluation launch
     reload_all()
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.begin(K)
-    for k in range(K):
-        ev0[k].record()
-        B.step_part(0)
-        ev1[k].record()
-        B.step_part(1)
-    torch.cuda.synchronize()
-    t_eager = time.perf_counter() - t0
-    st_e, mv_e, cost_e = B.collect()
-    dur_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
-    evals = np.where(st_e < K, st_e + 1, K)
-    active = np.arange(K)[:, None] < evals[None, :]
-    bytes_per_launch = (active * ebytes[None, :]).sum(axis=1)
-    achieved_gbs = bytes_per_launch.sum() / (dur_ms.sum() * 1e-3) / 1e9
+    ev = eager_pass(B, K, ebytes, sbytes)
+    st_e, mv_e, cost_e = ev["steps"], ev["moves"], ev["cost"]
     moves_total = int(mv_e.sum())
+    roof = roofline_entry(ev)
     log("eager: %.3f s for %d steps, %d moves, eval launch avg %.1f us (first %.1f us, last %.1f us), "
-        "%.0f GB/s algorithmic" % (t_eager, K, moves_total, dur_ms.mean() * 1e3, dur_ms[0] * 1e3,
-                                    dur_ms[-1] * 1e3, achieved_gbs))
+        "%.0f GB/s algorithmic (%.3f of peak), %.0f GB/s streamed" % (
+            ev["seconds"], K, moves_total, roof["avg_launch_us"], ev["dur_ms"][0] * 1e3, ev["dur_ms"][-1] * 1e3,
+            roof["achieved"], roof["frac"], roof["streamed"]["achieved"]))
 
     # ---- graph pass (the step loop captured once, replayed from the initial state)
     reload_all()
@@ -314,28 +467,16 @@ def main():
                          np.array_equal(cost_p, cost_e))
         plain_value = int(mv_p.sum()) / t_plain / 1e9
         log("plain: %.3f s -> %.2f GMoves/s, bit-exact with batched: %s" % (t_plain, plain_value, bit_exact))
-        # best-move latency of the plain form on the solution closest to n = 1000
-        b1k = int(np.argmin([abs(i.n - 1000) for i, _ in pairs]))
-        s = sols[b1k]
-        s.reload(pairs[b1k][1].offsets, pairs[b1k][1].customers)
-        lat = []
-        for _ in range(60):
-            t1 = time.perf_counter()
-            m = s.eval()
-            lat.append((time.perf_counter() - t1) * 1e6)
-            if m is None or m.delta >= 0:
-                break
-            s.apply(m)
-        lat = np.array(lat)
         out_plain = {
             "value": round(plain_value, 4), "unit": "GMoves/s", "seconds": round(t_plain, 4),
             "form": "one solution per launch sequence (device-resident loop per solution)",
-            "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
-                                     "p99": round(float(np.percentile(lat, 99)), 1),
-                                     "n": pairs[b1k][0].n, "kind": pairs[b1k][0].kind,
-                                     "evals": int(lat.size)},
+            "configs": plain_configs(),
             "n1000": n1000_comparison(min(K, 50)),
         }
+
+    out_served = None
+    if not args.no_served and args.served_leg_requests > 0:
+        out_served = served_run(args, args.served_leg_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -354,10 +495,13 @@ def main():
         t_cpu = time.perf_counter() - t0
         cpu = {"value": round(mv / t_cpu / 1e9, 5), "unit": "GMoves/s", "cores": threads, "kind": "oracle",
                "sample": "one full-neighbourhood evaluation of the initial state of %d of the 256 solutions "
-                         "(%d moves, %.1f s)" % (len(sample), mv, t_cpu)}
-        log("cpu oracle: %.4f GMoves/s on %d threads" % (cpu["value"], threads))
+                         "(%d moves, %.1f s)" % (len(sample), mv, t_cpu),
+               "cpu_model": cpu_model(),
+               "configs": oracle_configs(threads)}
+        log("cpu oracle: %.4f GMoves/s on %d threads (%s)" % (cpu["value"], threads, cpu["cpu_model"]))
 
-    traffic = committed_traffic(bytes_per_launch.mean())
+    roof["traffic"] = traffic_entry(roof["avg_bytes_per_launch"])
+    roof["valu"] = valu_entry(roof["avg_launch_us"])
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -380,26 +524,19 @@ def main():
             "dist_bytes_resident": int(sum(4 * (i.n + 1) ** 2 for i, _ in pairs)),
             "dist_bytes_streamed_per_eval": int(sum(I.dist_bytes * (i.n + 1) ** 2 for I, (i, _) in zip(insts, pairs))),
             "moves_evaluated": moves_total,
+            "moves_counted": "every move of N(S) per evaluation (delta of each; feasibility and id only "
+                             "where the delta can still be the step's best)",
             "accepted_moves": int(st_e.sum()),
             "form": "batched: persistent evaluation launch(es) + one finalize launch per step, "
                     "step loop captured in a HIP graph",
             "schedule": schedule,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_eval_batch<3>",
-            "achieved": round(achieved_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "avg_launch_us": round(float(dur_ms.mean() * 1e3), 2),
-            "avg_bytes_per_launch": int(bytes_per_launch.mean()),
-        },
-        "eager_value": round(moves_total / t_eager / 1e9, 4),
+        "roofline": roof,
+        "eager_value": round(moves_total / ev["seconds"] / 1e9, 4),
         "plain": out_plain,
         "batched_over_plain": round(value / out_plain["value"], 3) if out_plain else None,
         "bit_exact_batched_vs_plain": bit_exact,
+        "served": out_served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

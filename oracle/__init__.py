@@ -50,6 +50,12 @@ def _load():
         lib.oracle_check_full.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P, u32, i64]
         lib.oracle_ls.restype = ctypes.c_int
         lib.oracle_ls.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i32, i32, P, P, P]
+        lib.oracle_eval_pen.restype = ctypes.c_int
+        lib.oracle_eval_pen.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_ls_pen.restype = ctypes.c_int
+        lib.oracle_ls_pen.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i64, i64, i32, i32, P, P, P]
+        lib.oracle_violations.restype = None
+        lib.oracle_violations.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -73,10 +79,11 @@ class Best:
 
 
 def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
-                       dump: bool = False):
+                       dump: bool = False, penalty=None):
     """Best admissible move of N(S) (and, with dump=True, per-move delta and
     feasibility arrays indexed by move id; non-moves keep delta 0 and feas
-    0xFF)."""
+    0xFF).  penalty=(w_load, w_tw): penalised mode, where every move is
+    admissible and `delta` is the score dD + w_load dL_V + w_tw dT_V."""
     lib = _load()
     D, nd = _inst_args(inst)
     off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
@@ -89,10 +96,17 @@ def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
     bd = np.zeros(1, np.int64)
     bid = np.zeros(1, np.uint32)
     mv = np.zeros(1, np.int64)
-    found = lib.oracle_eval(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
-                            off.shape[0] - 1, _p(off), _p(cust), op_mask, threads,
-                            _p(dd) if dump else None, _p(df) if dump else None,
-                            _p(bd), _p(bid), _p(mv))
+    if penalty is None:
+        found = lib.oracle_eval(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                off.shape[0] - 1, _p(off), _p(cust), op_mask, threads,
+                                _p(dd) if dump else None, _p(df) if dump else None,
+                                _p(bd), _p(bid), _p(mv))
+    else:
+        found = lib.oracle_eval_pen(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                    off.shape[0] - 1, _p(off), _p(cust), op_mask,
+                                    int(penalty[0]), int(penalty[1]), threads,
+                                    _p(dd) if dump else None, _p(df) if dump else None,
+                                    _p(bd), _p(bid), _p(mv))
     best = Best(bool(found), int(bd[0]), int(bid[0]), int(mv[0]))
     if dump:
         return best, dd, df
@@ -153,10 +167,24 @@ def check_full(inst, sol, dump_delta, dump_feas, op_mask: int = OPS_ALL,
                                      _p(dump_feas), op_mask, sample_every))
 
 
+def violations(inst, sol):
+    """(total load excess, total time warp) of S (penalised mode's terms)."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
+    lv = np.zeros(1, np.int64)
+    tv = np.zeros(1, np.int64)
+    lib.oracle_violations(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw, off.shape[0] - 1,
+                          _p(off), _p(cust), _p(lv), _p(tv))
+    return int(lv[0]), int(tv[0])
+
+
 def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
-                 threads: int = 0):
+                 threads: int = 0, penalty=None):
     """Best-improvement local search.  Returns (final Solution, ids, deltas,
-    total moves evaluated)."""
+    total moves evaluated).  penalty=(w_load, w_tw): penalised mode (deltas
+    are then scores)."""
     lib = _load()
     D, nd = _inst_args(inst)
     off = np.array(sol.offsets, dtype=np.int32)
@@ -164,9 +192,14 @@ def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
     ids = np.zeros(max(1, max_steps), np.uint32)
     deltas = np.zeros(max(1, max_steps), np.int32)
     mv = np.zeros(1, np.int64)
-    steps = lib.oracle_ls(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
-                          off.shape[0] - 1, _p(off), _p(cust), op_mask, max_steps, threads,
-                          _p(ids), _p(deltas), _p(mv))
+    if penalty is None:
+        steps = lib.oracle_ls(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                              off.shape[0] - 1, _p(off), _p(cust), op_mask, max_steps, threads,
+                              _p(ids), _p(deltas), _p(mv))
+    else:
+        steps = lib.oracle_ls_pen(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                  off.shape[0] - 1, _p(off), _p(cust), op_mask, int(penalty[0]),
+                                  int(penalty[1]), max_steps, threads, _p(ids), _p(deltas), _p(mv))
     return Routes(off, cust), ids[:steps].copy(), deltas[:steps].copy(), int(mv[0])
 
 

@@ -29,6 +29,19 @@
  *          the score equal to the distance delta and an infinite score for
  *          infeasible moves; lowest id breaks ties).
  *
+ * Penalised mode (feasible and infeasible search, Alg. A2; the scoring
+ * function of eq. scoring_tensor read as a weighted sum of the three
+ * attribute deltas of Section 5.3.3): every move of N(S) is admissible and
+ * scores
+ *       score(m) = dD + w_L * dL_V + w_T * dT_V
+ * over the touched route slots, where for one route
+ *       L_V = max(load - capacity, 0)                      (load excess),
+ *       T_V = time warp of the forward simulation: leave the depot at e_0,
+ *             wait when early, and when arriving after l_i pay the lateness
+ *             as warp and start service at l_i; arriving back after l_0 pays
+ *             the lateness too (the time-warp technique of Section 4.3.3).
+ * best = lexicographic minimum of (score, id) over all moves.
+ *
  * Operators (Section 4.1, Fig. 2; the move space is the reading recorded in
  * the design notes):
  *   op 0 RELOCATE  k=1  a = customer u, b = any ref v of another route:
@@ -111,6 +124,35 @@ static int route_windows_ok(const Inst *I, const int32_t *c, int L) {
     return back <= nd[2];
 }
 
+/* Load excess of a route (penalised mode). */
+static int64_t route_load_excess(const Inst *I, const int32_t *c, int L) {
+    int64_t q = route_load(I, c, L);
+    return q > I->cap ? q - I->cap : 0;
+}
+
+/* Time warp of a route, simulated forward (penalised mode; 0 without
+ * windows). */
+static int64_t route_time_warp(const Inst *I, const int32_t *c, int L) {
+    if (!I->has_tw) return 0;
+    const int32_t *nd = I->node4;
+    int64_t t = nd[1], warp = 0;
+    int prev = 0;
+    for (int i = 0; i < L; i++) {
+        int x = c[i];
+        int64_t arrive = t + nd[4 * prev + 3] + dist(I, prev, x);
+        if (arrive > nd[4 * x + 2]) {
+            warp += arrive - nd[4 * x + 2];
+            t = nd[4 * x + 2];
+        } else {
+            t = arrive > nd[4 * x + 1] ? arrive : nd[4 * x + 1];
+        }
+        prev = x;
+    }
+    int64_t back = t + nd[4 * prev + 3] + dist(I, prev, 0);
+    if (back > nd[2]) warp += back - nd[2];
+    return warp;
+}
+
 static int route_feas(const Inst *I, const int32_t *c, int L) {
     int f = 0;
     if (route_load(I, c, L) <= I->cap) f |= 1;
@@ -145,6 +187,8 @@ typedef struct {
     int32_t *route_of; /* by customer id, 1..n */
     int32_t *pos_of;
     int64_t *rdist;    /* current distance per route */
+    int64_t *rlv;      /* current load excess per route */
+    int64_t *rtv;      /* current time warp per route */
 } Index;
 
 static void index_build(const Inst *I, const Sol *S, Index *X) {
@@ -154,6 +198,8 @@ static void index_build(const Inst *I, const Sol *S, Index *X) {
     X->route_of = calloc((size_t)I->n + 1, sizeof(int32_t));
     X->pos_of = calloc((size_t)I->n + 1, sizeof(int32_t));
     X->rdist = calloc((size_t)S->R + 1, sizeof(int64_t));
+    X->rlv = calloc((size_t)S->R + 1, sizeof(int64_t));
+    X->rtv = calloc((size_t)S->R + 1, sizeof(int64_t));
     for (int r = 0; r < S->R; r++) {
         int L = S->off[r + 1] - S->off[r];
         for (int p = 0; p < L; p++) {
@@ -162,6 +208,8 @@ static void index_build(const Inst *I, const Sol *S, Index *X) {
             X->pos_of[c] = p + 1;
         }
         X->rdist[r] = route_distance(I, S->cust + S->off[r], L);
+        X->rlv[r] = route_load_excess(I, S->cust + S->off[r], L);
+        X->rtv[r] = route_time_warp(I, S->cust + S->off[r], L);
     }
 }
 
@@ -169,6 +217,8 @@ static void index_free(Index *X) {
     free(X->route_of);
     free(X->pos_of);
     free(X->rdist);
+    free(X->rlv);
+    free(X->rtv);
 }
 
 /* Route and position of a ref. */
@@ -287,6 +337,8 @@ typedef struct {
     const Sol *S;
     const Index *X;
     uint32_t op_mask;
+    int pen;             /* penalised mode */
+    int64_t w_load, w_tw;
     int32_t *dump_delta;
     uint8_t *dump_feas;
     int64_t *count;      /* per-thread move counts */
@@ -311,11 +363,20 @@ static void consider(Ctx *C, int tid, Move m, int32_t *b1, int32_t *b2) {
         delta += route_distance(I, b2, L2) - C->X->rdist[r2];
         feas &= route_feas(I, b2, L2);
     }
+    if (C->pen) {
+        int64_t dlv = route_load_excess(I, b1, L1) - C->X->rlv[r1];
+        int64_t dtv = route_time_warp(I, b1, L1) - C->X->rtv[r1];
+        if (touched == 2) {
+            dlv += route_load_excess(I, b2, L2) - C->X->rlv[r2];
+            dtv += route_time_warp(I, b2, L2) - C->X->rtv[r2];
+        }
+        delta += C->w_load * dlv + C->w_tw * dtv;  /* the score */
+    }
     uint32_t id = move_id(C->X->Q, m.op, m.k, m.a, m.b);
     if (C->dump_delta) C->dump_delta[id] = (int32_t)delta;
     if (C->dump_feas) C->dump_feas[id] = (uint8_t)feas;
     C->count[tid]++;
-    if (feas == 3) {
+    if (feas == 3 || C->pen) {
         Best *bt = &C->best[tid];
         if (!bt->found || delta < bt->delta || (delta == bt->delta && id < bt->id)) {
             bt->found = 1;
@@ -398,10 +459,11 @@ static int resolve_threads(int nthreads) {
  * exists (written to *best_*), 0 otherwise.  Optional dumps are indexed by
  * move id and must hold 20 * Q * Q entries; entries that are not moves are
  * left untouched.  *moves receives |N(S)| for the enabled operators. */
-int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-                int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
-                int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
-                int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
+static int eval_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                     int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                     int pen, int64_t w_load, int64_t w_tw,
+                     int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                     int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
     Inst I = {n, D, node4, cap, has_tw};
     Sol S = {R, off, cust};
     Index X;
@@ -413,6 +475,9 @@ int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int 
     C.S = &S;
     C.X = &X;
     C.op_mask = op_mask;
+    C.pen = pen;
+    C.w_load = w_load;
+    C.w_tw = w_tw;
     C.dump_delta = dump_delta;
     C.dump_feas = dump_feas;
     C.nthreads = T;
@@ -450,6 +515,26 @@ int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int 
     free(C.count);
     index_free(&X);
     return b.found;
+}
+
+int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
+    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 0, 0, 0, nthreads, dump_delta,
+                     dump_feas, best_delta, best_id, moves);
+}
+
+/* Penalised mode: as oracle_eval, but every move is admissible, the dumped
+ * and returned value is the score dD + w_load * dL_V + w_tw * dT_V, and
+ * dump_feas still holds the hard capacity / window bits of the touched
+ * routes.  Returns 1 when N(S) has a move. */
+int oracle_eval_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                    int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                    int64_t w_load, int64_t w_tw, int nthreads, int32_t *dump_score,
+                    uint8_t *dump_feas, int64_t *best_score, uint32_t *best_id, int64_t *moves) {
+    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 1, w_load, w_tw, nthreads,
+                     dump_score, dump_feas, best_score, best_id, moves);
 }
 
 /* Apply move `id` to (off, cust) in place.  Returns 0 on success, -1 if the
@@ -583,16 +668,17 @@ typedef struct {
  * move while its delta is negative, stop at a local optimum or after
  * max_steps.  Writes the accepted moves to `traj` (max_steps entries) and
  * updates (off, cust) in place.  Returns the number of accepted moves. */
-int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-              int R, int32_t *off, int32_t *cust, uint32_t op_mask, int max_steps,
-              int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
+static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, int pen, int64_t w_load,
+                   int64_t w_tw, int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_delta,
+                   int64_t *moves_total) {
     int steps = 0;
     int64_t mv_sum = 0;
     while (steps < max_steps) {
         int64_t bd = 0, mv = 0;
         uint32_t bid = 0;
-        int found = oracle_eval(n, D, node4, cap, has_tw, R, off, cust, op_mask, nthreads,
-                                NULL, NULL, &bd, &bid, &mv);
+        int found = eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, pen, w_load, w_tw,
+                              nthreads, NULL, NULL, &bd, &bid, &mv);
         mv_sum += mv;
         if (!found || bd >= 0) break;
         if (oracle_apply(n, D, node4, cap, has_tw, R, off, cust, bid) != 0) break;
@@ -602,4 +688,37 @@ int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int ha
     }
     if (moves_total) *moves_total = mv_sum;
     return steps;
+}
+
+int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+              int R, int32_t *off, int32_t *cust, uint32_t op_mask, int max_steps,
+              int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
+    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 0, 0, 0, max_steps, nthreads,
+                   traj_id, traj_delta, moves_total);
+}
+
+/* Penalised local search: repeat {best move by score; apply it if its score
+ * is negative} (feasible and infeasible search, Alg. A2). */
+int oracle_ls_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                  int R, int32_t *off, int32_t *cust, uint32_t op_mask, int64_t w_load, int64_t w_tw,
+                  int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_score,
+                  int64_t *moves_total) {
+    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 1, w_load, w_tw, max_steps, nthreads,
+                   traj_id, traj_score, moves_total);
+}
+
+/* Penalty terms of S: total load excess and total time warp over the routes
+ * (as in penalised mode). */
+void oracle_violations(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                       int R, const int32_t *off, const int32_t *cust, int64_t *load_excess,
+                       int64_t *time_warp) {
+    Inst I = {n, D, node4, cap, has_tw};
+    int64_t lv = 0, tv = 0;
+    for (int r = 0; r < R; r++) {
+        int L = off[r + 1] - off[r];
+        lv += route_load_excess(&I, cust + off[r], L);
+        tv += route_time_warp(&I, cust + off[r], L);
+    }
+    *load_excess = lv;
+    *time_warp = tv;
 }

@@ -54,6 +54,12 @@ def _load():
         lib.oracle_eval_pen.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i64, i64, i32, P, P, P, P, P]
         lib.oracle_ls_pen.restype = ctypes.c_int
         lib.oracle_ls_pen.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, i64, i64, i32, i32, P, P, P]
+        lib.oracle_granular_mask.restype = None
+        lib.oracle_granular_mask.argtypes = [i32, P, i32, P]
+        lib.oracle_eval_gran.restype = ctypes.c_int
+        lib.oracle_eval_gran.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, P, i32, P, P, P, P, P]
+        lib.oracle_ls_gran.restype = ctypes.c_int
+        lib.oracle_ls_gran.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, P, i32, i32, P, P, P]
         lib.oracle_violations.restype = None
         lib.oracle_violations.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P]
         _lib = lib
@@ -78,12 +84,24 @@ class Best:
     moves: int
 
 
+def granular_mask(inst, theta: int) -> np.ndarray:
+    """(n+1) x (n+1) uint8 pair mask of granular mode: {i, j} is kept when
+    either node is among the theta closest to the other."""
+    lib = _load()
+    D = np.ascontiguousarray(inst.dist, dtype=np.int32)
+    m = np.zeros((inst.n + 1, inst.n + 1), np.uint8)
+    lib.oracle_granular_mask(inst.n, _p(D), int(theta), _p(m))
+    return m
+
+
 def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
-                       dump: bool = False, penalty=None):
+                       dump: bool = False, penalty=None, theta=None, mask=None):
     """Best admissible move of N(S) (and, with dump=True, per-move delta and
     feasibility arrays indexed by move id; non-moves keep delta 0 and feas
     0xFF).  penalty=(w_load, w_tw): penalised mode, where every move is
-    admissible and `delta` is the score dD + w_load dL_V + w_tw dT_V."""
+    admissible and `delta` is the score dD + w_load dL_V + w_tw dT_V.
+    theta (or a prebuilt granular mask): granular mode, the inter-route
+    moves restricted to the granular pairs."""
     lib = _load()
     D, nd = _inst_args(inst)
     off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
@@ -96,7 +114,15 @@ def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
     bd = np.zeros(1, np.int64)
     bid = np.zeros(1, np.uint32)
     mv = np.zeros(1, np.int64)
-    if penalty is None:
+    if theta is not None and mask is None:
+        mask = granular_mask(inst, theta)
+    if mask is not None:
+        assert penalty is None
+        found = lib.oracle_eval_gran(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                     off.shape[0] - 1, _p(off), _p(cust), op_mask, _p(mask), threads,
+                                     _p(dd) if dump else None, _p(df) if dump else None,
+                                     _p(bd), _p(bid), _p(mv))
+    elif penalty is None:
         found = lib.oracle_eval(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
                                 off.shape[0] - 1, _p(off), _p(cust), op_mask, threads,
                                 _p(dd) if dump else None, _p(df) if dump else None,
@@ -181,10 +207,10 @@ def violations(inst, sol):
 
 
 def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
-                 threads: int = 0, penalty=None):
+                 threads: int = 0, penalty=None, theta=None, mask=None):
     """Best-improvement local search.  Returns (final Solution, ids, deltas,
     total moves evaluated).  penalty=(w_load, w_tw): penalised mode (deltas
-    are then scores)."""
+    are then scores); theta / mask: granular mode."""
     lib = _load()
     D, nd = _inst_args(inst)
     off = np.array(sol.offsets, dtype=np.int32)
@@ -192,7 +218,14 @@ def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
     ids = np.zeros(max(1, max_steps), np.uint32)
     deltas = np.zeros(max(1, max_steps), np.int32)
     mv = np.zeros(1, np.int64)
-    if penalty is None:
+    if theta is not None and mask is None:
+        mask = granular_mask(inst, theta)
+    if mask is not None:
+        assert penalty is None
+        steps = lib.oracle_ls_gran(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
+                                   off.shape[0] - 1, _p(off), _p(cust), op_mask, _p(mask), max_steps,
+                                   threads, _p(ids), _p(deltas), _p(mv))
+    elif penalty is None:
         steps = lib.oracle_ls(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
                               off.shape[0] - 1, _p(off), _p(cust), op_mask, max_steps, threads,
                               _p(ids), _p(deltas), _p(mv))

@@ -42,6 +42,16 @@
  *             the lateness too (the time-warp technique of Section 4.3.3).
  * best = lexicographic minimum of (score, id) over all moves.
  *
+ * Granular mode (edge-based neighbourhood reduction, Section 5.3.1 edge-based
+ * extraction with the granularity threshold theta of the experiments): node
+ * j is a neighbour of node i when it is among the theta nodes closest to i
+ * (distance, then node id; the depot is node 0 and every start depot of a
+ * route stands for it); the mask keeps the pairs {i, j} where either is a
+ * neighbour of the other.  The inter-route moves (RELOCATE, SWAP of
+ * customers in different routes, 2OPT*) are kept only when the nodes of
+ * their two refs form such a pair; intra-route moves (2OPT, OR-OPT, SWAP
+ * within a route) are all kept.
+ *
  * Operators (Section 4.1, Fig. 2; the move space is the reading recorded in
  * the design notes):
  *   op 0 RELOCATE  k=1  a = customer u, b = any ref v of another route:
@@ -337,6 +347,7 @@ typedef struct {
     const Sol *S;
     const Index *X;
     uint32_t op_mask;
+    const uint8_t *gran; /* (n+1) x (n+1) pair mask, or NULL for the full neighbourhood */
     int pen;             /* penalised mode */
     int64_t w_load, w_tw;
     int32_t *dump_delta;
@@ -387,6 +398,15 @@ static void consider(Ctx *C, int tid, Move m, int32_t *b1, int32_t *b2) {
     }
 }
 
+static int ref_node(const Index *X, int ref) { return ref < X->n ? ref + 1 : 0; }
+
+/* Granular mask test of an inter-route move's refs (1 without a mask). */
+static int gran_ok(const Ctx *C, int a, int b) {
+    if (!C->gran) return 1;
+    const int n = C->I->n;
+    return C->gran[(size_t)ref_node(C->X, a) * (n + 1) + ref_node(C->X, b)];
+}
+
 /* Task t covers operator op = t / n and first ref a = t % n (customers), or
  * for 2OPT* any first ref; OR-OPT tasks run over (k, a). */
 static void run_task(Ctx *C, int tid, int t, int32_t *b1, int32_t *b2) {
@@ -400,18 +420,21 @@ static void run_task(Ctx *C, int tid, int t, int32_t *b1, int32_t *b2) {
         for (int b = 0; b < Q; b++) {
             int rb, pb;
             ref_where(X, b, &rb, &pb);
-            if (rb == ra) continue;
+            if (rb == ra || !gran_ok(C, a, b)) continue;
             consider(C, tid, (Move){0, 1, a, b}, b1, b2);
         }
     } else if (op == 1 && (C->op_mask & 2) && a < n) {
-        for (int b = a + 1; b < n; b++) consider(C, tid, (Move){1, 1, a, b}, b1, b2);
+        for (int b = a + 1; b < n; b++) {
+            if (X->route_of[a + 1] != X->route_of[b + 1] && !gran_ok(C, a, b)) continue;
+            consider(C, tid, (Move){1, 1, a, b}, b1, b2);
+        }
     } else if (op == 2 && (C->op_mask & 4)) {
         int ra, pa;
         ref_where(X, a, &ra, &pa);
         for (int b = a + 1; b < Q; b++) {
             int rb, pb;
             ref_where(X, b, &rb, &pb);
-            if (rb == ra) continue;
+            if (rb == ra || !gran_ok(C, a, b)) continue;
             consider(C, tid, (Move){2, 0, a, b}, b1, b2);
         }
     } else if (op == 3 && (C->op_mask & 8) && a < n) {
@@ -461,7 +484,7 @@ static int resolve_threads(int nthreads) {
  * left untouched.  *moves receives |N(S)| for the enabled operators. */
 static int eval_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
                      int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
-                     int pen, int64_t w_load, int64_t w_tw,
+                     const uint8_t *gran, int pen, int64_t w_load, int64_t w_tw,
                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
                      int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
     Inst I = {n, D, node4, cap, has_tw};
@@ -475,6 +498,7 @@ static int eval_core(int n, const int32_t *D, const int32_t *node4, int64_t cap,
     C.S = &S;
     C.X = &X;
     C.op_mask = op_mask;
+    C.gran = gran;
     C.pen = pen;
     C.w_load = w_load;
     C.w_tw = w_tw;
@@ -521,7 +545,7 @@ int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int 
                 int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                 int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
                 int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
-    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 0, 0, 0, nthreads, dump_delta,
+    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, nthreads, dump_delta,
                      dump_feas, best_delta, best_id, moves);
 }
 
@@ -533,7 +557,7 @@ int oracle_eval_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, 
                     int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                     int64_t w_load, int64_t w_tw, int nthreads, int32_t *dump_score,
                     uint8_t *dump_feas, int64_t *best_score, uint32_t *best_id, int64_t *moves) {
-    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 1, w_load, w_tw, nthreads,
+    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, nthreads,
                      dump_score, dump_feas, best_score, best_id, moves);
 }
 
@@ -669,7 +693,8 @@ typedef struct {
  * max_steps.  Writes the accepted moves to `traj` (max_steps entries) and
  * updates (off, cust) in place.  Returns the number of accepted moves. */
 static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, int pen, int64_t w_load,
+                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *gran,
+                   int pen, int64_t w_load,
                    int64_t w_tw, int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_delta,
                    int64_t *moves_total) {
     int steps = 0;
@@ -677,7 +702,7 @@ static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, i
     while (steps < max_steps) {
         int64_t bd = 0, mv = 0;
         uint32_t bid = 0;
-        int found = eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, pen, w_load, w_tw,
+        int found = eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, gran, pen, w_load, w_tw,
                               nthreads, NULL, NULL, &bd, &bid, &mv);
         mv_sum += mv;
         if (!found || bd >= 0) break;
@@ -693,7 +718,7 @@ static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, i
 int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
               int R, int32_t *off, int32_t *cust, uint32_t op_mask, int max_steps,
               int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
-    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 0, 0, 0, max_steps, nthreads,
+    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, max_steps, nthreads,
                    traj_id, traj_delta, moves_total);
 }
 
@@ -703,8 +728,51 @@ int oracle_ls_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, in
                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, int64_t w_load, int64_t w_tw,
                   int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_score,
                   int64_t *moves_total) {
-    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, 1, w_load, w_tw, max_steps, nthreads,
+    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, max_steps, nthreads,
                    traj_id, traj_score, moves_total);
+}
+
+/* The granular pair mask: mask[i * (n+1) + j] = 1 when j is among the
+ * theta nodes closest to i (distance, then id; i itself excluded) or i is
+ * among the theta closest to j.  Plain selection by sorting each row. */
+static int cmp_key(const void *x, const void *y) {
+    const int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return a < b ? -1 : a > b;
+}
+
+void oracle_granular_mask(int n, const int32_t *D, int theta, uint8_t *mask) {
+    const int N = n + 1;
+    memset(mask, 0, (size_t)N * N);
+    int64_t *key = malloc(sizeof(int64_t) * N);
+    for (int i = 0; i < N; i++) {
+        int m = 0;
+        for (int j = 0; j < N; j++)
+            if (j != i) key[m++] = ((int64_t)D[(int64_t)i * N + j] << 20) | j;
+        qsort(key, m, sizeof(int64_t), cmp_key);
+        for (int k = 0; k < theta && k < m; k++) {
+            int j = (int)(key[k] & ((1 << 20) - 1));
+            mask[(size_t)i * N + j] = 1;
+            mask[(size_t)j * N + i] = 1;
+        }
+    }
+    free(key);
+}
+
+/* Granular mode (hard feasibility): as oracle_eval over the reduced
+ * neighbourhood of the mask built by oracle_granular_mask. */
+int oracle_eval_gran(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                     int R, const int32_t *off, const int32_t *cust, uint32_t op_mask, const uint8_t *mask,
+                     int nthreads, int32_t *dump_delta, uint8_t *dump_feas, int64_t *best_delta,
+                     uint32_t *best_id, int64_t *moves) {
+    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, nthreads, dump_delta,
+                     dump_feas, best_delta, best_id, moves);
+}
+
+int oracle_ls_gran(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
+                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *mask, int max_steps,
+                   int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
+    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, max_steps, nthreads,
+                   traj_id, traj_delta, moves_total);
 }
 
 /* Penalty terms of S: total load excess and total time warp over the routes

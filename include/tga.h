@@ -71,7 +71,10 @@ enum {
     TGA_OP_2OPTSTAR = 1u << 2,
     TGA_OP_2OPT = 1u << 3,
     TGA_OP_OROPT = 1u << 4,
-    TGA_OP_ALL = 0x1Fu
+    TGA_OP_ALL = 0x1Fu,
+    /* modifier: inter-route operators restricted to the granular pairs of the
+     * instance (tga_instance_set_granular); single-solution calls only */
+    TGA_OP_GRANULAR = 1u << 5
 };
 
 #define TGA_MAX_Q 14654
@@ -112,6 +115,27 @@ size_t tga_solution_workspace_bytes(int32_t n, int32_t R);
 int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *node4, int32_t capacity,
                       int32_t has_tw, void *ws, size_t ws_bytes, void *stream,
                       tga_instance_t *out);
+
+/* Section 5.3.1 (edge-based extraction) with the granularity threshold
+ * theta of the paper's experiments: the neighbourhood reduction of the
+ * edge-implemented form.  Node j is a neighbour of node i when it is among
+ * the theta nodes closest to i (distance, then node id; i excluded; node 0
+ * is the depot and stands for the start depot of every route); the mask
+ * keeps the pairs {i, j} where either is a neighbour of the other.  With
+ * TGA_OP_GRANULAR in op_mask, tga_eval_neighborhood and tga_ls_run evaluate
+ * the inter-route moves (RELOCATE, SWAP across routes, 2OPT*) only for refs
+ * whose nodes form a kept pair; intra-route moves stay complete.  Move ids
+ * are unchanged.  The neighbour lists are computed on the device
+ * (1 <= theta <= min(n, 512)); the pair lists live in `ws`
+ * (tga_granular_workspace_bytes(n, theta) bytes, 256-byte aligned, caller
+ * owned, borrowed for the instance's lifetime).  Synchronises `stream`. */
+size_t tga_granular_workspace_bytes(int32_t n, int32_t theta);
+int tga_instance_set_granular(tga_instance_t inst, int32_t theta, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjacency entries of the customer rows of the granular pairs (each kept
+ * pair of customers counted twice, a customer-depot pair once); 0 before
+ * tga_instance_set_granular. */
+int32_t tga_instance_granular_pairs(tga_instance_t inst);
 
 /* Bytes per distance the inter-route kernels stream for this instance: 2
  * when every distance is below 2^16 (tga_load_instance then keeps a 16-bit

@@ -22,6 +22,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local tga_move_t *g_pin = nullptr;  // pinned staging, 4 KiB per host thread
+thread_local int32_t *g_pin_dev = nullptr;  // the same memory as kernels address it (null: copy instead)
 
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...) {
@@ -47,6 +48,11 @@ int pinned(void **p) {
             g_pin = nullptr;
             return fail(TGA_EDEVICE, "hipHostMalloc: %s", hipGetErrorString(e));
         }
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, g_pin, 0) == hipSuccess)
+            g_pin_dev = (int32_t *)dp;
+        else
+            (void)hipGetLastError();
     }
     *p = g_pin;
     return TGA_OK;
@@ -188,6 +194,10 @@ struct tga_instance {
     int32_t stride16;
     const int4 *node4;
     int32_t maxD, maxE, maxL, maxS, maxDem;
+    // granular neighbourhood (tga_instance_set_granular): adjacency entries of
+    // the customer rows, source and neighbour node, in a caller workspace
+    int32_t theta = 0, gnnz = 0;
+    const int32_t *gsrc = nullptr, *gadj = nullptr;
 };
 
 struct tga_solution {
@@ -337,6 +347,65 @@ extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *
     *out = I;
     return TGA_OK;
 }
+
+extern "C" size_t tga_granular_workspace_bytes(int32_t n, int32_t theta) {
+    if (n < 1 || n > TGA_MAX_Q - 1 || theta < 1 || theta > n || theta > kKnnMax) return 0;
+    const size_t np1 = (size_t)n + 1;
+    // theta nearest of every node, then source and neighbour of up to
+    // 2 theta (n+1) adjacency entries
+    return align_up(4 * np1 * theta, 256) + 2 * align_up(4 * 2 * np1 * (size_t)theta, 256);
+}
+
+extern "C" int tga_instance_set_granular(tga_instance_t inst, int32_t theta, void *ws, size_t ws_bytes,
+                                         void *stream) {
+    if (!inst || !ws) return fail(TGA_EINVAL, "null argument");
+    const int n = inst->n, np1 = n + 1;
+    const size_t need = tga_granular_workspace_bytes(n, theta);
+    if (!need) return fail(TGA_ERANGE, "theta = %d outside [1, min(n, %d)]", theta, kKnnMax);
+    if (ws_bytes < need) return fail(TGA_ENOMEM, "granular workspace %zu < %zu", ws_bytes, need);
+    if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *nn = (int32_t *)ws;
+    k_knn<<<np1, 256, 0, st>>>(inst->D, np1, theta, nn);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> h((size_t)np1 * theta);
+    HIPCHK(hipMemcpyAsync(h.data(), nn, 4 * h.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // symmetric closure: j is listed under i when either is among the other's
+    // theta nearest; only the rows of customers are kept (the depot's pairs
+    // are walked from its customers)
+    std::vector<std::vector<int32_t>> adj(np1);
+    for (int i = 0; i < np1; ++i)
+        for (int k = 0; k < theta; ++k) {
+            const int j = h[(size_t)i * theta + k];
+            if (j < 0 || j > n || j == i) return fail(TGA_EDEVICE, "neighbour list of node %d is corrupt", i);
+            adj[i].push_back(j);
+            adj[j].push_back(i);
+        }
+    std::vector<int32_t> src, dst;
+    for (int i = 1; i < np1; ++i) {
+        std::sort(adj[i].begin(), adj[i].end());
+        adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+        for (int j : adj[i]) {
+            src.push_back(i);
+            dst.push_back(j);
+        }
+    }
+    int32_t *gsrc = (int32_t *)((char *)ws + align_up(4 * (size_t)np1 * theta, 256));
+    int32_t *gadj = (int32_t *)((char *)gsrc + align_up(4 * 2 * (size_t)np1 * theta, 256));
+    if (!src.empty()) {
+        HIPCHK(hipMemcpyAsync(gsrc, src.data(), 4 * src.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(gadj, dst.data(), 4 * dst.size(), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    inst->theta = theta;
+    inst->gnnz = (int32_t)src.size();
+    inst->gsrc = gsrc;
+    inst->gadj = gadj;
+    return TGA_OK;
+}
+
+extern "C" int32_t tga_instance_granular_pairs(tga_instance_t inst) { return inst ? inst->gnnz : 0; }
 
 extern "C" int32_t tga_instance_dist_bytes(tga_instance_t inst) {
     if (!inst) return 0;
@@ -550,6 +619,41 @@ extern "C" int tga_free_solution(tga_solution_t sol) {
 
 extern "C" uint32_t tga_solution_version(tga_solution_t sol) { return sol ? sol->version : 0; }
 
+// Granular mode: the inter-route moves of the granular pairs (one launch of
+// k_eval_gran), the intra-route ones complete (k_eval_intra).
+static void launch_eval_gran(const tga_instance *I, const SolDev *d, const IntraItem *intra, int nintra,
+                             int has_tw, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
+    const bool dump = dd != nullptr;
+    if ((op_mask & 7) && I->gnnz > 0) {
+        const int grid = (I->gnnz + 255) / 256;
+        if (has_tw) {
+            if (dump)
+                k_eval_gran<true, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+            else
+                k_eval_gran<true, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_gran<false, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+            else
+                k_eval_gran<false, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+        }
+    }
+    if ((op_mask & (2 | 8 | 16)) && nintra > 0) {
+        const size_t ilds = (size_t)kInterWaves * kIntraRegionBytes;
+        if (has_tw) {
+            if (dump)
+                k_eval_intra<true, true><<<nintra, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
+            else
+                k_eval_intra<true, false><<<nintra, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_intra<false, true><<<nintra, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
+            else
+                k_eval_intra<false, false><<<nintra, kInterThreads, ilds, st>>>(d, intra, nintra, op_mask, dd, df);
+        }
+    }
+}
+
 static void launch_eval(const SolDev *d, const InterItem *items, int nitems, const IntraItem *intra,
                         int nintra, int has_tw, uint32_t op_mask, size_t lds, int grid_inter,
                         int32_t *dd, uint8_t *df, hipStream_t st) {
@@ -624,13 +728,35 @@ static void to_move(const int32_t *rec, tga_move_t *m) {
 // One evaluation of a solution whose workspace is set up: evaluation launch,
 // record-mode finalize, and one copy of the record and state[0..3] into
 // `host` (48 bytes; pinned or pageable).
+// Launch one evaluation of a solution (granular or full neighbourhood).
+static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
+    if (op_mask & TGA_OP_GRANULAR)
+        launch_eval_gran(sol->inst, sol->d, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
+    else
+        launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask, sol->lds,
+                    sol->nitems, dd, df, st);
+}
+
+// Operator mask of a single-solution call: the five operators plus the
+// granular modifier (only once the instance has its granular pairs).
+static int check_mask(const tga_solution *sol, uint32_t op_mask) {
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_GRANULAR)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if ((op_mask & TGA_OP_GRANULAR) && !sol->inst->gnnz)
+        return fail(TGA_EINVAL, "TGA_OP_GRANULAR before tga_instance_set_granular");
+    return TGA_OK;
+}
+
+// `host_pinned`: `host` is this thread's pinned buffer, which the finalize
+// kernel writes directly (through its device address); otherwise (pageable
+// memory, or no device address) the record is copied after it.
 static int eval_record(tga_solution *sol, uint32_t op_mask, tga_move_t *best, int32_t *dump_delta,
-                       uint8_t *dump_feas, hipStream_t st, int32_t *host) {
-    launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask,
-                sol->lds, sol->nitems, dump_delta, dump_feas, st);
-    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr);
+                       uint8_t *dump_feas, hipStream_t st, int32_t *host, bool host_pinned) {
+    int32_t *dev_view = host_pinned ? g_pin_dev : nullptr;  // where the kernel may write `host`
+    launch_solution_eval(sol, op_mask, dump_delta, dump_feas, st);
+    k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, op_mask, nullptr, dev_view);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(host, sol->h.rec, 32 + 16, hipMemcpyDeviceToHost, st));  // record, state[0..3]
+    if (!dev_view)
+        HIPCHK(hipMemcpyAsync(host, sol->h.rec, 32 + 16, hipMemcpyDeviceToHost, st));  // record, state[0..3]
     HIPCHK(hipStreamSynchronize(st));
     if (host[8 + kStStatus] == 1) {
         memset(best, 0, sizeof *best);
@@ -647,14 +773,14 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
     if (!sol || !best) return fail(TGA_EINVAL, "null argument");
     if ((dump_delta == nullptr) != (dump_feas == nullptr))
         return fail(TGA_EINVAL, "dump_delta and dump_feas must both be set or both be null");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
-    DevProps P;
-    int rc = props(&P);
+    int rc = check_mask(sol, op_mask);
     if (rc) return rc;
+    DevProps P;
+    if ((rc = props(&P))) return rc;
     void *pin;
     if ((rc = pinned(&pin))) return rc;
-    return eval_record(sol, op_mask, best, dump_delta, dump_feas, (hipStream_t)stream, (int32_t *)pin);
+    return eval_record(sol, op_mask, best, dump_delta, dump_feas, (hipStream_t)stream, (int32_t *)pin, true);
 }
 
 // ------------------------------------------------- no-allocation variant ----
@@ -706,7 +832,7 @@ extern "C" int tga_eval_routes_static(tga_instance_t inst, int32_t R, const int3
     tga_solution S{};  // lives for this call only; its arrays are in the scratch
     if ((rc = solution_init(&S, inst, R, offsets, customers, ws, st))) return rc;
     int32_t host[12];  // record and state[0..3]: pageable, so nothing is allocated
-    return eval_record(&S, op_mask, best, nullptr, nullptr, st, host);
+    return eval_record(&S, op_mask, best, nullptr, nullptr, st, host, false);
 }
 
 extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_t *new_cost, void *stream) {
@@ -744,12 +870,12 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
                           int64_t *moves_evaluated, int64_t *cost, void *stream) {
     if (!sol) return fail(TGA_EINVAL, "null solution");
     if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    int rc = check_mask(sol, op_mask);
+    if (rc) return rc;
     if (max_steps < 0) return fail(TGA_EINVAL, "max_steps < 0");
     hipStream_t st = (hipStream_t)stream;
     void *pin;
-    int rc = pinned(&pin);
-    if (rc) return rc;
+    if ((rc = pinned(&pin))) return rc;
     int32_t *p = (int32_t *)pin;
     k_reset_state<<<1, 64, 0, st>>>(sol->d, 1, max_steps);
     HIPCHK(hipGetLastError());
@@ -761,8 +887,7 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
     while (launched < max_steps) {
         const int todo = std::min(chunk, max_steps - launched);
         for (int i = 0; i < todo; ++i) {
-            launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw,
-                        op_mask | kImprovingOnly, sol->lds, sol->nitems, nullptr, nullptr, st);
+            launch_solution_eval(sol, op_mask | kImprovingOnly, nullptr, nullptr, st);
             k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask, nullptr);
         }
         HIPCHK(hipGetLastError());

@@ -99,6 +99,10 @@ constexpr int kAdmissibleBound = 1 << 29;
 // apply — is found exactly as before.
 constexpr uint32_t kImprovingOnly = 1u << 31;
 
+// Operator-mask modifier (TGA_OP_GRANULAR): inter-route operators restricted
+// to the granular pairs of the instance.
+constexpr uint32_t kGranular = 1u << 5;
+
 __device__ __forceinline__ int initial_bound(uint32_t op_mask) {
     return (op_mask & kImprovingOnly) ? 0 : kAdmissibleBound;
 }
@@ -1117,6 +1121,158 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+// ------------------------------------------- granular inter-route eval ---
+// Edge-based extraction (Section 5.3.1): only the node pairs kept by the
+// granular mask, the symmetric closure of each node's theta nearest
+// neighbours, get their inter-route moves evaluated.  The mask is an
+// adjacency list over nodes 0..n (CSR; node 0 is the depot and stands for
+// the start depot of every route).  One thread per adjacency entry (u, v) of
+// a customer u: the pair of slots (slot(u), slot(v)) is evaluated by the
+// entry whose row route comes first (each pair once, as in the full kernel:
+// row route < column route); an entry (u, depot) evaluates u against the
+// start depot of every other route.  The depot's own row is never walked:
+// its pairs are those of its customers.  Attributes are gathered per thread
+// (no LDS staging): E is small next to the Q^2 pairs of the full
+// neighbourhood.
+
+// Column attributes of slot t for one thread (the fields pair_moves reads).
+__device__ __forceinline__ void lane_col_single(const SolDev &S, int t, LaneCol &L) {
+    L.ta = gld(S.a4 + t);
+    L.tb = gld(S.b4 + t);
+    if (S.has_tw) {
+        L.tt = gld(S.t4 + t);
+        L.tw = gld(S.w4 + t);
+    } else {
+        L.tt = make_int4(0, 0, 0, 0);
+        L.tw = make_int4(0, 0, 0, 0);
+    }
+    L.node = nodeof(L.ta.x);
+    const int fl = flagsof(L.ta.x);
+    const bool cust = fl & kFlagCustomer;
+    L.refT = cust ? L.node - 1 : S.n + L.ta.y;
+    L.tyOwn = L.ta.y - 1;
+    L.tInval = cust ? 0 : (int)0x80000000;
+    L.tRemCap = (fl & kFlagRemCap) ? 0 : (int)0x80000000;
+    L.tRemTw = (fl & kFlagRemTw) ? 0 : (int)0x80000000;
+    L.negTz = -L.ta.z;
+    L.negTw = -L.tb.w;
+    L.zx = L.tb.z - L.tb.x;
+    L.zy = L.tb.z - L.tb.y;
+}
+
+// The four inter-route moves of row slot x against column slot t (route(x)
+// < route(t)), with every attribute gathered from the slot arrays and D.
+// Returns the number of moves of N_theta(S) the pair stands for.
+template <bool TW, bool DUMP>
+__device__ __forceinline__ int gran_pair(const SolDev &S, int x, int t, uint32_t op_mask,
+                                         int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
+                                         int &bd, uint32_t &bid) {
+    const bool opRel = op_mask & 1, opSwap = op_mask & 2, op2s = op_mask & 4;
+    LaneCol L;
+    lane_col_single(S, t, L);
+    const int4 ra = gld(S.a4 + x), rb = gld(S.b4 + x);
+    int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
+    if (TW) {
+        rt = gld(S.t4 + x);
+        rw = gld(S.w4 + x);
+    }
+    const RowVals R = row_vals(ra, rb, S.cap, S.n);
+    const int np1 = S.np1;
+    const int nx = nodeof(ra.x), npx = nodeof(gld(S.a4 + max(x - 1, 0)).x), nsx = nodeof(gld(S.a4 + x + 1).x);
+    const int nt = L.node, npt = nodeof(gld(S.a4 + t - 1).x), nst = nodeof(gld(S.a4 + t + 1).x);
+    const int32_t *D = S.D;
+    const int g = gld(D + (size_t)nx * np1 + nt), gp = gld(D + (size_t)npx * np1 + nt),
+              gn = gld(D + (size_t)nsx * np1 + nt), gR = gld(D + (size_t)nx * np1 + nst),
+              gL = gld(D + (size_t)nx * np1 + npt);
+    pair_moves<TW, DUMP>(L, R, rt, rw, gp, g, gn, gR, gL, (uint32_t)S.Q, opRel, opSwap, op2s, dump_delta,
+                         dump_feas, bd, bid);
+    const bool cx = R.sInval == 0, ct = L.tInval == 0;
+    return (opRel ? (int)cx + (int)ct : 0) + (opSwap && cx && ct ? 1 : 0) + (op2s ? 1 : 0);
+}
+
+// gsrc / gadj: the adjacency entries of the customer rows (source node and
+// neighbour node), e in [0, gnnz).  The inter-route moves of N_theta(S)
+// evaluated are added to S.acc[kAccGranInter].
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ sols, const int32_t *__restrict__ gsrc,
+                                                   const int32_t *__restrict__ gadj, int gnnz, uint32_t op_mask,
+                                                   int32_t *__restrict__ dump_delta,
+                                                   uint8_t *__restrict__ dump_feas) {
+    __shared__ unsigned long long red[256 / 64];
+    __shared__ long long cnt_sh;
+    const SolDev &S = sols[0];
+    if (skip_solution(S, op_mask)) return;  // uniform for the grid
+    if (threadIdx.x == 0) cnt_sh = 0;
+    __syncthreads();
+    int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
+    uint32_t bid = 0xFFFFFFFFu;
+    long long cnt = 0;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < gnnz) {
+        const int u = gsrc[e], v = gadj[e];
+        const int x = gld(S.ref2slot + u - 1);
+        const int rx = gld(S.a4 + x).y;
+        if (v > 0) {
+            const int t = gld(S.ref2slot + v - 1);
+            if (gld(S.a4 + t).y > rx) cnt += gran_pair<TW, DUMP>(S, x, t, op_mask, dump_delta, dump_feas, bd, bid);
+        } else {
+            for (int r = 0; r < S.R; ++r) {
+                if (r == rx) continue;
+                const int d = gld(S.roff + r);  // start depot slot of route r
+                cnt += r > rx ? gran_pair<TW, DUMP>(S, x, d, op_mask, dump_delta, dump_feas, bd, bid)
+                              : gran_pair<TW, DUMP>(S, d, x, op_mask, dump_delta, dump_feas, bd, bid);
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long *)&cnt_sh, (unsigned long long)cnt);
+    block_argmin_commit(bd, bid, S.best_key, red);  // its barriers also order cnt_sh
+    if (threadIdx.x == 0 && cnt_sh) atomicAdd((unsigned long long *)(S.acc + kAccGranInter), (unsigned long long)cnt_sh);
+}
+
+// theta nearest neighbours of every node (distance, then node id; the node
+// itself excluded), one workgroup per node: the theta-th smallest key
+// (d << 14 | j) is found by bisection over the key range with block-wide
+// counts, then the theta keys at or below it are collected and ranked.
+// out: (n+1) x theta node ids, nearest first.  Requires theta <= n and
+// theta <= kKnnMax.
+constexpr int kKnnMax = 512;
+
+__global__ __launch_bounds__(256) void k_knn(const int32_t *__restrict__ D, int np1, int theta,
+                                             int32_t *__restrict__ out) {
+    __shared__ unsigned long long keys[kKnnMax];
+    __shared__ int cnt_w[4];
+    __shared__ int nsel;
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const int32_t *row = D + (size_t)i * np1;
+    auto key = [&](int j) { return ((unsigned long long)(uint32_t)gld(row + j) << 14) | (unsigned)j; };
+    unsigned long long lo = 0, hi = (1ull << 38) - 1;  // the answer is in [lo, hi]
+    while (lo < hi) {
+        const unsigned long long mid = lo + (hi - lo) / 2;
+        int c = 0;
+        for (int j = tid; j < np1; j += 256) c += (j != i && key(j) <= mid) ? 1 : 0;
+        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+        if ((tid & 63) == 0) cnt_w[tid >> 6] = c;
+        __syncthreads();
+        const int total = cnt_w[0] + cnt_w[1] + cnt_w[2] + cnt_w[3];
+        __syncthreads();
+        if (total >= theta)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    if (tid == 0) nsel = 0;
+    __syncthreads();
+    for (int j = tid; j < np1; j += 256)
+        if (j != i && key(j) <= lo) keys[atomicAdd(&nsel, 1)] = key(j);
+    __syncthreads();
+    for (int a = tid; a < theta; a += 256) {
+        int rank = 0;
+        for (int b = 0; b < theta; ++b) rank += keys[b] < keys[a] ? 1 : 0;
+        out[(size_t)i * theta + rank] = (int32_t)(keys[a] & 0x3FFF);
+    }
+}
+
 // ------------------------------------------------------ intra-route eval ---
 // One wavefront per route (the route-based extraction of Section 5.3.1,
 // eq. 2_opt, eq. ext_intra_relocate, eq. ext_intra_swap).  Lane i takes the
@@ -1862,10 +2018,18 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
             *S.best_key = ~0ull;
             if (mode == kModeLS) {
                 long long m = 0;
-                for (int op = 0; op < 5; ++op)
-                    if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
+                if (op_mask & kGranular) {  // inter-route moves as counted; intra-route ones complete
+                    m = S.acc[kAccGranInter];
+                    if (op_mask & 2) m += S.acc[kAccCnt0 + 3];  // same-route swaps: L(L-1)/2 per route, as 2-opt
+                    if (op_mask & 8) m += S.acc[kAccCnt0 + 3];
+                    if (op_mask & 16) m += S.acc[kAccCnt0 + 4];
+                } else {
+                    for (int op = 0; op < 5; ++op)
+                        if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
+                }
                 S.acc[kAccMoves] += m;
             }
+            S.acc[kAccGranInter] = 0;
             if (key == ~0ull) {
                 for (int q = 0; q < 8; ++q) S.rec[q] = 0;
                 S.rec[7] = S.state[kStVersion];
@@ -1906,12 +2070,21 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
 }
 
 // `steps` (nullable): a batch's step counter, advanced once per launch.
-// Empty slots of a slot batch (Q = 0) are skipped.
+// Empty slots of a slot batch (Q = 0) are skipped.  host_out (nullable,
+// single solution): pinned host memory that receives the move record and
+// state[0..3] straight from the kernel (12 ints), so that no copy follows.
 __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__restrict__ sols, int mode,
-                                                            uint32_t op_mask, int *__restrict__ steps) {
+                                                            uint32_t op_mask, int *__restrict__ steps,
+                                                            int32_t *__restrict__ host_out = nullptr) {
     if (steps && blockIdx.x == 0 && threadIdx.x == 0) *steps += 1;
     if (sols[blockIdx.x].Q == 0) return;
-    finalize_block(sols[blockIdx.x], mode, op_mask);
+    const SolDev &S = sols[blockIdx.x];
+    finalize_block(S, mode, op_mask);
+    if (host_out && threadIdx.x == 0) {  // thread 0 wrote the record and state itself
+        for (int q = 0; q < 8; ++q) host_out[q] = S.rec[q];
+        for (int q = 0; q < 4; ++q) host_out[8 + q] = S.state[q];
+        __threadfence_system();
+    }
 }
 
 

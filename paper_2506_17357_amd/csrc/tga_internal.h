@@ -70,6 +70,7 @@ enum {
     kAccCost = 0,       // total distance of the current solution
     kAccMoves = 1,      // sum of |N(S_t)| over evaluations run in LS mode
     kAccCnt0 = 2,       // |N(S)| per operator, 5 entries
+    kAccGranInter = 7,  // inter-route moves of the granular neighbourhood counted by the last evaluation
     kAccCount = 8
 };
 
@@ -92,7 +93,7 @@ constexpr int kRouteBlockMaxP = 40;
 constexpr int kRouteBlockNodes = 2;
 constexpr int kRouteBlockData = kRouteBlockNodes + kRouteBlockMaxP;
 constexpr int kRouteBlockWords = 1664;  // >= kRouteBlockData + kRouteBlockMaxP^2, a multiple of 64
-static_assert(kRouteBlockData + kRouteBlockMaxP * kRouteBlockMaxP <= kRouteBlockWords, "route block entry");  // accelerator dies (each with its own L2) the batched items are spread over
+static_assert(kRouteBlockData + kRouteBlockMaxP * kRouteBlockMaxP <= kRouteBlockWords, "route block entry");
 
 struct InterItem {  // row slots [s0, s1) of solution `sol`
     int32_t sol, s0, s1, pad;

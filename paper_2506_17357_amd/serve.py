@@ -90,6 +90,8 @@ class Server:
         self.ticks = 0
         self.rebuilds = 0       # plan updates (membership changes)
         self.rebuild_s = 0.0    # host time spent in them
+        self.upload_s = 0.0     # upload worker busy time (all workers)
+        self.uploads = 0
         self.config = None
 
     # ---------------------------------------------------------------- upload
@@ -99,10 +101,14 @@ class Server:
             if req is None:
                 return
             try:
+                tu = time.perf_counter()
                 with torch.cuda.stream(self.copy):
                     I = tga.Instance.from_workload(req.inst, device=self.device, stream=self.copy)
                     S = tga.Solution(I, req.sol.offsets, req.sol.customers, stream=self.copy)
-                ready.put((req, I, S, time.perf_counter() - t0, None))
+                now = time.perf_counter()
+                self.upload_s += now - tu
+                self.uploads += 1
+                ready.put((req, I, S, now - t0, None))
             except Exception as e:  # handed to the serving loop, which raises it
                 ready.put((req, None, None, 0.0, e))
 

@@ -21,6 +21,7 @@ TGA_OK, TGA_ENOMOVE = 0, 1
 TGA_EINVAL, TGA_ERANGE, TGA_ENOMEM, TGA_EDEVICE, TGA_ESTALE = -1, -2, -3, -4, -5
 OP_RELOCATE, OP_SWAP, OP_2OPTSTAR, OP_2OPT, OP_OROPT = 1, 2, 4, 8, 16
 OPS_ALL = 0x1F
+OP_GRANULAR = 1 << 5  # modifier: inter-route operators on the granular pairs only
 MAX_Q = 14654
 
 _lib = None
@@ -63,6 +64,7 @@ EXPORTS = [
     "tga_instance_dist_bytes", "tga_batch_get_config", "tga_batch_set_config", "tga_batch_autotune",
     "tga_eval_routes_static", "tga_batch_slots_workspace_bytes", "tga_batch_create_slots",
     "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
+    "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
 ]
 
 
@@ -85,6 +87,9 @@ def lib():
         "tga_eval_neighborhood": (i32, [P, u32, ctypes.POINTER(Move), P, P, P]),
         "tga_eval_routes_static": (i32, [P, i32, P, P, u32, ctypes.POINTER(Move), P]),
         "tga_batch_slots_workspace_bytes": (sz, [i32, i32, i32]),
+        "tga_granular_workspace_bytes": (sz, [i32, i32]),
+        "tga_instance_set_granular": (i32, [P, i32, P, sz, P]),
+        "tga_instance_granular_pairs": (i32, [P]),
         "tga_batch_create_slots": (i32, [i32, i32, i32, P, sz, P, pp]),
         "tga_batch_set_members": (i32, [P, P, P]),
         "tga_batch_tick": (i32, [P, u32, i32, P, P]),
@@ -164,6 +169,21 @@ class Instance:
                                    self.has_tw, _dev_ptr(self.ws), nbytes, _stream(stream),
                                    ctypes.byref(h)))
         self.h = h
+
+    def set_granular(self, theta: int, stream=None):
+        """Granular pairs of the theta nearest neighbours (edge-based
+        neighbourhood reduction); evaluations then accept OP_GRANULAR."""
+        L = lib()
+        nbytes = L.tga_granular_workspace_bytes(self.n, int(theta))
+        if nbytes == 0:
+            raise TGAError(TGA_ERANGE, "theta = %d out of range" % theta)
+        self.gws = torch.empty(nbytes, dtype=torch.uint8, device=self.dist.device)
+        _check(L.tga_instance_set_granular(self.h, int(theta), _dev_ptr(self.gws), nbytes, _stream(stream)))
+        self.theta = int(theta)
+
+    @property
+    def granular_pairs(self) -> int:
+        return int(lib().tga_instance_granular_pairs(self.h))
 
     @property
     def dist_bytes(self) -> int:

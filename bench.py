@@ -170,6 +170,85 @@ def roofline_entry(ev, kernel="k_eval_batch<3>"):
     }
 
 
+GRANULAR_THETA = {"c1": 20, "c2": 20, "c3": 100}  # the paper's tuned thresholds: CVRP 20, VRPTW 100
+
+
+def granular_config(tga, I, S, inst, sol, name):
+    """Granular mode (edge-based neighbourhood reduction, theta nearest
+    neighbours) on the same instance: local search to the local optimum of
+    the reduced neighbourhood and the best-move latency along it."""
+    import torch
+    theta = GRANULAR_THETA[name]
+    t0 = time.perf_counter()
+    I.set_granular(theta)
+    t_set = time.perf_counter() - t0
+    mask = tga.OPS_ALL | tga.OP_GRANULAR
+    S.reload(sol.offsets, sol.customers)
+    S.ls_run(5, mask)
+    S.reload(sol.offsets, sol.customers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, moves, cost = S.ls_run(100000 if name != "c1" else 100, mask)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    S.reload(sol.offsets, sol.customers)
+    lat = []
+    for _ in range(steps + 1):
+        t1 = time.perf_counter()
+        m = S.eval(mask)
+        lat.append((time.perf_counter() - t1) * 1e6)
+        if m is None or m.delta >= 0:
+            break
+        S.apply(m)
+    lat = np.array(lat)
+    S.reload(sol.offsets, sol.customers)
+    log("%s granular theta=%d: %d steps in %.4f s, %.2f GMoves/s, latency p50 %.1f us" % (
+        name, theta, steps, t, moves / t / 1e9, np.percentile(lat, 50)))
+    return {"theta": theta, "pair_entries": I.granular_pairs, "setup_s": round(t_set, 4), "steps": int(steps),
+            "moves_evaluated": int(moves), "final_cost": int(cost), "seconds": round(t, 5),
+            "gmoves_s": round(moves / t / 1e9, 3),
+            "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
+                                     "p99": round(float(np.percentile(lat, 99)), 1), "evals": int(lat.size)}}
+
+
+PENALTY = {"c1": (10, 0), "c2": (10, 0), "c3": (10, 10)}  # (w_load, w_tw); the paper fixes no weights
+
+
+def penalised_config(tga, I, inst, sol, name):
+    """Penalised mode (feasible and infeasible search: every move admissible,
+    scored by dD + w_L dL_V + w_T dT_V) from the same start: local search to
+    its local optimum (at most 2000 steps) and the best-move latency."""
+    import torch
+    w = PENALTY[name]
+    S = tga.Solution(I, sol.offsets, sol.customers)
+    S.set_penalty(*w)
+    S.ls_run(5)
+    S.reload(sol.offsets, sol.customers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, moves, cost = S.ls_run(100 if name == "c1" else 2000)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    lv, tv = S.violations()
+    S.reload(sol.offsets, sol.customers)
+    lat = []
+    for _ in range(min(steps, 200) + 1):
+        t1 = time.perf_counter()
+        m = S.eval()
+        lat.append((time.perf_counter() - t1) * 1e6)
+        if m is None or m.delta >= 0:
+            break
+        S.apply(m)
+    lat = np.array(lat)
+    log("%s penalised w=%s: %d steps in %.4f s, %.2f GMoves/s, latency p50 %.1f us, final distance %d, "
+        "load excess %d, time warp %d" % (name, w, steps, t, moves / t / 1e9, np.percentile(lat, 50), cost, lv, tv))
+    return {"weights": list(w), "steps": int(steps), "moves_evaluated": int(moves), "final_cost": int(cost),
+            "final_load_excess": lv, "final_time_warp": tv, "seconds": round(t, 5),
+            "gmoves_s": round(moves / t / 1e9, 3),
+            "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
+                                     "p99": round(float(np.percentile(lat, 99)), 1), "evals": int(lat.size)}}
+
+
 def plain_configs(log_lat=True):
     """The single-solution configurations on the plain form: moves per
     second of the device-resident loop to the local optimum (100 steps for
@@ -199,8 +278,12 @@ def plain_configs(log_lat=True):
                 break
             S.apply(m)
         lat = np.array(lat)
+        gran = granular_config(tga, I, S, inst, sol, name)
+        pen = penalised_config(tga, I, inst, sol, name)
         out[name] = {"workload": "%s: n = %d %s, seed %d, sweep start, R = %d" % (
                          name, inst.n, inst.kind, inst.seed, sol.R),
+                     "granular": gran,
+                     "penalised": pen,
                      "steps": int(steps), "moves_evaluated": int(moves), "final_cost": int(cost),
                      "seconds": round(t, 5), "gmoves_s": round(moves / t / 1e9, 3),
                      "best_move_latency_us": {"p50": round(float(np.percentile(lat, 50)), 1),
@@ -228,6 +311,13 @@ def oracle_configs(threads):
             t = time.perf_counter() - t0
             row["t%d" % T] = {"gmoves_s": round(r.moves / t / 1e9, 5), "seconds": round(t, 4)}
         row["moves"] = int(r.moves)
+        theta = GRANULAR_THETA[name]
+        mask = oracle.granular_mask(inst, theta)
+        t0 = time.perf_counter()
+        rg = oracle.eval_neighbourhood(inst, sol, threads=threads, mask=mask)
+        tg = time.perf_counter() - t0
+        row["granular"] = {"theta": theta, "moves": int(rg.moves), "t%d" % threads: {
+            "gmoves_s": round(rg.moves / tg / 1e9, 5), "seconds": round(tg, 4)}}
         out[name] = row
     return out
 
@@ -310,8 +400,9 @@ def served_run(args, count):
     cap_qps = len(reqs) / t_closed
     qps = 0.7 * cap_qps
     log("served closed loop: %.2f s, %.1f GMoves/s, capacity %.2f requests/s -> offered %.2f requests/s "
-        "(%d plan updates, %.3f s)" % (t_closed, moves0 / t_closed / 1e9, cap_qps, qps, srv.rebuilds,
-                                       srv.rebuild_s))
+        "(%d plan updates, %.3f s; uploads busy %.2f s; peak %d requests on the device; %d ticks)" % (
+            t_closed, moves0 / t_closed / 1e9, cap_qps, qps, srv.rebuilds, srv.rebuild_s, srv.upload_s,
+            srv.peak_active, srv.ticks))
     arrivals = W.request_stream(count, qps=qps, max_steps=args.served_steps)
     for q, a in zip(reqs, arrivals):
         q.arrival_s = a.arrival_s
@@ -338,6 +429,7 @@ def served_run(args, count):
                        "max": round(float(lat.max()), 2)},
         "makespan_s": round(t_open, 3),
         "steps_per_tick": srv.steps_per_tick,
+        "upload_busy_s": round(srv.upload_s, 3),
         "plan_updates": srv.rebuilds,
         "plan_update_s": round(srv.rebuild_s, 3),
         "peak_active_requests": srv.peak_active,

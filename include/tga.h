@@ -223,6 +223,27 @@ int tga_solution_begin(tga_solution_t sol, int32_t max_steps, void *stream);
 int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, int64_t *cost,
                      void *stream);
 
+/* Feasible and infeasible search (Alg. A2) with the scoring function of
+ * eq. scoring_tensor read as a weighted sum of the attribute deltas of
+ * Section 5.3.3: with w_load >= 0 the solution switches to penalised mode,
+ * where every move of N(S) is admissible and scores
+ *     dD + w_load * dL_V + w_tw * dT_V
+ * over the touched routes; L_V = a route's load above the capacity, T_V =
+ * its time warp (Section 4.3.3: arriving after l_i costs the lateness and
+ * service starts at l_i; leaving the depot at e_0, waiting when early).  The
+ * best move is the lexicographic minimum of (score, id); tga_ls_run applies
+ * it while the score is negative; tga_move_t.delta is the score and the
+ * dumps hold scores (dump_feas still has the hard capacity / window bits).
+ * w_load < 0 returns to hard feasibility.  w_tw must be 0 without windows.
+ * TGA_ERANGE when the weights could take a score outside +-2^29.  Penalised
+ * solutions are evaluated one at a time (no batch, no TGA_OP_GRANULAR).
+ * Synchronises `stream`. */
+int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int32_t w_tw, void *stream);
+
+/* Penalised mode: total load excess and total time warp of the current
+ * solution (nullable outputs).  Synchronises `stream`. */
+int tga_solution_violations(tga_solution_t sol, int64_t *load_excess, int64_t *time_warp, void *stream);
+
 /* Counters of a solution (all nullable): accepted moves since the last
  * begin / ls_run, converged flag, moves evaluated since then, current total
  * distance.  Synchronises `stream`. */

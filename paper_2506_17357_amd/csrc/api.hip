@@ -145,7 +145,7 @@ long long count_items(int Q, int rows) {
 }
 
 struct SolLayout {
-    size_t desc, a4, b4, t4, w4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, rblk, best_key, rec,
+    size_t desc, a4, b4, t4, w4, pf4, pb4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, rblk, best_key, rec,
         state, acc, items, intra, total;
     int max_items;
 };
@@ -164,6 +164,8 @@ SolLayout sol_layout(int n, int R) {
     L.b4 = take(16 * S);
     L.t4 = take(16 * S);
     L.w4 = take(16 * S);
+    L.pf4 = take(16 * S);
+    L.pb4 = take(16 * S);
     L.pdist = take(4 * S);
     L.ref2slot = take(4 * Q);
     L.roff = take(4 * (R + 1));
@@ -488,6 +490,8 @@ static int solution_init(tga_solution *S, tga_instance_t inst, int32_t R, const 
     h.b4 = (int4 *)(base + L.b4);
     h.t4 = (int4 *)(base + L.t4);
     h.w4 = (int4 *)(base + L.w4);
+    h.pf4 = (int4 *)(base + L.pf4);
+    h.pb4 = (int4 *)(base + L.pb4);
     h.pdist = (int32_t *)(base + L.pdist);
     h.ref2slot = (int32_t *)(base + L.ref2slot);
     h.roff = (int32_t *)(base + L.roff);
@@ -728,9 +732,38 @@ static void to_move(const int32_t *rec, tga_move_t *m) {
 // One evaluation of a solution whose workspace is set up: evaluation launch,
 // record-mode finalize, and one copy of the record and state[0..3] into
 // `host` (48 bytes; pinned or pageable).
-// Launch one evaluation of a solution (granular or full neighbourhood).
+// Penalised mode: inter-route pairs (16 x 16 tiles on and above the
+// diagonal) and intra-route walks (one thread per slot).
+static void launch_eval_pen(const tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
+    const bool tw = sol->h.has_tw, dump = dd != nullptr;
+    if (op_mask & 7) {
+        const int tiles = (sol->Q + 15) / 16, grid = tiles * (tiles + 1) / 2;
+        if (tw) {
+            if (dump) k_eval_pen_pairs<true, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
+            else k_eval_pen_pairs<true, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
+        } else {
+            if (dump) k_eval_pen_pairs<false, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
+            else k_eval_pen_pairs<false, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
+        }
+    }
+    if (op_mask & (2 | 8 | 16)) {
+        const int grid = (sol->Q + 255) / 256;
+        if (tw) {
+            if (dump) k_eval_pen_intra<true, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
+            else k_eval_pen_intra<true, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
+        } else {
+            if (dump) k_eval_pen_intra<false, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
+            else k_eval_pen_intra<false, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
+        }
+    }
+}
+
+// Launch one evaluation of a solution (penalised, granular or full
+// neighbourhood).
 static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
-    if (op_mask & TGA_OP_GRANULAR)
+    if (sol->h.pen)
+        launch_eval_pen(sol, op_mask, dd, df, st);
+    else if (op_mask & TGA_OP_GRANULAR)
         launch_eval_gran(sol->inst, sol->d, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
     else
         launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask, sol->lds,
@@ -743,6 +776,47 @@ static int check_mask(const tga_solution *sol, uint32_t op_mask) {
     if (op_mask & ~(TGA_OP_ALL | TGA_OP_GRANULAR)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if ((op_mask & TGA_OP_GRANULAR) && !sol->inst->gnnz)
         return fail(TGA_EINVAL, "TGA_OP_GRANULAR before tga_instance_set_granular");
+    if ((op_mask & TGA_OP_GRANULAR) && sol->h.pen)
+        return fail(TGA_EINVAL, "TGA_OP_GRANULAR with penalised scoring is not supported");
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int32_t w_tw, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    const tga_instance *I = sol->inst;
+    const bool pen = w_load >= 0;
+    if (pen) {
+        if (w_tw < 0) return fail(TGA_EINVAL, "w_tw must be >= 0 with w_load >= 0");
+        if (!I->has_tw && w_tw != 0) return fail(TGA_EINVAL, "w_tw must be 0 without time windows");
+        // every score and summary must stay exact in int32
+        const double np1 = (double)I->n + 1;
+        const double tb = I->has_tw ? np1 * ((double)I->maxS + I->maxD + I->maxE) + I->maxL : 0.0;
+        const double bound = 2.0 * w_tw * tb + 2.0 * w_load * (double)I->n * I->maxDem +
+                             4.0 * ((double)sol->Q + 1) * I->maxD;
+        if (tb >= (double)(1 << 28) || bound >= (double)(1 << 29))
+            return fail(TGA_ERANGE, "penalty weights (%d, %d) could take a score beyond 2^29", w_load, w_tw);
+    }
+    sol->h.pen = pen ? 1 : 0;
+    sol->h.wL = pen ? w_load : 0;
+    sol->h.wT = pen ? w_tw : 0;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(sol->d, &sol->h, sizeof(SolDev), hipMemcpyHostToDevice, st));
+    k_pen_init<<<1, kApplyThreads, 0, st>>>(sol->d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_violations(tga_solution_t sol, int64_t *load_excess, int64_t *time_warp, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (!sol->h.pen) return fail(TGA_EINVAL, "the solution is not in penalised mode");
+    hipStream_t st = (hipStream_t)stream;
+    long long v[2];
+    HIPCHK(hipMemcpyAsync(v, sol->h.acc + kAccLoadExcess, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (load_excess) *load_excess = v[0];
+    if (time_warp) *time_warp = v[1];
     return TGA_OK;
 }
 
@@ -1322,6 +1396,7 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     for (auto *s : v) {
         if (!s) return fail(TGA_EINVAL, "null solution in batch");
         if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
+        if (s->h.pen) return fail(TGA_EINVAL, "penalised solutions are evaluated one at a time");
     }
     for (size_t i = 0; i < v.size(); ++i)
         for (size_t j = i + 1; j < v.size(); ++j)
@@ -1383,6 +1458,7 @@ extern "C" int tga_batch_set_members(tga_batch_t B, const tga_solution_t *sols, 
         bool ours = false;
         for (auto *o : B->sols) ours = ours || o == s;
         if (s->in_batch && !ours) return fail(TGA_EINVAL, "solution in slot %d belongs to another batch", i);
+        if (s->h.pen) return fail(TGA_EINVAL, "penalised solutions are evaluated one at a time");
         for (int j = 0; j < i; ++j)
             if (sols[j] == s) return fail(TGA_EINVAL, "solution listed in slots %d and %d", j, i);
         sq += s->Q;

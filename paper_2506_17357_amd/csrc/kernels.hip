@@ -618,16 +618,121 @@ __device__ __forceinline__ void rebuild(const SolDev &S, int2 *nr, const int32_t
     rebuild_range(S, nr, roffn, 0, S.Q, true, sh);
 }
 
+// ------------------------------------------------------ penalised mode ---
+// Time-warp summaries (Section 4.3.3): a subsequence sigma carries its
+// duration T_D, earliest and latest start T_E / T_L and time warp T_V; a node
+// is {s, e, l, 0}; two subsequences joined by an edge of travel time t
+// concatenate as below (the garbled shift read as T_D(a) - T_V(a) + t).  A
+// route's time warp is the T_V of depot, customers, depot.
+
+struct Tw {
+    int d, e, l, v;
+};
+
+__device__ __forceinline__ Tw tw_of(int4 x) { return Tw{x.x, x.y, x.z, x.w}; }
+__device__ __forceinline__ int4 tw_pack(const Tw &x) { return make_int4(x.d, x.e, x.l, x.v); }
+__device__ __forceinline__ Tw tw_node(int e, int l, int s) { return Tw{s, e, l, 0}; }
+
+__device__ __forceinline__ Tw tw_cat(const Tw &a, int t, const Tw &b) {
+    const int dt = a.d - a.v + t;
+    const int dw = max(b.e - dt - a.l, 0);
+    const int dv = max(a.e + dt - b.l, 0);
+    return Tw{a.d + t + dw + b.d, max(a.e, b.e - dt) - dw, min(a.l, b.l - dt) + dv, a.v + dv + b.v};
+}
+
+__device__ __forceinline__ Tw tw_depot(const SolDev &S) {
+    const int4 q = gld(S.node4);
+    return tw_node(q.y, q.z, q.w);
+}
+
+// Prefix and suffix summaries of route r (one thread; TW instances only).
+__device__ __forceinline__ void pen_route(const SolDev &S, int r) {
+    const int off = gld(S.roff + r), L = gld(S.roff + r + 1) - off - 1;
+    const Tw dep = tw_depot(S);
+    Tw f = dep;
+    gst(S.pf4 + off, tw_pack(f));
+    for (int p = 1; p <= L; ++p) {
+        const int4 w = gld(S.w4 + off + p);
+        f = tw_cat(f, gld(S.a4 + off + p - 1).z, tw_node(w.x, w.y, w.z));
+        gst(S.pf4 + off + p, tw_pack(f));
+    }
+    Tw b = dep;
+    for (int p = L; p >= 1; --p) {
+        const int4 w = gld(S.w4 + off + p);
+        b = tw_cat(tw_node(w.x, w.y, w.z), gld(S.a4 + off + p).z, b);
+        gst(S.pb4 + off + p, tw_pack(b));
+    }
+    gst(S.pb4 + off, tw_pack(tw_cat(dep, gld(S.a4 + off).z, b)));
+}
+
+// Load excess of route r (from its load, kept in every slot's b4.z).
+__device__ __forceinline__ int route_excess(const SolDev &S, int r) {
+    return max(gld(S.b4 + gld(S.roff + r)).z - S.cap, 0);
+}
+
+// Time warp of route r (the suffix summary at its start depot).
+__device__ __forceinline__ int route_warp(const SolDev &S, int r) {
+    return S.has_tw ? gld(S.pb4 + gld(S.roff + r)).w : 0;
+}
+
+// Totals of load excess and time warp over the routes (every thread of the
+// block calls it; the summaries must be current).
+__device__ __forceinline__ void pen_totals(const SolDev &S, ApplyShared &sh) {
+    long long lv = 0, tv = 0;
+    for (int r = threadIdx.x; r < S.R; r += blockDim.x) {
+        lv += route_excess(S, r);
+        tv += route_warp(S, r);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        lv += __shfl_xor(lv, off);
+        tv += __shfl_xor(tv, off);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh.red[threadIdx.x >> 6][0] = lv;
+        sh.red[threadIdx.x >> 6][1] = tv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a += sh.red[w][0];
+            b += sh.red[w][1];
+        }
+        S.acc[kAccLoadExcess] = a;
+        S.acc[kAccTimeWarp] = b;
+    }
+    __syncthreads();
+}
+
+// Summaries of every route and the totals (one block).
+__device__ __forceinline__ void pen_all(const SolDev &S, ApplyShared &sh) {
+    if (S.has_tw)
+        for (int r = threadIdx.x; r < S.R; r += blockDim.x) pen_route(S, r);
+    __threadfence_block();
+    __syncthreads();
+    pen_totals(S, sh);
+}
+
 // Build the attributes of a freshly uploaded layout (nr_alt, roff_alt).
 __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restrict__ sols) {
     __shared__ ApplyShared sh;
     const SolDev &S = sols[blockIdx.x];
     rebuild(S, S.nr_alt, S.roff_alt, sh);
+    if (S.pen) pen_all(S, sh);
     if (threadIdx.x == 0) {
         *S.best_key = ~0ull;
         S.state[kStDone] = 0;
         S.state[kStStatus] = 0;
     }
+}
+
+// Switch penalised mode on for a solution whose descriptor now says so:
+// summaries of every route and the totals.
+__global__ __launch_bounds__(kApplyThreads) void k_pen_init(const SolDev *__restrict__ sols) {
+    __shared__ ApplyShared sh;
+    const SolDev &S = sols[blockIdx.x];
+    if (S.pen) pen_all(S, sh);
 }
 
 // ------------------------------------------------------ inter-route eval ---
@@ -1228,6 +1333,219 @@ __global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ so
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long *)&cnt_sh, (unsigned long long)cnt);
     block_argmin_commit(bd, bid, S.best_key, red);  // its barriers also order cnt_sh
     if (threadIdx.x == 0 && cnt_sh) atomicAdd((unsigned long long *)(S.acc + kAccGranInter), (unsigned long long)cnt_sh);
+}
+
+// ------------------------------------------- penalised-mode evaluation ---
+// Feasible and infeasible search (Alg. A2): every move of N(S) is admissible
+// and scores dD + w_L dL_V + w_T dT_V over the touched routes (Section 5.3.3
+// attribute deltas, eq. scoring_tensor).  New routes are concatenations of
+// the stored prefix / suffix summaries with the moved nodes (Section 4.3.3);
+// loads come from the prefix loads.  One thread per pair of slots (inter-
+// route) or per first position of an intra-route walk: the attributes are
+// gathered, nothing is staged (this mode serves the search, not the
+// headline rate).  The dumps hold the score and the hard capacity / window
+// bits of the touched routes (load excess and time warp both zero).
+
+// Suffix summary strictly after slot x (the end depot when x is last).
+__device__ __forceinline__ Tw tw_after(const SolDev &S, int x, const Tw &dep) {
+    return nodeof(gld(S.a4 + x + 1).x) == 0 ? dep : tw_of(gld(S.pb4 + x + 1));
+}
+
+__device__ __forceinline__ Tw tw_node_at(const SolDev &S, int x) {
+    const int4 w = gld(S.w4 + x);
+    return tw_node(w.x, w.y, w.z);
+}
+
+__device__ __forceinline__ void pen_record(int score, int feas, uint32_t id, bool dump, int32_t *dd,
+                                           uint8_t *df, int &bd, uint32_t &bid) {
+    if (dump) {
+        dd[id] = score;
+        df[id] = (uint8_t)feas;
+    }
+    consider(score, id, bd, bid);
+}
+
+// The four inter-route moves of slots x, t (route(x) < route(t)).
+template <bool TW, bool DUMP>
+__device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t op_mask, int32_t *dd, uint8_t *df,
+                                         int &bd, uint32_t &bid) {
+    const int np1 = S.np1, n = S.n, cap = S.cap;
+    const int32_t *D = S.D;
+    const uint32_t uQ = (uint32_t)S.Q;
+    const int4 ax = gld(S.a4 + x), at = gld(S.a4 + t), bx = gld(S.b4 + x), bt = gld(S.b4 + t);
+    const bool cx = flagsof(ax.x) & kFlagCustomer, ct = flagsof(at.x) & kFlagCustomer;
+    const int nx = nodeof(ax.x), nt = nodeof(at.x);
+    const int npx = nodeof(gld(S.a4 + max(x - 1, 0)).x), nsx = nodeof(gld(S.a4 + x + 1).x);
+    const int npt = nodeof(gld(S.a4 + t - 1).x), nst = nodeof(gld(S.a4 + t + 1).x);
+    auto d = [&](int i, int j) { return gld(D + (size_t)i * np1 + j); };
+    const int refX = cx ? nx - 1 : n + ax.y, refT = ct ? nt - 1 : n + at.y;
+    const int Lx = bx.z, Lt = bt.z, dx = bx.x, dtt = bt.x;
+    const int lvOld = max(Lx - cap, 0) + max(Lt - cap, 0);
+    int tvOld = 0;
+    Tw dep{}, Fx{}, Ft{}, Fpx{}, Fpt{}, Bax{}, Bat{}, Nx{}, Nt{};
+    if (TW) {
+        dep = tw_depot(S);
+        Fx = tw_of(gld(S.pf4 + x));
+        Ft = tw_of(gld(S.pf4 + t));
+        Fpx = tw_of(gld(S.pf4 + max(x - 1, 0)));
+        Fpt = tw_of(gld(S.pf4 + t - 1));
+        Bax = tw_after(S, x, dep);
+        Bat = tw_after(S, t, dep);
+        Nx = tw_node_at(S, x);
+        Nt = tw_node_at(S, t);
+        tvOld = route_warp(S, ax.y) + route_warp(S, at.y);
+    }
+    const int exx = d(nx, nsx), ett = d(nt, nst);  // edges leaving x and t
+    auto score = [&](int dD, int lx, int lt, int tvx, int tvt, uint32_t id) {
+        const int lv = max(lx - cap, 0) + max(lt - cap, 0);
+        const int sc = dD + S.wL * (lv - lvOld) + S.wT * (tvx + tvt - tvOld);
+        const int feas = (lv == 0 ? 1 : 0) | (tvx + tvt == 0 ? 2 : 0);
+        pen_record(sc, feas, id, DUMP, dd, df, bd, bid);
+    };
+    if ((op_mask & 1) && cx) {  // RELOCATE x -> right after t
+        const int dD = d(nt, nx) + d(nx, nst) - ett + d(npx, nsx) - d(npx, nx) - exx;
+        const int tvx = TW ? tw_cat(Fpx, d(npx, nsx), Bax).v : 0;
+        const int tvt = TW ? tw_cat(tw_cat(Ft, d(nt, nx), Nx), d(nx, nst), Bat).v : 0;
+        score(dD, Lx - dx, Lt + dx, tvx, tvt, (uQ + (uint32_t)refX) * uQ + (uint32_t)refT);
+    }
+    if ((op_mask & 1) && ct) {  // RELOCATE t -> right after x
+        const int dD = d(nx, nt) + d(nt, nsx) - exx + d(npt, nst) - d(npt, nt) - ett;
+        const int tvx = TW ? tw_cat(tw_cat(Fx, d(nx, nt), Nt), d(nt, nsx), Bax).v : 0;
+        const int tvt = TW ? tw_cat(Fpt, d(npt, nst), Bat).v : 0;
+        score(dD, Lx + dtt, Lt - dtt, tvx, tvt, (uQ + (uint32_t)refT) * uQ + (uint32_t)refX);
+    }
+    const uint32_t lo = min((uint32_t)refX, (uint32_t)refT), hi = max((uint32_t)refX, (uint32_t)refT);
+    if ((op_mask & 2) && cx && ct) {  // SWAP x <-> t
+        const int dD = d(npx, nt) + d(nt, nsx) + d(npt, nx) + d(nx, nst) - d(npx, nx) - exx - d(npt, nt) - ett;
+        const int tvx = TW ? tw_cat(tw_cat(Fpx, d(npx, nt), Nt), d(nt, nsx), Bax).v : 0;
+        const int tvt = TW ? tw_cat(tw_cat(Fpt, d(npt, nx), Nx), d(nx, nst), Bat).v : 0;
+        score(dD, Lx - dx + dtt, Lt - dtt + dx, tvx, tvt, (5u * uQ + lo) * uQ + hi);
+    }
+    if (op_mask & 4) {  // 2OPT*: heads keep their routes, tails exchanged
+        const int dD = d(nx, nst) + d(nt, nsx) - exx - ett;
+        const int tvx = TW ? tw_cat(Fx, d(nx, nst), Bat).v : 0;
+        const int tvt = TW ? tw_cat(Ft, d(nt, nsx), Bax).v : 0;
+        score(dD, bx.y + (Lt - bt.y), bt.y + (Lx - bx.y), tvx, tvt, (8u * uQ + lo) * uQ + hi);
+    }
+}
+
+// Inter-route pairs: 16 x 16 tiles of (row slot, column slot) on and above
+// the diagonal, blockIdx.x enumerating the tiles row by row.
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict__ sols, int tiles, uint32_t op_mask,
+                                                        int32_t *__restrict__ dd, uint8_t *__restrict__ df) {
+    __shared__ unsigned long long red[4];
+    const SolDev &S = sols[0];
+    if (skip_solution(S, op_mask)) return;
+    int bi = 0, rem = blockIdx.x;  // tile row bi holds tiles - bi tiles
+    while (rem >= tiles - bi) {
+        rem -= tiles - bi;
+        ++bi;
+    }
+    const int bj = bi + rem;
+    const int x = bi * 16 + (threadIdx.x >> 4), t = bj * 16 + (threadIdx.x & 15);
+    int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
+    uint32_t bid = 0xFFFFFFFFu;
+    if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y)
+        pen_pair<TW, DUMP>(S, x, t, op_mask, dd, df, bd, bid);
+    block_argmin_commit(bd, bid, S.best_key, red);
+}
+
+// Intra-route moves whose first position is the customer at slot s: the
+// 2-opt / same-route swap walk and the or-opt walks, the middle summaries
+// growing one node per step.  One thread per slot.
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict__ sols, uint32_t op_mask,
+                                                        int32_t *__restrict__ dd, uint8_t *__restrict__ df) {
+    __shared__ unsigned long long red[4];
+    const SolDev &S = sols[0];
+    if (skip_solution(S, op_mask)) return;
+    int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
+    uint32_t bid = 0xFFFFFFFFu;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S.Q && (flagsof(gld(S.a4 + s).x) & kFlagCustomer)) {
+        const int r = gld(S.a4 + s).y, off = gld(S.roff + r), L = gld(S.roff + r + 1) - off - 1, i = s - off;
+        const int n = S.n, np1 = S.np1;
+        const uint32_t uQ = (uint32_t)S.Q;
+        const int32_t *D = S.D;
+        const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
+        auto node = [&](int p) { return (p == 0 || p > L) ? 0 : nodeof(gld(S.a4 + off + p).x); };
+        auto d = [&](int a, int b) { return gld(D + (size_t)a * np1 + b); };
+        auto ref = [&](int p) { return p == 0 ? (uint32_t)(n + r) : (uint32_t)(node(p) - 1); };
+        auto edge = [&](int p) { return gld(S.a4 + off + p).z; };  // position p to p + 1
+        const Tw dep = TW ? tw_depot(S) : Tw{};
+        auto Npos = [&](int p) { return TW ? tw_node_at(S, off + p) : Tw{}; };
+        auto Fpos = [&](int p) { return TW ? tw_of(gld(S.pf4 + off + p)) : Tw{}; };
+        auto Bafter = [&](int p) { return TW ? (p >= L ? dep : tw_of(gld(S.pb4 + off + p + 1))) : Tw{}; };
+        const int lvR = max(gld(S.b4 + off).z - S.cap, 0);
+        const int tvR = TW ? gld(S.pb4 + off).w : 0;
+        auto score = [&](int dD, int tvNew, uint32_t id) {
+            const int sc = dD + S.wT * (tvNew - tvR);
+            const int feas = (lvR == 0 ? 1 : 0) | (tvNew == 0 ? 2 : 0);
+            pen_record(sc, feas, id, DUMP, dd, df, bd, bid);
+        };
+        const int cI = node(i), cP = node(i - 1);
+        const int eP = edge(i - 1), eI = edge(i);
+        const Tw Fi1 = Fpos(i - 1);
+        // ---- 2OPT(i, j) and SWAP(i, j), j > i
+        if (op2o || opSwap) {
+            Tw rev = Npos(i), mid{};
+            for (int j = i + 1; j <= L; ++j) {
+                const int cJ = node(j), cJ1 = node(j + 1), ej = edge(j), ejm = edge(j - 1);
+                if (TW) rev = tw_cat(Npos(j), ejm, rev);
+                const int d1 = d(cP, cJ), d2 = d(cI, cJ1);
+                const uint32_t lo = min(ref(i), ref(j)), hi = max(ref(i), ref(j));
+                const Tw Ba = Bafter(j);
+                if (op2o) {
+                    const int tv = TW ? tw_cat(tw_cat(Fi1, d1, rev), d2, Ba).v : 0;
+                    score(d1 + d2 - eP - ej, tv, (12u * uQ + lo) * uQ + hi);
+                }
+                if (opSwap) {
+                    int dS, tv = 0;
+                    if (j == i + 1) {
+                        dS = d1 + d2 - eP - ej;
+                        if (TW) tv = tw_cat(tw_cat(tw_cat(Fi1, d1, Npos(j)), ejm, Npos(i)), d2, Ba).v;
+                    } else {
+                        const int dA = d(cJ, node(i + 1)), dB = d(node(j - 1), cI);
+                        dS = d1 + dA + dB + d2 - eP - eI - ejm - ej;
+                        if (TW)
+                            tv = tw_cat(tw_cat(tw_cat(tw_cat(Fi1, d1, Npos(j)), dA, mid), dB, Npos(i)), d2, Ba).v;
+                    }
+                    score(dS, tv, (5u * uQ + lo) * uQ + hi);
+                }
+                if (TW) mid = (j == i + 1) ? Npos(j) : tw_cat(mid, ejm, Npos(j));  // c_{i+1} .. c_j
+            }
+        }
+        // ---- OR-OPT: segment c_i .. c_{i+k-1} moved right after c_j
+        if (opOr) {
+            for (int k = 1; k <= 3 && i + k - 1 <= L; ++k) {
+                const int g = i + k - 1, w = i + k, cG = node(g), cW = node(w);
+                const int base = d(cP, cW) - eP - edge(g);
+                Tw sig{};
+                if (TW) {
+                    sig = Npos(i);
+                    for (int q = 1; q < k; ++q) sig = tw_cat(sig, edge(i + q - 1), Npos(i + q));
+                }
+                Tw mid{};
+                for (int j = w; j <= L; ++j) {  // forward: middle c_{i+k} .. c_j
+                    const int cJ = node(j), cJ1 = node(j + 1);
+                    if (TW) mid = (j == w) ? Npos(j) : tw_cat(mid, edge(j - 1), Npos(j));
+                    const int dVF = d(cJ, cI), dGV = d(cG, cJ1);
+                    const int tv = TW ? tw_cat(tw_cat(tw_cat(Fi1, d(cP, cW), mid), dVF, sig), dGV, Bafter(j)).v : 0;
+                    score(base + dVF + dGV - edge(j), tv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
+                }
+                for (int j = i - 2; j >= 0; --j) {  // backward: middle c_{j+1} .. c_{i-1}
+                    const int cJ = node(j), cJ1 = node(j + 1);
+                    if (TW) mid = (j == i - 2) ? Npos(i - 1) : tw_cat(Npos(j + 1), edge(j + 1), mid);
+                    const int dVF = d(cJ, cI), dGV = d(cG, cJ1);
+                    const int tv =
+                        TW ? tw_cat(tw_cat(tw_cat(Fpos(j), dVF, sig), dGV, mid), d(cP, cW), Bafter(g)).v : 0;
+                    score(base + dVF + dGV - edge(j), tv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
+                }
+            }
+        }
+    }
+    block_argmin_commit(bd, bid, S.best_key, red);
 }
 
 // theta nearest neighbours of every node (distance, then node id; the node
@@ -1955,7 +2273,7 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                 const int rk = d < 0 ? k : rounds - 1 - k;
                 const int src = lo + rk * T + tid;
                 const bool on = src < hi;
-                int4 a = make_int4(0, 0, 0, 0), b = a, t = a, w = a;
+                int4 a = make_int4(0, 0, 0, 0), b = a, t = a, w = a, pf = a, pb = a;
                 int pd = 0;
                 if (on) {
                     a = S.a4[src];
@@ -1963,6 +2281,10 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     t = S.t4[src];
                     w = S.w4[src];
                     pd = S.pdist[src];
+                    if (S.pen) {
+                        pf = S.pf4[src];
+                        pb = S.pb4[src];
+                    }
                 }
                 __syncthreads();
                 if (on) {
@@ -1972,6 +2294,10 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     S.t4[dst] = t;
                     S.w4[dst] = w;
                     S.pdist[dst] = pd;
+                    if (S.pen) {
+                        S.pf4[dst] = pf;
+                        S.pb4[dst] = pb;
+                    }
                     const int node = nodeof(a.x);
                     S.ref2slot[(flagsof(a.x) & kFlagCustomer) ? node - 1 : S.n + a.y] = dst;
                 }
@@ -1995,6 +2321,15 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
     } else {
         rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
         if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
+    }
+    if (S.pen) {  // summaries of the touched routes, then the totals
+        __threadfence_block();
+        __syncthreads();
+        if (S.has_tw && threadIdx.x == 0) pen_route(S, m.ra);
+        if (S.has_tw && threadIdx.x == 64 && inter) pen_route(S, m.rb);
+        __threadfence_block();
+        __syncthreads();
+        pen_totals(S, sh);
     }
 }
 

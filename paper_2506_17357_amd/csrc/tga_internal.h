@@ -49,6 +49,13 @@ struct SolDev {
     int32_t *roff_alt;// R+1
     // per route: the route's distance sub-block as last staged (see kRouteBlock*)
     int32_t *rblk;
+    // penalised mode (feasible and infeasible search): per slot the
+    // time-warp summary {T_D, T_E, T_L, T_V} of the route prefix ending at
+    // the slot (start depot included) and of the suffix starting there (end
+    // depot included); weights of load excess and time warp
+    int4 *pf4;
+    int4 *pb4;
+    int32_t pen, wL, wT, pad1;
     // per-solution state
     unsigned long long *best_key;  // running minimum of (delta, id) keys
     int32_t *rec;     // 8 ints: the tga_move_t of the last finalize
@@ -71,7 +78,9 @@ enum {
     kAccMoves = 1,      // sum of |N(S_t)| over evaluations run in LS mode
     kAccCnt0 = 2,       // |N(S)| per operator, 5 entries
     kAccGranInter = 7,  // inter-route moves of the granular neighbourhood counted by the last evaluation
-    kAccCount = 8
+    kAccLoadExcess = 8, // penalised mode: total load above capacity
+    kAccTimeWarp = 9,   // penalised mode: total time warp
+    kAccCount = 10
 };
 
 // Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the

@@ -65,6 +65,7 @@ EXPORTS = [
     "tga_eval_routes_static", "tga_batch_slots_workspace_bytes", "tga_batch_create_slots",
     "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
     "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
+    "tga_solution_set_penalty", "tga_solution_violations",
 ]
 
 
@@ -88,6 +89,8 @@ def lib():
         "tga_eval_routes_static": (i32, [P, i32, P, P, u32, ctypes.POINTER(Move), P]),
         "tga_batch_slots_workspace_bytes": (sz, [i32, i32, i32]),
         "tga_granular_workspace_bytes": (sz, [i32, i32]),
+        "tga_solution_set_penalty": (i32, [P, i32, i32, P]),
+        "tga_solution_violations": (i32, [P, P, P, P]),
         "tga_instance_set_granular": (i32, [P, i32, P, sz, P]),
         "tga_instance_granular_pairs": (i32, [P]),
         "tga_batch_create_slots": (i32, [i32, i32, i32, P, sz, P, pp]),
@@ -224,6 +227,18 @@ class Solution:
         off = np.ascontiguousarray(offsets, dtype=np.int32)
         cust = np.ascontiguousarray(customers, dtype=np.int32)
         _check(lib().tga_solution_reload(self.h, _np_ptr(off), _np_ptr(cust), _stream(stream)))
+
+    def set_penalty(self, w_load: int, w_tw: int = 0, stream=None):
+        """Penalised scoring dD + w_load dL_V + w_tw dT_V (every move
+        admissible); w_load < 0 returns to hard feasibility."""
+        _check(lib().tga_solution_set_penalty(self.h, int(w_load), int(w_tw), _stream(stream)))
+
+    def violations(self, stream=None):
+        """(total load excess, total time warp) in penalised mode."""
+        lv = ctypes.c_int64()
+        tv = ctypes.c_int64()
+        _check(lib().tga_solution_violations(self.h, ctypes.byref(lv), ctypes.byref(tv), _stream(stream)))
+        return int(lv.value), int(tv.value)
 
     def begin(self, max_steps: int, stream=None):
         """Clear counters and set the step cap before joining a running batch."""

@@ -61,13 +61,23 @@ def _load():
         lib.oracle_ls_gran.restype = ctypes.c_int
         lib.oracle_ls_gran.argtypes = [i32, P, P, i64, i32, i32, P, P, u32, P, i32, i32, P, P, P]
         lib.oracle_violations.restype = None
-        lib.oracle_violations.argtypes = [i32, P, P, i64, i32, i32, P, P, P, P]
+        lib.oracle_violations.argtypes = [i32, P, P, P, i64, i32, i32, P, P, P, P]
+        lib.oracle_eval_ex.restype = ctypes.c_int
+        lib.oracle_eval_ex.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, P, i32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_ls_ex.restype = ctypes.c_int
+        lib.oracle_ls_ex.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, P, i32, i64, i64, i32, i32, P, P, P]
         _lib = lib
     return _lib
 
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pickups(inst):
+    """Pickup amounts per node (VRPSPDTW), or None."""
+    p = getattr(inst, "pickup", None)
+    return None if p is None else np.ascontiguousarray(p, dtype=np.int32)
 
 
 def _inst_args(inst):
@@ -116,7 +126,16 @@ def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
     mv = np.zeros(1, np.int64)
     if theta is not None and mask is None:
         mask = granular_mask(inst, theta)
-    if mask is not None:
+    pick = _pickups(inst)
+    if pick is not None:
+        pen = penalty if penalty is not None else (0, 0)
+        found = lib.oracle_eval_ex(inst.n, _p(D), _p(nd), _p(pick), inst.capacity, inst.has_tw,
+                                   off.shape[0] - 1, _p(off), _p(cust), op_mask,
+                                   _p(mask) if mask is not None else None, int(penalty is not None),
+                                   int(pen[0]), int(pen[1]), threads,
+                                   _p(dd) if dump else None, _p(df) if dump else None,
+                                   _p(bd), _p(bid), _p(mv))
+    elif mask is not None:
         assert penalty is None
         found = lib.oracle_eval_gran(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
                                      off.shape[0] - 1, _p(off), _p(cust), op_mask, _p(mask), threads,
@@ -169,7 +188,8 @@ def apply_move(inst, sol, move_id: int):
 
 
 def cost(inst, sol):
-    """(total distance, #capacity-violating routes, #window-violating routes)."""
+    """(total distance, #capacity-violating routes, #window-violating routes);
+    the counts ignore pickups (use violations() for VRPSPDTW)."""
     lib = _load()
     D, nd = _inst_args(inst)
     off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
@@ -201,8 +221,9 @@ def violations(inst, sol):
     cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
     lv = np.zeros(1, np.int64)
     tv = np.zeros(1, np.int64)
-    lib.oracle_violations(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw, off.shape[0] - 1,
-                          _p(off), _p(cust), _p(lv), _p(tv))
+    pick = _pickups(inst)
+    lib.oracle_violations(inst.n, _p(D), _p(nd), _p(pick) if pick is not None else None, inst.capacity,
+                          inst.has_tw, off.shape[0] - 1, _p(off), _p(cust), _p(lv), _p(tv))
     return int(lv[0]), int(tv[0])
 
 
@@ -220,7 +241,14 @@ def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
     mv = np.zeros(1, np.int64)
     if theta is not None and mask is None:
         mask = granular_mask(inst, theta)
-    if mask is not None:
+    pick = _pickups(inst)
+    if pick is not None:
+        pen = penalty if penalty is not None else (0, 0)
+        steps = lib.oracle_ls_ex(inst.n, _p(D), _p(nd), _p(pick), inst.capacity, inst.has_tw,
+                                 off.shape[0] - 1, _p(off), _p(cust), op_mask,
+                                 _p(mask) if mask is not None else None, int(penalty is not None),
+                                 int(pen[0]), int(pen[1]), max_steps, threads, _p(ids), _p(deltas), _p(mv))
+    elif mask is not None:
         assert penalty is None
         steps = lib.oracle_ls_gran(inst.n, _p(D), _p(nd), inst.capacity, inst.has_tw,
                                    off.shape[0] - 1, _p(off), _p(cust), op_mask, _p(mask), max_steps,

@@ -15,8 +15,12 @@
  *         distance  = sum of c_ij over consecutive nodes, both depot edges
  *                     included (the objective with mu1 = 0, mu2 = 1; Section 2,
  *                     eq. objective),
- *         load      = sum of delivery demands, feasible iff <= capacity
- *                     (Section 2; Section 4.3, load concatenation with p = 0),
+ *         load      = the largest load carried: the sum of delivery demands
+ *                     (the vehicle leaves with them and only unloads); with
+ *                     pickups (VRPSPDTW) the largest load over the depot
+ *                     departure and every customer after unloading its
+ *                     delivery and loading its pickup; feasible iff <= capacity
+ *                     (Section 2; Section 4.3.2 load attributes),
  *         windows   = forward simulation: leave the depot at e_0, wait when
  *                     early, infeasible when arriving after l_i, back at the
  *                     depot by l_0 (Section 2),
@@ -81,6 +85,7 @@ typedef struct {
     const int32_t *node4; /* (n+1) x {demand, e, l, s} */
     int64_t cap;
     int has_tw;
+    const int32_t *pick;  /* (n+1) pickup amounts (VRPSPDTW), or NULL */
 } Inst;
 
 typedef struct {
@@ -111,10 +116,21 @@ static int64_t route_distance(const Inst *I, const int32_t *c, int L) {
     return d + dist(I, prev, 0);
 }
 
+/* The largest load the vehicle carries on the route.  Without pickups the
+ * vehicle leaves the depot with all deliveries and only unloads, so this is
+ * the sum of the demands.  With pickups (VRPSPDTW, Section 2) it leaves with
+ * all deliveries, and at each customer unloads its delivery and loads its
+ * pickup; every point of the route counts (Section 4.3.2). */
 static int64_t route_load(const Inst *I, const int32_t *c, int L) {
     int64_t q = 0;
     for (int i = 0; i < L; i++) q += I->node4[4 * c[i] + 0];
-    return q;
+    if (!I->pick) return q;
+    int64_t peak = q;
+    for (int i = 0; i < L; i++) {
+        q += I->pick[c[i]] - I->node4[4 * c[i] + 0];
+        if (q > peak) peak = q;
+    }
+    return peak;
 }
 
 /* Hard time windows, simulated forward (Section 2). */
@@ -482,12 +498,12 @@ static int resolve_threads(int nthreads) {
  * exists (written to *best_*), 0 otherwise.  Optional dumps are indexed by
  * move id and must hold 20 * Q * Q entries; entries that are not moves are
  * left untouched.  *moves receives |N(S)| for the enabled operators. */
-static int eval_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-                     int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                     int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                      const uint8_t *gran, int pen, int64_t w_load, int64_t w_tw,
                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
                      int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
-    Inst I = {n, D, node4, cap, has_tw};
+    Inst I = {n, D, node4, cap, has_tw, pick};
     Sol S = {R, off, cust};
     Index X;
     index_build(&I, &S, &X);
@@ -545,8 +561,8 @@ int oracle_eval(int n, const int32_t *D, const int32_t *node4, int64_t cap, int 
                 int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                 int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
                 int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
-    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, nthreads, dump_delta,
-                     dump_feas, best_delta, best_id, moves);
+    return eval_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, nthreads,
+                     dump_delta, dump_feas, best_delta, best_id, moves);
 }
 
 /* Penalised mode: as oracle_eval, but every move is admissible, the dumped
@@ -557,7 +573,7 @@ int oracle_eval_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, 
                     int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                     int64_t w_load, int64_t w_tw, int nthreads, int32_t *dump_score,
                     uint8_t *dump_feas, int64_t *best_score, uint32_t *best_id, int64_t *moves) {
-    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, nthreads,
+    return eval_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, nthreads,
                      dump_score, dump_feas, best_score, best_id, moves);
 }
 
@@ -565,7 +581,7 @@ int oracle_eval_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, 
  * id does not name a move of N(S). */
 int oracle_apply(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
                  int R, int32_t *off, int32_t *cust, uint32_t id) {
-    Inst I = {n, D, node4, cap, has_tw};
+    Inst I = {n, D, node4, cap, has_tw, NULL};
     Sol S = {R, off, cust};
     Index X;
     index_build(&I, &S, &X);
@@ -630,7 +646,7 @@ int oracle_apply(int n, const int32_t *D, const int32_t *node4, int64_t cap, int
  * routes that violate capacity (*cap_bad) or windows (*tw_bad). */
 int64_t oracle_cost(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
                     int R, const int32_t *off, const int32_t *cust, int *cap_bad, int *tw_bad) {
-    Inst I = {n, D, node4, cap, has_tw};
+    Inst I = {n, D, node4, cap, has_tw, NULL};
     int64_t c = 0;
     int cb = 0, tb = 0;
     for (int r = 0; r < R; r++) {
@@ -652,7 +668,7 @@ int64_t oracle_check_full(int n, const int32_t *D, const int32_t *node4, int64_t
                           int has_tw, int R, const int32_t *off, const int32_t *cust,
                           const int32_t *dump_delta, const uint8_t *dump_feas,
                           uint32_t op_mask, int64_t sample_every) {
-    Inst I = {n, D, node4, cap, has_tw};
+    Inst I = {n, D, node4, cap, has_tw, NULL};
     Sol S = {R, off, cust};
     Index X;
     index_build(&I, &S, &X);
@@ -692,8 +708,8 @@ typedef struct {
  * move while its delta is negative, stop at a local optimum or after
  * max_steps.  Writes the accepted moves to `traj` (max_steps entries) and
  * updates (off, cust) in place.  Returns the number of accepted moves. */
-static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *gran,
+static int ls_core(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                   int has_tw, int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *gran,
                    int pen, int64_t w_load,
                    int64_t w_tw, int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_delta,
                    int64_t *moves_total) {
@@ -702,7 +718,7 @@ static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, i
     while (steps < max_steps) {
         int64_t bd = 0, mv = 0;
         uint32_t bid = 0;
-        int found = eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, gran, pen, w_load, w_tw,
+        int found = eval_core(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, gran, pen, w_load, w_tw,
                               nthreads, NULL, NULL, &bd, &bid, &mv);
         mv_sum += mv;
         if (!found || bd >= 0) break;
@@ -718,7 +734,7 @@ static int ls_core(int n, const int32_t *D, const int32_t *node4, int64_t cap, i
 int oracle_ls(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
               int R, int32_t *off, int32_t *cust, uint32_t op_mask, int max_steps,
               int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
-    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, max_steps, nthreads,
+    return ls_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, NULL, 0, 0, 0, max_steps, nthreads,
                    traj_id, traj_delta, moves_total);
 }
 
@@ -728,8 +744,8 @@ int oracle_ls_pen(int n, const int32_t *D, const int32_t *node4, int64_t cap, in
                   int R, int32_t *off, int32_t *cust, uint32_t op_mask, int64_t w_load, int64_t w_tw,
                   int max_steps, int nthreads, uint32_t *traj_id, int32_t *traj_score,
                   int64_t *moves_total) {
-    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, max_steps, nthreads,
-                   traj_id, traj_score, moves_total);
+    return ls_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, NULL, 1, w_load, w_tw, max_steps,
+                   nthreads, traj_id, traj_score, moves_total);
 }
 
 /* The granular pair mask: mask[i * (n+1) + j] = 1 when j is among the
@@ -764,23 +780,41 @@ int oracle_eval_gran(int n, const int32_t *D, const int32_t *node4, int64_t cap,
                      int R, const int32_t *off, const int32_t *cust, uint32_t op_mask, const uint8_t *mask,
                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas, int64_t *best_delta,
                      uint32_t *best_id, int64_t *moves) {
-    return eval_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, nthreads, dump_delta,
-                     dump_feas, best_delta, best_id, moves);
+    return eval_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, nthreads,
+                     dump_delta, dump_feas, best_delta, best_id, moves);
 }
 
 int oracle_ls_gran(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
                    int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *mask, int max_steps,
                    int nthreads, uint32_t *traj_id, int32_t *traj_delta, int64_t *moves_total) {
-    return ls_core(n, D, node4, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, max_steps, nthreads,
+    return ls_core(n, D, node4, NULL, cap, has_tw, R, off, cust, op_mask, mask, 0, 0, 0, max_steps, nthreads,
                    traj_id, traj_delta, moves_total);
+}
+
+/* General entry points: optional pickups (VRPSPDTW), optional granular
+ * mask, hard or penalised scoring (pen = 0 / 1). */
+int oracle_eval_ex(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap, int has_tw,
+                   int R, const int32_t *off, const int32_t *cust, uint32_t op_mask, const uint8_t *mask,
+                   int pen, int64_t w_load, int64_t w_tw, int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                   int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
+    return eval_core(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, mask, pen, w_load, w_tw, nthreads,
+                     dump_delta, dump_feas, best_delta, best_id, moves);
+}
+
+int oracle_ls_ex(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap, int has_tw,
+                 int R, int32_t *off, int32_t *cust, uint32_t op_mask, const uint8_t *mask, int pen,
+                 int64_t w_load, int64_t w_tw, int max_steps, int nthreads, uint32_t *traj_id,
+                 int32_t *traj_delta, int64_t *moves_total) {
+    return ls_core(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, mask, pen, w_load, w_tw, max_steps,
+                   nthreads, traj_id, traj_delta, moves_total);
 }
 
 /* Penalty terms of S: total load excess and total time warp over the routes
  * (as in penalised mode). */
-void oracle_violations(int n, const int32_t *D, const int32_t *node4, int64_t cap, int has_tw,
-                       int R, const int32_t *off, const int32_t *cust, int64_t *load_excess,
+void oracle_violations(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                       int has_tw, int R, const int32_t *off, const int32_t *cust, int64_t *load_excess,
                        int64_t *time_warp) {
-    Inst I = {n, D, node4, cap, has_tw};
+    Inst I = {n, D, node4, cap, has_tw, pick};
     int64_t lv = 0, tv = 0;
     for (int r = 0; r < R; r++) {
         int L = off[r + 1] - off[r];

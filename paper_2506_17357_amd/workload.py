@@ -51,12 +51,15 @@ class Instance:
     kind: str
     seed: int
     meta: dict = field(default_factory=dict)
+    pickup: np.ndarray | None = None  # (n+1,) int32 pickup amounts (VRPSPDTW), node 0 = 0
 
     def sha256(self) -> str:
         h = hashlib.sha256()
         h.update(np.int64([self.n, self.capacity, self.has_tw]).tobytes())
         h.update(np.ascontiguousarray(self.dist).tobytes())
         h.update(np.ascontiguousarray(self.node4).tobytes())
+        if self.pickup is not None:
+            h.update(np.ascontiguousarray(self.pickup, dtype=np.int32).tobytes())
         return h.hexdigest()
 
 
@@ -140,6 +143,32 @@ def make_vrptw(n: int, seed: int, clusters: int = 8, sigma: float = 60.0,
                     {"clusters": clusters, "sigma": sigma, "horizon": horizon})
 
 
+def make_vrpspdtw(n: int, seed: int, pickup_max: int = 30, **kw) -> Instance:
+    """Clustered VRPTW (as make_vrptw) with a pickup amount per customer,
+    uniform 1..pickup_max: simultaneous pickup and delivery with windows."""
+    inst = make_vrptw(n, seed, **kw)
+    rng = np.random.Generator(np.random.PCG64(seed + (1 << 20)))
+    pick = np.zeros(n + 1, np.int32)
+    pick[1:] = rng.integers(1, pickup_max + 1, size=n)
+    inst.pickup = pick
+    inst.kind = "vrpspdtw"
+    inst.meta["pickup_max"] = pickup_max
+    return inst
+
+
+def peak_load(inst: Instance, route: list[int]) -> int:
+    """Largest load the vehicle carries on the route: all deliveries at the
+    depot, then at each customer its delivery off and its pickup on."""
+    q = sum(int(inst.node4[c, 0]) for c in route)
+    if inst.pickup is None:
+        return q
+    peak = q
+    for c in route:
+        q += int(inst.pickup[c]) - int(inst.node4[c, 0])
+        peak = max(peak, q)
+    return peak
+
+
 # ---------------------------------------------------------------- sweep -----
 
 def _angle_order(inst: Instance) -> list[int]:
@@ -186,8 +215,9 @@ def _tw_schedule_ok(inst: Instance, route: list[int]) -> bool:
 
 def sweep(inst: Instance) -> Solution:
     """Sweep construction.  CVRP: fill routes in angle order up to capacity.
-    VRPTW: insert each customer (angle order) at the cheapest position of the
-    current route that keeps capacity and windows, else open a new route."""
+    VRPTW (and VRPSPDTW): insert each customer (angle order) at the cheapest
+    position of the current route that keeps capacity (the peak load with
+    pickups) and windows, else open a new route."""
     order = _angle_order(inst)
     dem = inst.node4[:, 0]
     D = inst.dist
@@ -212,7 +242,7 @@ def sweep(inst: Instance) -> Solution:
                 if best is not None and inc >= best[0]:
                     continue
                 cand = cur[:p] + [c] + cur[p:]
-                if _tw_schedule_ok(inst, cand):
+                if _tw_schedule_ok(inst, cand) and (inst.pickup is None or peak_load(inst, cand) <= inst.capacity):
                     best = (inc, p)
         if best is None:
             if cur:
@@ -231,6 +261,13 @@ def sweep(inst: Instance) -> Solution:
 def c1() -> tuple[Instance, Solution]:
     """Plain CVRP, 100 customers, demand 1..10, capacity 50, seed 101."""
     inst = make_cvrp(100, 101, demand_max=10, capacity=50)
+    return inst, sweep(inst)
+
+
+def c6(n: int = 1000) -> tuple[Instance, Solution]:
+    """VRPSPDTW, n customers (default 1000), the clustered VRPTW generator
+    with pickups 1..30, seed 106."""
+    inst = make_vrpspdtw(n, 106)
     return inst, sweep(inst)
 
 

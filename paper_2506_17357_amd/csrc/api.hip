@@ -196,9 +196,11 @@ struct tga_instance {
     int32_t stride16;
     const int4 *node4;
     int32_t maxD, maxE, maxL, maxS, maxDem;
-    // granular neighbourhood (tga_instance_set_granular): adjacency entries of
-    // the customer rows, source and neighbour node, in a caller workspace
-    int32_t theta = 0, gnnz = 0;
+    // granular neighbourhood (tga_instance_set_granular), in a caller
+    // workspace: the customer-customer adjacency entries (source and
+    // neighbour node, both orders) first, then the customers paired with the
+    // depot (gsrc only)
+    int32_t theta = 0, gnnz = 0, gcc = 0, gdep = 0;
     const int32_t *gsrc = nullptr, *gadj = nullptr;
 };
 
@@ -384,15 +386,22 @@ extern "C" int tga_instance_set_granular(tga_instance_t inst, int32_t theta, voi
             adj[i].push_back(j);
             adj[j].push_back(i);
         }
-    std::vector<int32_t> src, dst;
+    std::vector<int32_t> src, dst, dep;
     for (int i = 1; i < np1; ++i) {
         std::sort(adj[i].begin(), adj[i].end());
         adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
         for (int j : adj[i]) {
+            if (j == 0) {
+                dep.push_back(i);
+                continue;
+            }
             src.push_back(i);
             dst.push_back(j);
         }
     }
+    const int32_t gcc = (int32_t)src.size(), gdep = (int32_t)dep.size();
+    src.insert(src.end(), dep.begin(), dep.end());
+    dst.resize(src.size(), 0);
     int32_t *gsrc = (int32_t *)((char *)ws + align_up(4 * (size_t)np1 * theta, 256));
     int32_t *gadj = (int32_t *)((char *)gsrc + align_up(4 * 2 * (size_t)np1 * theta, 256));
     if (!src.empty()) {
@@ -402,6 +411,8 @@ extern "C" int tga_instance_set_granular(tga_instance_t inst, int32_t theta, voi
     HIPCHK(hipStreamSynchronize(st));
     inst->theta = theta;
     inst->gnnz = (int32_t)src.size();
+    inst->gcc = gcc;
+    inst->gdep = gdep;
     inst->gsrc = gsrc;
     inst->gadj = gadj;
     return TGA_OK;
@@ -625,21 +636,23 @@ extern "C" uint32_t tga_solution_version(tga_solution_t sol) { return sol ? sol-
 
 // Granular mode: the inter-route moves of the granular pairs (one launch of
 // k_eval_gran), the intra-route ones complete (k_eval_intra).
-static void launch_eval_gran(const tga_instance *I, const SolDev *d, const IntraItem *intra, int nintra,
+static void launch_eval_gran(const tga_instance *I, const SolDev *d, int R, const IntraItem *intra, int nintra,
                              int has_tw, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
     const bool dump = dd != nullptr;
-    if ((op_mask & 7) && I->gnnz > 0) {
-        const int grid = (I->gnnz + 255) / 256;
+    const long long work = I->gcc + (long long)I->gdep * R;
+    if ((op_mask & 7) && work > 0) {
+        const int grid = (int)((work + 255) / 256);
+        const int a = I->gcc, b = I->gdep;
         if (has_tw) {
             if (dump)
-                k_eval_gran<true, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+                k_eval_gran<true, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, a, b, op_mask, dd, df);
             else
-                k_eval_gran<true, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+                k_eval_gran<true, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, a, b, op_mask, dd, df);
         } else {
             if (dump)
-                k_eval_gran<false, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+                k_eval_gran<false, true><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, a, b, op_mask, dd, df);
             else
-                k_eval_gran<false, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, I->gnnz, op_mask, dd, df);
+                k_eval_gran<false, false><<<grid, 256, 0, st>>>(d, I->gsrc, I->gadj, a, b, op_mask, dd, df);
         }
     }
     if ((op_mask & (2 | 8 | 16)) && nintra > 0) {
@@ -764,7 +777,7 @@ static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *d
     if (sol->h.pen)
         launch_eval_pen(sol, op_mask, dd, df, st);
     else if (op_mask & TGA_OP_GRANULAR)
-        launch_eval_gran(sol->inst, sol->d, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
+        launch_eval_gran(sol->inst, sol->d, sol->R, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
     else
         launch_eval(sol->d, sol->items, sol->nitems, sol->intra, sol->nintra, sol->h.has_tw, op_mask, sol->lds,
                     sol->nitems, dd, df, st);

@@ -1295,13 +1295,15 @@ __device__ __forceinline__ int gran_pair(const SolDev &S, int x, int t, uint32_t
     return (opRel ? (int)cx + (int)ct : 0) + (opSwap && cx && ct ? 1 : 0) + (op2s ? 1 : 0);
 }
 
-// gsrc / gadj: the adjacency entries of the customer rows (source node and
-// neighbour node), e in [0, gnnz).  The inter-route moves of N_theta(S)
-// evaluated are added to S.acc[kAccGranInter].
+// Work items: e < gcc, a customer-customer adjacency entry (gsrc[e],
+// gadj[e]); gcc <= e < gcc + gdep * R, customer gsrc[gcc + (e - gcc) / R]
+// (one the depot is paired with) against the start depot of route
+// (e - gcc) % R, so that no thread walks every route.  The inter-route moves
+// of N_theta(S) evaluated are added to S.acc[kAccGranInter].
 template <bool TW, bool DUMP>
 __global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ sols, const int32_t *__restrict__ gsrc,
-                                                   const int32_t *__restrict__ gadj, int gnnz, uint32_t op_mask,
-                                                   int32_t *__restrict__ dump_delta,
+                                                   const int32_t *__restrict__ gadj, int gcc, int gdep,
+                                                   uint32_t op_mask, int32_t *__restrict__ dump_delta,
                                                    uint8_t *__restrict__ dump_feas) {
     __shared__ unsigned long long red[256 / 64];
     __shared__ long long cnt_sh;
@@ -1313,20 +1315,18 @@ __global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ so
     uint32_t bid = 0xFFFFFFFFu;
     long long cnt = 0;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < gnnz) {
-        const int u = gsrc[e], v = gadj[e];
-        const int x = gld(S.ref2slot + u - 1);
+    if (e < gcc) {
+        const int x = gld(S.ref2slot + gsrc[e] - 1), t = gld(S.ref2slot + gadj[e] - 1);
+        if (gld(S.a4 + t).y > gld(S.a4 + x).y)
+            cnt += gran_pair<TW, DUMP>(S, x, t, op_mask, dump_delta, dump_feas, bd, bid);
+    } else if (e - gcc < gdep * S.R) {
+        const int k = (e - gcc) / S.R, r = (e - gcc) - k * S.R;
+        const int x = gld(S.ref2slot + gsrc[gcc + k] - 1);
         const int rx = gld(S.a4 + x).y;
-        if (v > 0) {
-            const int t = gld(S.ref2slot + v - 1);
-            if (gld(S.a4 + t).y > rx) cnt += gran_pair<TW, DUMP>(S, x, t, op_mask, dump_delta, dump_feas, bd, bid);
-        } else {
-            for (int r = 0; r < S.R; ++r) {
-                if (r == rx) continue;
-                const int d = gld(S.roff + r);  // start depot slot of route r
-                cnt += r > rx ? gran_pair<TW, DUMP>(S, x, d, op_mask, dump_delta, dump_feas, bd, bid)
-                              : gran_pair<TW, DUMP>(S, d, x, op_mask, dump_delta, dump_feas, bd, bid);
-            }
+        if (r != rx) {
+            const int d = gld(S.roff + r);  // start depot slot of route r
+            cnt += r > rx ? gran_pair<TW, DUMP>(S, x, d, op_mask, dump_delta, dump_feas, bd, bid)
+                          : gran_pair<TW, DUMP>(S, d, x, op_mask, dump_delta, dump_feas, bd, bid);
         }
     }
     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);

@@ -3,9 +3,9 @@
 Requests (an instance, a starting solution, a step cap) arrive over time.
 A request is admitted, first come first served, when its device bytes
 (distance matrix, node data, instance and solution workspaces) fit in the
-HBM budget still free and a slot of the engine is free.  An upload thread
-copies its data to the device on a copy stream while the compute stream
-keeps stepping the requests already there.
+HBM budget still free and a slot of the engine is free.  Upload threads
+(each with its own copy stream) copy its data to the device while the
+compute stream keeps stepping the requests already there.
 
 The engine is one slot batch (tga_batch_create_slots): a fixed number of
 slots whose members change while it runs.  Every tick enqueues
@@ -71,7 +71,8 @@ def device_bytes(inst, R: int) -> int:
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
                  device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
-                 max_sum_r: int = 1 << 17, autotune: bool = True, ticks_ahead: int = 2):
+                 max_sum_r: int = 1 << 17, autotune: bool = True, ticks_ahead: int = 2,
+                 upload_workers: int = 4):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.steps_per_tick = int(steps_per_tick)
@@ -82,8 +83,9 @@ class Server:
         self.autotune = autotune
         self.ticks_ahead = int(ticks_ahead)
         self.compute = torch.cuda.Stream(device=device)
-        self.copy = torch.cuda.Stream(device=device)
+        self.copies = [torch.cuda.Stream(device=device) for _ in range(max(1, int(upload_workers)))]
         self.readback = torch.cuda.Stream(device=device)
+        self._stat_lock = threading.Lock()
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
@@ -95,19 +97,20 @@ class Server:
         self.config = None
 
     # ---------------------------------------------------------------- upload
-    def _upload_loop(self, todo: queue_mod.Queue, ready: queue_mod.Queue, t0: float):
+    def _upload_loop(self, copy, todo: queue_mod.Queue, ready: queue_mod.Queue, t0: float):
         while True:
             req = todo.get()
             if req is None:
                 return
             try:
                 tu = time.perf_counter()
-                with torch.cuda.stream(self.copy):
-                    I = tga.Instance.from_workload(req.inst, device=self.device, stream=self.copy)
-                    S = tga.Solution(I, req.sol.offsets, req.sol.customers, stream=self.copy)
+                with torch.cuda.stream(copy):
+                    I = tga.Instance.from_workload(req.inst, device=self.device, stream=copy)
+                    S = tga.Solution(I, req.sol.offsets, req.sol.customers, stream=copy)
                 now = time.perf_counter()
-                self.upload_s += now - tu
-                self.uploads += 1
+                with self._stat_lock:
+                    self.upload_s += now - tu
+                    self.uploads += 1
                 ready.put((req, I, S, now - t0, None))
             except Exception as e:  # handed to the serving loop, which raises it
                 ready.put((req, None, None, 0.0, e))
@@ -127,8 +130,10 @@ class Server:
         tuned = not self.autotune
         B = tga.SlotBatch(self.max_slots, self.max_sum_q, self.max_sum_r, device=self.device, stream=self.compute)
         t0 = time.perf_counter()
-        worker = threading.Thread(target=self._upload_loop, args=(todo, ready, t0), daemon=True)
-        worker.start()
+        workers = [threading.Thread(target=self._upload_loop, args=(c, todo, ready, t0), daemon=True)
+                   for c in self.copies]
+        for w in workers:
+            w.start()
         in_flight = 0      # ticks enqueued and not yet seen finished
         last_seen = -1     # newest tick whose status was processed
         next_tick = 0      # number the next tick will get
@@ -233,8 +238,10 @@ class Server:
                 elif not active and pending and not waiting and not uploading:
                     time.sleep(max(0.0, min(0.001, pending[0].arrival_s - (time.perf_counter() - t0))))
         finally:
-            todo.put(None)
-            worker.join()
+            for _ in workers:
+                todo.put(None)
+            for w in workers:
+                w.join()
             torch.cuda.synchronize()
             B.close()
         return sorted(results, key=lambda r: r.rid)

@@ -132,6 +132,19 @@ int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *node4, int3
 size_t tga_granular_workspace_bytes(int32_t n, int32_t theta);
 int tga_instance_set_granular(tga_instance_t inst, int32_t theta, void *ws, size_t ws_bytes, void *stream);
 
+/* Simultaneous pickup and delivery (VRPSPDTW; Section 2 and the load
+ * attributes of Section 4.3.2): pickup amounts per node, device, (n+1)
+ * int32, 0 at the depot, borrowed for the instance's lifetime.  The vehicle
+ * leaves the depot with all of its route's deliveries (node4 demands) and
+ * at each customer unloads the delivery and loads the pickup; feas bit0
+ * then requires the largest load on every touched route to be within the
+ * capacity, intra-route moves included.  Solutions set up after this call
+ * use it; they are evaluated one at a time (no batch, no TGA_OP_GRANULAR)
+ * by the kernels that concatenate per-slot load and time-warp summaries,
+ * in hard or (tga_solution_set_penalty) penalised mode.  TGA_EINVAL for a
+ * negative amount or a nonzero depot entry.  Synchronises `stream`. */
+int tga_instance_set_pickups(tga_instance_t inst, const int32_t *pickup, void *stream);
+
 /* Adjacency entries of the customer rows of the granular pairs (each kept
  * pair of customers counted twice, a customer-depot pair once); 0 before
  * tga_instance_set_granular. */
@@ -236,7 +249,8 @@ int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, i
  * dumps hold scores (dump_feas still has the hard capacity / window bits).
  * w_load < 0 returns to hard feasibility.  w_tw must be 0 without windows.
  * TGA_ERANGE when the weights could take a score outside +-2^29.  Penalised
- * solutions are evaluated one at a time (no batch, no TGA_OP_GRANULAR).
+ * solutions are evaluated one at a time (no batch, no TGA_OP_GRANULAR); with
+ * pickups L_V is the largest load's excess.
  * Synchronises `stream`. */
 int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int32_t w_tw, void *stream);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstdio>
@@ -82,7 +83,9 @@ int props(DevProps *out) {
                              (const void *)k_eval_batch<1>, (const void *)k_eval_batch<2>,
                              (const void *)k_eval_batch<3>,
                              (const void *)k_eval_solution<false, false>, (const void *)k_eval_solution<true, false>,
-                             (const void *)k_eval_solution<false, true>, (const void *)k_eval_solution<true, true>};
+                             (const void *)k_eval_solution<false, true>, (const void *)k_eval_solution<true, true>,
+                             (const void *)k_eval_gran_fused<false, false>, (const void *)k_eval_gran_fused<true, false>,
+                             (const void *)k_eval_gran_fused<false, true>, (const void *)k_eval_gran_fused<true, true>};
         bool ok = dyn > 65536;
         for (const void *f : fns)
             if (ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) ok = false;
@@ -145,7 +148,7 @@ long long count_items(int Q, int rows) {
 }
 
 struct SolLayout {
-    size_t desc, a4, b4, t4, w4, pf4, pb4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, rblk, best_key, rec,
+    size_t desc, a4, b4, t4, w4, pf4, pb4, pl4, ql4, pdist, ref2slot, roff, rdist, nr_alt, roff_alt, rblk, best_key, rec,
         state, acc, items, intra, total;
     int max_items;
 };
@@ -166,6 +169,8 @@ SolLayout sol_layout(int n, int R) {
     L.w4 = take(16 * S);
     L.pf4 = take(16 * S);
     L.pb4 = take(16 * S);
+    L.pl4 = take(16 * S);
+    L.ql4 = take(16 * S);
     L.pdist = take(4 * S);
     L.ref2slot = take(4 * Q);
     L.roff = take(4 * (R + 1));
@@ -202,6 +207,10 @@ struct tga_instance {
     // depot (gsrc only)
     int32_t theta = 0, gnnz = 0, gcc = 0, gdep = 0;
     const int32_t *gsrc = nullptr, *gadj = nullptr;
+    // pickups (tga_instance_set_pickups), borrowed; null without
+    const int32_t *pick = nullptr;
+    int32_t maxPick = 0;
+    void *ws = nullptr;  // the instance workspace (check results, 16-bit copy of D)
 };
 
 struct tga_solution {
@@ -348,6 +357,7 @@ extern "C" int tga_load_instance(int32_t n, const int32_t *dist, const int32_t *
     I->maxL = (int32_t)maxL;
     I->maxS = (int32_t)maxS;
     I->maxDem = (int32_t)maxDem;
+    I->ws = ws;
     *out = I;
     return TGA_OK;
 }
@@ -419,6 +429,27 @@ extern "C" int tga_instance_set_granular(tga_instance_t inst, int32_t theta, voi
 }
 
 extern "C" int32_t tga_instance_granular_pairs(tga_instance_t inst) { return inst ? inst->gnnz : 0; }
+
+extern "C" int tga_instance_set_pickups(tga_instance_t inst, const int32_t *pickup, void *stream) {
+    if (!inst || !pickup) return fail(TGA_EINVAL, "null argument");
+    const int np1 = inst->n + 1;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t chk[2] = {0, 0};
+    // the check results go through the instance workspace's check area (its first 256 bytes)
+    int32_t *dchk = (int32_t *)((char *)inst->ws + 64);
+    k_zero_i32<<<1, 64, 0, st>>>(dchk, 2);
+    k_check_pick<<<(np1 + 255) / 256, 256, 0, st>>>(pickup, np1, dchk);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(chk, dchk, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (chk[0] & 1) return fail(TGA_EINVAL, "pickups must be >= 0, with 0 at the depot");
+    const int64_t maxP = chk[1];
+    if ((int64_t)inst->n * std::max<int64_t>(maxP, inst->maxDem) * 2 >= (1 << 30))
+        return fail(TGA_ERANGE, "loads with pickups may exceed 2^30");
+    inst->pick = pickup;
+    inst->maxPick = (int32_t)maxP;
+    return TGA_OK;
+}
 
 extern "C" int32_t tga_instance_dist_bytes(tga_instance_t inst) {
     if (!inst) return 0;
@@ -503,6 +534,10 @@ static int solution_init(tga_solution *S, tga_instance_t inst, int32_t R, const 
     h.w4 = (int4 *)(base + L.w4);
     h.pf4 = (int4 *)(base + L.pf4);
     h.pb4 = (int4 *)(base + L.pb4);
+    h.pl4 = (int4 *)(base + L.pl4);
+    h.ql4 = (int4 *)(base + L.ql4);
+    h.pick = inst->pick;
+    h.pd = inst->pick != nullptr;
     h.pdist = (int32_t *)(base + L.pdist);
     h.ref2slot = (int32_t *)(base + L.ref2slot);
     h.roff = (int32_t *)(base + L.roff);
@@ -640,6 +675,28 @@ static void launch_eval_gran(const tga_instance *I, const SolDev *d, int R, cons
                              int has_tw, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
     const bool dump = dd != nullptr;
     const long long work = I->gcc + (long long)I->gdep * R;
+    if ((op_mask & 7) && work > 0 && (op_mask & (2 | 8 | 16)) && nintra > 0) {
+        // both kinds in one launch: the intra-route groups first, then the pairs
+        const int grid = nintra + (int)((work + kInterThreads - 1) / kInterThreads);
+        const size_t l = (size_t)kInterWaves * kIntraRegionBytes;
+        const int a = I->gcc, b = I->gdep;
+        if (has_tw) {
+            if (dump)
+                k_eval_gran_fused<true, true><<<grid, kInterThreads, l, st>>>(d, I->gsrc, I->gadj, a, b, intra, nintra,
+                                                                             op_mask, dd, df);
+            else
+                k_eval_gran_fused<true, false><<<grid, kInterThreads, l, st>>>(d, I->gsrc, I->gadj, a, b, intra,
+                                                                              nintra, op_mask, dd, df);
+        } else {
+            if (dump)
+                k_eval_gran_fused<false, true><<<grid, kInterThreads, l, st>>>(d, I->gsrc, I->gadj, a, b, intra,
+                                                                              nintra, op_mask, dd, df);
+            else
+                k_eval_gran_fused<false, false><<<grid, kInterThreads, l, st>>>(d, I->gsrc, I->gadj, a, b, intra,
+                                                                               nintra, op_mask, dd, df);
+        }
+        return;
+    }
     if ((op_mask & 7) && work > 0) {
         const int grid = (int)((work + 255) / 256);
         const int a = I->gcc, b = I->gdep;
@@ -747,34 +804,35 @@ static void to_move(const int32_t *rec, tga_move_t *m) {
 // `host` (48 bytes; pinned or pageable).
 // Penalised mode: inter-route pairs (16 x 16 tiles on and above the
 // diagonal) and intra-route walks (one thread per slot).
-static void launch_eval_pen(const tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
-    const bool tw = sol->h.has_tw, dump = dd != nullptr;
+template <bool TW, bool PD>
+static void launch_eval_gen(const tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
+    const bool dump = dd != nullptr;
     if (op_mask & 7) {
         const int tiles = (sol->Q + 15) / 16, grid = tiles * (tiles + 1) / 2;
-        if (tw) {
-            if (dump) k_eval_pen_pairs<true, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
-            else k_eval_pen_pairs<true, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
-        } else {
-            if (dump) k_eval_pen_pairs<false, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
-            else k_eval_pen_pairs<false, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
-        }
+        if (dump) k_eval_pen_pairs<TW, PD, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
+        else k_eval_pen_pairs<TW, PD, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
     }
     if (op_mask & (2 | 8 | 16)) {
         const int grid = (sol->Q + 255) / 256;
-        if (tw) {
-            if (dump) k_eval_pen_intra<true, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
-            else k_eval_pen_intra<true, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
-        } else {
-            if (dump) k_eval_pen_intra<false, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
-            else k_eval_pen_intra<false, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
-        }
+        if (dump) k_eval_pen_intra<TW, PD, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
+        else k_eval_pen_intra<TW, PD, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
     }
+}
+
+// General path (penalised mode or pickups): gathers per pair and per walk,
+// every attribute of a new route concatenated from the stored summaries.
+static void launch_eval_pen(const tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
+    const bool tw = sol->h.has_tw, pd = sol->h.pd;
+    if (tw && pd) launch_eval_gen<true, true>(sol, op_mask, dd, df, st);
+    else if (tw) launch_eval_gen<true, false>(sol, op_mask, dd, df, st);
+    else if (pd) launch_eval_gen<false, true>(sol, op_mask, dd, df, st);
+    else launch_eval_gen<false, false>(sol, op_mask, dd, df, st);
 }
 
 // Launch one evaluation of a solution (penalised, granular or full
 // neighbourhood).
 static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
-    if (sol->h.pen)
+    if (sol->h.pen || sol->h.pd)
         launch_eval_pen(sol, op_mask, dd, df, st);
     else if (op_mask & TGA_OP_GRANULAR)
         launch_eval_gran(sol->inst, sol->d, sol->R, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
@@ -789,8 +847,8 @@ static int check_mask(const tga_solution *sol, uint32_t op_mask) {
     if (op_mask & ~(TGA_OP_ALL | TGA_OP_GRANULAR)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if ((op_mask & TGA_OP_GRANULAR) && !sol->inst->gnnz)
         return fail(TGA_EINVAL, "TGA_OP_GRANULAR before tga_instance_set_granular");
-    if ((op_mask & TGA_OP_GRANULAR) && sol->h.pen)
-        return fail(TGA_EINVAL, "TGA_OP_GRANULAR with penalised scoring is not supported");
+    if ((op_mask & TGA_OP_GRANULAR) && (sol->h.pen || sol->h.pd))
+        return fail(TGA_EINVAL, "TGA_OP_GRANULAR with penalised scoring or pickups is not supported");
     return TGA_OK;
 }
 
@@ -805,7 +863,7 @@ extern "C" int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int3
         // every score and summary must stay exact in int32
         const double np1 = (double)I->n + 1;
         const double tb = I->has_tw ? np1 * ((double)I->maxS + I->maxD + I->maxE) + I->maxL : 0.0;
-        const double bound = 2.0 * w_tw * tb + 2.0 * w_load * (double)I->n * I->maxDem +
+        const double bound = 2.0 * w_tw * tb + 2.0 * w_load * (double)I->n * std::max(I->maxDem, I->maxPick) +
                              4.0 * ((double)sol->Q + 1) * I->maxD;
         if (tb >= (double)(1 << 28) || bound >= (double)(1 << 29))
             return fail(TGA_ERANGE, "penalty weights (%d, %d) could take a score beyond 2^29", w_load, w_tw);
@@ -1099,6 +1157,21 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
     return batch_layout(v.size(), batch_max_items(v, 1), nintra).total;
 }
 
+// Rows per inter-route item of the batched form when none are given: one
+// LDS sub-block, or for large solutions (fewer than kItemRowsMin rows per
+// sub-block) several whole sub-blocks, so that the two boundary rows carried
+// from one sub-block to the next spare re-reading them (a one-row sub-block
+// would otherwise read every row three times) — but never so few items that
+// the workgroups the solution's share of the work occupies (wgs) get fewer
+// than four items each (long items of a triangle balance badly).
+constexpr int kItemRowsMin = 16;
+static int default_item_rows(int tile_rows, int Q, double wgs) {
+    if (tile_rows >= kItemRowsMin) return tile_rows;
+    const int want = (kItemRowsMin + tile_rows - 1) / tile_rows;           // sub-blocks per item
+    const int cap = (int)std::floor(Q / (4.0 * std::max(1.0, wgs)) / tile_rows);  // keeps >= 4 items per wg
+    return tile_rows * std::max(1, std::min(want, cap));
+}
+
 // Rows per LDS sub-block for an LDS budget of `budget` bytes.
 static int tile_rows_for(int np1, bool w16, size_t budget) {
     int h = 1;
@@ -1202,9 +1275,13 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     std::vector<std::vector<InterItem>> own(count);
     std::vector<double> sol_work(count, 0.0);
     double total = 0.0;
+    double pairs_all = 0.0;  // the pair count of each solution estimates its share of the launch
+    for (int i = 0; i < count; ++i)
+        if (v[i]) pairs_all += 0.5 * (double)v[i]->Q * v[i]->Q;
     for (int i = 0; i < count; ++i) {
         if (!v[i]) continue;
-        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : trs[i],
+        const double wgs = grid_inter * (0.5 * (double)v[i]->Q * v[i]->Q) / std::max(1.0, pairs_all);
+        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i], v[i]->Q, wgs),
                       [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
         for (const auto &it : own[i]) sol_work[i] += (double)work(it);
         total += sol_work[i];
@@ -1409,7 +1486,8 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     for (auto *s : v) {
         if (!s) return fail(TGA_EINVAL, "null solution in batch");
         if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
-        if (s->h.pen) return fail(TGA_EINVAL, "penalised solutions are evaluated one at a time");
+        if (s->h.pen || s->h.pd)
+            return fail(TGA_EINVAL, "penalised solutions and pickups are evaluated one at a time");
     }
     for (size_t i = 0; i < v.size(); ++i)
         for (size_t j = i + 1; j < v.size(); ++j)
@@ -1471,7 +1549,8 @@ extern "C" int tga_batch_set_members(tga_batch_t B, const tga_solution_t *sols, 
         bool ours = false;
         for (auto *o : B->sols) ours = ours || o == s;
         if (s->in_batch && !ours) return fail(TGA_EINVAL, "solution in slot %d belongs to another batch", i);
-        if (s->h.pen) return fail(TGA_EINVAL, "penalised solutions are evaluated one at a time");
+        if (s->h.pen || s->h.pd)
+            return fail(TGA_EINVAL, "penalised solutions and pickups are evaluated one at a time");
         for (int j = 0; j < i; ++j)
             if (sols[j] == s) return fail(TGA_EINVAL, "solution listed in slots %d and %d", j, i);
         sq += s->Q;

@@ -665,9 +665,56 @@ __device__ __forceinline__ void pen_route(const SolDev &S, int r) {
     gst(S.pb4 + off, tw_pack(tw_cat(dep, gld(S.a4 + off).z, b)));
 }
 
-// Load excess of route r (from its load, kept in every slot's b4.z).
-__device__ __forceinline__ int route_excess(const SolDev &S, int r) {
-    return max(gld(S.b4 + gld(S.roff + r)).z - S.cap, 0);
+// Load summaries (Section 4.3.2): {L_I delivered, L_O picked up, L_M the
+// largest load on board}; a node is {d, p, max(d, p)}; concatenation keeps
+// the later part's deliveries on board through the earlier part, and the
+// earlier part's pickups through the later one.
+struct Ld {
+    int li, lo, lm;
+};
+
+__device__ __forceinline__ Ld ld_of(int4 x) { return Ld{x.x, x.y, x.z}; }
+__device__ __forceinline__ int4 ld_pack(const Ld &x) { return make_int4(x.li, x.lo, x.lm, 0); }
+__device__ __forceinline__ Ld ld_cat(const Ld &a, const Ld &b) {
+    return Ld{a.li + b.li, a.lo + b.lo, max(a.lm + b.li, a.lo + b.lm)};
+}
+__device__ __forceinline__ Ld ld_node_at(const SolDev &S, int x) {
+    const int node = nodeof(gld(S.a4 + x).x);
+    const int d = gld(S.b4 + x).x, p = node ? gld(S.pick + node) : 0;
+    return Ld{d, p, max(d, p)};
+}
+
+// Prefix and suffix load summaries of route r (one thread; pickups only).
+__device__ __forceinline__ void pd_route(const SolDev &S, int r) {
+    const int off = gld(S.roff + r), L = gld(S.roff + r + 1) - off - 1;
+    Ld f{0, 0, 0};
+    gst(S.pl4 + off, ld_pack(f));
+    for (int p = 1; p <= L; ++p) {
+        f = ld_cat(f, ld_node_at(S, off + p));
+        gst(S.pl4 + off + p, ld_pack(f));
+    }
+    Ld b{0, 0, 0};
+    for (int p = L; p >= 1; --p) {
+        b = ld_cat(ld_node_at(S, off + p), b);
+        gst(S.ql4 + off + p, ld_pack(b));
+    }
+    gst(S.ql4 + off, ld_pack(b));
+}
+
+// Largest load on route r: the route load without pickups (kept in every
+// slot's b4.z), the suffix summary's L_M at the start depot with them.
+__device__ __forceinline__ int route_peak(const SolDev &S, int r) {
+    const int off = gld(S.roff + r);
+    return S.pd ? gld(S.ql4 + off).z : gld(S.b4 + off).z;
+}
+
+// Load excess of route r.
+__device__ __forceinline__ int route_excess(const SolDev &S, int r) { return max(route_peak(S, r) - S.cap, 0); }
+
+// Summaries the general evaluation path reads (penalised mode or pickups).
+__device__ __forceinline__ void gen_route(const SolDev &S, int r) {
+    if (S.has_tw) pen_route(S, r);
+    if (S.pd) pd_route(S, r);
 }
 
 // Time warp of route r (the suffix summary at its start depot).
@@ -707,8 +754,7 @@ __device__ __forceinline__ void pen_totals(const SolDev &S, ApplyShared &sh) {
 
 // Summaries of every route and the totals (one block).
 __device__ __forceinline__ void pen_all(const SolDev &S, ApplyShared &sh) {
-    if (S.has_tw)
-        for (int r = threadIdx.x; r < S.R; r += blockDim.x) pen_route(S, r);
+    for (int r = threadIdx.x; r < S.R; r += blockDim.x) gen_route(S, r);
     __threadfence_block();
     __syncthreads();
     pen_totals(S, sh);
@@ -719,7 +765,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
     __shared__ ApplyShared sh;
     const SolDev &S = sols[blockIdx.x];
     rebuild(S, S.nr_alt, S.roff_alt, sh);
-    if (S.pen) pen_all(S, sh);
+    if (S.pen || S.pd) pen_all(S, sh);
     if (threadIdx.x == 0) {
         *S.best_key = ~0ull;
         S.state[kStDone] = 0;
@@ -732,7 +778,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
 __global__ __launch_bounds__(kApplyThreads) void k_pen_init(const SolDev *__restrict__ sols) {
     __shared__ ApplyShared sh;
     const SolDev &S = sols[blockIdx.x];
-    if (S.pen) pen_all(S, sh);
+    if (S.pen || S.pd) pen_all(S, sh);
 }
 
 // ------------------------------------------------------ inter-route eval ---
@@ -1079,8 +1125,29 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
         const int sb = s0 + i * h;
         const int nr = min(h, s1 - sb);  // rows of this sub-block
         __syncthreads();                 // rows of sub-block i resident (i = 0), or i - 1 consumed
-        if (i > 0) {                     // the rows of sub-block i with its halo rows
-            drow_issue<W16>(S, rows, sb - 1, sb - 1, nr + 2, wave);
+        if (i > 0) {
+            // The previous sub-block (h rows) ended with rows sb - 1 and sb
+            // at positions h and h + 1: they become this one's first halo
+            // row and first row, so only rows sb + 1 .. sb + nr come from
+            // memory and a strip of sub-blocks reads each row once.
+            {
+                const int words = (int)((size_t)rs * sizeof(DT) / 4);  // dwords per row
+                int *blk = (int *)rows;
+                const int *from = blk + h * words;
+                if (h >= 2) {  // positions h, h + 1 and 0, 1 do not overlap
+                    for (int w = threadIdx.x; w < 2 * words; w += blockDim.x) blk[w] = from[w];
+                } else {  // position 1 is source and destination: read a chunk, wait, write it
+                    for (int w0 = 0; w0 < 2 * words; w0 += blockDim.x) {
+                        const int w = w0 + threadIdx.x;
+                        const int v = w < 2 * words ? from[w] : 0;
+                        __syncthreads();
+                        if (w < 2 * words) blk[w] = v;
+                        __syncthreads();
+                    }
+                }
+            }
+            __syncthreads();
+            drow_issue<W16>(S, rows, sb - 1, sb + 1, nr, wave);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
@@ -1300,21 +1367,19 @@ __device__ __forceinline__ int gran_pair(const SolDev &S, int x, int t, uint32_t
 // (one the depot is paired with) against the start depot of route
 // (e - gcc) % R, so that no thread walks every route.  The inter-route moves
 // of N_theta(S) evaluated are added to S.acc[kAccGranInter].
+// One block of work items, item e for this thread (every thread of the
+// block calls it; red holds blockDim / 64 keys).
 template <bool TW, bool DUMP>
-__global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ sols, const int32_t *__restrict__ gsrc,
-                                                   const int32_t *__restrict__ gadj, int gcc, int gdep,
-                                                   uint32_t op_mask, int32_t *__restrict__ dump_delta,
-                                                   uint8_t *__restrict__ dump_feas) {
-    __shared__ unsigned long long red[256 / 64];
-    __shared__ long long cnt_sh;
-    const SolDev &S = sols[0];
-    if (skip_solution(S, op_mask)) return;  // uniform for the grid
-    if (threadIdx.x == 0) cnt_sh = 0;
+__device__ __forceinline__ void gran_block(const SolDev &S, const int32_t *__restrict__ gsrc,
+                                           const int32_t *__restrict__ gadj, int gcc, int gdep, int e,
+                                           uint32_t op_mask, int32_t *__restrict__ dump_delta,
+                                           uint8_t *__restrict__ dump_feas, unsigned long long *red,
+                                           long long *cnt_sh) {
+    if (threadIdx.x == 0) *cnt_sh = 0;
     __syncthreads();
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
     long long cnt = 0;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < gcc) {
         const int x = gld(S.ref2slot + gsrc[e] - 1), t = gld(S.ref2slot + gadj[e] - 1);
         if (gld(S.a4 + t).y > gld(S.a4 + x).y)
@@ -1330,9 +1395,22 @@ __global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ so
         }
     }
     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long *)&cnt_sh, (unsigned long long)cnt);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long *)cnt_sh, (unsigned long long)cnt);
     block_argmin_commit(bd, bid, S.best_key, red);  // its barriers also order cnt_sh
-    if (threadIdx.x == 0 && cnt_sh) atomicAdd((unsigned long long *)(S.acc + kAccGranInter), (unsigned long long)cnt_sh);
+    if (threadIdx.x == 0 && *cnt_sh) atomicAdd((unsigned long long *)(S.acc + kAccGranInter), (unsigned long long)*cnt_sh);
+}
+
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(256) void k_eval_gran(const SolDev *__restrict__ sols, const int32_t *__restrict__ gsrc,
+                                                   const int32_t *__restrict__ gadj, int gcc, int gdep,
+                                                   uint32_t op_mask, int32_t *__restrict__ dump_delta,
+                                                   uint8_t *__restrict__ dump_feas) {
+    __shared__ unsigned long long red[256 / 64];
+    __shared__ long long cnt_sh;
+    const SolDev &S = sols[0];
+    if (skip_solution(S, op_mask)) return;  // uniform for the grid
+    gran_block<TW, DUMP>(S, gsrc, gadj, gcc, gdep, blockIdx.x * blockDim.x + threadIdx.x, op_mask, dump_delta,
+                         dump_feas, red, &cnt_sh);
 }
 
 // ------------------------------------------- penalised-mode evaluation ---
@@ -1356,17 +1434,29 @@ __device__ __forceinline__ Tw tw_node_at(const SolDev &S, int x) {
     return tw_node(w.x, w.y, w.z);
 }
 
-__device__ __forceinline__ void pen_record(int score, int feas, uint32_t id, bool dump, int32_t *dd,
-                                           uint8_t *df, int &bd, uint32_t &bid) {
+// Record one move of the general path.  Penalised mode: the score is
+// dD + w_L dL_V + w_T dT_V and every move is admissible.  Otherwise (pickups
+// with hard feasibility): the distance delta, admissible when the touched
+// routes have no load excess and no time warp.  The dumps hold the score
+// (penalised) or the delta, and the hard capacity / window bits.
+__device__ __forceinline__ void gen_record(const SolDev &S, int dD, int dlv, int dtv, bool capok, bool twok, uint32_t id,
+                                           bool dump, int32_t *dd, uint8_t *df, int &bd, uint32_t &bid) {
+    const int feas = (capok ? 1 : 0) | (twok ? 2 : 0);
+    const int score = S.pen ? dD + S.wL * dlv + S.wT * dtv : dD;
     if (dump) {
         dd[id] = score;
         df[id] = (uint8_t)feas;
     }
-    consider(score, id, bd, bid);
+    consider(S.pen || feas == 3 ? score : score + kPenalty, id, bd, bid);
+}
+
+// Load summary strictly after slot x (the end depot: empty, when x is last).
+__device__ __forceinline__ Ld ld_after(const SolDev &S, int x) {
+    return nodeof(gld(S.a4 + x + 1).x) == 0 ? Ld{0, 0, 0} : ld_of(gld(S.ql4 + x + 1));
 }
 
 // The four inter-route moves of slots x, t (route(x) < route(t)).
-template <bool TW, bool DUMP>
+template <bool TW, bool PD, bool DUMP>
 __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t op_mask, int32_t *dd, uint8_t *df,
                                          int &bd, uint32_t &bid) {
     const int np1 = S.np1, n = S.n, cap = S.cap;
@@ -1380,7 +1470,7 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
     auto d = [&](int i, int j) { return gld(D + (size_t)i * np1 + j); };
     const int refX = cx ? nx - 1 : n + ax.y, refT = ct ? nt - 1 : n + at.y;
     const int Lx = bx.z, Lt = bt.z, dx = bx.x, dtt = bt.x;
-    const int lvOld = max(Lx - cap, 0) + max(Lt - cap, 0);
+    const int lvOld = route_excess(S, ax.y) + route_excess(S, at.y);
     int tvOld = 0;
     Tw dep{}, Fx{}, Ft{}, Fpx{}, Fpt{}, Bax{}, Bat{}, Nx{}, Nt{};
     if (TW) {
@@ -1395,43 +1485,61 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
         Nt = tw_node_at(S, t);
         tvOld = route_warp(S, ax.y) + route_warp(S, at.y);
     }
+    Ld Px{}, Pt{}, Ppx{}, Ppt{}, Sax{}, Sat{}, Mx{}, Mt{};
+    if (PD) {
+        Px = ld_of(gld(S.pl4 + x));
+        Pt = ld_of(gld(S.pl4 + t));
+        Ppx = ld_of(gld(S.pl4 + max(x - 1, 0)));
+        Ppt = ld_of(gld(S.pl4 + t - 1));
+        Sax = ld_after(S, x);
+        Sat = ld_after(S, t);
+        Mx = ld_node_at(S, x);
+        Mt = ld_node_at(S, t);
+    }
     const int exx = d(nx, nsx), ett = d(nt, nst);  // edges leaving x and t
-    auto score = [&](int dD, int lx, int lt, int tvx, int tvt, uint32_t id) {
+    // peak loads of the two new routes are passed in (lx, lt)
+    auto rec = [&](int dD, int lx, int lt, int tvx, int tvt, uint32_t id) {
         const int lv = max(lx - cap, 0) + max(lt - cap, 0);
-        const int sc = dD + S.wL * (lv - lvOld) + S.wT * (tvx + tvt - tvOld);
-        const int feas = (lv == 0 ? 1 : 0) | (tvx + tvt == 0 ? 2 : 0);
-        pen_record(sc, feas, id, DUMP, dd, df, bd, bid);
+        gen_record(S, dD, lv - lvOld, tvx + tvt - tvOld, lv == 0, tvx + tvt == 0, id, DUMP, dd, df, bd, bid);
     };
     if ((op_mask & 1) && cx) {  // RELOCATE x -> right after t
         const int dD = d(nt, nx) + d(nx, nst) - ett + d(npx, nsx) - d(npx, nx) - exx;
         const int tvx = TW ? tw_cat(Fpx, d(npx, nsx), Bax).v : 0;
         const int tvt = TW ? tw_cat(tw_cat(Ft, d(nt, nx), Nx), d(nx, nst), Bat).v : 0;
-        score(dD, Lx - dx, Lt + dx, tvx, tvt, (uQ + (uint32_t)refX) * uQ + (uint32_t)refT);
+        const int lx = PD ? ld_cat(Ppx, Sax).lm : Lx - dx;
+        const int lt = PD ? ld_cat(ld_cat(Pt, Mx), Sat).lm : Lt + dx;
+        rec(dD, lx, lt, tvx, tvt, (uQ + (uint32_t)refX) * uQ + (uint32_t)refT);
     }
     if ((op_mask & 1) && ct) {  // RELOCATE t -> right after x
         const int dD = d(nx, nt) + d(nt, nsx) - exx + d(npt, nst) - d(npt, nt) - ett;
         const int tvx = TW ? tw_cat(tw_cat(Fx, d(nx, nt), Nt), d(nt, nsx), Bax).v : 0;
         const int tvt = TW ? tw_cat(Fpt, d(npt, nst), Bat).v : 0;
-        score(dD, Lx + dtt, Lt - dtt, tvx, tvt, (uQ + (uint32_t)refT) * uQ + (uint32_t)refX);
+        const int lx = PD ? ld_cat(ld_cat(Px, Mt), Sax).lm : Lx + dtt;
+        const int lt = PD ? ld_cat(Ppt, Sat).lm : Lt - dtt;
+        rec(dD, lx, lt, tvx, tvt, (uQ + (uint32_t)refT) * uQ + (uint32_t)refX);
     }
     const uint32_t lo = min((uint32_t)refX, (uint32_t)refT), hi = max((uint32_t)refX, (uint32_t)refT);
     if ((op_mask & 2) && cx && ct) {  // SWAP x <-> t
         const int dD = d(npx, nt) + d(nt, nsx) + d(npt, nx) + d(nx, nst) - d(npx, nx) - exx - d(npt, nt) - ett;
         const int tvx = TW ? tw_cat(tw_cat(Fpx, d(npx, nt), Nt), d(nt, nsx), Bax).v : 0;
         const int tvt = TW ? tw_cat(tw_cat(Fpt, d(npt, nx), Nx), d(nx, nst), Bat).v : 0;
-        score(dD, Lx - dx + dtt, Lt - dtt + dx, tvx, tvt, (5u * uQ + lo) * uQ + hi);
+        const int lx = PD ? ld_cat(ld_cat(Ppx, Mt), Sax).lm : Lx - dx + dtt;
+        const int lt = PD ? ld_cat(ld_cat(Ppt, Mx), Sat).lm : Lt - dtt + dx;
+        rec(dD, lx, lt, tvx, tvt, (5u * uQ + lo) * uQ + hi);
     }
     if (op_mask & 4) {  // 2OPT*: heads keep their routes, tails exchanged
         const int dD = d(nx, nst) + d(nt, nsx) - exx - ett;
         const int tvx = TW ? tw_cat(Fx, d(nx, nst), Bat).v : 0;
         const int tvt = TW ? tw_cat(Ft, d(nt, nsx), Bax).v : 0;
-        score(dD, bx.y + (Lt - bt.y), bt.y + (Lx - bx.y), tvx, tvt, (8u * uQ + lo) * uQ + hi);
+        const int lx = PD ? ld_cat(Px, Sat).lm : bx.y + (Lt - bt.y);
+        const int lt = PD ? ld_cat(Pt, Sax).lm : bt.y + (Lx - bx.y);
+        rec(dD, lx, lt, tvx, tvt, (8u * uQ + lo) * uQ + hi);
     }
 }
 
 // Inter-route pairs: 16 x 16 tiles of (row slot, column slot) on and above
 // the diagonal, blockIdx.x enumerating the tiles row by row.
-template <bool TW, bool DUMP>
+template <bool TW, bool PD, bool DUMP>
 __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict__ sols, int tiles, uint32_t op_mask,
                                                         int32_t *__restrict__ dd, uint8_t *__restrict__ df) {
     __shared__ unsigned long long red[4];
@@ -1447,14 +1555,15 @@ __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
     if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y)
-        pen_pair<TW, DUMP>(S, x, t, op_mask, dd, df, bd, bid);
+        pen_pair<TW, PD, DUMP>(S, x, t, op_mask, dd, df, bd, bid);
     block_argmin_commit(bd, bid, S.best_key, red);
 }
 
 // Intra-route moves whose first position is the customer at slot s: the
 // 2-opt / same-route swap walk and the or-opt walks, the middle summaries
-// growing one node per step.  One thread per slot.
-template <bool TW, bool DUMP>
+// (time warp and, with pickups, load) growing one node per step.  One thread
+// per slot.
+template <bool TW, bool PD, bool DUMP>
 __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict__ sols, uint32_t op_mask,
                                                         int32_t *__restrict__ dd, uint8_t *__restrict__ df) {
     __shared__ unsigned long long red[4];
@@ -1465,7 +1574,7 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < S.Q && (flagsof(gld(S.a4 + s).x) & kFlagCustomer)) {
         const int r = gld(S.a4 + s).y, off = gld(S.roff + r), L = gld(S.roff + r + 1) - off - 1, i = s - off;
-        const int n = S.n, np1 = S.np1;
+        const int n = S.n, np1 = S.np1, cap = S.cap;
         const uint32_t uQ = (uint32_t)S.Q;
         const int32_t *D = S.D;
         const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
@@ -1477,43 +1586,55 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
         auto Npos = [&](int p) { return TW ? tw_node_at(S, off + p) : Tw{}; };
         auto Fpos = [&](int p) { return TW ? tw_of(gld(S.pf4 + off + p)) : Tw{}; };
         auto Bafter = [&](int p) { return TW ? (p >= L ? dep : tw_of(gld(S.pb4 + off + p + 1))) : Tw{}; };
-        const int lvR = max(gld(S.b4 + off).z - S.cap, 0);
+        auto LNpos = [&](int p) { return PD ? ld_node_at(S, off + p) : Ld{}; };
+        auto LFpos = [&](int p) { return PD ? ld_of(gld(S.pl4 + off + p)) : Ld{}; };
+        auto LBafter = [&](int p) { return PD ? (p >= L ? Ld{0, 0, 0} : ld_of(gld(S.ql4 + off + p + 1))) : Ld{}; };
+        const int lvR = route_excess(S, r);
         const int tvR = TW ? gld(S.pb4 + off).w : 0;
-        auto score = [&](int dD, int tvNew, uint32_t id) {
-            const int sc = dD + S.wT * (tvNew - tvR);
-            const int feas = (lvR == 0 ? 1 : 0) | (tvNew == 0 ? 2 : 0);
-            pen_record(sc, feas, id, DUMP, dd, df, bd, bid);
+        // new route: time warp tvNew, largest load peakNew (without pickups
+        // an intra-route move keeps the load)
+        auto rec = [&](int dD, int tvNew, int lvNew, uint32_t id) {
+            gen_record(S, dD, lvNew - lvR, tvNew - tvR, lvNew == 0, tvNew == 0, id, DUMP, dd, df, bd, bid);
         };
+        auto excess = [&](const Ld &x) { return PD ? max(x.lm - cap, 0) : lvR; };
         const int cI = node(i), cP = node(i - 1);
         const int eP = edge(i - 1), eI = edge(i);
         const Tw Fi1 = Fpos(i - 1);
+        const Ld LFi1 = LFpos(i - 1);
         // ---- 2OPT(i, j) and SWAP(i, j), j > i
         if (op2o || opSwap) {
             Tw rev = Npos(i), mid{};
+            Ld lrev = LNpos(i), lmid{};
             for (int j = i + 1; j <= L; ++j) {
                 const int cJ = node(j), cJ1 = node(j + 1), ej = edge(j), ejm = edge(j - 1);
                 if (TW) rev = tw_cat(Npos(j), ejm, rev);
+                if (PD) lrev = ld_cat(LNpos(j), lrev);
                 const int d1 = d(cP, cJ), d2 = d(cI, cJ1);
                 const uint32_t lo = min(ref(i), ref(j)), hi = max(ref(i), ref(j));
                 const Tw Ba = Bafter(j);
+                const Ld LBa = LBafter(j);
                 if (op2o) {
                     const int tv = TW ? tw_cat(tw_cat(Fi1, d1, rev), d2, Ba).v : 0;
-                    score(d1 + d2 - eP - ej, tv, (12u * uQ + lo) * uQ + hi);
+                    const int lv = excess(ld_cat(ld_cat(LFi1, lrev), LBa));
+                    rec(d1 + d2 - eP - ej, tv, lv, (12u * uQ + lo) * uQ + hi);
                 }
                 if (opSwap) {
-                    int dS, tv = 0;
+                    int dS, tv = 0, lv;
                     if (j == i + 1) {
                         dS = d1 + d2 - eP - ej;
                         if (TW) tv = tw_cat(tw_cat(tw_cat(Fi1, d1, Npos(j)), ejm, Npos(i)), d2, Ba).v;
+                        lv = excess(ld_cat(ld_cat(ld_cat(LFi1, LNpos(j)), LNpos(i)), LBa));
                     } else {
                         const int dA = d(cJ, node(i + 1)), dB = d(node(j - 1), cI);
                         dS = d1 + dA + dB + d2 - eP - eI - ejm - ej;
                         if (TW)
                             tv = tw_cat(tw_cat(tw_cat(tw_cat(Fi1, d1, Npos(j)), dA, mid), dB, Npos(i)), d2, Ba).v;
+                        lv = excess(ld_cat(ld_cat(ld_cat(ld_cat(LFi1, LNpos(j)), lmid), LNpos(i)), LBa));
                     }
-                    score(dS, tv, (5u * uQ + lo) * uQ + hi);
+                    rec(dS, tv, lv, (5u * uQ + lo) * uQ + hi);
                 }
                 if (TW) mid = (j == i + 1) ? Npos(j) : tw_cat(mid, ejm, Npos(j));  // c_{i+1} .. c_j
+                if (PD) lmid = (j == i + 1) ? LNpos(j) : ld_cat(lmid, LNpos(j));
             }
         }
         // ---- OR-OPT: segment c_i .. c_{i+k-1} moved right after c_j
@@ -1522,25 +1643,35 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
                 const int g = i + k - 1, w = i + k, cG = node(g), cW = node(w);
                 const int base = d(cP, cW) - eP - edge(g);
                 Tw sig{};
+                Ld lsig{};
                 if (TW) {
                     sig = Npos(i);
                     for (int q = 1; q < k; ++q) sig = tw_cat(sig, edge(i + q - 1), Npos(i + q));
                 }
+                if (PD) {
+                    lsig = LNpos(i);
+                    for (int q = 1; q < k; ++q) lsig = ld_cat(lsig, LNpos(i + q));
+                }
                 Tw mid{};
+                Ld lmid{};
                 for (int j = w; j <= L; ++j) {  // forward: middle c_{i+k} .. c_j
                     const int cJ = node(j), cJ1 = node(j + 1);
                     if (TW) mid = (j == w) ? Npos(j) : tw_cat(mid, edge(j - 1), Npos(j));
+                    if (PD) lmid = (j == w) ? LNpos(j) : ld_cat(lmid, LNpos(j));
                     const int dVF = d(cJ, cI), dGV = d(cG, cJ1);
                     const int tv = TW ? tw_cat(tw_cat(tw_cat(Fi1, d(cP, cW), mid), dVF, sig), dGV, Bafter(j)).v : 0;
-                    score(base + dVF + dGV - edge(j), tv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
+                    const int lv = excess(ld_cat(ld_cat(ld_cat(LFi1, lmid), lsig), LBafter(j)));
+                    rec(base + dVF + dGV - edge(j), tv, lv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
                 }
                 for (int j = i - 2; j >= 0; --j) {  // backward: middle c_{j+1} .. c_{i-1}
                     const int cJ = node(j), cJ1 = node(j + 1);
                     if (TW) mid = (j == i - 2) ? Npos(i - 1) : tw_cat(Npos(j + 1), edge(j + 1), mid);
+                    if (PD) lmid = (j == i - 2) ? LNpos(i - 1) : ld_cat(LNpos(j + 1), lmid);
                     const int dVF = d(cJ, cI), dGV = d(cG, cJ1);
                     const int tv =
                         TW ? tw_cat(tw_cat(tw_cat(Fpos(j), dVF, sig), dGV, mid), d(cP, cW), Bafter(g)).v : 0;
-                    score(base + dVF + dGV - edge(j), tv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
+                    const int lv = excess(ld_cat(ld_cat(ld_cat(LFpos(j), lsig), lmid), LBafter(g)));
+                    rec(base + dVF + dGV - edge(j), tv, lv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
                 }
             }
         }
@@ -2087,6 +2218,31 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+// Granular mode with both operator kinds in one launch (as k_eval_solution):
+// workgroups below nintra take the intra-route groups (one per group, seven
+// wavefronts with one walk each), the others kInterThreads granular work
+// items each.
+template <bool TW, bool DUMP>
+__global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_gran_fused(
+    const SolDev *__restrict__ sols, const int32_t *__restrict__ gsrc, const int32_t *__restrict__ gadj, int gcc,
+    int gdep, const IntraItem *__restrict__ intra, int nintra, uint32_t op_mask, int32_t *__restrict__ dump_delta,
+    uint8_t *__restrict__ dump_feas) {
+    extern __shared__ int4 smem4[];
+    __shared__ unsigned long long red[kInterWaves];
+    __shared__ long long cnt_sh;
+    const SolDev &S = sols[0];
+    if (skip_solution(S, op_mask)) return;  // uniform for the grid
+    if ((int)blockIdx.x < nintra) {
+        const int wave = threadIdx.x >> 6;
+        int *region = (int *)smem4 + wave * (kIntraRegionBytes / 4);
+        if (wave < kIntraWalks)
+            intra_group<TW, DUMP, true>(S, intra[blockIdx.x], op_mask, wave, dump_delta, dump_feas, region);
+        return;
+    }
+    gran_block<TW, DUMP>(S, gsrc, gadj, gcc, gdep, ((int)blockIdx.x - nintra) * blockDim.x + threadIdx.x, op_mask,
+                         dump_delta, dump_feas, red, &cnt_sh);
+}
+
 // Batched form: persistent launches evaluate every solution of the batch.
 // PH bit 1: intra-route groups (one wavefront per group of routes); PH bit 0:
 // inter-route items (whole workgroup per item, largest first).  PH = 3 runs
@@ -2273,7 +2429,7 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                 const int rk = d < 0 ? k : rounds - 1 - k;
                 const int src = lo + rk * T + tid;
                 const bool on = src < hi;
-                int4 a = make_int4(0, 0, 0, 0), b = a, t = a, w = a, pf = a, pb = a;
+                int4 a = make_int4(0, 0, 0, 0), b = a, t = a, w = a, pf = a, pb = a, pl = a, ql = a;
                 int pd = 0;
                 if (on) {
                     a = S.a4[src];
@@ -2281,9 +2437,11 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     t = S.t4[src];
                     w = S.w4[src];
                     pd = S.pdist[src];
-                    if (S.pen) {
+                    if (S.pen || S.pd) {
                         pf = S.pf4[src];
                         pb = S.pb4[src];
+                        pl = S.pl4[src];
+                        ql = S.ql4[src];
                     }
                 }
                 __syncthreads();
@@ -2294,9 +2452,11 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     S.t4[dst] = t;
                     S.w4[dst] = w;
                     S.pdist[dst] = pd;
-                    if (S.pen) {
+                    if (S.pen || S.pd) {
                         S.pf4[dst] = pf;
                         S.pb4[dst] = pb;
+                        S.pl4[dst] = pl;
+                        S.ql4[dst] = ql;
                     }
                     const int node = nodeof(a.x);
                     S.ref2slot[(flagsof(a.x) & kFlagCustomer) ? node - 1 : S.n + a.y] = dst;
@@ -2322,11 +2482,11 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
         rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
         if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
     }
-    if (S.pen) {  // summaries of the touched routes, then the totals
+    if (S.pen || S.pd) {  // summaries of the touched routes, then the totals
         __threadfence_block();
         __syncthreads();
-        if (S.has_tw && threadIdx.x == 0) pen_route(S, m.ra);
-        if (S.has_tw && threadIdx.x == 64 && inter) pen_route(S, m.rb);
+        if (threadIdx.x == 0) gen_route(S, m.ra);
+        if (threadIdx.x == 64 && inter) gen_route(S, m.rb);
         __threadfence_block();
         __syncthreads();
         pen_totals(S, sh);
@@ -2479,6 +2639,16 @@ __global__ __launch_bounds__(256) void k_check_nodes(const int4 *__restrict__ nd
 }
 
 // Marks every route's distance-block cache entry empty.
+// Pickup amounts: chk[0] |= 1 for a negative amount or a nonzero depot
+// entry; chk[1] = the largest amount.
+__global__ __launch_bounds__(256) void k_check_pick(const int32_t *__restrict__ pick, int np1, int32_t *chk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np1) return;
+    const int v = pick[i];
+    if (v < 0 || (i == 0 && v != 0)) atomicOr(chk, 1);
+    atomicMax(chk + 1, v);
+}
+
 __global__ void k_route_blocks_clear(int32_t *rblk, int R) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < R) rblk[(size_t)r * kRouteBlockWords] = -1;

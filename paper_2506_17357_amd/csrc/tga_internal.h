@@ -55,7 +55,13 @@ struct SolDev {
     // depot included); weights of load excess and time warp
     int4 *pf4;
     int4 *pb4;
-    int32_t pen, wL, wT, pad1;
+    int32_t pen, wL, wT, pd;  // pd: pickups (VRPSPDTW), evaluated by the same path
+    // pickups: per node amount (borrowed), per slot the load summary
+    // {L_I, L_O, L_M, 0} of the prefix ending at the slot and of the suffix
+    // starting there (Section 4.3.2)
+    const int32_t *pick;
+    int4 *pl4;
+    int4 *ql4;
     // per-solution state
     unsigned long long *best_key;  // running minimum of (delta, id) keys
     int32_t *rec;     // 8 ints: the tga_move_t of the last finalize

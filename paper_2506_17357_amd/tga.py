@@ -65,7 +65,7 @@ EXPORTS = [
     "tga_eval_routes_static", "tga_batch_slots_workspace_bytes", "tga_batch_create_slots",
     "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
     "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
-    "tga_solution_set_penalty", "tga_solution_violations",
+    "tga_solution_set_penalty", "tga_solution_violations", "tga_instance_set_pickups",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
         "tga_batch_slots_workspace_bytes": (sz, [i32, i32, i32]),
         "tga_granular_workspace_bytes": (sz, [i32, i32]),
         "tga_solution_set_penalty": (i32, [P, i32, i32, P]),
+        "tga_instance_set_pickups": (i32, [P, P, P]),
         "tga_solution_violations": (i32, [P, P, P, P]),
         "tga_instance_set_granular": (i32, [P, i32, P, sz, P]),
         "tga_instance_granular_pairs": (i32, [P]),
@@ -193,9 +194,18 @@ class Instance:
         """Bytes per distance the inter-route kernels stream (2 or 4)."""
         return int(lib().tga_instance_dist_bytes(self.h))
 
+    def set_pickups(self, pickup, stream=None):
+        """Pickup amount per node (VRPSPDTW); solutions set up afterwards use it."""
+        self.pickup = torch.as_tensor(np.ascontiguousarray(pickup, dtype=np.int32)).to(self.dist.device) \
+            if not isinstance(pickup, torch.Tensor) else pickup
+        _check(lib().tga_instance_set_pickups(self.h, _dev_ptr(self.pickup), _stream(stream)))
+
     @staticmethod
     def from_workload(inst, device="cuda", stream=None) -> "Instance":
-        return Instance(inst.n, inst.dist, inst.node4, inst.capacity, inst.has_tw, device, stream)
+        I = Instance(inst.n, inst.dist, inst.node4, inst.capacity, inst.has_tw, device, stream)
+        if getattr(inst, "pickup", None) is not None:
+            I.set_pickups(inst.pickup, stream)
+        return I
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

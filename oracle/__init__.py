@@ -19,7 +19,14 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OPS_ALL = 0x1F
+OPS_EXT = 0xE0  # segment relocate (op 5), reversed relocate (op 6), cross-exchange (ops 7..9)
 NOT_A_MOVE = 0xFF
+
+
+def id_span(op_mask: int) -> int:
+    """Move ids are below id_span * Q^2: 20 for operators 0..4, 40 with the
+    operator variants (ops 5..9)."""
+    return 40 if op_mask & OPS_EXT else 20
 
 
 def build(force: bool = True) -> str:
@@ -119,8 +126,9 @@ def eval_neighbourhood(inst, sol, op_mask: int = OPS_ALL, threads: int = 0,
     Q = inst.n + off.shape[0] - 1
     dd = df = None
     if dump:
-        dd = np.zeros(20 * Q * Q, np.int32)
-        df = np.full(20 * Q * Q, NOT_A_MOVE, np.uint8)
+        span = id_span(op_mask) * Q * Q
+        dd = np.zeros(span, np.int32)
+        df = np.full(span, NOT_A_MOVE, np.uint8)
     bd = np.zeros(1, np.int64)
     bid = np.zeros(1, np.uint32)
     mv = np.zeros(1, np.int64)

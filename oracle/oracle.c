@@ -70,6 +70,17 @@
  *                       the same route not inside [pred(a), last of segment]:
  *                       the segment is moved, in its orientation, to right
  *                       after b.
+ * Operator variants (the extensions Section 4.1 and Section 7 name: segments
+ * of N > 1 nodes in inter-route moves, reversed insertion, cross-exchange):
+ *   op 5 SEGMENT RELOCATE   k=2,3  the k-node segment starting at customer a
+ *                       moves, orientation kept, right after ref b of another
+ *                       route.
+ *   op 6 REVERSED RELOCATE  k=2,3  the same with the segment reversed.
+ *   op 7..9 CROSS-EXCHANGE  the segment of op-6 nodes starting at customer a
+ *                       and the segment of k = 1..3 nodes starting at customer
+ *                       b (a < b, different routes) exchange places, each in
+ *                       its orientation; op 7 with k = 1 is SWAP and is left
+ *                       out.
  * Refs: customer c -> c - 1; start depot of route r -> n + r; Q = n + R.
  * Move id = ((op * 4 + k) * Q + a) * Q + b.
  */
@@ -334,6 +345,39 @@ static int edit_move(const Inst *I, const Sol *S, const Index *X, Move m,
         *L1 = LA;
         return 1;
     }
+    if (m.op == 5 || m.op == 6) { /* segment of k from route A to right after b in route B */
+        const int k = m.k;
+        int32_t seg[3];
+        for (int q = 0; q < k; q++) seg[q] = A[pa - 1 + (m.op == 5 ? q : k - 1 - q)];
+        int l = 0;
+        for (int i = 0; i < LA; i++)
+            if (i < pa - 1 || i >= pa - 1 + k) out1[l++] = A[i];
+        *L1 = l;
+        l = 0;
+        if (m.b >= n)
+            for (int q = 0; q < k; q++) out2[l++] = seg[q];
+        for (int i = 0; i < LB; i++) {
+            out2[l++] = B[i];
+            if (B[i] == m.b + 1)
+                for (int q = 0; q < k; q++) out2[l++] = seg[q];
+        }
+        *L2 = l;
+        return 2;
+    }
+    if (m.op >= 7) { /* cross-exchange: segment (a, op-6) <-> segment (b, k) */
+        const int ka = m.op - 6, kb = m.k;
+        int l = 0;
+        for (int i = 0; i < pa - 1; i++) out1[l++] = A[i];
+        for (int q = 0; q < kb; q++) out1[l++] = B[pb - 1 + q];
+        for (int i = pa - 1 + ka; i < LA; i++) out1[l++] = A[i];
+        *L1 = l;
+        l = 0;
+        for (int i = 0; i < pb - 1; i++) out2[l++] = B[i];
+        for (int q = 0; q < ka; q++) out2[l++] = A[pa - 1 + q];
+        for (int i = pb - 1 + kb; i < LB; i++) out2[l++] = B[i];
+        *L2 = l;
+        return 2;
+    }
     /* op 4 OR-OPT: remove segment of k starting at a, reinsert after b */
     {
         int k = m.k;
@@ -430,7 +474,7 @@ static void run_task(Ctx *C, int tid, int t, int32_t *b1, int32_t *b2) {
     const Sol *S = C->S;
     const Index *X = C->X;
     int op = t / Q, a = t % Q;
-    if (op > 6) return;
+    if (op > 11) return;
     if (op == 0 && (C->op_mask & 1) && a < n) {
         int ra = X->route_of[a + 1];
         for (int b = 0; b < Q; b++) {
@@ -457,7 +501,32 @@ static void run_task(Ctx *C, int tid, int t, int32_t *b1, int32_t *b2) {
         int ra = X->route_of[a + 1];
         for (int b = a + 1; b < n; b++)
             if (X->route_of[b + 1] == ra) consider(C, tid, (Move){3, 0, a, b}, b1, b2);
-    } else if (op >= 4 && (C->op_mask & 16) && a < n) {
+    } else if ((op == 7 || op == 8) && (C->op_mask & (32 | 64)) && a < n) {
+        int k = op - 5; /* 2, 3 */
+        int ra = X->route_of[a + 1], pa = X->pos_of[a + 1];
+        if (pa + k - 1 > S->off[ra + 1] - S->off[ra]) return;
+        for (int b = 0; b < Q; b++) {
+            int rb, pb;
+            ref_where(X, b, &rb, &pb);
+            if (rb == ra) continue;
+            if (C->op_mask & 32) consider(C, tid, (Move){5, k, a, b}, b1, b2);
+            if (C->op_mask & 64) consider(C, tid, (Move){6, k, a, b}, b1, b2);
+        }
+    } else if (op >= 9 && (C->op_mask & 128) && a < n) {
+        int ka = op - 8; /* 1..3 */
+        int ra = X->route_of[a + 1], pa = X->pos_of[a + 1];
+        if (pa + ka - 1 > S->off[ra + 1] - S->off[ra]) return;
+        for (int b = a + 1; b < n; b++) {
+            int rb = X->route_of[b + 1], pb = X->pos_of[b + 1];
+            if (rb == ra) continue;
+            int Lb = S->off[rb + 1] - S->off[rb];
+            for (int kb = 1; kb <= 3; kb++) {
+                if (ka == 1 && kb == 1) continue;
+                if (pb + kb - 1 > Lb) break;
+                consider(C, tid, (Move){6 + ka, kb, a, b}, b1, b2);
+            }
+        }
+    } else if (op >= 4 && op <= 6 && (C->op_mask & 16) && a < n) {
         int k = op - 3; /* 1..3 */
         int r = X->route_of[a + 1], i = X->pos_of[a + 1];
         int L = S->off[r + 1] - S->off[r];
@@ -496,7 +565,7 @@ static int resolve_threads(int nthreads) {
 
 /* Evaluate N(S) restricted to op_mask.  Returns 1 if an admissible move
  * exists (written to *best_*), 0 otherwise.  Optional dumps are indexed by
- * move id and must hold 20 * Q * Q entries; entries that are not moves are
+ * move id and must hold 20 * Q * Q entries (40 * Q * Q with ops 5..9); entries that are not moves are
  * left untouched.  *moves receives |N(S)| for the enabled operators. */
 static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
                      int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
@@ -521,7 +590,7 @@ static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_
     C.dump_delta = dump_delta;
     C.dump_feas = dump_feas;
     C.nthreads = T;
-    C.ntasks = 7 * X.Q;
+    C.ntasks = 12 * X.Q;
     C.best = calloc((size_t)T, sizeof(Best));
     C.count = calloc((size_t)T, sizeof(int64_t));
     pthread_t *th = malloc(sizeof(pthread_t) * T);
@@ -588,7 +657,7 @@ int oracle_apply(int n, const int32_t *D, const int32_t *node4, int64_t cap, int
     int Q = X.Q;
     Move m = move_decode(Q, id);
     int ok = 1;
-    if (m.a >= Q || m.b >= Q || m.op > 4) ok = 0;
+    if (m.a >= Q || m.b >= Q || m.op > 9) ok = 0;
     int ra = 0, pa = 0, rb = 0, pb = 0;
     if (ok) {
         ref_where(&X, m.a, &ra, &pa);
@@ -603,6 +672,14 @@ int oracle_apply(int n, const int32_t *D, const int32_t *node4, int64_t cap, int
             ok = m.k >= 1 && m.k <= 3 && m.a < n && ra == rb && pa + m.k - 1 <= La &&
                  !(pb >= pa - 1 && pb <= pa + m.k - 1);
             break;
+        case 5:
+        case 6: ok = m.k >= 2 && m.k <= 3 && m.a < n && ra != rb && pa + m.k - 1 <= La; break;
+        default: {
+            const int Lb = off[rb + 1] - off[rb];
+            ok = m.k >= 1 && m.k <= 3 && m.a < m.b && m.b < n && ra != rb && pa + (m.op - 6) - 1 <= La &&
+                 pb + m.k - 1 <= Lb && !(m.op == 7 && m.k == 1);
+            break;
+        }
         }
     }
     if (!ok) {

@@ -115,11 +115,60 @@ def neighbours(inst, routes, op_mask=0x1F):
                         yield mid(4, k, seg[0] - 1, b), new, (r,)
 
 
+def neighbours_ext(inst, routes, op_mask):
+    """Operator variants (ops 5..9), enumerated by segment start index and
+    insertion index: (id, new_routes, touched_slots)."""
+    n = inst.n
+    R = len(routes)
+    Q = n + R
+
+    def mid(op, k, a, b):
+        return ((op * 4 + k) * Q + a) * Q + b
+
+    for r1 in range(R):
+        A = routes[r1]
+        for k in (2, 3):
+            for s0 in range(len(A) - k + 1):
+                seg = A[s0:s0 + k]
+                for r2 in range(R):
+                    if r2 == r1:
+                        continue
+                    B = routes[r2]
+                    for idx in range(len(B) + 1):
+                        b = n + r2 if idx == 0 else B[idx - 1] - 1
+                        for op, piece in ((5, seg), (6, seg[::-1])):
+                            if not op_mask & (32 if op == 5 else 64):
+                                continue
+                            new = [list(x) for x in routes]
+                            new[r1] = A[:s0] + A[s0 + k:]
+                            new[r2] = B[:idx] + list(piece) + B[idx:]
+                            yield mid(op, k, seg[0] - 1, b), new, (r1, r2)
+    if op_mask & 128:
+        for r1 in range(R):
+            for r2 in range(R):
+                if r1 == r2:
+                    continue
+                A, B = routes[r1], routes[r2]
+                for i in range(len(A)):
+                    for j in range(len(B)):
+                        if A[i] >= B[j]:
+                            continue  # the segment starting at the lower customer comes first
+                        for ka in (1, 2, 3):
+                            for kb in (1, 2, 3):
+                                if (ka, kb) == (1, 1) or i + ka > len(A) or j + kb > len(B):
+                                    continue
+                                new = [list(x) for x in routes]
+                                new[r1] = A[:i] + B[j:j + kb] + A[i + ka:]
+                                new[r2] = B[:j] + A[i:i + ka] + B[j + kb:]
+                                yield mid(6 + ka, kb, A[i] - 1, B[j] - 1), new, (r1, r2)
+
+
 def evaluate_all(inst, routes, op_mask=0x1F):
     """dict id -> (delta, feas, new_routes)."""
     base = total_cost(inst, routes)
     out = {}
-    for mid, new, touched in neighbours(inst, routes, op_mask):
+    gen = itertools.chain(neighbours(inst, routes, op_mask), neighbours_ext(inst, routes, op_mask))
+    for mid, new, touched in gen:
         feas = 0
         if all(route_ok_cap(inst, new[r]) for r in touched):
             feas |= 1

@@ -72,12 +72,26 @@ enum {
     TGA_OP_2OPT = 1u << 3,
     TGA_OP_OROPT = 1u << 4,
     TGA_OP_ALL = 0x1Fu,
+    /* operator variants (general path only, tga_solution_set_general):
+     *   op 5 SEGMENT RELOCATE  k=2,3: the k-segment starting at customer a
+     *        moves, orientation kept, right after ref b of another route
+     *   op 6 REVERSED RELOCATE k=2,3: the same, the segment reversed
+     *   op 7..9 CROSS-EXCHANGE: the (op-6)-segment starting at customer a and
+     *        the k-segment (k=1..3) starting at customer b (a < b, different
+     *        routes) exchange places, each in its orientation (op 7, k=1 is
+     *        SWAP and is left out) */
+    TGA_OP_SEGREL = 1u << 5,
+    TGA_OP_SEGREL_REV = 1u << 6,
+    TGA_OP_CROSS = 1u << 7,
+    TGA_OP_VARIANTS = 0xE0u,
     /* modifier: inter-route operators restricted to the granular pairs of the
      * instance (tga_instance_set_granular); single-solution calls only */
-    TGA_OP_GRANULAR = 1u << 5
+    TGA_OP_GRANULAR = 1u << 16
 };
 
 #define TGA_MAX_Q 14654
+/* with the operator variants ids reach 40*Q*Q */
+#define TGA_MAX_Q_VARIANTS 10362
 
 typedef struct tga_instance *tga_instance_t;
 typedef struct tga_solution *tga_solution_t;
@@ -254,7 +268,16 @@ int tga_get_solution(tga_solution_t sol, int32_t *offsets, int32_t *customers, i
  * Synchronises `stream`. */
 int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int32_t w_tw, void *stream);
 
-/* Penalised mode: total load excess and total time warp of the current
+/* General path on (on = 1) or off (0): evaluations concatenate per-slot
+ * time-warp and load summaries per pair of slots and per intra-route walk
+ * (the kernels penalised mode and pickups use), which the operator variants
+ * (TGA_OP_SEGREL, TGA_OP_SEGREL_REV, TGA_OP_CROSS; n + R <=
+ * TGA_MAX_Q_VARIANTS, dumps of 40*Q*Q entries) require.  Results of the
+ * five base operators are identical on either path.  Synchronises
+ * `stream`. */
+int tga_solution_set_general(tga_solution_t sol, int32_t on, void *stream);
+
+/* General path: total load excess and total time warp of the current
  * solution (nullable outputs).  Synchronises `stream`. */
 int tga_solution_violations(tga_solution_t sol, int64_t *load_excess, int64_t *time_warp, void *stream);
 

@@ -807,7 +807,7 @@ static void to_move(const int32_t *rec, tga_move_t *m) {
 template <bool TW, bool PD>
 static void launch_eval_gen(const tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
     const bool dump = dd != nullptr;
-    if (op_mask & 7) {
+    if (op_mask & (7 | TGA_OP_VARIANTS)) {
         const int tiles = (sol->Q + 15) / 16, grid = tiles * (tiles + 1) / 2;
         if (dump) k_eval_pen_pairs<TW, PD, true><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
         else k_eval_pen_pairs<TW, PD, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
@@ -832,7 +832,7 @@ static void launch_eval_pen(const tga_solution *sol, uint32_t op_mask, int32_t *
 // Launch one evaluation of a solution (penalised, granular or full
 // neighbourhood).
 static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *dd, uint8_t *df, hipStream_t st) {
-    if (sol->h.pen || sol->h.pd)
+    if (sol->h.pen || sol->h.pd || sol->h.gen)
         launch_eval_pen(sol, op_mask, dd, df, st);
     else if (op_mask & TGA_OP_GRANULAR)
         launch_eval_gran(sol->inst, sol->d, sol->R, sol->intra, sol->nintra, sol->h.has_tw, op_mask, dd, df, st);
@@ -844,11 +844,18 @@ static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *d
 // Operator mask of a single-solution call: the five operators plus the
 // granular modifier (only once the instance has its granular pairs).
 static int check_mask(const tga_solution *sol, uint32_t op_mask) {
-    if (op_mask & ~(TGA_OP_ALL | TGA_OP_GRANULAR)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_VARIANTS | TGA_OP_GRANULAR))
+        return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & TGA_OP_VARIANTS) {
+        if (!(sol->h.pen || sol->h.pd || sol->h.gen))
+            return fail(TGA_EINVAL, "operator variants need the general path (tga_solution_set_general)");
+        if (sol->Q > TGA_MAX_Q_VARIANTS)
+            return fail(TGA_ERANGE, "operator variants need n + R <= %d (move ids below 2^32)", TGA_MAX_Q_VARIANTS);
+    }
     if ((op_mask & TGA_OP_GRANULAR) && !sol->inst->gnnz)
         return fail(TGA_EINVAL, "TGA_OP_GRANULAR before tga_instance_set_granular");
-    if ((op_mask & TGA_OP_GRANULAR) && (sol->h.pen || sol->h.pd))
-        return fail(TGA_EINVAL, "TGA_OP_GRANULAR with penalised scoring or pickups is not supported");
+    if ((op_mask & TGA_OP_GRANULAR) && (sol->h.pen || sol->h.pd || sol->h.gen))
+        return fail(TGA_EINVAL, "TGA_OP_GRANULAR on the general path (penalties, pickups, variants) is not supported");
     return TGA_OK;
 }
 
@@ -879,9 +886,22 @@ extern "C" int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int3
     return TGA_OK;
 }
 
+extern "C" int tga_solution_set_general(tga_solution_t sol, int32_t on, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    if (on != 0 && on != 1) return fail(TGA_EINVAL, "on must be 0 or 1");
+    sol->h.gen = on;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(sol->d, &sol->h, sizeof(SolDev), hipMemcpyHostToDevice, st));
+    k_pen_init<<<1, kApplyThreads, 0, st>>>(sol->d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return TGA_OK;
+}
+
 extern "C" int tga_solution_violations(tga_solution_t sol, int64_t *load_excess, int64_t *time_warp, void *stream) {
     if (!sol) return fail(TGA_EINVAL, "null solution");
-    if (!sol->h.pen) return fail(TGA_EINVAL, "the solution is not in penalised mode");
+    if (!(sol->h.pen || sol->h.pd || sol->h.gen)) return fail(TGA_EINVAL, "the solution is not on the general path");
     hipStream_t st = (hipStream_t)stream;
     long long v[2];
     HIPCHK(hipMemcpyAsync(v, sol->h.acc + kAccLoadExcess, 16, hipMemcpyDeviceToHost, st));
@@ -986,7 +1006,7 @@ extern "C" int tga_apply_move(tga_solution_t sol, const tga_move_t *move, int64_
     if (move->version != sol->version)
         return fail(TGA_ESTALE, "move version %u != solution version %u", move->version, sol->version);
     const uint64_t qq = (uint64_t)sol->Q * sol->Q;
-    if ((uint64_t)move->id >= 20 * qq) return fail(TGA_EINVAL, "move id %u out of range", move->id);
+    if ((uint64_t)move->id >= 40 * qq) return fail(TGA_EINVAL, "move id %u out of range", move->id);
     hipStream_t st = (hipStream_t)stream;
     void *pin;
     int rc = pinned(&pin);
@@ -1161,15 +1181,11 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
 // LDS sub-block, or for large solutions (fewer than kItemRowsMin rows per
 // sub-block) several whole sub-blocks, so that the two boundary rows carried
 // from one sub-block to the next spare re-reading them (a one-row sub-block
-// would otherwise read every row three times) — but never so few items that
-// the workgroups the solution's share of the work occupies (wgs) get fewer
-// than four items each (long items of a triangle balance badly).
+// would otherwise read every row three times).
 constexpr int kItemRowsMin = 16;
-static int default_item_rows(int tile_rows, int Q, double wgs) {
+static int default_item_rows(int tile_rows) {
     if (tile_rows >= kItemRowsMin) return tile_rows;
-    const int want = (kItemRowsMin + tile_rows - 1) / tile_rows;           // sub-blocks per item
-    const int cap = (int)std::floor(Q / (4.0 * std::max(1.0, wgs)) / tile_rows);  // keeps >= 4 items per wg
-    return tile_rows * std::max(1, std::min(want, cap));
+    return tile_rows * ((kItemRowsMin + tile_rows - 1) / tile_rows);
 }
 
 // Rows per LDS sub-block for an LDS budget of `budget` bytes.
@@ -1275,13 +1291,9 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     std::vector<std::vector<InterItem>> own(count);
     std::vector<double> sol_work(count, 0.0);
     double total = 0.0;
-    double pairs_all = 0.0;  // the pair count of each solution estimates its share of the launch
-    for (int i = 0; i < count; ++i)
-        if (v[i]) pairs_all += 0.5 * (double)v[i]->Q * v[i]->Q;
     for (int i = 0; i < count; ++i) {
         if (!v[i]) continue;
-        const double wgs = grid_inter * (0.5 * (double)v[i]->Q * v[i]->Q) / std::max(1.0, pairs_all);
-        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i], v[i]->Q, wgs),
+        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i]),
                       [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
         for (const auto &it : own[i]) sol_work[i] += (double)work(it);
         total += sol_work[i];
@@ -1486,8 +1498,8 @@ extern "C" int tga_batch_create(const tga_solution_t *sols, int32_t count, int32
     for (auto *s : v) {
         if (!s) return fail(TGA_EINVAL, "null solution in batch");
         if (s->in_batch) return fail(TGA_EINVAL, "solution already in a batch");
-        if (s->h.pen || s->h.pd)
-            return fail(TGA_EINVAL, "penalised solutions and pickups are evaluated one at a time");
+        if (s->h.pen || s->h.pd || s->h.gen)
+            return fail(TGA_EINVAL, "solutions on the general path are evaluated one at a time");
     }
     for (size_t i = 0; i < v.size(); ++i)
         for (size_t j = i + 1; j < v.size(); ++j)
@@ -1549,8 +1561,8 @@ extern "C" int tga_batch_set_members(tga_batch_t B, const tga_solution_t *sols, 
         bool ours = false;
         for (auto *o : B->sols) ours = ours || o == s;
         if (s->in_batch && !ours) return fail(TGA_EINVAL, "solution in slot %d belongs to another batch", i);
-        if (s->h.pen || s->h.pd)
-            return fail(TGA_EINVAL, "penalised solutions and pickups are evaluated one at a time");
+        if (s->h.pen || s->h.pd || s->h.gen)
+            return fail(TGA_EINVAL, "solutions on the general path are evaluated one at a time");
         for (int j = 0; j < i; ++j)
             if (sols[j] == s) return fail(TGA_EINVAL, "solution listed in slots %d and %d", j, i);
         sq += s->Q;

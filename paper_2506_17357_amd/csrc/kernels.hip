@@ -101,7 +101,7 @@ constexpr uint32_t kImprovingOnly = 1u << 31;
 
 // Operator-mask modifier (TGA_OP_GRANULAR): inter-route operators restricted
 // to the granular pairs of the instance.
-constexpr uint32_t kGranular = 1u << 5;
+constexpr uint32_t kGranular = 1u << 16;
 
 __device__ __forceinline__ int initial_bound(uint32_t op_mask) {
     return (op_mask & kImprovingOnly) ? 0 : kAdmissibleBound;
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
     __shared__ ApplyShared sh;
     const SolDev &S = sols[blockIdx.x];
     rebuild(S, S.nr_alt, S.roff_alt, sh);
-    if (S.pen || S.pd) pen_all(S, sh);
+    if (S.pen || S.pd || S.gen) pen_all(S, sh);
     if (threadIdx.x == 0) {
         *S.best_key = ~0ull;
         S.state[kStDone] = 0;
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_build(const SolDev *__restric
 __global__ __launch_bounds__(kApplyThreads) void k_pen_init(const SolDev *__restrict__ sols) {
     __shared__ ApplyShared sh;
     const SolDev &S = sols[blockIdx.x];
-    if (S.pen || S.pd) pen_all(S, sh);
+    if (S.pen || S.pd || S.gen) pen_all(S, sh);
 }
 
 // ------------------------------------------------------ inter-route eval ---
@@ -1458,7 +1458,7 @@ __device__ __forceinline__ Ld ld_after(const SolDev &S, int x) {
 // The four inter-route moves of slots x, t (route(x) < route(t)).
 template <bool TW, bool PD, bool DUMP>
 __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t op_mask, int32_t *dd, uint8_t *df,
-                                         int &bd, uint32_t &bid) {
+                                         int &bd, uint32_t &bid, int &cntExt) {
     const int np1 = S.np1, n = S.n, cap = S.cap;
     const int32_t *D = S.D;
     const uint32_t uQ = (uint32_t)S.Q;
@@ -1535,6 +1535,102 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
         const int lt = PD ? ld_cat(Pt, Sax).lm : bt.y + (Lx - bx.y);
         rec(dD, lx, lt, tvx, tvt, (8u * uQ + lo) * uQ + hi);
     }
+    if (!(op_mask & 0xE0u)) return;
+    // ---- operator variants: segments of up to three customers starting at
+    // x and at t (kept and reversed summaries, the slot after each segment)
+    struct Seg3 {
+        int k;         // customers available from the slot on, within its route (<= 3)
+        int node[3];   // the segment's nodes
+        int after[3];  // node after the first k customers (0: the end depot)
+        int dem[3];    // deliveries of the first k customers
+        Tw f[3], r[3];
+        Ld lf[3], lr[3];
+        Tw sa[3];
+        Ld la[3];
+    };
+    auto seg3 = [&](int y, Seg3 &g) {
+        const int last = gld(S.roff + gld(S.a4 + y).y + 1) - 1;
+        g.k = min(3, last - y + 1);
+        int dsum = 0;
+        for (int q = 0; q < 3; ++q) {
+            const bool in = q < g.k;
+            g.node[q] = in ? nodeof(gld(S.a4 + y + q).x) : 0;
+            g.after[q] = in ? nodeof(gld(S.a4 + y + q + 1).x) : 0;
+            dsum += in ? gld(S.b4 + y + q).x : 0;
+            g.dem[q] = dsum;
+            if (!in) continue;
+            if (TW) {
+                const Tw nq = tw_node_at(S, y + q);
+                g.f[q] = q == 0 ? nq : tw_cat(g.f[q - 1], gld(S.a4 + y + q - 1).z, nq);
+                g.r[q] = q == 0 ? nq : tw_cat(nq, gld(S.a4 + y + q - 1).z, g.r[q - 1]);
+                g.sa[q] = tw_after(S, y + q, dep);
+            }
+            if (PD) {
+                const Ld lq = ld_node_at(S, y + q);
+                g.lf[q] = q == 0 ? lq : ld_cat(g.lf[q - 1], lq);
+                g.lr[q] = q == 0 ? lq : ld_cat(lq, g.lr[q - 1]);
+                g.la[q] = ld_after(S, y + q);
+            }
+        }
+    };
+    Seg3 gx, gt;
+    if (cx) seg3(x, gx);
+    if (ct) seg3(t, gt);
+    // SEGMENT RELOCATE (op 5 kept, op 6 reversed), k = 2, 3: a segment of
+    // route `from` (predecessor np, prefix summaries Fp / Pp, route load
+    // Lf) moves right after slot y of route `to` (node ny, successor ns,
+    // prefix Fy / Py, suffix after it Bay / Say, route load Lto).
+    auto segrel = [&](const Seg3 &g, int np, const Tw &Fp, const Ld &Pp, int Lf, int ny, int ns, const Tw &Fy,
+                      const Ld &Py, const Tw &Bay, const Ld &Say, int Lto, bool fromIsX, uint32_t refA,
+                      uint32_t refB) {
+        for (int k = 2; k <= g.k; ++k) {
+            const int f = g.node[0], gl = g.node[k - 1], na = g.after[k - 1];
+            const int cut = d(np, na) - d(np, f) - d(gl, na);
+            for (int op = 5; op <= 6; ++op) {
+                if (!(op_mask & (op == 5 ? 32u : 64u))) continue;
+                const int first = op == 5 ? f : gl, lastn = op == 5 ? gl : f;
+                const int dD = cut + d(ny, first) + d(lastn, ns) - d(ny, ns);
+                int tvFrom = 0, tvTo = 0;
+                if (TW) {
+                    tvFrom = tw_cat(Fp, d(np, na), g.sa[k - 1]).v;
+                    tvTo = tw_cat(tw_cat(Fy, d(ny, first), op == 5 ? g.f[k - 1] : g.r[k - 1]), d(lastn, ns), Bay).v;
+                }
+                const int lFrom = PD ? ld_cat(Pp, g.la[k - 1]).lm : Lf - g.dem[k - 1];
+                const int lTo = PD ? ld_cat(ld_cat(Py, op == 5 ? g.lf[k - 1] : g.lr[k - 1]), Say).lm : Lto + g.dem[k - 1];
+                const uint32_t id = (((uint32_t)op * 4u + (uint32_t)k) * uQ + refA) * uQ + refB;
+                if (fromIsX)
+                    rec(dD, lFrom, lTo, tvFrom, tvTo, id);
+                else
+                    rec(dD, lTo, lFrom, tvTo, tvFrom, id);
+                ++cntExt;
+            }
+        }
+    };
+    if (cx) segrel(gx, npx, Fpx, Ppx, Lx, nt, nst, Ft, Pt, Bat, Sat, Lt, true, (uint32_t)refX, (uint32_t)refT);
+    if (ct) segrel(gt, npt, Fpt, Ppt, Lt, nx, nsx, Fx, Px, Bax, Sax, Lx, false, (uint32_t)refT, (uint32_t)refX);
+    // CROSS-EXCHANGE (ops 7..9): x's first ka customers and t's first kb
+    if ((op_mask & 128u) && cx && ct) {
+        for (int ka = 1; ka <= gx.k; ++ka)
+            for (int kb = 1; kb <= gt.k; ++kb) {
+                if (ka == 1 && kb == 1) continue;
+                const int xl = gx.node[ka - 1], xa = gx.after[ka - 1], tl = gt.node[kb - 1], ta = gt.after[kb - 1];
+                const int dD = d(npx, nt) + d(tl, xa) + d(npt, nx) + d(xl, ta) - d(npx, nx) - d(xl, xa) -
+                               d(npt, nt) - d(tl, ta);
+                int tvx = 0, tvt = 0;
+                if (TW) {
+                    tvx = tw_cat(tw_cat(Fpx, d(npx, nt), gt.f[kb - 1]), d(tl, xa), gx.sa[ka - 1]).v;
+                    tvt = tw_cat(tw_cat(Fpt, d(npt, nx), gx.f[ka - 1]), d(xl, ta), gt.sa[kb - 1]).v;
+                }
+                const int lx = PD ? ld_cat(ld_cat(Ppx, gt.lf[kb - 1]), gx.la[ka - 1]).lm
+                                  : Lx - gx.dem[ka - 1] + gt.dem[kb - 1];
+                const int lt = PD ? ld_cat(ld_cat(Ppt, gx.lf[ka - 1]), gt.la[kb - 1]).lm
+                                  : Lt - gt.dem[kb - 1] + gx.dem[ka - 1];
+                const bool xFirst = refX < refT;
+                const uint32_t op = 6u + (uint32_t)(xFirst ? ka : kb), k = (uint32_t)(xFirst ? kb : ka);
+                rec(dD, lx, lt, tvx, tvt, ((op * 4u + k) * uQ + lo) * uQ + hi);
+                ++cntExt;
+            }
+    }
 }
 
 // Inter-route pairs: 16 x 16 tiles of (row slot, column slot) on and above
@@ -1554,8 +1650,18 @@ __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict
     const int x = bi * 16 + (threadIdx.x >> 4), t = bj * 16 + (threadIdx.x & 15);
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
+    int ext = 0;  // operator-variant moves of this thread's pair
     if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y)
-        pen_pair<TW, PD, DUMP>(S, x, t, op_mask, dd, df, bd, bid);
+        pen_pair<TW, PD, DUMP>(S, x, t, op_mask, dd, df, bd, bid, ext);
+    if (op_mask & 0xE0u) {  // one atomic per workgroup
+        __shared__ int ext_sh;
+        if (threadIdx.x == 0) ext_sh = 0;
+        __syncthreads();
+        for (int off = 32; off >= 1; off >>= 1) ext += __shfl_xor(ext, off);
+        if ((threadIdx.x & 63) == 0 && ext) atomicAdd(&ext_sh, ext);
+        __syncthreads();
+        if (threadIdx.x == 0 && ext_sh) atomicAdd((unsigned long long *)(S.acc + kAccExtMoves), (unsigned long long)ext_sh);
+    }
     block_argmin_commit(bd, bid, S.best_key, red);
 }
 
@@ -2339,6 +2445,28 @@ __device__ __forceinline__ int new_node(const SolDev &S, const MoveInfo &m, int 
         const int i = min(m.pa, m.pb), j = max(m.pa, m.pb);
         return (p >= i && p <= j) ? old_node(S, r, i + j - p) : old_node(S, r, p);
     }
+    case 5:
+    case 6: {  // the k-segment at (ra, pa) moves right after position pb of rb, kept or reversed
+        const int k = m.k;
+        if (r == m.ra) return p < m.pa ? old_node(S, r, p) : old_node(S, r, p + k);
+        if (p <= m.pb) return old_node(S, r, p);
+        if (p > m.pb + k) return old_node(S, r, p - k);
+        const int q = p - m.pb - 1;
+        return old_node(S, m.ra, m.pa + (m.op == 5 ? q : k - 1 - q));
+    }
+    case 7:
+    case 8:
+    case 9: {  // segments (ra, pa, ka) and (rb, pb, kb) exchange places
+        const int ka = m.op - 6, kb = m.k;
+        if (r == m.ra) {
+            if (p < m.pa) return old_node(S, r, p);
+            if (p < m.pa + kb) return old_node(S, m.rb, m.pb + p - m.pa);
+            return old_node(S, r, p - kb + ka);
+        }
+        if (p < m.pb) return old_node(S, r, p);
+        if (p < m.pb + ka) return old_node(S, m.ra, m.pa + p - m.pb);
+        return old_node(S, r, p - ka + kb);
+    }
     default: {
         const int i = m.pa, j = m.pb, k = m.k;
         if (j > i) {  // forward
@@ -2362,7 +2490,7 @@ __device__ __forceinline__ void decode_move(const SolDev &S, uint32_t id, MoveIn
     m.a = (int)(rem / Q);
     m.b = (int)(rem % Q);
     m.valid = 0;
-    if (m.op > 4) return;
+    if (m.op > 9) return;
     const int sa = S.ref2slot[m.a], sb = S.ref2slot[m.b];
     m.ra = S.a4[sa].y;
     m.rb = S.a4[sb].y;
@@ -2392,6 +2520,20 @@ __device__ __forceinline__ void decode_move(const SolDev &S, uint32_t id, MoveIn
         ok = m.k >= 1 && m.k <= 3 && aC && m.ra == m.rb && m.pa + m.k - 1 <= m.La &&
              !(m.pb >= m.pa - 1 && m.pb <= m.pa + m.k - 1);
         break;
+    case 5:
+    case 6:
+        ok = m.k >= 2 && m.k <= 3 && aC && m.ra != m.rb && m.pa + m.k - 1 <= m.La;
+        m.nLa = m.La - m.k;
+        m.nLb = m.Lb + m.k;
+        break;
+    default: {  // 7..9: cross-exchange of (a, op - 6) and (b, k)
+        const int ka = m.op - 6, kb = m.k;
+        ok = kb >= 1 && kb <= 3 && m.a < m.b && bC && m.ra != m.rb && m.pa + ka - 1 <= m.La &&
+             m.pb + kb - 1 <= m.Lb && !(ka == 1 && kb == 1);
+        m.nLa = m.La - ka + kb;
+        m.nLb = m.Lb - kb + ka;
+        break;
+    }
     }
     m.valid = ok;
 }
@@ -2437,7 +2579,7 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     t = S.t4[src];
                     w = S.w4[src];
                     pd = S.pdist[src];
-                    if (S.pen || S.pd) {
+                    if (S.pen || S.pd || S.gen) {
                         pf = S.pf4[src];
                         pb = S.pb4[src];
                         pl = S.pl4[src];
@@ -2452,7 +2594,7 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
                     S.t4[dst] = t;
                     S.w4[dst] = w;
                     S.pdist[dst] = pd;
-                    if (S.pen || S.pd) {
+                    if (S.pen || S.pd || S.gen) {
                         S.pf4[dst] = pf;
                         S.pb4[dst] = pb;
                         S.pl4[dst] = pl;
@@ -2482,7 +2624,7 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
         rebuild_range(S, S.nr_alt, S.roff_alt, baseA, baseA + m.nLa + 1, false, sh);
         if (inter) rebuild_range(S, S.nr_alt, S.roff_alt, baseB, baseB + m.nLb + 1, false, sh);
     }
-    if (S.pen || S.pd) {  // summaries of the touched routes, then the totals
+    if (S.pen || S.pd || S.gen) {  // summaries of the touched routes, then the totals
         __threadfence_block();
         __syncthreads();
         if (threadIdx.x == 0) gen_route(S, m.ra);
@@ -2513,6 +2655,7 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
             *S.best_key = ~0ull;
             if (mode == kModeLS) {
                 long long m = 0;
+                if (op_mask & 0xE0u) m += S.acc[kAccExtMoves];  // operator variants, as counted
                 if (op_mask & kGranular) {  // inter-route moves as counted; intra-route ones complete
                     m = S.acc[kAccGranInter];
                     if (op_mask & 2) m += S.acc[kAccCnt0 + 3];  // same-route swaps: L(L-1)/2 per route, as 2-opt
@@ -2525,6 +2668,7 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
                 S.acc[kAccMoves] += m;
             }
             S.acc[kAccGranInter] = 0;
+            S.acc[kAccExtMoves] = 0;
             if (key == ~0ull) {
                 for (int q = 0; q < 8; ++q) S.rec[q] = 0;
                 S.rec[7] = S.state[kStVersion];

@@ -56,6 +56,7 @@ struct SolDev {
     int4 *pf4;
     int4 *pb4;
     int32_t pen, wL, wT, pd;  // pd: pickups (VRPSPDTW), evaluated by the same path
+    int32_t gen, pad2;        // gen: evaluated by the general path (operator variants)
     // pickups: per node amount (borrowed), per slot the load summary
     // {L_I, L_O, L_M, 0} of the prefix ending at the slot and of the suffix
     // starting there (Section 4.3.2)
@@ -86,7 +87,8 @@ enum {
     kAccGranInter = 7,  // inter-route moves of the granular neighbourhood counted by the last evaluation
     kAccLoadExcess = 8, // penalised mode: total load above capacity
     kAccTimeWarp = 9,   // penalised mode: total time warp
-    kAccCount = 10
+    kAccExtMoves = 10,  // operator-variant moves counted by the last evaluation
+    kAccCount = 11
 };
 
 // Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the

@@ -21,7 +21,9 @@ TGA_OK, TGA_ENOMOVE = 0, 1
 TGA_EINVAL, TGA_ERANGE, TGA_ENOMEM, TGA_EDEVICE, TGA_ESTALE = -1, -2, -3, -4, -5
 OP_RELOCATE, OP_SWAP, OP_2OPTSTAR, OP_2OPT, OP_OROPT = 1, 2, 4, 8, 16
 OPS_ALL = 0x1F
-OP_GRANULAR = 1 << 5  # modifier: inter-route operators on the granular pairs only
+OP_SEGREL, OP_SEGREL_REV, OP_CROSS = 1 << 5, 1 << 6, 1 << 7  # operator variants (general path)
+OPS_VARIANTS = 0xE0
+OP_GRANULAR = 1 << 16  # modifier: inter-route operators on the granular pairs only
 MAX_Q = 14654
 
 _lib = None
@@ -66,6 +68,7 @@ EXPORTS = [
     "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
     "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
     "tga_solution_set_penalty", "tga_solution_violations", "tga_instance_set_pickups",
+    "tga_solution_set_general",
 ]
 
 
@@ -91,6 +94,7 @@ def lib():
         "tga_granular_workspace_bytes": (sz, [i32, i32]),
         "tga_solution_set_penalty": (i32, [P, i32, i32, P]),
         "tga_instance_set_pickups": (i32, [P, P, P]),
+        "tga_solution_set_general": (i32, [P, i32, P]),
         "tga_solution_violations": (i32, [P, P, P, P]),
         "tga_instance_set_granular": (i32, [P, i32, P, sz, P]),
         "tga_instance_granular_pairs": (i32, [P]),
@@ -243,6 +247,11 @@ class Solution:
         admissible); w_load < 0 returns to hard feasibility."""
         _check(lib().tga_solution_set_penalty(self.h, int(w_load), int(w_tw), _stream(stream)))
 
+    def set_general(self, on: bool = True, stream=None):
+        """Evaluate through the general (concatenation) path, which the
+        operator variants need."""
+        _check(lib().tga_solution_set_general(self.h, int(bool(on)), _stream(stream)))
+
     def violations(self, stream=None):
         """(total load excess, total time warp) in penalised mode."""
         lv = ctypes.c_int64()
@@ -261,7 +270,7 @@ class Solution:
         m = Move()
         dd = df = None
         if dump:
-            size = 20 * self.Q * self.Q
+            size = (40 if op_mask & OPS_VARIANTS else 20) * self.Q * self.Q
             dd = torch.zeros(size, dtype=torch.int32, device=self.ws.device)
             df = torch.full((size,), 0xFF, dtype=torch.uint8, device=self.ws.device)
         rc = _check(L.tga_eval_neighborhood(self.h, op_mask, ctypes.byref(m),

@@ -540,6 +540,14 @@ def main():
         "graph and eager passes disagree"
     value = moves_total / t_graph / 1e9
     log("graph: %.3f s -> %.1f GMoves/s" % (t_graph, value))
+    # ---- screening statistics: the same steps with the counting instantiation (untimed)
+    reload_all()
+    st_c, mv_c, cost_c = B.ls_run(K, tga.OPS_ALL | tga.OP_COUNT_FULL, use_graph=False)
+    assert np.array_equal(st_c, st_e) and np.array_equal(mv_c, mv_e) and np.array_equal(cost_c, cost_e), \
+        "counting pass disagrees"
+    screen = B.screen_stats()
+    log("screens: %d of %d inter-route slot pairs evaluated in full (%.5f)" % (
+        screen[0], screen[1], screen[0] / max(1, screen[1])))
     B.close()
 
     out_plain = None
@@ -619,6 +627,12 @@ def main():
             "moves_counted": "every move of N(S) per evaluation (delta of each; feasibility and id only "
                              "where the delta can still be the step's best)",
             "accepted_moves": int(st_e.sum()),
+            "full_eval_fraction": round(screen[0] / max(1, screen[1]), 5),
+            "full_eval_fraction_means": "share of the inter-route slot pairs visited whose RELOCATE / SWAP / "
+                                        "2OPT* moves were evaluated in full (feasibility and ids); the others "
+                                        "were dropped by their deltas or the capacity screen, which never "
+                                        "drops the step's best move (%d of %d pairs; counted in an untimed "
+                                        "pass of the same steps)" % screen,
             "form": "batched: persistent evaluation launch(es) + one finalize launch per step, "
                     "step loop captured in a HIP graph",
             "schedule": schedule,

@@ -86,7 +86,12 @@ enum {
     TGA_OP_VARIANTS = 0xE0u,
     /* modifier: inter-route operators restricted to the granular pairs of the
      * instance (tga_instance_set_granular); single-solution calls only */
-    TGA_OP_GRANULAR = 1u << 16
+    TGA_OP_GRANULAR = 1u << 16,
+    /* modifier (batched local search: tga_batch_ls_run, tga_batch_step_part,
+     * tga_batch_tick): run the instantiation of the evaluation launch that
+     * also counts the slot pairs evaluated in full (tga_batch_screen_stats);
+     * the same results, a few per cent slower */
+    TGA_OP_COUNT_FULL = 1u << 17
 };
 
 #define TGA_MAX_Q 14654
@@ -287,6 +292,44 @@ int tga_solution_violations(tga_solution_t sol, int64_t *load_excess, int64_t *t
 int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32_t *converged,
                        int64_t *moves_evaluated, int64_t *cost, void *stream);
 
+/* Screening counters of the batched local-search evaluations run with
+ * TGA_OP_COUNT_FULL since the last reset (tga_batch_begin, tga_batch_reset,
+ * tga_batch_ls_run), for this solution: pairs[0] = slot pairs of different
+ * routes whose inter-route moves (RELOCATE, SWAP, 2OPT*) were evaluated in
+ * full, feasibility and move ids, because some delta could still reach the
+ * evaluation's best (the argmin of Section 5.3.4 needs the mask only there);
+ * pairs[1] = slot pairs of different routes the same evaluations visited.
+ * Synchronises `stream`. */
+int tga_solution_screen_stats(tga_solution_t sol, int64_t pairs[2], void *stream);
+
+/* Schedules per problem kind and size, as an autotuner measured them (a
+ * table the caller loads, e.g. from a JSON file the tuner wrote): an entry
+ * applies to solutions of its kind (has_tw 0 = CVRP, 1 = with time windows
+ * or pickups) with n <= n_max, the entry with the smallest such n_max
+ * winning.  plain_rows: rows per inter-route item of the single-solution
+ * form (capped by what one workgroup's LDS holds); item_rows: rows per
+ * inter-route item of the batched form (up to one LDS sub-block: thin items;
+ * more: rounded up to whole sub-blocks); 0 keeps the built-in rule.  Results
+ * never depend on the schedule. */
+typedef struct {
+    int32_t has_tw, n_max, plain_rows, item_rows;
+} tga_tune_entry_t;
+
+/* Replace the process-wide table (count = 0 clears it).  It applies to
+ * solutions set up afterwards (tga_set_solution) and to tga_solution_set_rows
+ * with 0 arguments.  TGA_EINVAL for malformed entries.  Thread-safe. */
+int tga_set_tuning(const tga_tune_entry_t *entries, int32_t count);
+
+/* Set the schedule of one solution explicitly (an autotuner trying
+ * candidates): plain_rows / item_rows as in tga_tune_entry_t, 0 = the table's
+ * value or the built-in rule.  Not for a batch member.  Synchronises
+ * `stream`. */
+int tga_solution_set_rows(tga_solution_t sol, int32_t plain_rows, int32_t item_rows, void *stream);
+
+/* The schedule a solution uses (plain_rows after the LDS cap; item_rows 0 =
+ * the built-in rule). */
+int tga_solution_get_rows(tga_solution_t sol, int32_t *plain_rows, int32_t *item_rows);
+
 /* |N(S)| per operator for the current solution (5 entries, host). */
 int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream);
 
@@ -343,6 +386,10 @@ int tga_batch_create(const tga_solution_t *sols, int32_t count, int32_t rows_per
 int tga_batch_ls_run(tga_batch_t b, uint32_t op_mask, int32_t steps, int32_t use_graph,
                      int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost,
                      void *stream);
+
+/* The screening counters of tga_solution_screen_stats summed over the
+ * batch's solutions.  Synchronises `stream`. */
+int tga_batch_screen_stats(tga_batch_t batch, int64_t pairs[2], void *stream);
 
 /* The same loop driven by the caller, one step at a time, so that events or
  * other work can sit between the two launches of a step.

@@ -81,7 +81,8 @@ int props(DevProps *out) {
         const void *fns[] = {(const void *)k_eval_inter<false, false>, (const void *)k_eval_inter<true, false>,
                              (const void *)k_eval_inter<false, true>, (const void *)k_eval_inter<true, true>,
                              (const void *)k_eval_batch<1>, (const void *)k_eval_batch<2>,
-                             (const void *)k_eval_batch<3>,
+                             (const void *)k_eval_batch<3>, (const void *)k_eval_batch<5>,
+                             (const void *)k_eval_batch<7>,
                              (const void *)k_eval_solution<false, false>, (const void *)k_eval_solution<true, false>,
                              (const void *)k_eval_solution<false, true>, (const void *)k_eval_solution<true, true>,
                              (const void *)k_eval_gran_fused<false, false>, (const void *)k_eval_gran_fused<true, false>,
@@ -131,6 +132,22 @@ int default_tile_rows(int np1, bool w16) {
 // the LDS budget.
 int plain_rows(int Q, int np1, bool w16) {
     return std::max(1, std::min(default_tile_rows(np1, w16), (Q + 511) / 512));
+}
+
+// Tuning table (tga_set_tuning): per problem kind, entries sorted by n_max;
+// the first entry of the solution's kind with n <= n_max gives its rows.
+std::mutex g_tune_mu;
+std::vector<tga_tune_entry_t> g_tune;
+
+void tuned_rows(int has_tw, int n, int *plain, int *item) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *plain = *item = 0;
+    for (const tga_tune_entry_t &e : g_tune)
+        if (e.has_tw == has_tw && n <= e.n_max) {
+            *plain = e.plain_rows;
+            *item = e.item_rows;
+            return;
+        }
 }
 
 // Inter-route items of one solution: row blocks of `rows` rows, each against
@@ -184,8 +201,8 @@ SolLayout sol_layout(int n, int R) {
     L.rec = take(32 + 4 * 16 + 8 * kAccCount);
     L.state = L.rec + 32;
     L.acc = L.state + 4 * 16;
-    // the 16-bit matrix only ever allows more rows per item, so size for int32
-    L.max_items = (int)count_items((int)Q, plain_rows((int)Q, n + 1, false));
+    // room for one-row items (the smallest rows per item a schedule may give)
+    L.max_items = (int)Q;
     L.items = take(sizeof(InterItem) * L.max_items);
     L.intra = take(sizeof(IntraItem) * std::max(R, 1));  // at most one group per route
     L.total = off;
@@ -224,6 +241,7 @@ struct tga_solution {
     int nintra;
     int tile_rows;   // rows one workgroup's LDS budget holds (batched form)
     int plain_rows;  // rows per item of the single-solution form
+    int item_rows;   // rows per inter-route item of the batched form (0: the default rule)
     size_t lds;
     uint32_t version;
     int in_batch;
@@ -509,7 +527,10 @@ static int solution_init(tga_solution *S, tga_instance_t inst, int32_t R, const 
     S->Q = Q;
     const bool w16 = inst->D16 != nullptr;
     S->tile_rows = default_tile_rows(np1, w16);
-    S->plain_rows = plain_rows(Q, np1, w16);
+    int t_plain, t_item;
+    tuned_rows(inst->has_tw, n, &t_plain, &t_item);
+    S->plain_rows = t_plain > 0 ? std::min(t_plain, S->tile_rows) : plain_rows(Q, np1, w16);
+    S->item_rows = t_item;
     S->lds = rows_lds(np1, S->plain_rows, w16);
     if (S->lds > (size_t)P.max_lds)
         return fail(TGA_ERANGE, "n = %d needs %zu bytes of LDS per workgroup (device: %d)", n,
@@ -590,6 +611,53 @@ static int solution_init(tga_solution *S, tga_instance_t inst, int32_t R, const 
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(TGA_EDEVICE, "set_solution: %s", hipGetErrorString(e));
+    return TGA_OK;
+}
+
+extern "C" int tga_set_tuning(const tga_tune_entry_t *entries, int32_t count) {
+    if (count < 0 || (count > 0 && !entries)) return fail(TGA_EINVAL, "bad entry list");
+    std::vector<tga_tune_entry_t> t(entries, entries + count);
+    for (const tga_tune_entry_t &e : t)
+        if ((e.has_tw != 0 && e.has_tw != 1) || e.n_max < 1 || e.plain_rows < 0 || e.item_rows < 0 ||
+            e.plain_rows > TGA_MAX_Q || e.item_rows > TGA_MAX_Q)
+            return fail(TGA_EINVAL, "bad tuning entry (has_tw %d, n_max %d, rows %d / %d)", e.has_tw, e.n_max,
+                        e.plain_rows, e.item_rows);
+    std::stable_sort(t.begin(), t.end(), [](const tga_tune_entry_t &a, const tga_tune_entry_t &b) {
+        return a.has_tw != b.has_tw ? a.has_tw < b.has_tw : a.n_max < b.n_max;
+    });
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(t);
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_set_rows(tga_solution_t sol, int32_t plain_rows_, int32_t item_rows, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    if (plain_rows_ < 0 || item_rows < 0 || plain_rows_ > TGA_MAX_Q || item_rows > TGA_MAX_Q)
+        return fail(TGA_EINVAL, "rows out of range");
+    const bool w16 = sol->h.D16 != nullptr;
+    int t_plain, t_item;
+    tuned_rows(sol->inst->has_tw, sol->n, &t_plain, &t_item);
+    if (plain_rows_ == 0) plain_rows_ = t_plain;
+    sol->plain_rows = plain_rows_ > 0 ? std::min(plain_rows_, sol->tile_rows) : plain_rows(sol->Q, sol->n + 1, w16);
+    sol->item_rows = item_rows > 0 ? item_rows : t_item;
+    sol->lds = rows_lds(sol->n + 1, sol->plain_rows, w16);
+    sol->h.tile_rows = sol->plain_rows;
+    std::vector<InterItem> items;
+    std::vector<IntraItem> intra;
+    build_plain_items(sol, items, intra, 0);
+    sol->nitems = (int)items.size();
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(sol->items, items.data(), sizeof(InterItem) * items.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sol->d, &sol->h, sizeof(SolDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_get_rows(tga_solution_t sol, int32_t *plain_rows_, int32_t *item_rows) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (plain_rows_) *plain_rows_ = sol->plain_rows;
+    if (item_rows) *item_rows = sol->item_rows;
     return TGA_OK;
 }
 
@@ -1112,6 +1180,17 @@ extern "C" int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32
     return TGA_OK;
 }
 
+extern "C" int tga_solution_screen_stats(tga_solution_t sol, int64_t pairs[2], void *stream) {
+    if (!sol || !pairs) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    long long v[2];
+    HIPCHK(hipMemcpyAsync(v, sol->h.acc + kAccFullPairs, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pairs[0] = v[0];
+    pairs[1] = v[1];
+    return TGA_OK;
+}
+
 extern "C" int tga_move_counts(tga_solution_t sol, int64_t counts[5], void *stream) {
     if (!sol || !counts) return fail(TGA_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
@@ -1183,7 +1262,9 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
 // from one sub-block to the next spare re-reading them (a one-row sub-block
 // would otherwise read every row three times).
 constexpr int kItemRowsMin = 16;
-static int default_item_rows(int tile_rows) {
+static int default_item_rows(int tile_rows, int tuned) {
+    if (tuned > 0)  // tuned: thin items within one sub-block, else whole sub-blocks
+        return tuned <= tile_rows ? tuned : tile_rows * ((tuned + tile_rows - 1) / tile_rows);
     if (tile_rows >= kItemRowsMin) return tile_rows;
     return tile_rows * ((kItemRowsMin + tile_rows - 1) / tile_rows);
 }
@@ -1293,7 +1374,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     double total = 0.0;
     for (int i = 0; i < count; ++i) {
         if (!v[i]) continue;
-        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i]),
+        for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i], v[i]->item_rows),
                       [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
         for (const auto &it : own[i]) sol_work[i] += (double)work(it);
         total += sol_work[i];
@@ -1594,12 +1675,20 @@ extern "C" int tga_batch_set_members(tga_batch_t B, const tga_solution_t *sols, 
 static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream_t st) {
     if (!(op_mask & TGA_OP_ALL)) return;
     if (ls) op_mask |= kImprovingOnly;
+    const bool cnt = ls && (op_mask & TGA_OP_COUNT_FULL);
     if (!B->cfg.split) {
-        k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                     B->ixoff, B->nx, op_mask, B->steps);
+        if (cnt)
+            k_eval_batch<7><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
+                                                                         B->ixoff, B->nx, op_mask, B->steps);
+        else
+            k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
+                                                                         B->ixoff, B->nx, op_mask, B->steps);
         return;
     }
-    if (op_mask & 7)
+    if ((op_mask & 7) && cnt)
+        k_eval_batch<5><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
+                                                                     B->ixoff, B->nx, op_mask, B->steps);
+    else if (op_mask & 7)
         k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
                                                                      B->ixoff, B->nx, op_mask, B->steps);
     if (op_mask & (2 | 8 | 16))
@@ -1742,10 +1831,22 @@ static int batch_collect(tga_batch *B, int32_t *steps_done, int64_t *moves, int6
     return TGA_OK;
 }
 
+extern "C" int tga_batch_screen_stats(tga_batch_t B, int64_t pairs[2], void *stream) {
+    if (!B || !pairs) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    k_screen_sum<<<1, 64, 0, st>>>(B->d, (int)B->sols.size(), B->coll);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(B->coll_h, B->coll, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pairs[0] = B->coll_h[0];
+    pairs[1] = B->coll_h[1];
+    return TGA_OK;
+}
+
 extern "C" int tga_batch_ls_run(tga_batch_t B, uint32_t op_mask, int32_t steps, int32_t use_graph,
                                 int32_t *steps_done, int64_t *moves_evaluated, int64_t *cost, void *stream) {
     if (!B) return fail(TGA_EINVAL, "null batch");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_COUNT_FULL)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (steps < 0) return fail(TGA_EINVAL, "steps < 0");
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
@@ -1804,7 +1905,7 @@ extern "C" int tga_batch_poll(tga_batch_t B, int32_t *done, void *stream) {
 
 extern "C" int tga_batch_step_part(tga_batch_t B, uint32_t op_mask, int32_t part, void *stream) {
     if (!B) return fail(TGA_EINVAL, "null batch");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_COUNT_FULL)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (part != 0 && part != 1) return fail(TGA_EINVAL, "part must be 0 (evaluate) or 1 (finalize)");
     hipStream_t st = (hipStream_t)stream;
     if (part == 0)
@@ -1823,7 +1924,7 @@ extern "C" int tga_batch_collect(tga_batch_t B, int32_t *steps_done, int64_t *mo
 
 extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best, int32_t *status, void *stream) {
     if (!B || !best) return fail(TGA_EINVAL, "null argument");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_COUNT_FULL)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();
     // a record evaluation covers converged solutions too, so their flags and
@@ -1855,7 +1956,7 @@ extern "C" int tga_batch_eval(tga_batch_t B, uint32_t op_mask, tga_move_t *best,
 extern "C" int tga_batch_tick(tga_batch_t B, uint32_t op_mask, int32_t steps, int32_t *tick, void *stream) {
     if (!B) return fail(TGA_EINVAL, "null batch");
     if (!B->slotted) return fail(TGA_EINVAL, "not a slot batch");
-    if (op_mask & ~TGA_OP_ALL) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_COUNT_FULL)) return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (steps < 1 || steps > 64) return fail(TGA_ERANGE, "steps per tick in [1, 64]");
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)B->sols.size();

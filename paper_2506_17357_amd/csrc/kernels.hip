@@ -98,6 +98,9 @@ constexpr int kAdmissibleBound = 1 << 29;
 // evaluated in full, and the best improving move — the only one the step can
 // apply — is found exactly as before.
 constexpr uint32_t kImprovingOnly = 1u << 31;
+// Operator-mask modifier (TGA_OP_COUNT_FULL, batched form): the evaluation
+// launch is the instantiation that also counts the pairs evaluated in full.
+constexpr uint32_t kCountFull = 1u << 17;
 
 // Operator-mask modifier (TGA_OP_GRANULAR): inter-route operators restricted
 // to the granular pairs of the instance.
@@ -1093,7 +1096,7 @@ __device__ __forceinline__ void wave_share(int Q, int sb, int nr, int wave, int 
 // so no move that could be the minimum (or tie with it) is ever skipped.
 // With dump arrays every move is evaluated.  smem4 is the dynamic LDS area;
 // red holds kInterWaves keys.
-template <bool TW, bool DUMP, bool W16>
+template <bool TW, bool DUMP, bool W16, bool CNT = false>
 __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &item, uint32_t op_mask,
                            int32_t *__restrict__ dump_delta, uint8_t *__restrict__ dump_feas,
                            int4 *smem4, unsigned long long *red, int *thr_sh) {
@@ -1112,6 +1115,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
 
     int bd = initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
+    uint32_t nfull = 0;  // CNT: this wavefront's pairs evaluated in full (wave-uniform)
 
     // prologue: the distance rows of sub-block 0 (with its halo rows)
     __syncthreads();  // the previous item is done with LDS
@@ -1234,6 +1238,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                             const int e4 = ((cap - rB.y - L.zy) | (capB + rB.y - L.tb.y)) >= 0 ? d4 : kNoDelta;
                             full = min(min(e1, e2), min(e3, e4)) <= thr;
                         }
+                        if (CNT) nfull += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(full));
                     }
                     if (full) {
                         int4 rt = make_int4(0, 0, 0, 0), rw = make_int4(0, 0, 0, 0);
@@ -1270,6 +1275,8 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
             }
         }
     }
+    if (CNT && !DUMP && (op_mask & kImprovingOnly) && lane == 0 && nfull)
+        atomicAdd((unsigned long long *)(S.acc + kAccFullPairs), (unsigned long long)nfull);
     block_argmin_commit(bd, bid, S.best_key, red);
 }
 
@@ -2397,16 +2404,17 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const InterItem item = items[it];
             const SolDev &S = sols[item.sol];
             if (skip_solution(S, op_mask)) continue;
+            constexpr bool CNT = (PH & 4) != 0;
             if (S.has_tw) {
                 if (S.D16)
-                    inter_item<true, false, true>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                    inter_item<true, false, true, CNT>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
                 else
-                    inter_item<true, false, false>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                    inter_item<true, false, false, CNT>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
             } else {
                 if (S.D16)
-                    inter_item<false, false, true>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                    inter_item<false, false, true, CNT>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
                 else
-                    inter_item<false, false, false>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
+                    inter_item<false, false, false, CNT>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
             }
         }
     }
@@ -2666,6 +2674,8 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
                         if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
                 }
                 S.acc[kAccMoves] += m;
+                if ((op_mask & kCountFull) && (op_mask & 7))
+                    S.acc[kAccScreenPairs] += S.acc[kAccCnt0 + 2];  // = slot pairs of different routes
             }
             S.acc[kAccGranInter] = 0;
             S.acc[kAccExtMoves] = 0;
@@ -2842,7 +2852,22 @@ __global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int ma
     S.state[kStStatus] = 0;
     S.state[kStMaxSteps] = max_steps;
     S.acc[kAccMoves] = 0;
+    S.acc[kAccFullPairs] = 0;
+    S.acc[kAccScreenPairs] = 0;
     *S.best_key = ~0ull;
+}
+
+// Sum of the screening counters over a batch's solutions (one thread).
+__global__ void k_screen_sum(const SolDev *__restrict__ sols, int nsols, long long *out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    long long f = 0, p = 0;
+    for (int i = 0; i < nsols; ++i)
+        if (sols[i].Q) {
+            f += sols[i].acc[kAccFullPairs];
+            p += sols[i].acc[kAccScreenPairs];
+        }
+    out[0] = f;
+    out[1] = p;
 }
 
 }  // namespace tga

@@ -88,7 +88,9 @@ enum {
     kAccLoadExcess = 8, // penalised mode: total load above capacity
     kAccTimeWarp = 9,   // penalised mode: total time warp
     kAccExtMoves = 10,  // operator-variant moves counted by the last evaluation
-    kAccCount = 11
+    kAccFullPairs = 11, // local search: slot pairs of different routes evaluated in full (past the screens)
+    kAccScreenPairs = 12, // local search: slot pairs of different routes visited by those evaluations
+    kAccCount = 13
 };
 
 // Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the

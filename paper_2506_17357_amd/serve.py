@@ -72,7 +72,7 @@ class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
                  device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
                  max_sum_r: int = 1 << 17, autotune: bool = True, ticks_ahead: int = 2,
-                 upload_workers: int = 4):
+                 upload_workers: int = 4, schedule: dict | None = None):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.steps_per_tick = int(steps_per_tick)
@@ -80,7 +80,8 @@ class Server:
         self.device = device
         self.max_sum_q = int(max_sum_q)
         self.max_sum_r = int(max_sum_r)
-        self.autotune = autotune
+        self.autotune = autotune and schedule is None
+        self.schedule = schedule  # a fixed engine schedule (lds_kb, split) instead of autotuning
         self.ticks_ahead = int(ticks_ahead)
         self.compute = torch.cuda.Stream(device=device)
         self.copies = [torch.cuda.Stream(device=device) for _ in range(max(1, int(upload_workers)))]
@@ -129,6 +130,9 @@ class Server:
         q_used = r_used = 0
         tuned = not self.autotune
         B = tga.SlotBatch(self.max_slots, self.max_sum_q, self.max_sum_r, device=self.device, stream=self.compute)
+        if self.schedule is not None:
+            B.set_config(int(self.schedule["lds_kb"]), int(self.schedule.get("split", 0)), stream=self.compute)
+            self.config = B.config()
         t0 = time.perf_counter()
         workers = [threading.Thread(target=self._upload_loop, args=(c, todo, ready, t0), daemon=True)
                    for c in self.copies]

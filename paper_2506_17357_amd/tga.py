@@ -24,6 +24,7 @@ OPS_ALL = 0x1F
 OP_SEGREL, OP_SEGREL_REV, OP_CROSS = 1 << 5, 1 << 6, 1 << 7  # operator variants (general path)
 OPS_VARIANTS = 0xE0
 OP_GRANULAR = 1 << 16  # modifier: inter-route operators on the granular pairs only
+OP_COUNT_FULL = 1 << 17  # modifier (batched local search): count the pairs evaluated in full
 MAX_Q = 14654
 
 _lib = None
@@ -55,6 +56,16 @@ class BatchConfig(ctypes.Structure):
                 "sub_rows": self.sub_rows, "us_per_eval": round(float(self.us_per_eval), 2)}
 
 
+class TuneEntry(ctypes.Structure):
+    """One row of the schedule table (tga_tune_entry_t)."""
+    _fields_ = [("has_tw", ctypes.c_int32), ("n_max", ctypes.c_int32), ("plain_rows", ctypes.c_int32),
+                ("item_rows", ctypes.c_int32)]
+
+
+# The schedule table the autotuner (paper_2506_17357_amd/autotune.py) writes;
+# applied when the library is loaded.  TGA_TUNE_TABLE names another file ("" = none).
+TUNE_PATH = os.environ.get("TGA_TUNE_TABLE", os.path.join(HERE, "tune_table.json"))
+
 EXPORTS = [
     "tga_instance_workspace_bytes", "tga_solution_workspace_bytes", "tga_load_instance",
     "tga_set_solution", "tga_eval_neighborhood", "tga_apply_move", "tga_ls_run",
@@ -68,7 +79,8 @@ EXPORTS = [
     "tga_batch_set_members", "tga_batch_tick", "tga_batch_tick_status",
     "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
     "tga_solution_set_penalty", "tga_solution_violations", "tga_instance_set_pickups",
-    "tga_solution_set_general",
+    "tga_solution_set_general", "tga_solution_screen_stats", "tga_batch_screen_stats",
+    "tga_set_tuning", "tga_solution_set_rows", "tga_solution_get_rows",
 ]
 
 
@@ -95,6 +107,11 @@ def lib():
         "tga_solution_set_penalty": (i32, [P, i32, i32, P]),
         "tga_instance_set_pickups": (i32, [P, P, P]),
         "tga_solution_set_general": (i32, [P, i32, P]),
+        "tga_solution_screen_stats": (i32, [P, P, P]),
+        "tga_batch_screen_stats": (i32, [P, P, P]),
+        "tga_set_tuning": (i32, [P, i32]),
+        "tga_solution_set_rows": (i32, [P, i32, i32, P]),
+        "tga_solution_get_rows": (i32, [P, P, P]),
         "tga_solution_violations": (i32, [P, P, P, P]),
         "tga_instance_set_granular": (i32, [P, i32, P, sz, P]),
         "tga_instance_granular_pairs": (i32, [P]),
@@ -134,7 +151,25 @@ def lib():
         f.restype = res
         f.argtypes = args
     _lib = L
+    if TUNE_PATH and os.path.exists(TUNE_PATH):
+        load_tuning(TUNE_PATH)
     return L
+
+
+def set_tuning(entries):
+    """Install a schedule table: entries of dicts with kind ("cvrp" or
+    "vrptw"), n_max, plain_rows, item_rows (tga_set_tuning)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for k, e in enumerate(entries):
+        arr[k] = TuneEntry(int(e["kind"] != "cvrp"), int(e["n_max"]), int(e["plain_rows"]), int(e["item_rows"]))
+    _check(lib().tga_set_tuning(arr, len(entries)))
+
+
+def load_tuning(path: str):
+    """Install the table of a JSON file written by the autotuner."""
+    import json
+    with open(path) as f:
+        set_tuning(json.load(f)["entries"])
 
 
 def _check(rc: int, allow=(TGA_OK,)):
@@ -315,6 +350,24 @@ class Solution:
                                         ctypes.byref(cost), _stream(stream)))
         return int(st.value), bool(cv.value), int(mv.value), int(cost.value)
 
+    def set_rows(self, plain_rows: int = 0, item_rows: int = 0, stream=None):
+        """Schedule of this solution (tga_solution_set_rows; 0 = table / default)."""
+        _check(lib().tga_solution_set_rows(self.h, int(plain_rows), int(item_rows), _stream(stream)))
+
+    def rows(self):
+        """(rows per item of the single-solution form, of the batched form; 0 = default rule)."""
+        a = ctypes.c_int32()
+        b = ctypes.c_int32()
+        _check(lib().tga_solution_get_rows(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def screen_stats(self, stream=None):
+        """(pairs evaluated in full, pairs visited) by the inter-route
+        screens of the local-search evaluations since the last reset."""
+        c = np.zeros(2, np.int64)
+        _check(lib().tga_solution_screen_stats(self.h, _np_ptr(c), _stream(stream)))
+        return int(c[0]), int(c[1])
+
     def move_counts(self, stream=None) -> np.ndarray:
         c = np.zeros(5, np.int64)
         _check(lib().tga_move_counts(self.h, _np_ptr(c), _stream(stream)))
@@ -401,6 +454,12 @@ class Batch:
 
     def reset(self, stream=None):
         _check(lib().tga_batch_reset(self.h, _stream(stream)))
+
+    def screen_stats(self, stream=None):
+        """The solutions' screening counters summed (see Solution.screen_stats)."""
+        c = np.zeros(2, np.int64)
+        _check(lib().tga_batch_screen_stats(self.h, _np_ptr(c), _stream(stream)))
+        return int(c[0]), int(c[1])
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -54,3 +54,24 @@ def test_static_scratch_size_matches_header():
     assert m
     from paper_2506_17357_amd import tga
     assert tga.STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtga.so not built")
+def test_tuning_table_validation_needs_no_device():
+    """tga_set_tuning is host-only: malformed entries are refused, a good
+    table and an empty one are accepted."""
+    lib = ctypes.CDLL(LIB)
+
+    class E(ctypes.Structure):
+        _fields_ = [("has_tw", ctypes.c_int32), ("n_max", ctypes.c_int32), ("plain_rows", ctypes.c_int32),
+                    ("item_rows", ctypes.c_int32)]
+
+    lib.tga_set_tuning.restype = ctypes.c_int
+    lib.tga_set_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    good = (E * 3)(E(1, 1000, 4, 16), E(0, 300, 1, 0), E(0, 14654, 2, 32))
+    assert lib.tga_set_tuning(good, 3) == 0
+    for bad in (E(2, 100, 1, 1), E(0, 0, 1, 1), E(0, 100, -1, 0), E(1, 100, 0, -3)):
+        arr = (E * 1)(bad)
+        assert lib.tga_set_tuning(arr, 1) != 0
+    assert lib.tga_set_tuning(None, -1) != 0
+    assert lib.tga_set_tuning(None, 0) == 0

@@ -260,3 +260,65 @@ def test_slot_batch_other_calls_skip_empty_slots(tga):
         assert (steps[k], moves[k], cost[k]) == (len(ids), mv, oracle.cost(pairs[b][0], final)[0])
     assert B.poll().tolist()[0] == 1
     B.close()
+
+
+def inter_pairs(sol):
+    """Slot pairs of different routes (start depots included as slots)."""
+    P = np.diff(np.asarray(sol.offsets, np.int64)) + 1
+    return (int(P.sum()) ** 2 - int((P * P).sum())) // 2
+
+
+def screen_expectation(inst, sol, cap):
+    """(pairs visited by the inter-route screens over the oracle's
+    trajectory, accepted moves that are necessarily inter-route)."""
+    _, ids, _, _ = oracle.local_search(inst, sol, max_steps=cap)
+    Q = inst.n + sol.R
+    evals = min(len(ids) + 1, cap)
+    cur, visited, inter = sol, 0, 0
+    for k in range(evals):
+        visited += inter_pairs(cur)
+        if k < len(ids):
+            op = int(ids[k]) // (Q * Q) // 4
+            inter += op in (0, 2)
+            cur = oracle.apply_move(inst, cur, int(ids[k]))
+    return visited, inter
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_screen_counters(tga, use_graph):
+    """The screening counters (the counting instantiation of the batched
+    launch): pairs visited equal the slot pairs of different routes summed
+    over the evaluated states of the oracle's trajectory; pairs evaluated in
+    full cover at least every accepted inter-route move and stay a small
+    share of the visited ones; the results are those without counting."""
+    pairs = small_mix(6, seed=4)
+    insts, sols = make_solutions(tga, pairs)
+    B = tga.Batch(sols)
+    plain = B.ls_run(40, use_graph=use_graph)
+    assert B.screen_stats() == (0, 0)
+    for s, (_, sol) in zip(sols, pairs):
+        s.reload(sol.offsets, sol.customers)
+    counted = B.ls_run(40, tga.OPS_ALL | tga.OP_COUNT_FULL, use_graph=use_graph)
+    for a, b in zip(plain, counted):
+        assert np.array_equal(a, b)
+    full, visited = B.screen_stats()
+    exp = [screen_expectation(i, s, 40) for i, s in pairs]
+    assert visited == sum(v for v, _ in exp)
+    assert sum(a for _, a in exp) <= full < visited // 4
+    per = [s.screen_stats() for s in sols]
+    assert (sum(f for f, _ in per), sum(v for _, v in per)) == (full, visited)
+    assert [v for _, v in per] == [v for v, _ in exp]
+    B.eval()  # a record-mode evaluation leaves the counters alone
+    assert B.screen_stats() == (full, visited)
+    B.close()
+    inst, sol = W.c1()
+    I = tga.Instance.from_workload(inst)
+    S = tga.Solution(I, sol.offsets, sol.customers)
+    with pytest.raises(tga.TGAError):
+        S.ls_run(10, tga.OPS_ALL | tga.OP_COUNT_FULL)  # the batched form only
+    B = tga.Batch([S])
+    B.ls_run(1000, tga.OPS_ALL | tga.OP_COUNT_FULL)
+    full, visited = B.screen_stats()
+    v, a = screen_expectation(inst, sol, 1000)
+    assert visited == v and a <= full < visited // 4
+    B.close()

@@ -65,15 +65,6 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def kernel_source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "api.hip", "tga_internal.h"):
-        with open(os.path.join(ROOT, "paper_2506_17357_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
 def committed_counters(name):
     """A counter summary committed under profiles/ (rocprofv3 runs of the
     default benchmark's evaluation launch); None when missing or taken on
@@ -83,6 +74,7 @@ def committed_counters(name):
         return None
     with open(path) as f:
         t = json.load(f)
+    from paper_2506_17357_amd.counters import kernel_source_hash
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return t
@@ -96,6 +88,7 @@ def traffic_entry(alg_bytes_per_launch):
         return None
     return {"bytes_per_launch": t["bytes_per_launch"],
             "vs_algorithmic": round(t["bytes_per_launch"] / alg_bytes_per_launch, 3),
+            "unscaled_bytes_per_launch": t.get("unscaled_bytes_per_launch"),
             "source": "profiles/traffic_k_eval_batch_batched256.json"}
 
 
@@ -114,13 +107,19 @@ def valu_entry(avg_launch_us):
 
 
 def calibrate_copy():
-    """A plain device copy of exactly 1 GiB (read) + 1 GiB (write), so that a
-    profiler pass can scale FETCH_SIZE / WRITE_SIZE."""
+    """Calibration launches for a profiler pass: a plain device copy of
+    exactly 1 GiB (read) + 1 GiB (write), which scales WRITE_SIZE, and one
+    read of 1 GiB through the 16-byte LDS DMA the evaluation stages its
+    16-bit rows with (k_probe_stream), which scales FETCH_SIZE for that
+    request type."""
     import torch
+    from paper_2506_17357_amd import tga
     a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     b.copy_(a)
+    torch.cuda.synchronize()
+    tga.probe_stream_read(a)
     torch.cuda.synchronize()
     del a, b
 
@@ -391,7 +390,7 @@ def served_run(args, count):
                                                                   sum(q.inst.n for q in reqs)))
     budget = int(args.hbm_budget_gb * (1 << 30))
     srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
-    srv.run(reqs[: min(8, len(reqs))])  # warm: code paths, autotuned schedule
+    srv.run(reqs[: min(8, len(reqs))])  # warm: code paths
     srv = serve.Server(budget, steps_per_tick=args.steps_per_tick)
     t0 = time.perf_counter()
     res0 = srv.run(reqs)
@@ -429,6 +428,7 @@ def served_run(args, count):
                        "max": round(float(lat.max()), 2)},
         "makespan_s": round(t_open, 3),
         "steps_per_tick": srv.steps_per_tick,
+        "engine_schedule": srv.config,
         "upload_busy_s": round(srv.upload_s, 3),
         "plan_updates": srv.rebuilds,
         "plan_update_s": round(srv.rebuild_s, 3),
@@ -440,6 +440,50 @@ def served_run(args, count):
     log("served open loop: %.1f GMoves/s, p50 %.1f ms, p99 %.1f ms, same results %s" % (
         out["value"], out["latency_ms"]["p50"], out["latency_ms"]["p99"], same))
     return out
+
+
+def large_run(args):
+    """One request of exactly args.large customers (the served stream's
+    largest size; seeds as the large oracle-checked requests: 15000 CVRP,
+    15001 VRPTW) as a batch of one: args.steps local-search steps from the
+    sweep start, HIP events around every evaluation launch.  The single-GPU
+    view of the largest instances (one row-sliced D per evaluation)."""
+    import torch
+    from paper_2506_17357_amd import tga, workload as W
+    kind = args.large_kind
+    req = W.Request(10000 + (kind != "cvrp"), 0.0, args.large, kind, args.steps)
+    t = time.time()
+    inst = W.request_instance(req)
+    sol = W.sweep(inst)
+    log("large: %s n = %d generated in %.1f s (R = %d)" % (kind, inst.n, time.time() - t, sol.R))
+    I = tga.Instance.from_workload(inst)
+    S = tga.Solution(I, sol.offsets, sol.customers)
+    if args.large_item_rows:
+        S.set_rows(0, args.large_item_rows)
+    B = tga.Batch([S])
+    if args.large_lds_kb:
+        B.set_config(args.large_lds_kb, 0)
+        schedule = B.config()
+    else:
+        schedule = B.autotune(launches=3)
+    ebytes = np.array([eval_bytes(inst, sol.R)], np.float64)
+    sbytes = np.array([streamed_bytes(inst, sol.R, I.dist_bytes)], np.float64)
+    S.reload(sol.offsets, sol.customers)
+    ev = eager_pass(B, args.steps, ebytes, sbytes)
+    roof = roofline_entry(ev)
+    line = {"metric": "large request: evaluation launch vs the HBM roofline", "value": roof["achieved"],
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "int32",
+            "data": "synthetic", "config": {"workload": "one %s request of %d customers (seed %d), batch of one, "
+                                                        "%d local-search steps" % (kind, inst.n, 5000 + req.k,
+                                                                                   args.steps),
+                                            "R": sol.R, "schedule": schedule, "rows": S.rows(),
+                                            "accepted_moves": int(ev["steps"][0]),
+                                            "moves_evaluated": int(ev["moves"][0])},
+            "roofline": roof}
+    log("large: eval launch avg %.1f us, %.0f GB/s algorithmic (%.3f), %.0f GB/s streamed" % (
+        roof["avg_launch_us"], roof["achieved"], roof["frac"], roof["streamed"]["achieved"]))
+    B.close()
+    return line
 
 
 def main():
@@ -459,6 +503,11 @@ def main():
     ap.add_argument("--served-leg-requests", type=int, default=100,
                     help="requests of the served leg of the default run (0 = none)")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--large", type=int, default=0,
+                    help="instead: one request of this many customers as a batch of one (evaluation roofline)")
+    ap.add_argument("--large-kind", default="cvrp", choices=("cvrp", "vrptw"))
+    ap.add_argument("--large-item-rows", type=int, default=0, help="rows per inter-route item (0: the table)")
+    ap.add_argument("--large-lds-kb", type=int, default=0, help="LDS budget per workgroup (0: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a 1 GiB device copy (profiler scaling of FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -469,6 +518,13 @@ def main():
     K, Wm = args.steps, args.warmup
     from paper_2506_17357_amd import build_lib
     build_lib.ensure_built(verbose=True)
+    if args.large:
+        import torch
+        torch.cuda.set_device(0)
+        if args.calibrate_copy:
+            calibrate_copy()
+        print(json.dumps(large_run(args)), flush=True)
+        return
     if args.served:
         line = served_run(args, args.requests)
         line.update({"n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic"})
@@ -636,6 +692,8 @@ def main():
             "form": "batched: persistent evaluation launch(es) + one finalize launch per step, "
                     "step loop captured in a HIP graph",
             "schedule": schedule,
+            "rows_per_item_table": (os.path.relpath(tga.TUNE_PATH, os.path.dirname(os.path.abspath(__file__)))
+                                    if tga.TUNE_PATH and os.path.exists(tga.TUNE_PATH) else None),
         },
         "roofline": roof,
         "eager_value": round(moves_total / ev["seconds"] / 1e9, 4),
@@ -643,6 +701,8 @@ def main():
         "batched_over_plain": round(value / out_plain["value"], 3) if out_plain else None,
         "bit_exact_batched_vs_plain": bit_exact,
         "served": out_served,
+        "served_closed_loop_over_batched": (round(out_served["closed_loop_gmoves_s"] / value, 3)
+                                            if out_served else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -302,6 +302,14 @@ int tga_solution_stats(tga_solution_t sol, int32_t *steps_done, int32_t *converg
  * Synchronises `stream`. */
 int tga_solution_screen_stats(tga_solution_t sol, int64_t pairs[2], void *stream);
 
+/* Measurement aid (profiler calibration, not part of the method): reads
+ * `bytes` (a multiple of 1024) of device memory at `src` (16-byte aligned)
+ * once, through the same 16-byte LDS DMA that stages the 16-bit distance
+ * rows, and discards them, so that a hardware fetch counter can be scaled
+ * for that kind of request.  TGA_EINVAL for a misaligned source or size.
+ * Synchronises `stream`. */
+int tga_probe_stream_read(const void *src, size_t bytes, void *stream);
+
 /* Schedules per problem kind and size, as an autotuner measured them (a
  * table the caller loads, e.g. from a JSON file the tuner wrote): an entry
  * applies to solutions of its kind (has_tw 0 = CVRP, 1 = with time windows
@@ -429,7 +437,7 @@ int tga_batch_set_config(tga_batch_t b, const tga_batch_config_t *cfg, void *str
 /* The project's autotuner for the batched form: times `launches` evaluation
  * steps (each followed by a finalize that only records the best move, so no
  * solution changes) of the batch's current state under each candidate
- * schedule (lds_kb in {40, 52, 64, 78, 79} x split in {0, 1}, keeping
+ * schedule (lds_kb in {40, 52, 64, 78, 79, the whole LDS} x split in {0, 1}, keeping
  * rows_per_item and sub_rows), keeps the fastest and writes it to `best`
  * (nullable).  Drops a captured step loop.  Synchronises `stream`. */
 int tga_batch_autotune(tga_batch_t b, uint32_t op_mask, int32_t launches, tga_batch_config_t *best,

@@ -1746,7 +1746,11 @@ extern "C" int tga_batch_autotune(tga_batch_t B, uint32_t op_mask, int32_t launc
         return fail(TGA_EDEVICE, "hipEventCreate failed");
     }
     const tga_batch_config_t base = B->cfg;
-    static const int kLdsKb[] = {40, 52, 64, 78, 79};
+    // LDS budgets per inter-route workgroup: up to the largest that lets two
+    // workgroups share a compute unit, and the whole LDS of one workgroup
+    // (one per compute unit: fewer, longer-row sub-blocks, which suit very
+    // large solutions)
+    const int kLdsKb[] = {40, 52, 64, 78, 79, (int)(P.max_lds / 1024)};
     tga_batch_config_t chosen = base;
     float best_us = 0.f;
     bool any = false;
@@ -1828,6 +1832,24 @@ static int batch_collect(tga_batch *B, int32_t *steps_done, int64_t *moves, int6
         if (moves) moves[i] = r[2];
         if (cost) cost[i] = r[3];
     }
+    return TGA_OK;
+}
+
+extern "C" int tga_probe_stream_read(const void *src, size_t bytes, void *stream) {
+    if (!src) return fail(TGA_EINVAL, "null argument");
+    if (((uintptr_t)src) & 15) return fail(TGA_EINVAL, "src must be 16-byte aligned");
+    if (bytes % 1024) return fail(TGA_EINVAL, "bytes must be a multiple of 1024");
+    DevProps P;
+    int rc = props(&P);
+    if (rc) return rc;
+    const long long chunks = (long long)(bytes / 1024);
+    if (chunks == 0) return TGA_OK;
+    const long long want = (chunks + 3) / 4;
+    const int grid = (int)std::max(1LL, std::min<long long>(want, 8LL * P.cus));
+    hipStream_t st = (hipStream_t)stream;
+    k_probe_stream<<<grid, 256, 0, st>>>((const int *)src, chunks);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
     return TGA_OK;
 }
 

@@ -2857,6 +2857,23 @@ __global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int ma
     *S.best_key = ~0ull;
 }
 
+// Measurement aid: reads `chunks` KiB from src into LDS with the 16-byte
+// LDS DMA that stages 16-bit distance rows (one KiB per wavefront
+// instruction) and discards them, so that a profiler's fetch counter can be
+// scaled for exactly that kind of request.  Each wavefront cycles through
+// four 1 KiB slots of its own and drains them every fourth instruction.
+__global__ __launch_bounds__(256) void k_probe_stream(const int *__restrict__ src, long long chunks) {
+    __shared__ int4 buf[4 * 4 * 64];  // 4 wavefronts x 4 slots x 1 KiB
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int k = 0;
+    for (long long c = (long long)blockIdx.x * 4 + wave; c < chunks; c += (long long)gridDim.x * 4) {
+        int *dst = (int *)(buf + (wave * 4 + (k & 3)) * 64);
+        __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c * 256 + 4 * lane), (lds_void_ptr)dst, 16, 0, 0);
+        if ((++k & 3) == 0) __builtin_amdgcn_s_waitcnt(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Sum of the screening counters over a batch's solutions (one thread).
 __global__ void k_screen_sum(const SolDev *__restrict__ sols, int nsols, long long *out) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;

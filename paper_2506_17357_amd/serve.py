@@ -71,7 +71,7 @@ def device_bytes(inst, R: int) -> int:
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
                  device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
-                 max_sum_r: int = 1 << 17, autotune: bool = True, ticks_ahead: int = 2,
+                 max_sum_r: int = 1 << 17, autotune: bool = False, ticks_ahead: int = 2,
                  upload_workers: int = 4, schedule: dict | None = None):
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
@@ -80,8 +80,16 @@ class Server:
         self.device = device
         self.max_sum_q = int(max_sum_q)
         self.max_sum_r = int(max_sum_r)
+        # Engine schedule: by default the largest LDS budget per inter-route
+        # workgroup that still lets two of them share a compute unit, one
+        # launch per step (what the batch autotuner picks on full batches;
+        # autotuning the engine on the few members present early in a run
+        # picked smaller budgets that were slower once the engine filled up).
+        # autotune=True tunes once instead, when eight members are present.
+        if schedule is None and not autotune:
+            schedule = {"lds_kb": tga.device_limits()[1] // 2 // 1024, "split": 0}
         self.autotune = autotune and schedule is None
-        self.schedule = schedule  # a fixed engine schedule (lds_kb, split) instead of autotuning
+        self.schedule = schedule
         self.ticks_ahead = int(ticks_ahead)
         self.compute = torch.cuda.Stream(device=device)
         self.copies = [torch.cuda.Stream(device=device) for _ in range(max(1, int(upload_workers)))]

@@ -80,7 +80,7 @@ EXPORTS = [
     "tga_granular_workspace_bytes", "tga_instance_set_granular", "tga_instance_granular_pairs",
     "tga_solution_set_penalty", "tga_solution_violations", "tga_instance_set_pickups",
     "tga_solution_set_general", "tga_solution_screen_stats", "tga_batch_screen_stats",
-    "tga_set_tuning", "tga_solution_set_rows", "tga_solution_get_rows",
+    "tga_set_tuning", "tga_solution_set_rows", "tga_solution_get_rows", "tga_probe_stream_read",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
         "tga_solution_screen_stats": (i32, [P, P, P]),
         "tga_batch_screen_stats": (i32, [P, P, P]),
         "tga_set_tuning": (i32, [P, i32]),
+        "tga_probe_stream_read": (i32, [P, sz, P]),
         "tga_solution_set_rows": (i32, [P, i32, i32, P]),
         "tga_solution_get_rows": (i32, [P, P, P]),
         "tga_solution_violations": (i32, [P, P, P, P]),
@@ -513,6 +514,12 @@ class SlotBatch(Batch):
         if t.value < 0:
             return -1, None, None, None, None
         return int(t.value), self._cv.copy(), self._st.copy(), self._mv.copy(), self._cost.copy()
+
+
+def probe_stream_read(t: torch.Tensor, stream=None):
+    """Read a device tensor once through the 16-byte LDS DMA (profiler
+    calibration; see tga_probe_stream_read)."""
+    _check(lib().tga_probe_stream_read(_dev_ptr(t), t.numel() * t.element_size(), _stream(stream)))
 
 
 def device_limits():

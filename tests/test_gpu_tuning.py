@@ -65,7 +65,7 @@ def test_batched_item_rows_keep_results(tga, item_rows):
 
 def test_autotuner_table_round_trip(tga, tmp_path):
     from paper_2506_17357_amd import autotune
-    entries, meas = autotune.run(buckets=(80, 160), kinds=("cvrp", "vrptw"), steps_plain=5, steps_batch=3)
+    entries, meas = autotune.run(buckets=(80, 160), kinds=("cvrp", "vrptw"), steps_plain=5, steps_batch=3, mix=False)
     assert len(entries) == 4 and len(meas) == 4
     for e in entries:
         assert e["plain_rows"] >= 1 and e["item_rows"] >= 0

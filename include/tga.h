@@ -91,7 +91,12 @@ enum {
      * tga_batch_tick): run the instantiation of the evaluation launch that
      * also counts the slot pairs evaluated in full (tga_batch_screen_stats);
      * the same results, a few per cent slower */
-    TGA_OP_COUNT_FULL = 1u << 17
+    TGA_OP_COUNT_FULL = 1u << 17,
+    /* modifier (general path, after tga_solution_set_multi): several
+     * independent moves per local-search step (tga_ls_run), and the
+     * per-route-pair table that tga_solution_select_moves reads after
+     * tga_eval_neighborhood */
+    TGA_OP_MULTI = 1u << 18
 };
 
 #define TGA_MAX_Q 14654
@@ -281,6 +286,31 @@ int tga_solution_set_penalty(tga_solution_t sol, int32_t w_load, int32_t w_tw, v
  * five base operators are identical on either path.  Synchronises
  * `stream`. */
 int tga_solution_set_general(tga_solution_t sol, int32_t on, void *stream);
+
+/* Multi-move local search (Section 7: apply several independent moves per
+ * iteration instead of one, after Dynasearch).  Candidates: for every pair of
+ * route slots r1 <= r2 (r1 = r2: moves inside one route) the best admissible
+ * improving move touching exactly those routes.  Selection: candidates in
+ * (delta, id) order, each taken when none of its routes is taken yet
+ * (greedy, route-disjoint).  Moves on disjoint routes are independent: each
+ * keeps its delta and feasibility, so applying the selection in order
+ * improves the objective by the sum of the selected deltas.
+ *
+ * tga_multi_workspace_bytes: device bytes of the table and the selection for
+ * R routes.  tga_solution_set_multi: hand a caller-owned device workspace of
+ * that size (256-byte aligned; NULL turns multi-move off) to the solution;
+ * puts it on the general path (tga_solution_set_general); needs R <= 4096.
+ * Then tga_ls_run with TGA_OP_MULTI runs steps of {evaluate, select, apply
+ * the selection}: steps_done counts steps, tga_solution_multi_stats reports
+ * {steps, moves applied}.  tga_eval_neighborhood with TGA_OP_MULTI fills the
+ * table; tga_solution_select_moves then returns the selection (count moves,
+ * the first min(count, cap) written to `moves` in selection order) without
+ * applying it, and empties the table.  Synchronise `stream`. */
+size_t tga_multi_workspace_bytes(int32_t R);
+int tga_solution_set_multi(tga_solution_t sol, void *ws, size_t ws_bytes, void *stream);
+int tga_solution_select_moves(tga_solution_t sol, tga_move_t *moves, int32_t cap, int32_t *count,
+                              void *stream);
+int tga_solution_multi_stats(tga_solution_t sol, int64_t out[2], void *stream);
 
 /* General path: total load excess and total time warp of the current
  * solution (nullable outputs).  Synchronises `stream`. */

@@ -73,6 +73,12 @@ def _load():
         lib.oracle_eval_ex.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, P, i32, i64, i64, i32, P, P, P, P, P]
         lib.oracle_ls_ex.restype = ctypes.c_int
         lib.oracle_ls_ex.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, P, i32, i64, i64, i32, i32, P, P, P]
+        lib.oracle_multi_select.restype = ctypes.c_int
+        lib.oracle_multi_select.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, i32, i64, i64, i32, i32, P, P,
+                                            P, P]
+        lib.oracle_ls_multi.restype = ctypes.c_int
+        lib.oracle_ls_multi.argtypes = [i32, P, P, P, i64, i32, i32, P, P, u32, i32, i64, i64, i32, i32, i32, P, P,
+                                        P, P]
         _lib = lib
     return _lib
 
@@ -270,6 +276,55 @@ def local_search(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100,
                                   off.shape[0] - 1, _p(off), _p(cust), op_mask, int(penalty[0]),
                                   int(penalty[1]), max_steps, threads, _p(ids), _p(deltas), _p(mv))
     return Routes(off, cust), ids[:steps].copy(), deltas[:steps].copy(), int(mv[0])
+
+
+def multi_select(inst, sol, op_mask: int = OPS_ALL, threads: int = 0, penalty=None, candidates=False):
+    """Independent moves of one multi-move step (Section 7): per pair of
+    route slots the best admissible improving move touching exactly those
+    routes, then taken greedily in (delta, id) order when its routes are
+    still free.  Returns ([(id, delta)] in selection order, |N(S)|), and
+    with candidates=True also the number of route pairs with a candidate."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.ascontiguousarray(sol.offsets, dtype=np.int32)
+    cust = np.ascontiguousarray(sol.customers, dtype=np.int32)
+    R = off.shape[0] - 1
+    ids = np.zeros(R, np.uint32)
+    dl = np.zeros(R, np.int64)
+    mv = np.zeros(1, np.int64)
+    nc = np.zeros(1, np.int64)
+    pick = _pickups(inst)
+    pen = penalty if penalty is not None else (0, 0)
+    cnt = lib.oracle_multi_select(inst.n, _p(D), _p(nd), _p(pick) if pick is not None else None, inst.capacity,
+                                  inst.has_tw, R, _p(off), _p(cust), op_mask, int(penalty is not None),
+                                  int(pen[0]), int(pen[1]), threads, R, _p(ids), _p(dl), _p(mv), _p(nc))
+    sel = [(int(ids[q]), int(dl[q])) for q in range(cnt)]
+    return (sel, int(mv[0]), int(nc[0])) if candidates else (sel, int(mv[0]))
+
+
+def local_search_multi(inst, sol, op_mask: int = OPS_ALL, max_steps: int = 100, threads: int = 0,
+                       penalty=None):
+    """Multi-move local search: repeat {multi_select; apply the selection in
+    order} while something is selected, at most max_steps steps.  Returns
+    (final Routes, [(id, delta)] applied in order, moves per step, total
+    moves evaluated)."""
+    lib = _load()
+    D, nd = _inst_args(inst)
+    off = np.array(sol.offsets, dtype=np.int32)
+    cust = np.array(sol.customers, dtype=np.int32)
+    R = off.shape[0] - 1
+    cap = max(1, max_steps) * R
+    ids = np.zeros(cap, np.uint32)
+    dl = np.zeros(cap, np.int32)
+    per = np.zeros(max(1, max_steps), np.int32)
+    mv = np.zeros(1, np.int64)
+    pick = _pickups(inst)
+    pen = penalty if penalty is not None else (0, 0)
+    it = lib.oracle_ls_multi(inst.n, _p(D), _p(nd), _p(pick) if pick is not None else None, inst.capacity,
+                             inst.has_tw, R, _p(off), _p(cust), op_mask, int(penalty is not None), int(pen[0]),
+                             int(pen[1]), max_steps, threads, cap, _p(ids), _p(dl), _p(per), _p(mv))
+    nm = int(per[:it].sum())
+    return Routes(off, cust), [(int(ids[q]), int(dl[q])) for q in range(nm)], per[:it].tolist(), int(mv[0])
 
 
 def decode(Q: int, move_id: int):

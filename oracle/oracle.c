@@ -414,6 +414,7 @@ typedef struct {
     uint8_t *dump_feas;
     int64_t *count;      /* per-thread move counts */
     Best *best;          /* per-thread */
+    Best *pair;          /* multi-move: per thread, R x R best improving move per route pair, or NULL */
     int ntasks;
     int next_task;       /* atomic */
     int nthreads;
@@ -447,6 +448,17 @@ static void consider(Ctx *C, int tid, Move m, int32_t *b1, int32_t *b2) {
     if (C->dump_delta) C->dump_delta[id] = (int32_t)delta;
     if (C->dump_feas) C->dump_feas[id] = (uint8_t)feas;
     C->count[tid]++;
+    if (C->pair && (feas == 3 || C->pen) && delta < 0) {
+        int lo = touched == 2 && r2 < r1 ? r2 : r1, hi = touched == 2 && r2 > r1 ? r2 : r1;
+        const int R = C->X->R;
+        Best *pb = &C->pair[((size_t)tid * R + lo) * R + hi];
+        if (!pb->found || delta < pb->delta || (delta == pb->delta && id < pb->id)) {
+            pb->found = 1;
+            pb->delta = delta;
+            pb->id = id;
+            pb->feas = feas;
+        }
+    }
     if (feas == 3 || C->pen) {
         Best *bt = &C->best[tid];
         if (!bt->found || delta < bt->delta || (delta == bt->delta && id < bt->id)) {
@@ -567,11 +579,29 @@ static int resolve_threads(int nthreads) {
  * exists (written to *best_*), 0 otherwise.  Optional dumps are indexed by
  * move id and must hold 20 * Q * Q entries (40 * Q * Q with ops 5..9); entries that are not moves are
  * left untouched.  *moves receives |N(S)| for the enabled operators. */
+static int eval_core2(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                      int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                      const uint8_t *gran, int pen, int64_t w_load, int64_t w_tw,
+                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                      int64_t *best_delta, uint32_t *best_id, int64_t *moves, Best *pair_out);
+
 static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
                      int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
                      const uint8_t *gran, int pen, int64_t w_load, int64_t w_tw,
                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
                      int64_t *best_delta, uint32_t *best_id, int64_t *moves) {
+    return eval_core2(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, gran, pen, w_load, w_tw, nthreads,
+                      dump_delta, dump_feas, best_delta, best_id, moves, NULL);
+}
+
+/* As eval_core; pair_out (R x R, nullable) receives for every pair of route
+ * slots r1 <= r2 the best admissible improving move that touches exactly
+ * those routes (r1 = r2: one route). */
+static int eval_core2(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                      int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask,
+                      const uint8_t *gran, int pen, int64_t w_load, int64_t w_tw,
+                      int nthreads, int32_t *dump_delta, uint8_t *dump_feas,
+                      int64_t *best_delta, uint32_t *best_id, int64_t *moves, Best *pair_out) {
     Inst I = {n, D, node4, cap, has_tw, pick};
     Sol S = {R, off, cust};
     Index X;
@@ -593,6 +623,7 @@ static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_
     C.ntasks = 12 * X.Q;
     C.best = calloc((size_t)T, sizeof(Best));
     C.count = calloc((size_t)T, sizeof(int64_t));
+    if (pair_out) C.pair = calloc((size_t)T * R * R, sizeof(Best));
     pthread_t *th = malloc(sizeof(pthread_t) * T);
     Arg *args = malloc(sizeof(Arg) * T);
     for (int t = 0; t < T; t++) {
@@ -617,6 +648,17 @@ static int eval_core(int n, const int32_t *D, const int32_t *node4, const int32_
     if (b.found) {
         *best_delta = b.delta;
         *best_id = b.id;
+    }
+    if (pair_out) {
+        for (size_t q = 0; q < (size_t)R * R; q++) {
+            Best m = {0, 0, 0, 0};
+            for (int t = 0; t < T; t++) {
+                Best *x = &C.pair[(size_t)t * R * R + q];
+                if (x->found && (!m.found || x->delta < m.delta || (x->delta == m.delta && x->id < m.id))) m = *x;
+            }
+            pair_out[q] = m;
+        }
+        free(C.pair);
     }
     free(th);
     free(args);
@@ -884,6 +926,106 @@ int oracle_ls_ex(int n, const int32_t *D, const int32_t *node4, const int32_t *p
                  int32_t *traj_delta, int64_t *moves_total) {
     return ls_core(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, mask, pen, w_load, w_tw, max_steps,
                    nthreads, traj_id, traj_delta, moves_total);
+}
+
+/* ------------------------------------------------------- multi-move --- */
+
+typedef struct {
+    int64_t delta;
+    uint32_t id;
+    int r1, r2;
+} Cand;
+
+static int cmp_cand(const void *x, const void *y) {
+    const Cand *a = x, *b = y;
+    if (a->delta != b->delta) return a->delta < b->delta ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+/* Several independent moves per iteration (Section 7, after Dynasearch):
+ * the candidates are, for every pair of route slots {r1, r2} (r1 = r2 for
+ * moves inside one route), the best admissible improving move touching
+ * exactly those routes; taken in (delta, id) order, a candidate is selected
+ * when none of its routes is used by an earlier selection.  Moves on disjoint
+ * routes are independent: each keeps its delta and its feasibility, so the
+ * selected set improves the objective by the sum of their deltas.  Writes up
+ * to max_out selections in order; returns how many were selected. */
+static int multi_select(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                        int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask, int pen,
+                        int64_t w_load, int64_t w_tw, int nthreads, int max_out, uint32_t *ids,
+                        int64_t *deltas, int64_t *moves, int64_t *ncand) {
+    Best *pair = calloc((size_t)R * R, sizeof(Best));
+    int64_t bd = 0;
+    uint32_t bid = 0;
+    eval_core2(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, NULL, pen, w_load, w_tw, nthreads, NULL,
+               NULL, &bd, &bid, moves, pair);
+    Cand *c = malloc(sizeof(Cand) * (size_t)R * R);
+    int nc = 0;
+    for (int r1 = 0; r1 < R; r1++)
+        for (int r2 = r1; r2 < R; r2++) {
+            Best *b = &pair[(size_t)r1 * R + r2];
+            if (b->found) c[nc++] = (Cand){b->delta, b->id, r1, r2};
+        }
+    if (ncand) *ncand = nc;
+    qsort(c, (size_t)nc, sizeof(Cand), cmp_cand);
+    char *used = calloc((size_t)R, 1);
+    int cnt = 0;
+    for (int q = 0; q < nc && cnt < max_out; q++) {
+        if (used[c[q].r1] || used[c[q].r2]) continue;
+        used[c[q].r1] = used[c[q].r2] = 1;
+        ids[cnt] = c[q].id;
+        deltas[cnt] = c[q].delta;
+        cnt++;
+    }
+    free(used);
+    free(c);
+    free(pair);
+    return cnt;
+}
+
+int oracle_multi_select(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                        int has_tw, int R, const int32_t *off, const int32_t *cust, uint32_t op_mask, int pen,
+                        int64_t w_load, int64_t w_tw, int nthreads, int max_out, uint32_t *ids, int64_t *deltas,
+                        int64_t *moves, int64_t *ncand) {
+    return multi_select(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, pen, w_load, w_tw, nthreads,
+                        max_out, ids, deltas, moves, ncand);
+}
+
+/* Multi-move local search: repeat {select; apply every selected move, in
+ * selection order} until nothing improves or max_iters iterations.  Writes
+ * the applied moves in order (up to max_moves) and the count per iteration;
+ * updates (off, cust) in place; returns the number of iterations. */
+int oracle_ls_multi(int n, const int32_t *D, const int32_t *node4, const int32_t *pick, int64_t cap,
+                    int has_tw, int R, int32_t *off, int32_t *cust, uint32_t op_mask, int pen, int64_t w_load,
+                    int64_t w_tw, int max_iters, int nthreads, int max_moves, uint32_t *traj_id,
+                    int32_t *traj_delta, int32_t *per_iter, int64_t *moves_total) {
+    uint32_t *ids = malloc(sizeof(uint32_t) * (size_t)R);
+    int64_t *dl = malloc(sizeof(int64_t) * (size_t)R);
+    int it = 0, nm = 0;
+    int64_t mv_sum = 0;
+    while (it < max_iters) {
+        int64_t mv = 0;
+        int cnt = multi_select(n, D, node4, pick, cap, has_tw, R, off, cust, op_mask, pen, w_load, w_tw,
+                               nthreads, R, ids, dl, &mv, NULL);
+        mv_sum += mv;
+        if (cnt == 0) break;
+        for (int q = 0; q < cnt; q++) {
+            if (oracle_apply(n, D, node4, cap, has_tw, R, off, cust, ids[q]) != 0) {
+                cnt = q;
+                break;
+            }
+            if (nm < max_moves) {
+                traj_id[nm] = ids[q];
+                traj_delta[nm] = (int32_t)dl[q];
+            }
+            nm++;
+        }
+        per_iter[it++] = cnt;
+    }
+    free(ids);
+    free(dl);
+    if (moves_total) *moves_total = mv_sum;
+    return it;
 }
 
 /* Penalty terms of S: total load excess and total time warp over the routes

@@ -14,6 +14,7 @@ launch, the same dispatches.
 
     python -m paper_2506_17357_amd.counters traffic <fetch dir> <write dir> --last 200 --out <json>
     python -m paper_2506_17357_amd.counters valu <dir> --last 200 --out <json>
+    python -m paper_2506_17357_amd.counters trace <kernel-trace results.db> --last 200
 """
 from __future__ import annotations
 
@@ -116,9 +117,38 @@ def valu(path: str, kernel: str = "k_eval_batch<3>", last: int = 200) -> dict:
             "kernel_source_sha256": kernel_source_hash()}
 
 
+def trace(db: str, kernel: str = "k_eval_batch<3>", last: int = 200, top: int = 12) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace database: the mean
+    duration of the last `last` dispatches of `kernel` (one pass of the
+    benchmark; dispatch durations are in ns) and the per-kernel totals of
+    the whole run."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, duration from kernels order by start").fetchall()
+    durs = [d for n, d in rows if _match(n, kernel)]
+    if len(durs) < last:
+        raise ValueError("%d dispatches of %s, fewer than %d" % (len(durs), kernel, last))
+    tail = durs[-last:]
+    out = ["| quantity | value |", "|---|---|",
+           "| %s: dispatches in the run | %d |" % (kernel, len(durs)),
+           "| mean of the last %d dispatches (us) | %.2f |" % (last, sum(tail) / len(tail) / 1e3),
+           "| median of the last %d (us) | %.2f |" % (last, sorted(tail)[len(tail) // 2] / 1e3),
+           "| min / max of the last %d (us) | %.2f / %.2f |" % (last, min(tail) / 1e3, max(tail) / 1e3),
+           "", "| kernel (whole run) | calls | total (us) | mean (us) |", "|---|---|---|---|"]
+    for name, calls, total, avg, _ in c.execute("select * from top_kernels limit %d" % int(top)):
+        short = name.split("(")[0]
+        out.append("| `%s` | %d | %.1f | %.2f |" % (short, calls, total, avg))  # the view is in us
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
+    tr = sub.add_parser("trace")
+    tr.add_argument("db")
+    tr.add_argument("--kernel", default="k_eval_batch<3>")
+    tr.add_argument("--last", type=int, default=200)
+    tr.add_argument("--top", type=int, default=12)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -131,6 +161,9 @@ def main():
         p.add_argument("--workload", default="")
         p.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
+    if a.what == "trace":
+        print(trace(a.db, a.kernel, a.last, a.top))
+        return
     if a.what == "traffic":
         doc = traffic(a.fetch_dir, a.write_dir, a.kernel, a.last)
     else:

@@ -912,7 +912,7 @@ static void launch_solution_eval(tga_solution *sol, uint32_t op_mask, int32_t *d
 // Operator mask of a single-solution call: the five operators plus the
 // granular modifier (only once the instance has its granular pairs).
 static int check_mask(const tga_solution *sol, uint32_t op_mask) {
-    if (op_mask & ~(TGA_OP_ALL | TGA_OP_VARIANTS | TGA_OP_GRANULAR))
+    if (op_mask & ~(TGA_OP_ALL | TGA_OP_VARIANTS | TGA_OP_GRANULAR | TGA_OP_MULTI))
         return fail(TGA_EINVAL, "unknown operator bits 0x%x", op_mask);
     if (op_mask & TGA_OP_VARIANTS) {
         if (!(sol->h.pen || sol->h.pd || sol->h.gen))
@@ -920,6 +920,8 @@ static int check_mask(const tga_solution *sol, uint32_t op_mask) {
         if (sol->Q > TGA_MAX_Q_VARIANTS)
             return fail(TGA_ERANGE, "operator variants need n + R <= %d (move ids below 2^32)", TGA_MAX_Q_VARIANTS);
     }
+    if ((op_mask & TGA_OP_MULTI) && !sol->h.pairkey)
+        return fail(TGA_EINVAL, "TGA_OP_MULTI before tga_solution_set_multi");
     if ((op_mask & TGA_OP_GRANULAR) && !sol->inst->gnnz)
         return fail(TGA_EINVAL, "TGA_OP_GRANULAR before tga_instance_set_granular");
     if ((op_mask & TGA_OP_GRANULAR) && (sol->h.pen || sol->h.pd || sol->h.gen))
@@ -1013,7 +1015,84 @@ extern "C" int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_m
     if ((rc = props(&P))) return rc;
     void *pin;
     if ((rc = pinned(&pin))) return rc;
+    if (op_mask & TGA_OP_MULTI) {  // the per-route-pair table starts empty
+        const size_t RR = (size_t)sol->R * sol->R;
+        k_fill_u64<<<(int)std::min<size_t>((RR + 255) / 256, 1024), 256, 0, (hipStream_t)stream>>>(sol->h.pairkey, RR);
+        HIPCHK(hipGetLastError());
+    }
     return eval_record(sol, op_mask, best, dump_delta, dump_feas, (hipStream_t)stream, (int32_t *)pin, true);
+}
+
+extern "C" size_t tga_multi_workspace_bytes(int32_t R) {
+    if (R < 1) return 0;
+    return align_up((size_t)R * R * 8, 256) + align_up((size_t)(1 + 2 * R) * 4, 256);
+}
+
+extern "C" int tga_solution_set_multi(tga_solution_t sol, void *ws, size_t ws_bytes, void *stream) {
+    if (!sol) return fail(TGA_EINVAL, "null solution");
+    if (sol->in_batch) return fail(TGA_EINVAL, "solution belongs to a batch");
+    hipStream_t st = (hipStream_t)stream;
+    if (!ws) {
+        sol->h.pairkey = nullptr;
+        sol->h.msel = nullptr;
+    } else {
+        if (sol->R > kMultiMaxR) return fail(TGA_ERANGE, "multi-move needs R <= %d", kMultiMaxR);
+        if (ws_bytes < tga_multi_workspace_bytes(sol->R))
+            return fail(TGA_ENOMEM, "multi-move workspace %zu < %zu", ws_bytes, tga_multi_workspace_bytes(sol->R));
+        if (((uintptr_t)ws) & 255) return fail(TGA_EINVAL, "workspace must be 256-byte aligned");
+        const size_t RR = (size_t)sol->R * sol->R;
+        sol->h.pairkey = (unsigned long long *)ws;
+        sol->h.msel = (int32_t *)((char *)ws + align_up(RR * 8, 256));
+        sol->h.gen = 1;
+        k_fill_u64<<<(int)std::min<size_t>((RR + 255) / 256, 1024), 256, 0, st>>>(sol->h.pairkey, RR);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(sol->d, &sol->h, sizeof(SolDev), hipMemcpyHostToDevice, st));
+    k_pen_init<<<1, kApplyThreads, 0, st>>>(sol->d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_select_moves(tga_solution_t sol, tga_move_t *moves, int32_t cap, int32_t *count,
+                                         void *stream) {
+    if (!sol || !count || (cap > 0 && !moves) || cap < 0) return fail(TGA_EINVAL, "bad argument");
+    if (!sol->h.pairkey) return fail(TGA_EINVAL, "tga_solution_set_multi first");
+    hipStream_t st = (hipStream_t)stream;
+    k_multi_step<<<1, kApplyThreads, 0, st>>>(sol->d, kModeRecord, TGA_OP_ALL);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> sel(1 + 2 * (size_t)sol->R);
+    HIPCHK(hipMemcpyAsync(sel.data(), sol->h.msel, sel.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int ns = sel[0];
+    *count = ns;
+    const uint32_t Q = (uint32_t)sol->Q;
+    for (int q = 0; q < std::min(ns, cap); ++q) {
+        const uint32_t id = (uint32_t)sel[1 + 2 * q];
+        tga_move_t &m = moves[q];
+        m.op = (int32_t)(id / (Q * Q) / 4);
+        m.k = (int32_t)(id / (Q * Q) % 4);
+        m.a = (int32_t)(id % (Q * Q) / Q);
+        m.b = (int32_t)(id % Q);
+        m.delta = sel[2 + 2 * q];
+        m.feas = 3;
+        m.id = id;
+        m.version = sol->version;
+    }
+    return TGA_OK;
+}
+
+extern "C" int tga_solution_multi_stats(tga_solution_t sol, int64_t out[2], void *stream) {
+    if (!sol || !out) return fail(TGA_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t steps = 0;
+    long long applied = 0;
+    HIPCHK(hipMemcpyAsync(&steps, sol->h.state + kStSteps, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&applied, sol->h.acc + kAccMultiApplied, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out[0] = steps;
+    out[1] = applied;
+    return TGA_OK;
 }
 
 // ------------------------------------------------- no-allocation variant ----
@@ -1112,6 +1191,12 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
     int32_t *p = (int32_t *)pin;
     k_reset_state<<<1, 64, 0, st>>>(sol->d, 1, max_steps);
     HIPCHK(hipGetLastError());
+    const bool multi = (op_mask & TGA_OP_MULTI) != 0;
+    if (multi) {  // the per-route-pair table starts empty
+        const size_t RR = (size_t)sol->R * sol->R;
+        k_fill_u64<<<(int)std::min<size_t>((RR + 255) / 256, 1024), 256, 0, st>>>(sol->h.pairkey, RR);
+        HIPCHK(hipGetLastError());
+    }
     const int chunk = 16;
     int launched = 0;
     // max_steps evaluations suffice: an evaluation either finds no improving
@@ -1121,7 +1206,10 @@ extern "C" int tga_ls_run(tga_solution_t sol, uint32_t op_mask, int32_t max_step
         const int todo = std::min(chunk, max_steps - launched);
         for (int i = 0; i < todo; ++i) {
             launch_solution_eval(sol, op_mask | kImprovingOnly, nullptr, nullptr, st);
-            k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask, nullptr);
+            if (multi)
+                k_multi_step<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask);
+            else
+                k_finalize<<<1, kApplyThreads, 0, st>>>(sol->d, kModeLS, op_mask, nullptr);
         }
         HIPCHK(hipGetLastError());
         launched += todo;

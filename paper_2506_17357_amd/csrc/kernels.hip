@@ -101,6 +101,10 @@ constexpr uint32_t kImprovingOnly = 1u << 31;
 // Operator-mask modifier (TGA_OP_COUNT_FULL, batched form): the evaluation
 // launch is the instantiation that also counts the pairs evaluated in full.
 constexpr uint32_t kCountFull = 1u << 17;
+// Operator-mask modifier (TGA_OP_MULTI, general path): the evaluation also
+// keeps, per pair of route slots, the best improving move touching exactly
+// those routes (S.pairkey), for the selection of independent moves.
+constexpr uint32_t kMulti = 1u << 18;
 
 // Operator-mask modifier (TGA_OP_GRANULAR): inter-route operators restricted
 // to the granular pairs of the instance.
@@ -1658,8 +1662,12 @@ __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
     int ext = 0;  // operator-variant moves of this thread's pair
-    if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y)
+    if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y) {
         pen_pair<TW, PD, DUMP>(S, x, t, op_mask, dd, df, bd, bid, ext);
+        // every move of this pair of slots touches exactly their two routes
+        if ((op_mask & kMulti) && bd < 0 && bid != 0xFFFFFFFFu)
+            atomicMin(S.pairkey + (size_t)gld(S.a4 + x).y * S.R + gld(S.a4 + t).y, pack_key(bd, bid));
+    }
     if (op_mask & 0xE0u) {  // one atomic per workgroup
         __shared__ int ext_sh;
         if (threadIdx.x == 0) ext_sh = 0;
@@ -1788,6 +1796,8 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
                 }
             }
         }
+        if ((op_mask & kMulti) && bd < 0 && bid != 0xFFFFFFFFu)  // moves inside route r
+            atomicMin(S.pairkey + (size_t)r * S.R + r, pack_key(bd, bid));
     }
     block_argmin_commit(bd, bid, S.best_key, red);
 }
@@ -2643,6 +2653,27 @@ __device__ __forceinline__ void apply_move_block(const SolDev &S, const MoveInfo
     }
 }
 
+// Local-search accounting of one evaluation (thread 0): |N(S)| of the
+// enabled operators (granular: the inter-route moves as counted; variants:
+// as counted) into acc[kAccMoves], and with kCountFull the slot pairs the
+// screens visited.
+__device__ __forceinline__ void ls_count_moves(const SolDev &S, uint32_t op_mask) {
+    long long m = 0;
+    if (op_mask & 0xE0u) m += S.acc[kAccExtMoves];  // operator variants, as counted
+    if (op_mask & kGranular) {  // inter-route moves as counted; intra-route ones complete
+        m = S.acc[kAccGranInter];
+        if (op_mask & 2) m += S.acc[kAccCnt0 + 3];  // same-route swaps: L(L-1)/2 per route, as 2-opt
+        if (op_mask & 8) m += S.acc[kAccCnt0 + 3];
+        if (op_mask & 16) m += S.acc[kAccCnt0 + 4];
+    } else {
+        for (int op = 0; op < 5; ++op)
+            if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
+    }
+    S.acc[kAccMoves] += m;
+    if ((op_mask & kCountFull) && (op_mask & 7))
+        S.acc[kAccScreenPairs] += S.acc[kAccCnt0 + 2];  // = slot pairs of different routes
+}
+
 // One block per solution.  kModeRecord: publish the best move (status 1 if
 // none) and reset the key.  kModeLS: also apply it when its delta is negative
 // and the step cap allows, else mark the solution converged.  kModeApplyRec:
@@ -2661,22 +2692,7 @@ __device__ __forceinline__ void finalize_block(const SolDev &S, int mode, uint32
         } else if (!(mode == kModeLS && S.state[kStDone])) {
             const unsigned long long key = *S.best_key;
             *S.best_key = ~0ull;
-            if (mode == kModeLS) {
-                long long m = 0;
-                if (op_mask & 0xE0u) m += S.acc[kAccExtMoves];  // operator variants, as counted
-                if (op_mask & kGranular) {  // inter-route moves as counted; intra-route ones complete
-                    m = S.acc[kAccGranInter];
-                    if (op_mask & 2) m += S.acc[kAccCnt0 + 3];  // same-route swaps: L(L-1)/2 per route, as 2-opt
-                    if (op_mask & 8) m += S.acc[kAccCnt0 + 3];
-                    if (op_mask & 16) m += S.acc[kAccCnt0 + 4];
-                } else {
-                    for (int op = 0; op < 5; ++op)
-                        if (op_mask >> op & 1) m += S.acc[kAccCnt0 + op];
-                }
-                S.acc[kAccMoves] += m;
-                if ((op_mask & kCountFull) && (op_mask & 7))
-                    S.acc[kAccScreenPairs] += S.acc[kAccCnt0 + 2];  // = slot pairs of different routes
-            }
+            if (mode == kModeLS) ls_count_moves(S, op_mask);
             S.acc[kAccGranInter] = 0;
             S.acc[kAccExtMoves] = 0;
             if (key == ~0ull) {
@@ -2736,6 +2752,183 @@ __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__rest
     }
 }
 
+
+// ------------------------------------------------------------ multi-move --
+// Several independent moves per step (Section 7, after Dynasearch): the
+// candidates are the per-route-pair bests of the last evaluation
+// (S.pairkey); taken in (delta, id) order, a candidate is selected when
+// neither of its routes is used by an earlier selection.  Moves on disjoint
+// routes keep their deltas and feasibility when applied one after another.
+// Up to kMultiCands improving candidates are compacted into LDS and sorted
+// (bitonic); with more, the selection repeats a block-wide minimum over the
+// pairs whose routes are both free.  Requires R <= kMultiMaxR.
+constexpr int kMultiCands = 4096;
+constexpr int kMultiMaxR = 4096;
+
+__device__ __forceinline__ bool key_improving(unsigned long long k) { return k < 0x8000000000000000ull; }
+
+// kModeRecord: selection only, written to S.msel.  kModeLS: also apply the
+// selected moves in order, count the step, and mark the solution converged
+// when nothing is selected or the step cap is reached.  Clears S.pairkey.
+__global__ __launch_bounds__(kApplyThreads) void k_multi_step(const SolDev *__restrict__ sols, int mode,
+                                                              uint32_t op_mask) {
+    __shared__ ApplyShared sh;
+    __shared__ MoveInfo mi;
+    __shared__ unsigned long long keys[kMultiCands];
+    __shared__ int pidx[kMultiCands];
+    __shared__ unsigned char used[kMultiMaxR];
+    __shared__ int cnt_sh, nsel_sh, stop_sh;
+    __shared__ unsigned long long red[kApplyThreads / 64];
+    __shared__ int redq[kApplyThreads / 64];
+    const SolDev &S = sols[0];
+    const int tid = threadIdx.x, T = blockDim.x, R = S.R;
+    const size_t RR = (size_t)R * R;
+    if (mode == kModeLS && S.state[kStDone]) return;
+    if (tid == 0) {
+        cnt_sh = 0;
+        nsel_sh = 0;
+        if (mode == kModeLS) ls_count_moves(S, op_mask);
+        S.acc[kAccGranInter] = 0;
+        S.acc[kAccExtMoves] = 0;
+        *S.best_key = ~0ull;
+    }
+    for (int r = tid; r < R; r += T) used[r] = 0;
+    __syncthreads();
+    // 1. compact the improving candidates
+    for (size_t q = tid; q < RR; q += T) {
+        const unsigned long long k = S.pairkey[q];
+        if (key_improving(k)) {
+            const int slot = atomicAdd(&cnt_sh, 1);
+            if (slot < kMultiCands) {
+                keys[slot] = k;
+                pidx[slot] = (int)q;
+            }
+        }
+    }
+    __syncthreads();
+    const int cnt = cnt_sh;
+    int32_t *sel = S.msel + 1;  // (id, delta) per selected move
+    if (cnt <= kMultiCands) {
+        // 2a. sort (key, pair) ascending: bitonic over the next power of two
+        int np2 = 1;
+        while (np2 < cnt) np2 <<= 1;
+        for (int q = cnt + tid; q < np2; q += T) {
+            keys[q] = ~0ull;
+            pidx[q] = 0;
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= np2; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int q = tid; q < np2; q += T) {
+                    const int p = q ^ j;
+                    if (p > q) {
+                        const bool up = (q & kk) == 0;
+                        const unsigned long long a = keys[q], b = keys[p];
+                        if ((a > b) == up) {
+                            keys[q] = b;
+                            keys[p] = a;
+                            const int t2 = pidx[q];
+                            pidx[q] = pidx[p];
+                            pidx[p] = t2;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // greedy scan in order (one thread)
+        if (tid == 0) {
+            int ns = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const int r1 = pidx[q] / R, r2 = pidx[q] - r1 * R;
+                if (used[r1] || used[r2]) continue;
+                used[r1] = used[r2] = 1;
+                sel[2 * ns] = (int32_t)(uint32_t)(keys[q] & 0xFFFFFFFFu);
+                sel[2 * ns + 1] = (int)((uint32_t)(keys[q] >> 32) ^ 0x80000000u);
+                ++ns;
+            }
+            nsel_sh = ns;
+        }
+    } else {
+        // 2b. repeated minimum over the pairs whose routes are both free
+        for (;;) {
+            unsigned long long best = ~0ull;
+            int bq = -1;
+            for (size_t q = tid; q < RR; q += T) {
+                const unsigned long long k = S.pairkey[q];
+                if (!key_improving(k) || k >= best) continue;
+                const int r1 = (int)(q / R), r2 = (int)(q - (size_t)r1 * R);
+                if (used[r1] || used[r2]) continue;
+                best = k;
+                bq = (int)q;
+            }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const unsigned long long ob = __shfl_xor(best, off);
+                const int oq = __shfl_xor(bq, off);
+                if (ob < best) {
+                    best = ob;
+                    bq = oq;
+                }
+            }
+            if ((tid & 63) == 0) {
+                red[tid >> 6] = best;
+                redq[tid >> 6] = bq;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long b = ~0ull;
+                int q0 = -1;
+                for (int w = 0; w < T / 64; ++w)
+                    if (red[w] < b) {
+                        b = red[w];
+                        q0 = redq[w];
+                    }
+                stop_sh = q0 < 0;
+                if (q0 >= 0) {
+                    const int r1 = q0 / R, r2 = q0 - r1 * R;
+                    used[r1] = used[r2] = 1;
+                    const int ns = nsel_sh;
+                    sel[2 * ns] = (int32_t)(uint32_t)(b & 0xFFFFFFFFu);
+                    sel[2 * ns + 1] = (int)((uint32_t)(b >> 32) ^ 0x80000000u);
+                    nsel_sh = ns + 1;
+                }
+            }
+            __syncthreads();
+            if (stop_sh) break;
+        }
+    }
+    __syncthreads();
+    const int ns = nsel_sh;
+    if (tid == 0) S.msel[0] = ns;
+    // 3. clear the table for the next evaluation
+    for (size_t q = tid; q < RR; q += T) S.pairkey[q] = ~0ull;
+    __syncthreads();
+    if (mode != kModeLS) return;
+    // 4. apply the selected moves one after another (disjoint routes)
+    for (int q = 0; q < ns; ++q) {
+        if (tid == 0) {
+            decode_move(S, (uint32_t)sel[2 * q], mi);
+            mi.delta = sel[2 * q + 1];
+        }
+        __syncthreads();
+        const MoveInfo m = mi;
+        if (m.valid) apply_move_block(S, m, sh);
+        __syncthreads();
+        if (tid == 0 && m.valid) S.state[kStVersion] += 1;
+    }
+    if (tid == 0) {
+        if (ns > 0) {
+            const int q = 0;  // the record holds the first (best) selected move
+            S.rec[4] = sel[2 * q + 1];
+            S.rec[6] = sel[2 * q];
+            S.state[kStSteps] += 1;
+            S.acc[kAccMultiApplied] += ns;
+            S.state[kStStatus] = 0;
+        } else {
+            S.state[kStStatus] = 1;
+        }
+        if (ns == 0 || S.state[kStSteps] >= S.state[kStMaxSteps]) S.state[kStDone] = 1;
+    }
+}
 
 // ------------------------------------------------------ instance checks ----
 // out[0] |= 1 value out of range, 2 asymmetric, 4 nonzero diagonal,
@@ -2808,6 +3001,11 @@ __global__ void k_route_blocks_clear(int32_t *rblk, int R) {
     if (r < R) rblk[(size_t)r * kRouteBlockWords] = -1;
 }
 
+__global__ void k_fill_u64(unsigned long long *p, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = ~0ull;
+}
+
 __global__ void k_zero_i32(int32_t *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
@@ -2854,6 +3052,7 @@ __global__ void k_reset_state(const SolDev *__restrict__ sols, int nsols, int ma
     S.acc[kAccMoves] = 0;
     S.acc[kAccFullPairs] = 0;
     S.acc[kAccScreenPairs] = 0;
+    S.acc[kAccMultiApplied] = 0;
     *S.best_key = ~0ull;
 }
 

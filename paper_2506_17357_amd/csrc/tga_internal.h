@@ -63,6 +63,11 @@ struct SolDev {
     const int32_t *pick;
     int4 *pl4;
     int4 *ql4;
+    // multi-move (caller workspace, null when off): per pair of route slots
+    // r1 <= r2 the best improving key of the last evaluation (R x R, entry
+    // r1 * R + r2), and the selection {count, (id, delta) per move}
+    unsigned long long *pairkey;
+    int32_t *msel;
     // per-solution state
     unsigned long long *best_key;  // running minimum of (delta, id) keys
     int32_t *rec;     // 8 ints: the tga_move_t of the last finalize
@@ -90,7 +95,8 @@ enum {
     kAccExtMoves = 10,  // operator-variant moves counted by the last evaluation
     kAccFullPairs = 11, // local search: slot pairs of different routes evaluated in full (past the screens)
     kAccScreenPairs = 12, // local search: slot pairs of different routes visited by those evaluations
-    kAccCount = 13
+    kAccMultiApplied = 13, // multi-move local search: moves applied
+    kAccCount = 14
 };
 
 // Inter-route work item: rows [s0, s1) against column slots [c0, c0 + the

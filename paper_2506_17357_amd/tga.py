@@ -25,6 +25,7 @@ OP_SEGREL, OP_SEGREL_REV, OP_CROSS = 1 << 5, 1 << 6, 1 << 7  # operator variants
 OPS_VARIANTS = 0xE0
 OP_GRANULAR = 1 << 16  # modifier: inter-route operators on the granular pairs only
 OP_COUNT_FULL = 1 << 17  # modifier (batched local search): count the pairs evaluated in full
+OP_MULTI = 1 << 18  # modifier (general path): several independent moves per local-search step
 MAX_Q = 14654
 
 _lib = None
@@ -81,6 +82,7 @@ EXPORTS = [
     "tga_solution_set_penalty", "tga_solution_violations", "tga_instance_set_pickups",
     "tga_solution_set_general", "tga_solution_screen_stats", "tga_batch_screen_stats",
     "tga_set_tuning", "tga_solution_set_rows", "tga_solution_get_rows", "tga_probe_stream_read",
+    "tga_multi_workspace_bytes", "tga_solution_set_multi", "tga_solution_select_moves", "tga_solution_multi_stats",
 ]
 
 
@@ -111,6 +113,10 @@ def lib():
         "tga_batch_screen_stats": (i32, [P, P, P]),
         "tga_set_tuning": (i32, [P, i32]),
         "tga_probe_stream_read": (i32, [P, sz, P]),
+        "tga_multi_workspace_bytes": (sz, [i32]),
+        "tga_solution_set_multi": (i32, [P, P, sz, P]),
+        "tga_solution_select_moves": (i32, [P, ctypes.POINTER(Move), i32, P, P]),
+        "tga_solution_multi_stats": (i32, [P, P, P]),
         "tga_solution_set_rows": (i32, [P, i32, i32, P]),
         "tga_solution_get_rows": (i32, [P, P, P]),
         "tga_solution_violations": (i32, [P, P, P, P]),
@@ -350,6 +356,34 @@ class Solution:
         _check(lib().tga_solution_stats(self.h, ctypes.byref(st), ctypes.byref(cv), ctypes.byref(mv),
                                         ctypes.byref(cost), _stream(stream)))
         return int(st.value), bool(cv.value), int(mv.value), int(cost.value)
+
+    def set_multi(self, on: bool = True, stream=None):
+        """Multi-move local search (OP_MULTI): allocates the per-route-pair
+        table on the solution's device, or drops it."""
+        if on:
+            nb = int(lib().tga_multi_workspace_bytes(self.R))
+            self._multi_ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.ws.device)
+            base = self._multi_ws.data_ptr()
+            ptr = (base + 255) // 256 * 256
+            _check(lib().tga_solution_set_multi(self.h, ctypes.c_void_p(ptr), nb, _stream(stream)))
+        else:
+            _check(lib().tga_solution_set_multi(self.h, None, 0, _stream(stream)))
+            self._multi_ws = None
+
+    def select_moves(self, stream=None):
+        """The independent moves selected from the table the last
+        eval(op_mask | OP_MULTI) filled, in selection order (not applied)."""
+        cap = self.R
+        arr = (Move * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().tga_solution_select_moves(self.h, arr, cap, ctypes.byref(cnt), _stream(stream)))
+        return list(arr[:cnt.value])
+
+    def multi_stats(self, stream=None):
+        """(steps, moves applied) of the last multi-move tga_ls_run."""
+        c = np.zeros(2, np.int64)
+        _check(lib().tga_solution_multi_stats(self.h, _np_ptr(c), _stream(stream)))
+        return int(c[0]), int(c[1])
 
     def set_rows(self, plain_rows: int = 0, item_rows: int = 0, stream=None):
         """Schedule of this solution (tga_solution_set_rows; 0 = table / default)."""

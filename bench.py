@@ -294,6 +294,74 @@ def plain_configs(log_lat=True):
     return out
 
 
+def _ls_leg(S, sol, steps_cap, mask, lat_mask=None):
+    """Device-resident local search from the start (after a short warm-up)
+    and the best-move latency along the single-move trajectory."""
+    import torch
+    S.ls_run(3, mask)
+    S.reload(sol.offsets, sol.customers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, moves, cost = S.ls_run(steps_cap, mask)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"steps": int(steps), "moves_evaluated": int(moves), "final_cost": int(cost), "seconds": round(t, 5),
+           "gmoves_s": round(moves / t / 1e9, 3)}
+    if lat_mask is not None:
+        S.reload(sol.offsets, sol.customers)
+        lat = []
+        for _ in range(min(steps, 200) + 1):
+            t1 = time.perf_counter()
+            m = S.eval(lat_mask)
+            lat.append((time.perf_counter() - t1) * 1e6)
+            if m is None or m.delta >= 0:
+                break
+            S.apply(m)
+        out["best_move_latency_us"] = {"p50": round(float(np.percentile(lat, 50)), 1),
+                                       "p99": round(float(np.percentile(lat, 99)), 1), "evals": len(lat)}
+    return out
+
+
+def general_configs():
+    """The general (concatenation) path on the 1000-customer instances:
+    the operator variants (all ten operators), multi-move steps, and pickups
+    (VRPSPDTW, hard and penalised), each a local search to its local optimum
+    from the sweep start."""
+    from paper_2506_17357_amd import tga, workload as W
+    out = {}
+    for name in ("c2", "c3"):
+        inst, sol = getattr(W, name)()
+        I = tga.Instance.from_workload(inst)
+        S = tga.Solution(I, sol.offsets, sol.customers)
+        S.set_general(True)
+        row = {"base_general_path": _ls_leg(S, sol, 100000, tga.OPS_ALL),
+               "variants": _ls_leg(S, sol, 100000, tga.OPS_ALL | tga.OPS_VARIANTS, tga.OPS_ALL | tga.OPS_VARIANTS)}
+        S.set_multi(True)
+        row["multi_move"] = _ls_leg(S, sol, 100000, tga.OPS_ALL | tga.OP_MULTI)
+        row["multi_move"]["moves_applied"] = S.multi_stats()[1]
+        out[name] = row
+        log("%s general path: base %d steps %.4f s (%.1f GMoves/s); variants %d steps %.4f s (%.1f GMoves/s, "
+            "latency p50 %.1f us, final %d vs %d); multi-move %d steps / %d moves %.4f s (final %d)" % (
+                name, row["base_general_path"]["steps"], row["base_general_path"]["seconds"],
+                row["base_general_path"]["gmoves_s"], row["variants"]["steps"], row["variants"]["seconds"],
+                row["variants"]["gmoves_s"], row["variants"]["best_move_latency_us"]["p50"],
+                row["variants"]["final_cost"], row["base_general_path"]["final_cost"], row["multi_move"]["steps"],
+                row["multi_move"]["moves_applied"], row["multi_move"]["seconds"], row["multi_move"]["final_cost"]))
+    inst, sol = W.c6()
+    I = tga.Instance.from_workload(inst)
+    S = tga.Solution(I, sol.offsets, sol.customers)
+    row = {"workload": "c6: n = %d vrpspdtw, seed 106, sweep start, R = %d" % (inst.n, sol.R),
+           "hard": _ls_leg(S, sol, 100000, tga.OPS_ALL, tga.OPS_ALL)}
+    S.set_penalty(10, 10)
+    row["penalised"] = _ls_leg(S, sol, 100000, tga.OPS_ALL, tga.OPS_ALL)
+    row["penalised"]["weights"] = [10, 10]
+    out["c6"] = row
+    log("c6 pickups: hard %d steps %.4f s (%.1f GMoves/s, latency p50 %.1f us); penalised %d steps %.4f s" % (
+        row["hard"]["steps"], row["hard"]["seconds"], row["hard"]["gmoves_s"],
+        row["hard"]["best_move_latency_us"]["p50"], row["penalised"]["steps"], row["penalised"]["seconds"]))
+    return out
+
+
 def oracle_configs(threads):
     """The oracle on one full-neighbourhood evaluation of each
     single-solution configuration's starting state, at `threads` threads and
@@ -503,6 +571,8 @@ def main():
     ap.add_argument("--served-leg-requests", type=int, default=100,
                     help="requests of the served leg of the default run (0 = none)")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="instead: only the single-solution legs (configs, general path)")
     ap.add_argument("--large", type=int, default=0,
                     help="instead: one request of this many customers as a batch of one (evaluation roofline)")
     ap.add_argument("--large-kind", default="cvrp", choices=("cvrp", "vrptw"))
@@ -518,6 +588,11 @@ def main():
     K, Wm = args.steps, args.warmup
     from paper_2506_17357_amd import build_lib
     build_lib.ensure_built(verbose=True)
+    if args.plain_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"plain_configs": plain_configs(), "general_path": general_configs()}), flush=True)
+        return
     if args.large:
         import torch
         torch.cuda.set_device(0)
@@ -627,6 +702,7 @@ def main():
             "value": round(plain_value, 4), "unit": "GMoves/s", "seconds": round(t_plain, 4),
             "form": "one solution per launch sequence (device-resident loop per solution)",
             "configs": plain_configs(),
+            "general_path": general_configs(),
             "n1000": n1000_comparison(min(K, 50)),
         }
 

@@ -881,7 +881,7 @@ static void launch_eval_gen(const tga_solution *sol, uint32_t op_mask, int32_t *
         else k_eval_pen_pairs<TW, PD, false><<<grid, 256, 0, st>>>(sol->d, tiles, op_mask, dd, df);
     }
     if (op_mask & (2 | 8 | 16)) {
-        const int grid = (sol->Q + 255) / 256;
+        const int grid = (7 * sol->Q + 255) / 256;  // seven walks per slot
         if (dump) k_eval_pen_intra<TW, PD, true><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
         else k_eval_pen_intra<TW, PD, false><<<grid, 256, 0, st>>>(sol->d, op_mask, dd, df);
     }

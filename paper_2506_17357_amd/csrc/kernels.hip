@@ -1682,8 +1682,10 @@ __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict
 
 // Intra-route moves whose first position is the customer at slot s: the
 // 2-opt / same-route swap walk and the or-opt walks, the middle summaries
-// (time warp and, with pickups, load) growing one node per step.  One thread
-// per slot.
+// (time warp and, with pickups, load) growing one node per step.  Seven
+// threads per slot, one walk each (walk 0: 2-opt / swap; 1..3: or-opt of
+// k = walk nodes moved forward; 4..6: k = walk - 3 moved backward), so that a
+// launch has seven times the threads and each its own short chain.
 template <bool TW, bool PD, bool DUMP>
 __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict__ sols, uint32_t op_mask,
                                                         int32_t *__restrict__ dd, uint8_t *__restrict__ df) {
@@ -1692,8 +1694,9 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
     if (skip_solution(S, op_mask)) return;
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < S.Q && (flagsof(gld(S.a4 + s).x) & kFlagCustomer)) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int walk = gid / S.Q, s = gid - walk * S.Q;
+    if (walk < 7 && (flagsof(gld(S.a4 + s).x) & kFlagCustomer)) {
         const int r = gld(S.a4 + s).y, off = gld(S.roff + r), L = gld(S.roff + r + 1) - off - 1, i = s - off;
         const int n = S.n, np1 = S.np1, cap = S.cap;
         const uint32_t uQ = (uint32_t)S.Q;
@@ -1723,7 +1726,7 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
         const Tw Fi1 = Fpos(i - 1);
         const Ld LFi1 = LFpos(i - 1);
         // ---- 2OPT(i, j) and SWAP(i, j), j > i
-        if (op2o || opSwap) {
+        if ((op2o || opSwap) && walk == 0) {
             Tw rev = Npos(i), mid{};
             Ld lrev = LNpos(i), lmid{};
             for (int j = i + 1; j <= L; ++j) {
@@ -1759,8 +1762,10 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
             }
         }
         // ---- OR-OPT: segment c_i .. c_{i+k-1} moved right after c_j
-        if (opOr) {
-            for (int k = 1; k <= 3 && i + k - 1 <= L; ++k) {
+        if (opOr && walk >= 1) {
+            const int k = walk <= 3 ? walk : walk - 3;
+            const bool fwd = walk <= 3;
+            if (i + k - 1 <= L) {
                 const int g = i + k - 1, w = i + k, cG = node(g), cW = node(w);
                 const int base = d(cP, cW) - eP - edge(g);
                 Tw sig{};
@@ -1775,7 +1780,7 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
                 }
                 Tw mid{};
                 Ld lmid{};
-                for (int j = w; j <= L; ++j) {  // forward: middle c_{i+k} .. c_j
+                for (int j = w; fwd && j <= L; ++j) {  // forward: middle c_{i+k} .. c_j
                     const int cJ = node(j), cJ1 = node(j + 1);
                     if (TW) mid = (j == w) ? Npos(j) : tw_cat(mid, edge(j - 1), Npos(j));
                     if (PD) lmid = (j == w) ? LNpos(j) : ld_cat(lmid, LNpos(j));
@@ -1784,7 +1789,7 @@ __global__ __launch_bounds__(256) void k_eval_pen_intra(const SolDev *__restrict
                     const int lv = excess(ld_cat(ld_cat(ld_cat(LFi1, lmid), lsig), LBafter(j)));
                     rec(base + dVF + dGV - edge(j), tv, lv, ((16u + k) * uQ + ref(i)) * uQ + ref(j));
                 }
-                for (int j = i - 2; j >= 0; --j) {  // backward: middle c_{j+1} .. c_{i-1}
+                for (int j = i - 2; !fwd && j >= 0; --j) {  // backward: middle c_{j+1} .. c_{i-1}
                     const int cJ = node(j), cJ1 = node(j + 1);
                     if (TW) mid = (j == i - 2) ? Npos(i - 1) : tw_cat(Npos(j + 1), edge(j + 1), mid);
                     if (PD) lmid = (j == i - 2) ? LNpos(i - 1) : ld_cat(LNpos(j + 1), lmid);

@@ -223,7 +223,7 @@ int tga_eval_neighborhood(tga_solution_t sol, uint32_t op_mask, tga_move_t *best
  * Returns TGA_ENOMOVE as tga_eval_neighborhood does, and TGA_ERANGE when
  * the solution needs more than TGA_STATIC_SCRATCH_BYTES (the workspace size
  * tga_solution_workspace_bytes reports; 8 MiB holds n = 10^4 customers with
- * up to about 1000 routes).  Every call on one GPU uses that
+ * up to 990 routes).  Every call on one GPU uses that
  * GPU's one buffer and overwrites what the previous call left there: calls
  * that overlap on one GPU (other host threads, or other streams before the
  * previous call returned) race.  Synchronises `stream`. */

@@ -2908,17 +2908,79 @@ __global__ __launch_bounds__(kApplyThreads) void k_multi_step(const SolDev *__re
     for (size_t q = tid; q < RR; q += T) S.pairkey[q] = ~0ull;
     __syncthreads();
     if (mode != kModeLS) return;
-    // 4. apply the selected moves one after another (disjoint routes)
-    for (int q = 0; q < ns; ++q) {
-        if (tid == 0) {
-            decode_move(S, (uint32_t)sel[2 * q], mi);
-            mi.delta = sel[2 * q + 1];
+    // 4. apply the selection.  Routes are disjoint, so the new layout is the
+    // old one with each touched route replaced by its new node sequence: its
+    // nodes go into nr_alt (with the new route offsets), then one rebuild of
+    // every attribute.  The decoded moves reuse the key array; a selection
+    // too large for it is applied move by move instead.
+    MoveInfo *mv = reinterpret_cast<MoveInfo *>(keys);
+    constexpr int kBatchApply = (int)(sizeof(keys) / sizeof(MoveInfo));
+    if (ns <= kBatchApply) {
+        int *mov_of = pidx;  // per route: the selected move touching it, or -1
+        for (int r = tid; r < R; r += T) mov_of[r] = -1;
+        __syncthreads();
+        for (int q = tid; q < ns; q += T) {
+            decode_move(S, (uint32_t)sel[2 * q], mv[q]);
+            mv[q].delta = sel[2 * q + 1];
         }
         __syncthreads();
-        const MoveInfo m = mi;
-        if (m.valid) apply_move_block(S, m, sh);
+        for (int q = tid; q < ns; q += T)
+            if (mv[q].valid) {
+                mov_of[mv[q].ra] = q;
+                mov_of[mv[q].rb] = q;
+            }
         __syncthreads();
-        if (tid == 0 && m.valid) S.state[kStVersion] += 1;
+        auto newL = [&](int r) {
+            const int q = mov_of[r];
+            if (q < 0) return S.roff[r + 1] - S.roff[r] - 1;
+            return r == mv[q].ra ? mv[q].nLa : mv[q].nLb;
+        };
+        // new offsets: an exclusive scan of newL + 1 over the routes (each
+        // thread a contiguous run of routes, then the threads' totals)
+        const int per = (R + T - 1) / T, r0 = min(tid * per, R), r1 = min(r0 + per, R);
+        int own = 0;
+        for (int r = r0; r < r1; ++r) own += newL(r) + 1;
+        int incl = own;
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        if (lane == 63) sh.red[wave][0] = incl;
+        __syncthreads();
+        int before = incl - own;
+        for (int w = 0; w < wave; ++w) before += (int)sh.red[w][0];
+        for (int r = r0; r < r1; ++r) {
+            S.roff_alt[r] = before;
+            before += newL(r) + 1;
+        }
+        if (tid == 0) S.roff_alt[R] = S.Q;
+        __syncthreads();
+        // nodes of the new layout, one wavefront per route
+        for (int r = wave; r < R; r += T / 64) {
+            const int q = mov_of[r], base = S.roff_alt[r], nl = newL(r);
+            for (int p = lane; p <= nl; p += 64)
+                S.nr_alt[base + p] = make_int2(q < 0 ? old_node(S, r, p) : new_node(S, mv[q], r, p), r);
+        }
+        if (tid == 0) S.nr_alt[S.Q] = make_int2(0, R);
+        __threadfence_block();
+        __syncthreads();
+        rebuild(S, S.nr_alt, S.roff_alt, sh);
+        if (S.pen || S.pd || S.gen) pen_all(S, sh);
+        if (tid == 0)
+            for (int q = 0; q < ns; ++q) S.state[kStVersion] += mv[q].valid ? 1 : 0;
+    } else {
+        for (int q = 0; q < ns; ++q) {
+            if (tid == 0) {
+                decode_move(S, (uint32_t)sel[2 * q], mi);
+                mi.delta = sel[2 * q + 1];
+            }
+            __syncthreads();
+            const MoveInfo m = mi;
+            if (m.valid) apply_move_block(S, m, sh);
+            __syncthreads();
+            if (tid == 0 && m.valid) S.state[kStVersion] += 1;
+        }
     }
     if (tid == 0) {
         if (ns > 0) {

@@ -2765,8 +2765,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_finalize(const SolDev *__rest
 // neither of its routes is used by an earlier selection.  Moves on disjoint
 // routes keep their deltas and feasibility when applied one after another.
 // Up to kMultiCands improving candidates are compacted into LDS and sorted
-// (bitonic); with more, the selection repeats a block-wide minimum over the
-// pairs whose routes are both free.  Requires R <= kMultiMaxR.
+// (bitonic); with more, rounds of locally dominant candidates give the same
+// set.  Requires R <= kMultiMaxR.
 constexpr int kMultiCands = 4096;
 constexpr int kMultiMaxR = 4096;
 
@@ -2783,8 +2783,6 @@ __global__ __launch_bounds__(kApplyThreads) void k_multi_step(const SolDev *__re
     __shared__ int pidx[kMultiCands];
     __shared__ unsigned char used[kMultiMaxR];
     __shared__ int cnt_sh, nsel_sh, stop_sh;
-    __shared__ unsigned long long red[kApplyThreads / 64];
-    __shared__ int redq[kApplyThreads / 64];
     const SolDev &S = sols[0];
     const int tid = threadIdx.x, T = blockDim.x, R = S.R;
     const size_t RR = (size_t)R * R;
@@ -2854,51 +2852,71 @@ __global__ __launch_bounds__(kApplyThreads) void k_multi_step(const SolDev *__re
             nsel_sh = ns;
         }
     } else {
-        // 2b. repeated minimum over the pairs whose routes are both free
+        // 2b. rounds of locally dominant candidates: a candidate whose key is
+        // the smallest among the candidates at each of its (free) routes is
+        // taken by the sequential greedy too (no smaller key can take one of
+        // its routes first), and the candidates dominant in one round share
+        // no route; repeating on the routes still free gives the greedy set
+        // in a few passes.  The set is then sorted into (delta, id) order.
+        unsigned long long *bestr = keys;  // per route (R <= kMultiCands)
         for (;;) {
-            unsigned long long best = ~0ull;
-            int bq = -1;
+            for (int r = tid; r < R; r += T) bestr[r] = ~0ull;
+            if (tid == 0) stop_sh = 1;
+            __syncthreads();
             for (size_t q = tid; q < RR; q += T) {
                 const unsigned long long k = S.pairkey[q];
-                if (!key_improving(k) || k >= best) continue;
+                if (!key_improving(k)) continue;
                 const int r1 = (int)(q / R), r2 = (int)(q - (size_t)r1 * R);
                 if (used[r1] || used[r2]) continue;
-                best = k;
-                bq = (int)q;
-            }
-            for (int off = 32; off >= 1; off >>= 1) {
-                const unsigned long long ob = __shfl_xor(best, off);
-                const int oq = __shfl_xor(bq, off);
-                if (ob < best) {
-                    best = ob;
-                    bq = oq;
-                }
-            }
-            if ((tid & 63) == 0) {
-                red[tid >> 6] = best;
-                redq[tid >> 6] = bq;
+                atomicMin(&bestr[r1], k);
+                if (r2 != r1) atomicMin(&bestr[r2], k);
             }
             __syncthreads();
-            if (tid == 0) {
-                unsigned long long b = ~0ull;
-                int q0 = -1;
-                for (int w = 0; w < T / 64; ++w)
-                    if (red[w] < b) {
-                        b = red[w];
-                        q0 = redq[w];
-                    }
-                stop_sh = q0 < 0;
-                if (q0 >= 0) {
-                    const int r1 = q0 / R, r2 = q0 - r1 * R;
-                    used[r1] = used[r2] = 1;
-                    const int ns = nsel_sh;
-                    sel[2 * ns] = (int32_t)(uint32_t)(b & 0xFFFFFFFFu);
-                    sel[2 * ns + 1] = (int)((uint32_t)(b >> 32) ^ 0x80000000u);
-                    nsel_sh = ns + 1;
-                }
+            const int before = nsel_sh;
+            for (size_t q = tid; q < RR; q += T) {
+                const unsigned long long k = S.pairkey[q];
+                if (!key_improving(k)) continue;
+                const int r1 = (int)(q / R), r2 = (int)(q - (size_t)r1 * R);
+                if (used[r1] || used[r2] || bestr[r1] != k || bestr[r2] != k) continue;
+                const int slot = atomicAdd(&nsel_sh, 1);  // < R: the taken candidates share no route
+                pidx[slot] = (int)q;
+                sel[2 * slot] = (int32_t)(uint32_t)(k & 0xFFFFFFFFu);
+                sel[2 * slot + 1] = (int)((uint32_t)(k >> 32) ^ 0x80000000u);
+                stop_sh = 0;
+            }
+            __syncthreads();
+            for (int q = before + tid; q < nsel_sh; q += T) {
+                const int r1 = pidx[q] / R, r2 = pidx[q] - (pidx[q] / R) * R;
+                used[r1] = used[r2] = 1;
             }
             __syncthreads();
             if (stop_sh) break;
+        }
+        // (delta, id) order: sort the selection's keys (bitonic, in LDS)
+        const int cntSel = nsel_sh;
+        int np2 = 1;
+        while (np2 < cntSel) np2 <<= 1;
+        for (int q = tid; q < np2; q += T)
+            keys[q] = q < cntSel ? pack_key(sel[2 * q + 1], (uint32_t)sel[2 * q]) : ~0ull;
+        __syncthreads();
+        for (int kk = 2; kk <= np2; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int q = tid; q < np2; q += T) {
+                    const int p2 = q ^ jj;
+                    if (p2 > q) {
+                        const bool up = (q & kk) == 0;
+                        const unsigned long long a = keys[q], b = keys[p2];
+                        if ((a > b) == up) {
+                            keys[q] = b;
+                            keys[p2] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int q = tid; q < cntSel; q += T) {
+            sel[2 * q] = (int32_t)(uint32_t)(keys[q] & 0xFFFFFFFFu);
+            sel[2 * q + 1] = (int)((uint32_t)(keys[q] >> 32) ^ 0x80000000u);
         }
     }
     __syncthreads();

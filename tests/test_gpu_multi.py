@@ -135,3 +135,19 @@ def test_multi_errors(tga):
     S.set_multi(False)
     with pytest.raises(tga.TGAError):
         S.ls_run(5, 0x1F | tga.OP_MULTI)
+
+
+def test_large_selection_applied_move_by_move(tga):
+    """A selection larger than the one-pass apply holds (more than 546
+    moves) is applied move by move; the step must still equal the oracle's."""
+    inst = W.make_cvrp(3000, 3700)
+    sol = W.random_solution(inst, 1500, 3701)
+    ref, _ = oracle.multi_select(inst, sol, 0x1F, threads=4)
+    assert len(ref) > 546
+    final, applied, per, mv = oracle.local_search_multi(inst, sol, 0x1F, max_steps=1, threads=4)
+    assert per == [len(ref)]
+    I, S = gpu_multi(tga, inst, sol)
+    st, moves, cost = S.ls_run(1, 0x1F | tga.OP_MULTI)
+    assert (st, moves, cost) == (1, mv, oracle.cost(inst, final)[0])
+    off, cust, _ = S.get()
+    assert off.tolist() == final.offsets.tolist() and cust.tolist() == final.customers.tolist()

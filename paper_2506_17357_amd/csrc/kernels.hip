@@ -1466,19 +1466,34 @@ __device__ __forceinline__ Ld ld_after(const SolDev &S, int x) {
     return nodeof(gld(S.a4 + x + 1).x) == 0 ? Ld{0, 0, 0} : ld_of(gld(S.ql4 + x + 1));
 }
 
-// The four inter-route moves of slots x, t (route(x) < route(t)).
+// Distances of a 16 x 16 pair tile, staged in LDS: Dc[i][j] between the
+// row-side slot x0 - 1 + i and the column-side slot t0 - 1 + j (i, j < 20),
+// Rr[i][k - 1] between row-side slots x0 - 1 + i and x0 - 1 + i + k
+// (k = 1..4), Cc likewise on the column side.  Every distance a pair's
+// moves need is one of these (segments reach three slots past x or t).
+constexpr int kTileSpan = 20;
+struct PairTileD {
+    int Dc[kTileSpan][kTileSpan];
+    int Rr[kTileSpan][4];
+    int Cc[kTileSpan][4];
+};
+
+// The inter-route moves of slots x, t (route(x) < route(t)); T holds the
+// tile's distances, xi = x - x0 + 1 and tj = t - t0 + 1 locate the pair.
 template <bool TW, bool PD, bool DUMP>
-__device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t op_mask, int32_t *dd, uint8_t *df,
-                                         int &bd, uint32_t &bid, int &cntExt) {
-    const int np1 = S.np1, n = S.n, cap = S.cap;
-    const int32_t *D = S.D;
+__device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, const PairTileD &T, int xi, int tj,
+                                         uint32_t op_mask, int32_t *dd, uint8_t *df, int &bd, uint32_t &bid,
+                                         int &cntExt) {
+    const int n = S.n, cap = S.cap;
     const uint32_t uQ = (uint32_t)S.Q;
     const int4 ax = gld(S.a4 + x), at = gld(S.a4 + t), bx = gld(S.b4 + x), bt = gld(S.b4 + t);
     const bool cx = flagsof(ax.x) & kFlagCustomer, ct = flagsof(at.x) & kFlagCustomer;
     const int nx = nodeof(ax.x), nt = nodeof(at.x);
-    const int npx = nodeof(gld(S.a4 + max(x - 1, 0)).x), nsx = nodeof(gld(S.a4 + x + 1).x);
-    const int npt = nodeof(gld(S.a4 + t - 1).x), nst = nodeof(gld(S.a4 + t + 1).x);
-    auto d = [&](int i, int j) { return gld(D + (size_t)i * np1 + j); };
+    // X(a, b): distance between slots x + a and t + b; RX(a, k): between
+    // x + a and x + a + k; CT likewise on t's side
+    auto X = [&](int a, int b) { return T.Dc[xi + a][tj + b]; };
+    auto RX = [&](int a, int k) { return T.Rr[xi + a][k - 1]; };
+    auto CT = [&](int b, int k) { return T.Cc[tj + b][k - 1]; };
     const int refX = cx ? nx - 1 : n + ax.y, refT = ct ? nt - 1 : n + at.y;
     const int Lx = bx.z, Lt = bt.z, dx = bx.x, dtt = bt.x;
     const int lvOld = route_excess(S, ax.y) + route_excess(S, at.y);
@@ -1507,41 +1522,41 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
         Mx = ld_node_at(S, x);
         Mt = ld_node_at(S, t);
     }
-    const int exx = d(nx, nsx), ett = d(nt, nst);  // edges leaving x and t
+    const int exx = RX(0, 1), ett = CT(0, 1);  // edges leaving x and t
     // peak loads of the two new routes are passed in (lx, lt)
     auto rec = [&](int dD, int lx, int lt, int tvx, int tvt, uint32_t id) {
         const int lv = max(lx - cap, 0) + max(lt - cap, 0);
         gen_record(S, dD, lv - lvOld, tvx + tvt - tvOld, lv == 0, tvx + tvt == 0, id, DUMP, dd, df, bd, bid);
     };
     if ((op_mask & 1) && cx) {  // RELOCATE x -> right after t
-        const int dD = d(nt, nx) + d(nx, nst) - ett + d(npx, nsx) - d(npx, nx) - exx;
-        const int tvx = TW ? tw_cat(Fpx, d(npx, nsx), Bax).v : 0;
-        const int tvt = TW ? tw_cat(tw_cat(Ft, d(nt, nx), Nx), d(nx, nst), Bat).v : 0;
+        const int dD = X(0, 0) + X(0, 1) - ett + RX(-1, 2) - RX(-1, 1) - exx;
+        const int tvx = TW ? tw_cat(Fpx, RX(-1, 2), Bax).v : 0;
+        const int tvt = TW ? tw_cat(tw_cat(Ft, X(0, 0), Nx), X(0, 1), Bat).v : 0;
         const int lx = PD ? ld_cat(Ppx, Sax).lm : Lx - dx;
         const int lt = PD ? ld_cat(ld_cat(Pt, Mx), Sat).lm : Lt + dx;
         rec(dD, lx, lt, tvx, tvt, (uQ + (uint32_t)refX) * uQ + (uint32_t)refT);
     }
     if ((op_mask & 1) && ct) {  // RELOCATE t -> right after x
-        const int dD = d(nx, nt) + d(nt, nsx) - exx + d(npt, nst) - d(npt, nt) - ett;
-        const int tvx = TW ? tw_cat(tw_cat(Fx, d(nx, nt), Nt), d(nt, nsx), Bax).v : 0;
-        const int tvt = TW ? tw_cat(Fpt, d(npt, nst), Bat).v : 0;
+        const int dD = X(0, 0) + X(1, 0) - exx + CT(-1, 2) - CT(-1, 1) - ett;
+        const int tvx = TW ? tw_cat(tw_cat(Fx, X(0, 0), Nt), X(1, 0), Bax).v : 0;
+        const int tvt = TW ? tw_cat(Fpt, CT(-1, 2), Bat).v : 0;
         const int lx = PD ? ld_cat(ld_cat(Px, Mt), Sax).lm : Lx + dtt;
         const int lt = PD ? ld_cat(Ppt, Sat).lm : Lt - dtt;
         rec(dD, lx, lt, tvx, tvt, (uQ + (uint32_t)refT) * uQ + (uint32_t)refX);
     }
     const uint32_t lo = min((uint32_t)refX, (uint32_t)refT), hi = max((uint32_t)refX, (uint32_t)refT);
     if ((op_mask & 2) && cx && ct) {  // SWAP x <-> t
-        const int dD = d(npx, nt) + d(nt, nsx) + d(npt, nx) + d(nx, nst) - d(npx, nx) - exx - d(npt, nt) - ett;
-        const int tvx = TW ? tw_cat(tw_cat(Fpx, d(npx, nt), Nt), d(nt, nsx), Bax).v : 0;
-        const int tvt = TW ? tw_cat(tw_cat(Fpt, d(npt, nx), Nx), d(nx, nst), Bat).v : 0;
+        const int dD = X(-1, 0) + X(1, 0) + X(0, -1) + X(0, 1) - RX(-1, 1) - exx - CT(-1, 1) - ett;
+        const int tvx = TW ? tw_cat(tw_cat(Fpx, X(-1, 0), Nt), X(1, 0), Bax).v : 0;
+        const int tvt = TW ? tw_cat(tw_cat(Fpt, X(0, -1), Nx), X(0, 1), Bat).v : 0;
         const int lx = PD ? ld_cat(ld_cat(Ppx, Mt), Sax).lm : Lx - dx + dtt;
         const int lt = PD ? ld_cat(ld_cat(Ppt, Mx), Sat).lm : Lt - dtt + dx;
         rec(dD, lx, lt, tvx, tvt, (5u * uQ + lo) * uQ + hi);
     }
     if (op_mask & 4) {  // 2OPT*: heads keep their routes, tails exchanged
-        const int dD = d(nx, nst) + d(nt, nsx) - exx - ett;
-        const int tvx = TW ? tw_cat(Fx, d(nx, nst), Bat).v : 0;
-        const int tvt = TW ? tw_cat(Ft, d(nt, nsx), Bax).v : 0;
+        const int dD = X(0, 1) + X(1, 0) - exx - ett;
+        const int tvx = TW ? tw_cat(Fx, X(0, 1), Bat).v : 0;
+        const int tvt = TW ? tw_cat(Ft, X(1, 0), Bax).v : 0;
         const int lx = PD ? ld_cat(Px, Sat).lm : bx.y + (Lt - bt.y);
         const int lt = PD ? ld_cat(Pt, Sax).lm : bt.y + (Lx - bx.y);
         rec(dD, lx, lt, tvx, tvt, (8u * uQ + lo) * uQ + hi);
@@ -1551,8 +1566,6 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
     // x and at t (kept and reversed summaries, the slot after each segment)
     struct Seg3 {
         int k;         // customers available from the slot on, within its route (<= 3)
-        int node[3];   // the segment's nodes
-        int after[3];  // node after the first k customers (0: the end depot)
         int dem[3];    // deliveries of the first k customers
         Tw f[3], r[3];
         Ld lf[3], lr[3];
@@ -1565,8 +1578,6 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
         int dsum = 0;
         for (int q = 0; q < 3; ++q) {
             const bool in = q < g.k;
-            g.node[q] = in ? nodeof(gld(S.a4 + y + q).x) : 0;
-            g.after[q] = in ? nodeof(gld(S.a4 + y + q + 1).x) : 0;
             dsum += in ? gld(S.b4 + y + q).x : 0;
             g.dem[q] = dsum;
             if (!in) continue;
@@ -1587,24 +1598,26 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
     Seg3 gx, gt;
     if (cx) seg3(x, gx);
     if (ct) seg3(t, gt);
-    // SEGMENT RELOCATE (op 5 kept, op 6 reversed), k = 2, 3: a segment of
-    // route `from` (predecessor np, prefix summaries Fp / Pp, route load
-    // Lf) moves right after slot y of route `to` (node ny, successor ns,
-    // prefix Fy / Py, suffix after it Bay / Say, route load Lto).
-    auto segrel = [&](const Seg3 &g, int np, const Tw &Fp, const Ld &Pp, int Lf, int ny, int ns, const Tw &Fy,
-                      const Ld &Py, const Tw &Bay, const Ld &Say, int Lto, bool fromIsX, uint32_t refA,
-                      uint32_t refB) {
+    // SEGMENT RELOCATE (op 5 kept, op 6 reversed), k = 2, 3: the segment
+    // starting at slot y of route `from` (prefix summaries before it Fp /
+    // Pp, route load Lf) moves right after slot z of route `to` (prefix Fy /
+    // Py, suffix after it Bay / Say, route load Lto); (y, z) = (x, t) when
+    // fromIsX, else (t, x).
+    auto segrel = [&](const Seg3 &g, const Tw &Fp, const Ld &Pp, int Lf, const Tw &Fy, const Ld &Py, const Tw &Bay,
+                      const Ld &Say, int Lto, bool fromIsX, uint32_t refA, uint32_t refB) {
+        auto rf = [&](int a, int k) { return fromIsX ? RX(a, k) : CT(a, k); };  // within `from`
+        auto rt = [&](int b, int k) { return fromIsX ? CT(b, k) : RX(b, k); };  // within `to`
+        auto cr = [&](int a, int b) { return fromIsX ? X(a, b) : X(b, a); };    // y + a and z + b
         for (int k = 2; k <= g.k; ++k) {
-            const int f = g.node[0], gl = g.node[k - 1], na = g.after[k - 1];
-            const int cut = d(np, na) - d(np, f) - d(gl, na);
+            const int cut = rf(-1, k + 1) - rf(-1, 1) - rf(k - 1, 1);
             for (int op = 5; op <= 6; ++op) {
                 if (!(op_mask & (op == 5 ? 32u : 64u))) continue;
-                const int first = op == 5 ? f : gl, lastn = op == 5 ? gl : f;
-                const int dD = cut + d(ny, first) + d(lastn, ns) - d(ny, ns);
+                const int first = op == 5 ? 0 : k - 1, lastp = op == 5 ? k - 1 : 0;  // offsets from y
+                const int dD = cut + cr(first, 0) + cr(lastp, 1) - rt(0, 1);
                 int tvFrom = 0, tvTo = 0;
                 if (TW) {
-                    tvFrom = tw_cat(Fp, d(np, na), g.sa[k - 1]).v;
-                    tvTo = tw_cat(tw_cat(Fy, d(ny, first), op == 5 ? g.f[k - 1] : g.r[k - 1]), d(lastn, ns), Bay).v;
+                    tvFrom = tw_cat(Fp, rf(-1, k + 1), g.sa[k - 1]).v;
+                    tvTo = tw_cat(tw_cat(Fy, cr(first, 0), op == 5 ? g.f[k - 1] : g.r[k - 1]), cr(lastp, 1), Bay).v;
                 }
                 const int lFrom = PD ? ld_cat(Pp, g.la[k - 1]).lm : Lf - g.dem[k - 1];
                 const int lTo = PD ? ld_cat(ld_cat(Py, op == 5 ? g.lf[k - 1] : g.lr[k - 1]), Say).lm : Lto + g.dem[k - 1];
@@ -1617,20 +1630,20 @@ __device__ __forceinline__ void pen_pair(const SolDev &S, int x, int t, uint32_t
             }
         }
     };
-    if (cx) segrel(gx, npx, Fpx, Ppx, Lx, nt, nst, Ft, Pt, Bat, Sat, Lt, true, (uint32_t)refX, (uint32_t)refT);
-    if (ct) segrel(gt, npt, Fpt, Ppt, Lt, nx, nsx, Fx, Px, Bax, Sax, Lx, false, (uint32_t)refT, (uint32_t)refX);
+    if (cx) segrel(gx, Fpx, Ppx, Lx, Ft, Pt, Bat, Sat, Lt, true, (uint32_t)refX, (uint32_t)refT);
+    if (ct) segrel(gt, Fpt, Ppt, Lt, Fx, Px, Bax, Sax, Lx, false, (uint32_t)refT, (uint32_t)refX);
     // CROSS-EXCHANGE (ops 7..9): x's first ka customers and t's first kb
     if ((op_mask & 128u) && cx && ct) {
         for (int ka = 1; ka <= gx.k; ++ka)
             for (int kb = 1; kb <= gt.k; ++kb) {
                 if (ka == 1 && kb == 1) continue;
-                const int xl = gx.node[ka - 1], xa = gx.after[ka - 1], tl = gt.node[kb - 1], ta = gt.after[kb - 1];
-                const int dD = d(npx, nt) + d(tl, xa) + d(npt, nx) + d(xl, ta) - d(npx, nx) - d(xl, xa) -
-                               d(npt, nt) - d(tl, ta);
+                // segment x .. x + ka - 1 and t .. t + kb - 1 exchanged
+                const int dD = X(-1, 0) + X(ka, kb - 1) + X(0, -1) + X(ka - 1, kb) - RX(-1, 1) - RX(ka - 1, 1) -
+                               CT(-1, 1) - CT(kb - 1, 1);
                 int tvx = 0, tvt = 0;
                 if (TW) {
-                    tvx = tw_cat(tw_cat(Fpx, d(npx, nt), gt.f[kb - 1]), d(tl, xa), gx.sa[ka - 1]).v;
-                    tvt = tw_cat(tw_cat(Fpt, d(npt, nx), gx.f[ka - 1]), d(xl, ta), gt.sa[kb - 1]).v;
+                    tvx = tw_cat(tw_cat(Fpx, X(-1, 0), gt.f[kb - 1]), X(ka, kb - 1), gx.sa[ka - 1]).v;
+                    tvt = tw_cat(tw_cat(Fpt, X(0, -1), gx.f[ka - 1]), X(ka - 1, kb), gt.sa[kb - 1]).v;
                 }
                 const int lx = PD ? ld_cat(ld_cat(Ppx, gt.lf[kb - 1]), gx.la[ka - 1]).lm
                                   : Lx - gx.dem[ka - 1] + gt.dem[kb - 1];
@@ -1658,12 +1671,38 @@ __global__ __launch_bounds__(256) void k_eval_pen_pairs(const SolDev *__restrict
         ++bi;
     }
     const int bj = bi + rem;
-    const int x = bi * 16 + (threadIdx.x >> 4), t = bj * 16 + (threadIdx.x & 15);
+    const int x0 = bi * 16, t0 = bj * 16;
+    const int x = x0 + (threadIdx.x >> 4), t = t0 + (threadIdx.x & 15);
+    // the tile's distances: nodes of slots x0 - 1 .. x0 + 22 and t0 - 1 ..
+    // t0 + 22 (clamped to [0, Q]), then one gather per distance
+    __shared__ PairTileD T;
+    __shared__ int nodeX[kTileSpan + 4], nodeT[kTileSpan + 4];
+    {
+        const int Q = S.Q, np1 = S.np1;
+        const int32_t *D = S.D;
+        const int i = threadIdx.x;
+        if (i < kTileSpan + 4) nodeX[i] = nodeof(gld(S.a4 + min(max(x0 - 1 + i, 0), Q)).x);
+        else if (i >= 32 && i < 32 + kTileSpan + 4)
+            nodeT[i - 32] = nodeof(gld(S.a4 + min(max(t0 - 1 + i - 32, 0), Q)).x);
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTileSpan * kTileSpan; e += blockDim.x) {
+            const int a = e / kTileSpan, b = e - a * kTileSpan;
+            T.Dc[a][b] = gld(D + (size_t)nodeX[a] * np1 + nodeT[b]);
+        }
+        for (int e = threadIdx.x; e < 2 * kTileSpan * 4; e += blockDim.x) {
+            const int side = e / (kTileSpan * 4), a = (e / 4) % kTileSpan, k = e % 4 + 1;
+            const int *nd = side ? nodeT : nodeX;
+            const int v = gld(D + (size_t)nd[a] * np1 + nd[a + k]);
+            if (side) T.Cc[a][k - 1] = v;
+            else T.Rr[a][k - 1] = v;
+        }
+        __syncthreads();
+    }
     int bd = DUMP ? kAdmissibleBound : initial_bound(op_mask);
     uint32_t bid = 0xFFFFFFFFu;
     int ext = 0;  // operator-variant moves of this thread's pair
     if (x < S.Q && t < S.Q && gld(S.a4 + x).y < gld(S.a4 + t).y) {
-        pen_pair<TW, PD, DUMP>(S, x, t, op_mask, dd, df, bd, bid, ext);
+        pen_pair<TW, PD, DUMP>(S, x, t, T, x - x0 + 1, t - t0 + 1, op_mask, dd, df, bd, bid, ext);
         // every move of this pair of slots touches exactly their two routes
         if ((op_mask & kMulti) && bd < 0 && bid != 0xFFFFFFFFu)
             atomicMin(S.pairkey + (size_t)gld(S.a4 + x).y * S.R + gld(S.a4 + t).y, pack_key(bd, bid));

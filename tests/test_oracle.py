@@ -358,3 +358,21 @@ def test_threads_do_not_change_result():
     b = oracle.eval_neighbourhood(inst, sol, threads=7, dump=True)
     assert (a[0].delta, a[0].id, a[0].moves) == (b[0].delta, b[0].id, b[0].moves)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("has_tw", [0, 1])
+@pytest.mark.parametrize("n,R,mask", [(5, 2, 0x1F), (6, 3, 0x1F), (7, 3, 0xFF)])
+def test_apply_equals_brute_force_routes(has_tw, n, R, mask):
+    """The oracle's list edits give, for every move of N(S), exactly the new
+    routes the independent brute-force enumerator builds."""
+    import itertools
+    inst = W.tiny_instance(n, 4100 + n + R + has_tw, bool(has_tw))
+    sol = W.random_solution(inst, R, 4200 + n + R)
+    routes = [list(map(int, sol.customers[sol.offsets[r]:sol.offsets[r + 1]])) for r in range(R)]
+    gen = itertools.chain(brute.neighbours(inst, routes, mask & 0x1F), brute.neighbours_ext(inst, routes, mask))
+    count = 0
+    for mid, new, _ in gen:
+        got = oracle.apply_move(inst, sol, int(mid)).routes()
+        assert got == [list(r) for r in new], (mid, oracle.decode(n + R, mid))
+        count += 1
+    assert count > 20

@@ -11,7 +11,6 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <queue>
 #include <vector>
 
 #include "tga.h"
@@ -254,7 +253,8 @@ struct tga_batch {
     int nitems;
     IntraItem *intra;
     int nintra;
-    int *woff;      // device: inter items of workgroup b = items[woff[b] .. woff[b+1])
+    int *woff;      // device: inter items of XCD x = items[woff[x] .. woff[x+1]), largest first
+    uint32_t *qctr; // device: per XCD {items taken, workgroups done} of the launch in flight (zero between launches)
     int *ixoff;     // device: intra-route groups of XCD x = intra[ixoff[x] .. ixoff[x+1])
     int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
@@ -1308,7 +1308,8 @@ static BatchLayout batch_layout(size_t count, int max_items, int nintra) {
     L.desc = take(sizeof(SolDev) * count);
     L.items = take(sizeof(InterItem) * std::max(max_items, 1));
     L.intra = take(sizeof(IntraItem) * std::max(nintra, 1));
-    L.sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (count + 1));  // item list offsets, done flags, step counter
+    // item list offsets, done flags, step counter, item queue counters
+    L.sched = take(4 * (kMaxBatchGrid + 1) + 4 * (kMaxXcds + 1) + 4 * (count + 1) + 8 * kMaxXcds);
     L.coll = take(32 * count);  // collected results
     L.total = off;
     return L;
@@ -1500,34 +1501,19 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         }
         for (const auto &g : groups) xintra[rr++ % nx].push_back(g);
     }
-    // Within an XCD, items go to its workgroups longest first, each to the
-    // workgroup with the least estimated work so far (pairs, TW items
-    // weighted 1.1, plus a fixed cost per item for staging its rows).
+    // Within an XCD, the workgroups take the items from one queue, largest
+    // first (the evaluation launch pulls them with an atomic counter), so the
+    // work of a step spreads over the XCD's workgroups whatever the items
+    // and the intra-route groups cost and whichever solutions have converged.
     if (grid_inter > kMaxBatchGrid) return fail(TGA_ERANGE, "batch grid of %d workgroups", grid_inter);
-    auto cost = [&](const InterItem &a) {
-        return (double)work(a) * (v[a.sol]->h.has_tw ? 1.1 : 1.0) + 3000.0;
-    };
-    const int per_x = grid_inter / nx;
-    std::vector<std::vector<InterItem>> wl(grid_inter);
-    std::vector<int> woff(grid_inter + 1, 0), ixoff(nx + 1, 0);
+    std::vector<int> woff(nx + 1, 0), ixoff(nx + 1, 0);
     for (int x = 0; x < nx; ++x) {
         std::stable_sort(xitems[x].begin(), xitems[x].end(),
                          [&](const InterItem &a, const InterItem &b) { return work(a) > work(b); });
-        std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>,
-                            std::greater<std::pair<double, int>>> heap;
-        for (int j = 0; j < per_x; ++j) heap.push({0.0, j});
-        for (const auto &it : xitems[x]) {
-            auto top = heap.top();
-            heap.pop();
-            wl[x + top.second * nx].push_back(it);
-            heap.push({top.first + cost(it), top.second});
-        }
+        items.insert(items.end(), xitems[x].begin(), xitems[x].end());
+        woff[x + 1] = (int)items.size();
         intra.insert(intra.end(), xintra[x].begin(), xintra[x].end());
         ixoff[x + 1] = (int)intra.size();
-    }
-    for (int b = 0; b < grid_inter; ++b) {
-        items.insert(items.end(), wl[b].begin(), wl[b].end());
-        woff[b + 1] = (int)items.size();
     }
     if ((int)items.size() > B->max_items || (int)intra.size() > B->max_intra)
         return fail(TGA_ERANGE, "batch schedule exceeds its workspace");
@@ -1560,7 +1546,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
     if (e == hipSuccess && !intra.empty())
         e = hipMemcpyAsync(B->intra, intra.data(), sizeof(IntraItem) * intra.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(B->woff, woff.data(), sizeof(int) * (grid_inter + 1), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(B->woff, woff.data(), sizeof(int) * woff.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(B->steps, 0, sizeof(int32_t), st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->ixoff, ixoff.data(), sizeof(int) * (nx + 1), hipMemcpyHostToDevice, st);
@@ -1612,6 +1598,7 @@ static int batch_init(tga_batch *B, int max_items, int nintra, void *ws, hipStre
     B->ixoff = B->woff + (kMaxBatchGrid + 1);
     B->done = B->ixoff + (kMaxXcds + 1);
     B->steps = B->done + count;
+    B->qctr = (uint32_t *)(B->steps + 1);
     B->coll = (long long *)(base + L.coll);
     B->exec = nullptr;
     B->graph = nullptr;
@@ -1637,6 +1624,8 @@ static int batch_init(tga_batch *B, int max_items, int nintra, void *ws, hipStre
         k_zero_i32<<<1, 64, 0, st>>>(B->steps, 1);
         HIPCHK(hipGetLastError());
     }
+    k_zero_i32<<<1, 64, 0, st>>>((int32_t *)B->qctr, 2 * kMaxXcds);  // then kept at zero by the launches
+    HIPCHK(hipGetLastError());
     DevProps P;
     int rc = props(&P);
     if (rc) return rc;
@@ -1766,22 +1755,22 @@ static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream
     const bool cnt = ls && (op_mask & TGA_OP_COUNT_FULL);
     if (!B->cfg.split) {
         if (cnt)
-            k_eval_batch<7><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                         B->ixoff, B->nx, op_mask, B->steps);
+            k_eval_batch<7><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
+                                                                         B->intra, B->ixoff, B->nx, op_mask, B->steps);
         else
-            k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                         B->ixoff, B->nx, op_mask, B->steps);
+            k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
+                                                                         B->intra, B->ixoff, B->nx, op_mask, B->steps);
         return;
     }
     if ((op_mask & 7) && cnt)
-        k_eval_batch<5><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                     B->ixoff, B->nx, op_mask, B->steps);
+        k_eval_batch<5><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
+                                                                     B->intra, B->ixoff, B->nx, op_mask, B->steps);
     else if (op_mask & 7)
-        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->intra,
-                                                                     B->ixoff, B->nx, op_mask, B->steps);
+        k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
+                                                                     B->intra, B->ixoff, B->nx, op_mask, B->steps);
     if (op_mask & (2 | 8 | 16))
         k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
-            B->d, B->items, B->woff, B->intra, B->ixoff, B->nx, op_mask, B->steps);
+            B->d, B->items, B->woff, B->qctr, B->intra, B->ixoff, B->nx, op_mask, B->steps);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {

@@ -2117,14 +2117,13 @@ constexpr int kGatherBatch = 8;    // distance gathers in flight per lane while 
 // gathered and no entry is read or written.  Each lane keeps up to
 // kGatherBatch loads in flight before it stores them, so a group costs a
 // couple of memory round trips.
+__device__ __forceinline__ void gather_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],
+                                                   const int (&at)[kIntraMaxGroup], int G, int r0, uint32_t hit,
+                                                   uint32_t fill);
+
 __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],
                                                   const int (&at)[kIntraMaxGroup], int G, int r0, bool cache) {
     const int lane = threadIdx.x & 63;
-    int cum[kIntraMaxGroup + 1];
-    cum[0] = 0;
-#pragma unroll
-    for (int k = 0; k < kIntraMaxGroup; ++k) cum[k + 1] = cum[k] + (k < G ? P[k] * P[k] : 0);
-    const int E = cum[kIntraMaxGroup];
     // which routes' cached blocks are current (bit k), and which entries to rewrite
     uint32_t hit = 0, fill = 0;
 #pragma unroll
@@ -2150,7 +2149,22 @@ __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, 
                     __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
         }
     }
-    // the other routes: gathered from D
+    gather_dist_blocks(S, region, P, at, G, r0, hit, fill);
+}
+
+// The P x P blocks of the routes of the group not in `hit`, gathered from D
+// into the region (and, for the routes in `fill`, into their cache
+// entries); then, once every load issued before has landed, the nodes and
+// P of the rewritten entries.
+__device__ __forceinline__ void gather_dist_blocks(const SolDev &S, int *region, const int (&P)[kIntraMaxGroup],
+                                                   const int (&at)[kIntraMaxGroup], int G, int r0, uint32_t hit,
+                                                   uint32_t fill) {
+    const int lane = threadIdx.x & 63;
+    int cum[kIntraMaxGroup + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) cum[k + 1] = cum[k] + (k < G ? P[k] * P[k] : 0);
+    const int E = cum[kIntraMaxGroup];
     if (hit != (1u << G) - 1u) {
         for (int x0 = 0; x0 < E; x0 += 64 * kGatherBatch) {
             int val[kGatherBatch], dst[kGatherBatch], cst[kGatherBatch];
@@ -2188,7 +2202,7 @@ __device__ __forceinline__ void stage_dist_blocks(const SolDev &S, int *region, 
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the LDS DMA above has landed (the caller then syncs the wavefront)
+    __builtin_amdgcn_s_waitcnt(0);  // the gathers and the caller's LDS DMA have landed (the caller then syncs the wavefront)
     // entries rewritten above: their nodes, then P
 #pragma unroll
     for (int k = 0; k < kIntraMaxGroup; ++k) {
@@ -2317,6 +2331,331 @@ __device__ __forceinline__ void intra_group(const SolDev &S, const IntraItem &it
     if (lane == 0 && bd < kAdmissibleBound && bid != 0xFFFFFFFFu) atomicMin(S.best_key, pack_key(bd, bid));
 }
 
+// The intra-route moves of one (i, j) cell of route r (L customers, staged
+// view V, 1 <= i <= L, 0 <= j <= L): 2OPT(i, j) and SWAP(i, j) when i < j,
+// and the or-opt moves of the segments of length k = 1..3 that start at c_i
+// to right after c_j (j >= i + k forward, j <= i - 2 backward).  The cells of
+// the grid hold every intra-route move exactly once, with the deltas,
+// feasibility and ids of intra_moves; the deltas come first (every position
+// clamped into the route, invalid moves masked), and the time-window
+// summaries of a move are built only when its delta can still reach bd, in
+// the order intra_moves builds them.
+template <bool TW>
+__device__ __forceinline__ void intra_cell(const SolDev &S, const RouteLds &V, int r, int L, int i, int j,
+                                           bool opSwap, bool op2o, bool opOr, int &bd, uint32_t &bid) {
+    const int jm = max(j - 1, 0);
+    const int eP = V.edge(i - 1), eI = V.edge(i), eJ = V.edge(j), eJm = V.edge(jm);
+    const int d1 = V.dd(i - 1, j), d2 = V.dd(i, j + 1);  // j + 1 <= L + 1
+    const int dA = V.dd(j, i + 1), dB = V.dd(jm, i);
+    const int dVF = V.dd(j, i);
+    const bool up = j > i;
+    const int dlt2 = d1 + d2 - eP - eJ;
+    const int dS = j > i + 1 ? d1 + dA + dB + d2 - eP - eI - eJm - eJ : dlt2;
+    int m = kNoDelta;
+    if (up && op2o) m = min(m, dlt2);
+    if (up && opSwap) m = min(m, dS);
+    int dOr[3];
+    bool vOr[3];
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        const int g = min(i + k - 1, L);  // last node of the segment (clamped when it does not fit)
+        dOr[k - 1] = V.dd(i - 1, g + 1) - eP - V.edge(g) + dVF + V.dd(g, j + 1) - eJ;
+        vOr[k - 1] = opOr && i + k - 1 <= L && (j >= i + k || j <= i - 2);
+        if (vOr[k - 1]) m = min(m, dOr[k - 1]);
+    }
+    if (m > bd) return;  // rare late in a search: no move of the cell can reach the lane's best
+
+    const uint32_t uQ = (uint32_t)S.Q;
+    const uint32_t refI = (uint32_t)(V.node(i) - 1);
+    const uint32_t refJ = j == 0 ? (uint32_t)(S.n + r) : (uint32_t)(V.node(j) - 1);
+    const int depP = TW ? V.dep(i - 1) : 0;
+    auto segAt = [&](int p) { return seg_node(V.e(p), V.l(p), V.s(p)); };
+    if (up && min(op2o ? dlt2 : kNoDelta, opSwap ? dS : kNoDelta) <= bd) {
+        bool tw2 = true, twS = true;
+        if (TW) {
+            // c_i .. c_j reversed
+            Seg rev = segAt(i);
+            for (int q = i + 1; q <= j; ++q) rev = seg_cat(segAt(q), V.edge(q - 1), rev);
+            tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
+            twS = tw2;
+            if (j > i + 1) {
+                const int arr0 = depP + d1;
+                bool ok = arr0 <= V.l(j);
+                const int t0 = max(arr0, V.e(j)) + V.s(j);
+                // middle c_{i+1} .. c_{j-1}
+                Seg mid = segAt(i + 1);
+                for (int q = i + 2; q <= j - 1; ++q) mid = seg_cat(mid, V.edge(q - 1), segAt(q));
+                const int dM = seg_pass(mid, t0 + dA);
+                const int arrI = dM + dB;
+                ok = ok && dM < kInf && arrI <= V.l(i);
+                const int t2 = max(arrI, V.e(i)) + V.s(i);
+                twS = ok && (t2 + d2 <= V.z(j + 1));
+            }
+        }
+        const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
+        if (op2o && tw2) consider(dlt2, (12u * uQ + lo) * uQ + hi, bd, bid);
+        if (opSwap && twS) consider(dS, (5u * uQ + lo) * uQ + hi, bd, bid);
+    }
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        if (!vOr[k - 1] || dOr[k - 1] > bd) continue;
+        bool tw = true;
+        if (TW) {
+            const int g = i + k - 1, w = i + k;
+            Seg sig = segAt(i);
+            for (int q = 1; q < k; ++q) sig = seg_cat(sig, V.edge(i + q - 1), segAt(i + q));
+            const int dPW = V.dd(i - 1, w), dGV = V.dd(g, j + 1);
+            if (j >= w) {  // forward: middle c_w .. c_j
+                Seg mid = segAt(w);
+                for (int q = w + 1; q <= j; ++q) mid = seg_cat(mid, V.edge(q - 1), segAt(q));
+                const int dm = seg_pass(mid, depP + dPW);
+                const int ds = dm >= kInf ? kInf : seg_pass(sig, dm + dVF);
+                tw = ds < kInf && ds + dGV <= V.z(j + 1);
+            } else {  // backward: middle c_{j+1} .. c_{i-1}
+                Seg mid = segAt(i - 1);
+                for (int q = i - 2; q >= j + 1; --q) mid = seg_cat(segAt(q), V.edge(q), mid);
+                const int ds = seg_pass(sig, V.dep(j) + dVF);
+                const int dmm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
+                tw = dmm < kInf && dmm + dPW <= V.z(w);
+            }
+        }
+        if (tw) consider(dOr[k - 1], ((16u + k) * uQ + refI) * uQ + refJ, bd, bid);
+    }
+}
+
+// A route staged in a region has fewer than 64 positions, so a row of its
+// cell grid (L + 1 cells) fits the wavefront.
+static_assert(7 * 64 + 64 * 64 > kIntraRegionBytes / 4, "staged route within one wavefront row");
+
+// bits [lo, hi) of a 64-bit word (lo and hi clamped to [0, 64])
+__device__ __forceinline__ unsigned long long bit_range(int lo, int hi) {
+    lo = max(lo, 0);
+    hi = min(hi, 64);
+    if (lo >= hi) return 0ull;
+    const unsigned long long top = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return top & ~((1ull << lo) - 1ull);
+}
+
+// intra_group for the batched local-search launch (no dump, every walk of
+// every route of the group in one wavefront).  A group that fits the region
+// is staged with every load issued at once: the routes' per-position
+// attributes and loads, their cache entries' P and nodes, and the cached
+// distance blocks themselves (LDS DMA, before it is known whether they are
+// current; a route whose entry turns out stale is then gathered from D over
+// it).  With current entries the staging thus costs one memory round trip
+// after the route offsets instead of several per route.  The moves are then
+// taken one (i, j) cell per lane, the cells of a route laid over the
+// wavefront as rows of L + 1 lanes.  Any other group goes to intra_group.
+template <bool TW>
+__device__ __forceinline__ void intra_group_flat(const SolDev &S, const IntraItem &item, uint32_t op_mask,
+                                                 int *region) {
+    const int lane = threadIdx.x & 63;
+    const int G = min(item.r1 - item.r0, kIntraMaxGroup);
+    int offs[kIntraMaxGroup + 1];
+#pragma unroll
+    for (int k = 0; k <= kIntraMaxGroup; ++k) offs[k] = sld1(S.roff + min(item.r0 + k, item.r1));
+    int P[kIntraMaxGroup], at[kIntraMaxGroup], cumP[kIntraMaxGroup + 1];
+    int sumL = 0, words = 0;
+    cumP[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        P[k] = k < G ? offs[k + 1] - offs[k] + 1 : 0;
+        at[k] = words;
+        if (k < G) {
+            sumL += P[k] - 2;
+            words += 7 * P[k] + P[k] * P[k];
+        }
+        cumP[k + 1] = cumP[k] + P[k];
+    }
+    if (!(sumL <= 64 && words <= kIntraRegionBytes / 4)) {
+        intra_group<TW, false>(S, item, op_mask, -1, nullptr, nullptr, region);
+        return;
+    }
+    const int l0 = TW ? S.node4[0].z : kTwOff;
+    const int NP = cumP[kIntraMaxGroup];  // positions of the group, <= 64 + 2 * kIntraMaxGroup
+    // flat position f = lane + 64 u -> route k, position p: every load first
+    int4 va[2], vt[2], vw[2];
+    int cn[2], hd[2], ld[2], fk[2], fp[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int f = lane + 64 * u;
+        int k = 0, pk = P[0], ok = offs[0], ck = 0;
+#pragma unroll
+        for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
+            if (kk < G && f >= cumP[kk]) {
+                k = kk;
+                pk = P[kk];
+                ok = offs[kk];
+                ck = cumP[kk];
+            }
+        }
+        const int p = f - ck;
+        fk[u] = f < NP ? k : -1;
+        fp[u] = p;
+        va[u] = vt[u] = vw[u] = make_int4(0, 0, 0, 0);
+        cn[u] = hd[u] = -2;
+        ld[u] = 0;
+        if (f < NP) {
+            const int *c = S.rblk + (size_t)(item.r0 + k) * kRouteBlockWords;
+            if (p <= pk - 2) {
+                va[u] = gld(S.a4 + ok + p);
+                if (TW) {
+                    vt[u] = gld(S.t4 + ok + p);
+                    vw[u] = gld(S.w4 + ok + p);
+                }
+            }
+            if (pk <= kRouteBlockMaxP) cn[u] = gld(c + kRouteBlockNodes + p);
+            if (p == 0) {
+                hd[u] = gld(c);
+                ld[u] = gld(S.b4 + ok).z;
+            }
+        }
+    }
+    // the cached blocks, copied whether or not they are current
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if (k < G && P[k] <= kRouteBlockMaxP) {
+            const int *src = S.rblk + (size_t)(item.r0 + k) * kRouteBlockWords + kRouteBlockData;
+            int *dst = region + at[k] + 7 * P[k];
+            const int PP = P[k] * P[k];
+            for (int c = 0; c < PP; c += 64)
+                if (c + lane < PP)
+                    __builtin_amdgcn_global_load_lds((global_void_ptr)(src + c + lane), (lds_void_ptr)(dst + c), 4, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the DMA has landed before any of it is overwritten or read
+    // per-position arrays (as stage_route), and per route: cache entry
+    // current, route load within capacity (bits at the route's first
+    // flat position)
+    unsigned long long mism[2], hdok[2], capok[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        bool bad = false, hok = false, cok = false;
+        if (fk[u] >= 0) {
+            int k = 0;
+#pragma unroll
+            for (int kk = 1; kk < kIntraMaxGroup; ++kk) k = fk[u] == kk ? kk : k;
+            int pk = P[0], ak = at[0];
+#pragma unroll
+            for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
+                if (k == kk) {
+                    pk = P[kk];
+                    ak = at[kk];
+                }
+            }
+            const int p = fp[u];
+            int *b = region + ak;
+            int node;
+            if (p <= pk - 2) {
+                node = nodeof(va[u].x);
+                b[p] = node;
+                b[pk + p] = va[u].z;
+                if (TW) {
+                    b[2 * pk + p] = vt[u].x;
+                    b[3 * pk + p] = vt[u].w;
+                    b[4 * pk + p] = vw[u].x;
+                    b[5 * pk + p] = vw[u].y;
+                    b[6 * pk + p] = vw[u].z;
+                }
+            } else {
+                node = 0;
+                b[p] = 0;
+                b[pk + p] = 0;
+                b[3 * pk + p] = l0;
+            }
+            bad = pk <= kRouteBlockMaxP && cn[u] != node;
+            hok = p == 0 && hd[u] == pk;
+            cok = p == 0 && ld[u] <= S.cap;
+        }
+        mism[u] = __builtin_amdgcn_ballot_w64(bad);
+        hdok[u] = __builtin_amdgcn_ballot_w64(hok);
+        capok[u] = __builtin_amdgcn_ballot_w64(cok);
+    }
+    uint32_t hit = 0, fill = 0, capOK = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        if (k < G) {
+            const int c0 = cumP[k], c1 = cumP[k + 1];
+            const bool stale = ((mism[0] & bit_range(c0, c1)) | (mism[1] & bit_range(c0 - 64, c1 - 64))) != 0ull;
+            const bool hdr = ((c0 < 64 ? hdok[0] >> c0 : hdok[1] >> (c0 - 64)) & 1ull) != 0ull;
+            const bool cap = ((c0 < 64 ? capok[0] >> c0 : capok[1] >> (c0 - 64)) & 1ull) != 0ull;
+            if (P[k] <= kRouteBlockMaxP) {
+                const bool cur = hdr && !stale;
+                hit |= (cur ? 1u : 0u) << k;
+                fill |= (cur ? 0u : 1u) << k;
+            }
+            capOK |= (cap ? 1u : 0u) << k;
+        }
+    }
+    wave_lds_sync();  // the nodes are in place for the gathers
+    gather_dist_blocks(S, region, P, at, G, item.r0, hit, fill);
+    wave_lds_sync();
+
+    int bd = initial_bound(op_mask);
+    uint32_t bid = 0xFFFFFFFFu;
+    if (TW) {
+        // Time windows: most moves with a negative delta break a window, and
+        // the walks carry the segment summaries from one move to the next,
+        // so their check is O(1) where a cell's would be O(L): one lane per
+        // (route, first position), as intra_group.
+        int myk = -1, myi = 0, cum = 0;
+#pragma unroll
+        for (int k = 0; k < kIntraMaxGroup; ++k) {
+            const int L = P[k] - 2;
+            if (k < G && myk < 0 && lane < cum + L) {
+                myk = k;
+                myi = lane - cum + 1;
+            }
+            cum += k < G ? L : 0;
+        }
+        if (myk >= 0) {
+            int pk = P[0], ak = at[0];
+#pragma unroll
+            for (int kk = 1; kk < kIntraMaxGroup; ++kk) {
+                if (myk == kk) {
+                    pk = P[kk];
+                    ak = at[kk];
+                }
+            }
+            int *b = region + ak;
+            const RouteLds V{b, b + pk, b + 2 * pk, b + 3 * pk, b + 4 * pk, b + 5 * pk, b + 6 * pk, b + 7 * pk, pk};
+            intra_moves<TW, false, false>(S, V, item.r0 + myk, pk - 2, myi, 1 << 30, (capOK >> myk) & 1, op_mask, -1,
+                                          nullptr, nullptr, bd, bid);
+        }
+        wave_lds_sync();
+        wave_argmin(bd, bid);
+        if (lane == 0 && bd < kAdmissibleBound && bid != 0xFFFFFFFFu) atomicMin(S.best_key, pack_key(bd, bid));
+        return;
+    }
+    const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
+    // route k's P and region offset sit in lane k (read back uniformly below,
+    // so that the route loop is not unrolled)
+    int laneP = 0, laneAt = 0;
+#pragma unroll
+    for (int k = 0; k < kIntraMaxGroup; ++k) {
+        laneP = lane == k ? P[k] : laneP;
+        laneAt = lane == k ? at[k] : laneAt;
+    }
+#pragma unroll 1
+    for (int k = 0; k < G; ++k) {
+        const int Pk = __builtin_amdgcn_readlane(laneP, k), L = Pk - 2;
+        if (L < 1 || !((capOK >> k) & 1)) continue;  // over capacity: no admissible move
+        int *b = region + __builtin_amdgcn_readlane(laneAt, k);
+        const RouteLds V{b, b + Pk, b + 2 * Pk, b + 3 * Pk, b + 4 * Pk, b + 5 * Pk, b + 6 * Pk, b + 7 * Pk, Pk};
+        // cells per row, rows per pass (W <= 62, see above)
+        const int W = L + 1, rpi = 64 / W;
+        const int di = lane / W, j = lane - di * W;
+#pragma unroll 1
+        for (int i0 = 1; i0 <= L; i0 += rpi) {
+            const int i = i0 + di;
+            if (di < rpi && i <= L) intra_cell<TW>(S, V, item.r0 + k, L, i, j, opSwap, op2o, opOr, bd, bid);
+        }
+    }
+    wave_lds_sync();  // the region is free for the next group
+    wave_argmin(bd, bid);
+    if (lane == 0 && bd < kAdmissibleBound && bid != 0xFFFFFFFFu) atomicMin(S.best_key, pack_key(bd, bid));
+}
+
 template <bool TW, bool DUMP>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_intra(
     const SolDev *__restrict__ sols, const IntraItem *__restrict__ items, int nitems, uint32_t op_mask,
@@ -2418,17 +2757,22 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
 // inter-route items fill the tail; PH = 1 and PH = 2 are the two halves as
 // separate launches.
 // Solutions of both problem types and both distance widths share a launch;
-// each item takes the path of its own solution.  Static schedule planned on
-// the host: workgroup b (dispatched to XCD b mod nx) takes the inter-route
-// items items[woff[b] .. woff[b + 1]) (all of solutions placed on that XCD);
+// each item takes the path of its own solution.  Workgroup b is dispatched
+// to XCD x = b mod nx and works on the items of the solutions placed there:
 // its wavefronts take the intra-route groups j * 8 + wave, then every
-// (G' * 8)-th after it, of the XCD's group list, where j = b / nx and
-// G' = gridDim.x / nx.
+// (G' * 8)-th after it, of the XCD's group list (j = b / nx, G' =
+// gridDim.x / nx); then the workgroup pulls the XCD's inter-route items
+// items[woff[x] ..  woff[x + 1]) (largest first) from a queue, counter
+// qctr[2x] (items taken), so that whichever workgroup is free takes the
+// next one.  Each workgroup's next pull is issued while it evaluates its
+// current item.  A workgroup that finds the queue empty counts itself in
+// qctr[2x + 1]; the last of the XCD's workgroups to do so puts both
+// counters back to zero, ready for the next launch.
 template <int PH>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
     const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ woff,
-    const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx, uint32_t op_mask,
-    const int *__restrict__ steps) {
+    uint32_t *__restrict__ qctr, const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx,
+    uint32_t op_mask, const int *__restrict__ steps) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int thr_sh;
@@ -2442,22 +2786,30 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
             const SolDev &S = sols[item.sol];
             if (skip_solution(S, op_mask)) continue;
             if (S.has_tw)
-                intra_group<true, false>(S, item, op_mask, -1, nullptr, nullptr, region);
+                intra_group_flat<true>(S, item, op_mask, region);
             else
-                intra_group<false, false>(S, item, op_mask, -1, nullptr, nullptr, region);
+                intra_group_flat<false>(S, item, op_mask, region);
         }
     }
     __syncthreads();  // the intra-route regions and the inter-route rows share LDS
     if ((PH & 1) && (op_mask & 7)) {
-        // every other step walks the list backwards, so that a step starts on
-        // the distance rows the previous one read last (still in cache)
-        const int first = woff[blockIdx.x], cnt = woff[blockIdx.x + 1] - first;
-        const bool back = __builtin_amdgcn_readfirstlane(*steps) & 1;
-        for (int k = 0; k < cnt; ++k) {
-            const int it = back ? first + cnt - 1 - k : first + k;
-            const InterItem item = items[it];
+        __shared__ int q_sh[2];  // pulled item index, alternate slots by iteration
+        const int first = woff[x], cnt = woff[x + 1] - first;
+        uint32_t *taken = qctr + 2 * x, *finished = taken + 1;
+        if (threadIdx.x == 0) q_sh[0] = (int)atomicAdd(taken, 1u);
+        __syncthreads();
+        for (int round = 0;; ++round) {
+            const int k = q_sh[round & 1];
+            if (k >= cnt) break;  // the same for the whole workgroup
+            int next = 0;
+            if (threadIdx.x == 0) next = (int)atomicAdd(taken, 1u);  // lands while this item is evaluated
+            const InterItem item = items[first + k];
             const SolDev &S = sols[item.sol];
-            if (skip_solution(S, op_mask)) continue;
+            if (skip_solution(S, op_mask)) {
+                if (threadIdx.x == 0) q_sh[(round + 1) & 1] = next;
+                __syncthreads();
+                continue;
+            }
             constexpr bool CNT = (PH & 4) != 0;
             if (S.has_tw) {
                 if (S.D16)
@@ -2470,6 +2822,15 @@ __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4
                 else
                     inter_item<false, false, false, CNT>(S, item, op_mask, nullptr, nullptr, smem4, red, &thr_sh);
             }
+            // slot (round + 1) & 1 was last read in the previous round, before
+            // that round's closing barrier
+            if (threadIdx.x == 0) q_sh[(round + 1) & 1] = next;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && atomicAdd(finished, 1u) == gridDim.x / nx - 1) {
+            // every workgroup of the XCD has made its last pull
+            atomicExch(taken, 0u);
+            atomicExch(finished, 0u);
         }
     }
 }
@@ -2971,7 +3332,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_multi_step(const SolDev *__re
     // every attribute.  The decoded moves reuse the key array; a selection
     // too large for it is applied move by move instead.
     MoveInfo *mv = reinterpret_cast<MoveInfo *>(keys);
-    constexpr int kBatchApply = (int)(sizeof(keys) / sizeof(MoveInfo));
+    constexpr int kBatchApply = (int)(sizeof(keys) / (sizeof(MoveInfo)));
     if (ns <= kBatchApply) {
         int *mov_of = pidx;  // per route: the selected move touching it, or -1
         for (int r = tid; r < R; r += T) mov_of[r] = -1;

@@ -101,9 +101,15 @@ def valu_entry(avg_launch_us):
     if t is None:
         return None
     peak_per_us = 256 * 4 * 2400.0 / 4
-    return {"valu_insts_per_launch": t["valu_insts_per_launch"],
-            "frac": round(t["valu_insts_per_launch"] / (avg_launch_us * peak_per_us), 4),
-            "source": "profiles/valu_k_eval_batch_batched256.json"}
+    out = {"valu_insts_per_launch": t["valu_insts_per_launch"],
+           "frac": round(t["valu_insts_per_launch"] / (avg_launch_us * peak_per_us), 4),
+           "source": "profiles/valu_k_eval_batch_batched256.json"}
+    q = committed_counters("sq_k_eval_batch_batched256.json")
+    if q is not None and "wait_any_share" in q:
+        # share of the wavefronts' cycles spent waiting (s_waitcnt, barriers)
+        out["wave_cycles_waiting"] = q["wait_any_share"]
+        out["wait_source"] = "profiles/sq_k_eval_batch_batched256.json"
+    return out
 
 
 def calibrate_copy():

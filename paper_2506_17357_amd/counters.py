@@ -12,8 +12,15 @@ dispatches, one whole local-search pass of the benchmark.
 VALU: one run with --pmc SQ_INSTS_VALU; wavefront VALU instructions per
 launch, the same dispatches.
 
+SQ: runs with --pmc and up to eight SQ_ counters each; the mean of every
+counter over the same dispatches, and the shares of wave cycles spent
+waiting (SQ_WAIT_ANY, SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES) and issuing VALU
+instructions (SQ_ACTIVE_INST_VALU over SQ_WAVE_CYCLES; both in the same
+units).
+
     python -m paper_2506_17357_amd.counters traffic <fetch dir> <write dir> --last 200 --out <json>
     python -m paper_2506_17357_amd.counters valu <dir> --last 200 --out <json>
+    python -m paper_2506_17357_amd.counters sq <dir> [<dir> ...] --last 200 --out <json>
     python -m paper_2506_17357_amd.counters trace <kernel-trace results.db> --last 200
 """
 from __future__ import annotations
@@ -117,6 +124,27 @@ def valu(path: str, kernel: str = "k_eval_batch<3>", last: int = 200) -> dict:
             "kernel_source_sha256": kernel_source_hash()}
 
 
+def sq(paths, kernel: str = "k_eval_batch<3>", last: int = 200) -> dict:
+    means = {}
+    for path in paths:
+        names = set()
+        for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn, newline="") as f:
+                names.update(r["Counter_Name"] for r in csv.DictReader(f))
+        for c in sorted(names):
+            v = dispatch_values(load(path, c), kernel, last)
+            means[c] = sum(v) / len(v)
+    out = {"kernel": kernel, "dispatches": last, "means_per_launch": {k: round(v, 1) for k, v in means.items()}}
+    cyc = means.get("SQ_WAVE_CYCLES")
+    if cyc:
+        for num, name in (("SQ_WAIT_ANY", "wait_any_share"), ("SQ_WAIT_INST_ANY", "wait_inst_any_share"),
+                          ("SQ_ACTIVE_INST_VALU", "valu_active_share")):
+            if num in means:
+                out[name] = round(means[num] / cyc, 4)
+    out["kernel_source_sha256"] = kernel_source_hash()
+    return out
+
+
 def trace(db: str, kernel: str = "k_eval_batch<3>", last: int = 200, top: int = 12) -> str:
     """Markdown summary of a rocprofv3 --kernel-trace database: the mean
     duration of the last `last` dispatches of `kernel` (one pass of the
@@ -154,7 +182,9 @@ def main():
     t.add_argument("write_dir")
     v = sub.add_parser("valu")
     v.add_argument("dir")
-    for p in (t, v):
+    q = sub.add_parser("sq")
+    q.add_argument("dirs", nargs="+")
+    for p in (t, v, q):
         p.add_argument("--kernel", default="k_eval_batch<3>")
         p.add_argument("--last", type=int, default=200)
         p.add_argument("--out", required=True)
@@ -166,6 +196,8 @@ def main():
         return
     if a.what == "traffic":
         doc = traffic(a.fetch_dir, a.write_dir, a.kernel, a.last)
+    elif a.what == "sq":
+        doc = sq(a.dirs, a.kernel, a.last)
     else:
         doc = valu(a.dir, a.kernel, a.last)
     doc["workload"] = a.workload

@@ -322,3 +322,38 @@ def test_screen_counters(tga, use_graph):
     v, a = screen_expectation(inst, sol, 1000)
     assert visited == v and a <= full < visited // 4
     B.close()
+
+
+def shaped_solution(inst, lengths, seed):
+    """The customers in random order, cut into routes of the given lengths."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(np.arange(1, inst.n + 1)).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    assert off[-1] == inst.n
+    return W.Solution(off, perm)
+
+
+def test_batch_intra_route_shapes(tga):
+    """Route shapes that take every intra-route path of the batched launch:
+    groups that fit their wavefront's LDS region (one cell per lane for CVRP,
+    walks for VRPTW, empty routes among them), a group beyond the region's 64
+    first positions (its routes staged one at a time), a route too long to
+    stage (read from the slot arrays), and routes over capacity."""
+    shapes = [[70], [38, 30, 12, 10, 10], [0, 14, 9, 0, 16, 11, 0, 10]]
+    pairs = []
+    for k, lens in enumerate(shapes):
+        for tw in (False, True):
+            inst = W.tiny_instance(sum(lens), 5100 + 10 * k + tw, tw)
+            if k == 1:
+                inst.capacity = int(inst.node4[:, 0].sum() // 3)
+            pairs.append((inst, shaped_solution(inst, lens, 5200 + 10 * k + tw)))
+    insts, sols = make_solutions(tga, pairs)
+    print("intra-route shapes", [s.R for s in sols], flush=True)
+    B = tga.Batch(sols)
+    steps, moves, cost = B.ls_run(30)
+    B.close()
+    for b, (inst, sol) in enumerate(pairs):
+        final, ids, _, mv = oracle.local_search(inst, sol, max_steps=30)
+        assert (steps[b], moves[b], cost[b]) == (len(ids), mv, oracle.cost(inst, final)[0]), b
+        off, cust, _ = sols[b].get()
+        assert off.tolist() == final.offsets.tolist() and cust.tolist() == final.customers.tolist(), b

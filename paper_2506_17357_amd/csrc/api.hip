@@ -258,7 +258,7 @@ struct tga_batch {
     int *ixoff;     // device: intra-route groups of XCD x = intra[ixoff[x] .. ixoff[x+1])
     int nx;         // XCDs the items are spread over
     int32_t *done;  // per-solution converged flags gathered by tga_batch_poll
-    int32_t *steps; // device: evaluation steps run (the inter-route lists alternate direction)
+    int32_t *steps; // device: evaluation steps run (advanced by the finalize launch)
     long long *coll = nullptr;    // device: {steps, version, moves, cost} per solution (k_collect)
     long long *coll_h = nullptr;  // pinned host copy of coll
     size_t lds;

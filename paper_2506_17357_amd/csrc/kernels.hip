@@ -2427,6 +2427,129 @@ __device__ __forceinline__ void intra_cell(const SolDev &S, const RouteLds &V, i
 // cell grid (L + 1 cells) fits the wavefront.
 static_assert(7 * 64 + 64 * 64 > kIntraRegionBytes / 4, "staged route within one wavefront row");
 
+// The moves of intra_moves (no dump, every walk) whose first position is i,
+// in two walks of the second position instead of seven: forward (j = i + 1
+// .. L) the 2-opt and same-route swap moves together with the forward or-opt
+// moves of the three segment lengths, backward (j = i - 2 .. 0) the backward
+// or-opt moves, whose middle c_{j+1} .. c_{i-1} is the same for the three
+// lengths.  The walks share their reads of position j; the segment summaries
+// they carry are the ones intra_moves carries (the swap's middle
+// c_{i+1} .. c_{j-1} is the length-1 or-opt middle of the step before), and
+// concatenation is associative, so every feasibility test is the same.
+template <bool TW>
+__device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLds &V, int r, int L, int i,
+                                                  bool capOK, uint32_t op_mask, int &bd, uint32_t &bid) {
+    if (!capOK) return;  // over capacity: no admissible move
+    const bool opSwap = op_mask & 2, op2o = op_mask & 8, opOr = op_mask & 16;
+    const uint32_t uQ = (uint32_t)S.Q;
+    auto ref = [&](int p) { return p == 0 ? (uint32_t)(S.n + r) : (uint32_t)(V.node(p) - 1); };
+    auto segAt = [&](int p) { return seg_node(V.e(p), V.l(p), V.s(p)); };
+    const int eP = V.edge(i - 1), eI = V.edge(i);
+    const int depP = TW ? V.dep(i - 1) : 0;
+    const uint32_t refI = ref(i);
+    // or-opt segments c_i .. c_g (g = i + k - 1), then w = i + k
+    bool okK[3];
+    int baseK[3], dPW[3], zW[3];
+    Seg sig[3];
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        const int g = min(i + k - 1, L);
+        okK[k - 1] = opOr && i + k - 1 <= L;
+        dPW[k - 1] = V.dd(i - 1, g + 1);
+        baseK[k - 1] = dPW[k - 1] - eP - V.edge(g);
+        zW[k - 1] = TW ? V.z(g + 1) : 0;
+        if (TW) sig[k - 1] = k == 1 ? segAt(i) : seg_cat(sig[k - 2], V.edge(g - 1), segAt(g));
+    }
+    // ---- forward: j = i + 1 .. L
+    Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};  // c_i .. c_j reversed
+    Seg m1 = Seg{0, 0, 0, true}, m2 = m1, m3 = m1;  // c_{i+k} .. c_j (k = 1, 2, 3)
+#pragma unroll 1
+    for (int j = i + 1; j <= L; ++j) {
+        const int ej = V.edge(j), ejm = V.edge(j - 1);
+        Seg sj = Seg{0, 0, 0, true};
+        if (TW) {
+            sj = segAt(j);
+            rev = seg_cat(sj, ejm, rev);
+        }
+        const uint32_t refJ = ref(j);
+        if (op2o || opSwap) {
+            const int d1 = V.dd(i - 1, j), d2 = V.dd(i, j + 1);
+            const int dlt2 = d1 + d2 - eP - ej;
+            int dS = dlt2, dA = 0, dB = 0;
+            if (j > i + 1) {
+                dA = V.dd(j, i + 1);
+                dB = V.dd(j - 1, i);
+                dS = d1 + dA + dB + d2 - eP - eI - ejm - ej;
+            }
+            if (min(op2o ? dlt2 : kNoDelta, opSwap ? dS : kNoDelta) <= bd) {
+                bool tw2 = true;
+                if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
+                bool twS = tw2;
+                if (TW && j > i + 1) {
+                    const int arr0 = depP + d1;
+                    bool ok = arr0 <= V.l(j);
+                    const int t0 = max(arr0, V.e(j)) + V.s(j);
+                    const int dM = seg_pass(m1, t0 + dA);  // m1 is c_{i+1} .. c_{j-1} here
+                    const int arrI = dM + dB;
+                    ok = ok && dM < kInf && arrI <= V.l(i);
+                    const int t2 = max(arrI, V.e(i)) + V.s(i);
+                    twS = ok && (t2 + d2 <= V.z(j + 1));
+                }
+                const uint32_t lo = min(refI, refJ), hi = max(refI, refJ);
+                if (op2o && tw2) consider(dlt2, (12u * uQ + lo) * uQ + hi, bd, bid);
+                if (opSwap && twS) consider(dS, (5u * uQ + lo) * uQ + hi, bd, bid);
+            }
+        }
+        if (TW) {
+            m1 = j == i + 1 ? sj : seg_cat(m1, ejm, sj);
+            if (j >= i + 2) m2 = j == i + 2 ? sj : seg_cat(m2, ejm, sj);
+            if (j >= i + 3) m3 = j == i + 3 ? sj : seg_cat(m3, ejm, sj);
+        }
+        if (opOr) {
+            const int dVF = V.dd(j, i);
+#pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                if (!okK[k - 1] || j < i + k) continue;
+                const int dGV = V.dd(i + k - 1, j + 1);
+                const int dlt = baseK[k - 1] + dVF + dGV - ej;
+                if (dlt > bd) continue;
+                bool tw = true;
+                if (TW) {
+                    const Seg &mid = k == 1 ? m1 : (k == 2 ? m2 : m3);
+                    const int dm = seg_pass(mid, depP + dPW[k - 1]);
+                    const int ds = dm >= kInf ? kInf : seg_pass(sig[k - 1], dm + dVF);
+                    tw = ds < kInf && ds + dGV <= V.z(j + 1);
+                }
+                if (tw) consider(dlt, ((16u + k) * uQ + refI) * uQ + refJ, bd, bid);
+            }
+        }
+    }
+    if (!opOr) return;
+    // ---- backward: j = i - 2 .. 0, middle c_{j+1} .. c_{i-1}
+    Seg mid = Seg{0, 0, 0, true};
+#pragma unroll 1
+    for (int j = i - 2; j >= 0; --j) {
+        if (TW) mid = j == i - 2 ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
+        const int dVF = V.dd(j, i), ej = V.edge(j);
+        const int depJ = TW ? V.dep(j) : 0;
+        const uint32_t refJ = ref(j);
+#pragma unroll
+        for (int k = 1; k <= 3; ++k) {
+            if (!okK[k - 1]) continue;
+            const int dGV = V.dd(i + k - 1, j + 1);
+            const int dlt = baseK[k - 1] + dVF + dGV - ej;
+            if (dlt > bd) continue;
+            bool tw = true;
+            if (TW) {
+                const int ds = seg_pass(sig[k - 1], depJ + dVF);
+                const int dmm = ds >= kInf ? kInf : seg_pass(mid, ds + dGV);
+                tw = dmm < kInf && dmm + dPW[k - 1] <= zW[k - 1];
+            }
+            if (tw) consider(dlt, ((16u + k) * uQ + refI) * uQ + refJ, bd, bid);
+        }
+    }
+}
+
 // bits [lo, hi) of a 64-bit word (lo and hi clamped to [0, 64])
 __device__ __forceinline__ unsigned long long bit_range(int lo, int hi) {
     lo = max(lo, 0);
@@ -2619,8 +2742,7 @@ __device__ __forceinline__ void intra_group_flat(const SolDev &S, const IntraIte
             }
             int *b = region + ak;
             const RouteLds V{b, b + pk, b + 2 * pk, b + 3 * pk, b + 4 * pk, b + 5 * pk, b + 6 * pk, b + 7 * pk, pk};
-            intra_moves<TW, false, false>(S, V, item.r0 + myk, pk - 2, myi, 1 << 30, (capOK >> myk) & 1, op_mask, -1,
-                                          nullptr, nullptr, bd, bid);
+            intra_moves_joint<TW>(S, V, item.r0 + myk, pk - 2, myi, (capOK >> myk) & 1, op_mask, bd, bid);
         }
         wave_lds_sync();
         wave_argmin(bd, bid);

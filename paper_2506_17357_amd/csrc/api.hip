@@ -1458,6 +1458,10 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         const long long Q = v[a.sol]->Q, r = a.s1 - a.s0;
         return r * (2 * Q - a.s0 - a.s1 + 1);
     };
+    // a VRPTW pair costs more than a CVRP one (window tests, more routes and
+    // their walks): the XCD placement weighs VRPTW work 1.1, which evens the
+    // XCDs' finishing times on mixed batches
+    auto tw_weight = [&](int i) { return v[i]->h.has_tw ? 1.1 : 1.0; };
     std::vector<std::vector<InterItem>> own(count);
     std::vector<double> sol_work(count, 0.0);
     double total = 0.0;
@@ -1465,7 +1469,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
         if (!v[i]) continue;
         for_each_item(v[i]->Q, c.rows_per_item > 0 ? c.rows_per_item : default_item_rows(trs[i], v[i]->item_rows),
                       [&](int s0, int s1) { own[i].push_back(InterItem{i, s0, s1, 0}); });
-        for (const auto &it : own[i]) sol_work[i] += (double)work(it);
+        for (const auto &it : own[i]) sol_work[i] += (double)work(it) * tw_weight(i);
         total += sol_work[i];
     }
     const double share = total / nx;
@@ -1494,7 +1498,7 @@ static int batch_plan(tga_batch *B, const DevProps &P, hipStream_t st) {
             const int x = least();
             double w = 0.0;
             do {
-                w += (double)work(own[i][k]);
+                w += (double)work(own[i][k]) * tw_weight(i);
                 xitems[x].push_back(own[i][k++]);
             } while (k < own[i].size() && w < piece);
             load[x] += w;

@@ -1760,21 +1760,21 @@ static void batch_eval_launch(tga_batch *B, uint32_t op_mask, bool ls, hipStream
     if (!B->cfg.split) {
         if (cnt)
             k_eval_batch<7><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
-                                                                         B->intra, B->ixoff, B->nx, op_mask, B->steps);
+                                                                         B->intra, B->ixoff, B->nx, op_mask);
         else
             k_eval_batch<3><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
-                                                                         B->intra, B->ixoff, B->nx, op_mask, B->steps);
+                                                                         B->intra, B->ixoff, B->nx, op_mask);
         return;
     }
     if ((op_mask & 7) && cnt)
         k_eval_batch<5><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
-                                                                     B->intra, B->ixoff, B->nx, op_mask, B->steps);
+                                                                     B->intra, B->ixoff, B->nx, op_mask);
     else if (op_mask & 7)
         k_eval_batch<1><<<B->grid_inter, kInterThreads, B->lds, st>>>(B->d, B->items, B->woff, B->qctr,
-                                                                     B->intra, B->ixoff, B->nx, op_mask, B->steps);
+                                                                     B->intra, B->ixoff, B->nx, op_mask);
     if (op_mask & (2 | 8 | 16))
         k_eval_batch<2><<<B->grid_intra, kInterThreads, B->lds_intra, st>>>(
-            B->d, B->items, B->woff, B->qctr, B->intra, B->ixoff, B->nx, op_mask, B->steps);
+            B->d, B->items, B->woff, B->qctr, B->intra, B->ixoff, B->nx, op_mask);
 }
 
 static void batch_finalize_launch(tga_batch *B, uint32_t op_mask, int mode, hipStream_t st) {

@@ -2566,9 +2566,11 @@ __device__ __forceinline__ unsigned long long bit_range(int lo, int hi) {
 // distance blocks themselves (LDS DMA, before it is known whether they are
 // current; a route whose entry turns out stale is then gathered from D over
 // it).  With current entries the staging thus costs one memory round trip
-// after the route offsets instead of several per route.  The moves are then
-// taken one (i, j) cell per lane, the cells of a route laid over the
-// wavefront as rows of L + 1 lanes.  Any other group goes to intra_group.
+// after the route offsets instead of several per route.  The moves of a
+// VRPTW route are then taken by one lane per first position (the joint
+// walks of intra_moves_joint), those of a CVRP route one (i, j) cell per
+// lane (intra_cell), the cells laid over the wavefront as rows of L + 1
+// lanes.  Any other group goes to intra_group.
 template <bool TW>
 __device__ __forceinline__ void intra_group_flat(const SolDev &S, const IntraItem &item, uint32_t op_mask,
                                                  int *region) {
@@ -2894,7 +2896,7 @@ template <int PH>
 __global__ __launch_bounds__(kInterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_batch(
     const SolDev *__restrict__ sols, const InterItem *__restrict__ items, const int *__restrict__ woff,
     uint32_t *__restrict__ qctr, const IntraItem *__restrict__ intra, const int *__restrict__ ixoff, int nx,
-    uint32_t op_mask, const int *__restrict__ steps) {
+    uint32_t op_mask) {
     extern __shared__ int4 smem4[];
     __shared__ unsigned long long red[kInterWaves];
     __shared__ int thr_sh;

@@ -1093,11 +1093,12 @@ __device__ __forceinline__ void wave_share(int Q, int sb, int nr, int wave, int 
 //
 // Each pair first gets the deltas of its four moves only; the feasibility
 // conditions and move ids are evaluated only where some delta is <= the
-// lane's threshold: the smaller of its own best admissible delta and the
-// best any wavefront of the workgroup has published in LDS (thr_sh, read at
-// the start of a run, published at its end) or the solution has committed.
-// Every threshold is the delta of an admissible move of this neighbourhood,
-// so no move that could be the minimum (or tie with it) is ever skipped.
+// run's threshold: the best any wavefront of the workgroup has published in
+// LDS (thr_sh, read at the start of a run; each wavefront publishes its own
+// best at the end of a run) or the solution has committed, bounded by the
+// initial bound.  Every threshold is the delta of an admissible move of this
+// neighbourhood (or the bound), so no move that could be the minimum (or tie
+// with it) is ever skipped.
 // With dump arrays every move is evaluated.  smem4 is the dynamic LDS area;
 // red holds kInterWaves keys.
 template <bool TW, bool DUMP, bool W16, bool CNT = false>
@@ -1207,6 +1208,12 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 uint32_t ro = (uint32_t)x * 16u;  // byte offset of row x's slot attributes
                 int4 ra = sld_at(S.a4, ro), rb = sld_at(S.b4, ro);
                 const int thrRun = DUMP ? 0 : __hip_atomic_load(thr_sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // The passes screen against the run's threshold alone (the delta
+                // of an admissible move, or the initial bound): a lane's own
+                // better move found during the run tightens it only from the
+                // next run, which saves an instruction per pass and lets a few
+                // more pairs into the full evaluation.
+                const int thrScreen = min(thrRun, initial_bound(op_mask));
                 // Each pass first consumes what the previous one fetched, then
                 // fetches row x + 1 (attributes) and the gather of row x + 2,
                 // then evaluates row x from registers (the rare full
@@ -1223,7 +1230,7 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                     const int gL = from_prev_lane(w0);  // D[s][pred(t)]
                     bool full = true;
                     if (!DUMP) {
-                        const int thr = min(bd, thrRun);
+                        const int thr = thrScreen;
                         const int wz = wn - rA.z;  // shared by RELOCATE t -> s and 2OPT*
                         const int d1 = w0 + gR + (L.cRel + rA.w);
                         const int d2 = w0 + wz + L.cRel2;

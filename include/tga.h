@@ -235,7 +235,8 @@ int tga_eval_routes_static(tga_instance_t inst, int32_t R, const int32_t *offset
  * rebuild every attribute.  The move need not be improving or admissible.
  * Returns TGA_ESTALE if move->version is not the solution's current version
  * (checked on the host) and TGA_EINVAL if move->id is not a move of N(S):
- * ids of 20*Q*Q or more are refused on the host; whether a smaller id names
+ * ids of 40*Q*Q or more (beyond the ten operators' id range) are refused on
+ * the host; whether a smaller id names
  * a move of the current routes is decided on the device by the launch that
  * would apply it, which then leaves the solution unchanged.  On success the
  * version increases by one and *new_cost (nullable) receives the total

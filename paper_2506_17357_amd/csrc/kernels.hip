@@ -1218,8 +1218,8 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 // fetches row x + 1 (attributes) and the gather of row x + 2,
                 // then evaluates row x from registers (the rare full
                 // evaluation also reads the row's time attributes).  Passes
-                // go in pairs so that the two sets of row attributes take
-                // turns without copies.
+                // go in fours so that the two sets of row attributes and the
+                // four window registers take turns without copies.
                 auto pass = [&](const int4 &rA, const int4 &rB, int4 &rAn, int4 &rBn, int wp, int w0, int wn,
                                 int &wnn) {
                     pp = min(pp + rs, rowsLast);
@@ -1266,14 +1266,16 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 };
                 int4 ra2, rb2;
                 int g3 = 0;
+                // four passes per iteration: the four window registers take
+                // turns, so the window is back in gp, g, gn without copies
                 while (x < xlim) {
-                    pass(ra, rb, ra2, rb2, gp, g, gn, g3);
+                    pass(ra, rb, ra2, rb2, gp, g, gn, g3);  // rows x - 1, x, x + 1; fetches x + 2
                     if (x >= xlim) break;
                     pass(ra2, rb2, ra, rb, g, gn, g3, gp);
-                    const int w1 = gn;  // window (rows x - 1, x, x + 1) back in gp, g, gn
-                    gn = gp;
-                    gp = w1;
-                    g = g3;
+                    if (x >= xlim) break;
+                    pass(ra, rb, ra2, rb2, gn, g3, gp, g);
+                    if (x >= xlim) break;
+                    pass(ra2, rb2, ra, rb, g3, gp, g, gn);
                 }
                 // publish this wavefront's best to the workgroup (one lane, one
                 // LDS atomic, only when some lane improved on the shared value)

@@ -20,6 +20,7 @@
 // segments of intra-route moves.
 
 #include "tga_internal.h"
+#include <type_traits>
 
 namespace tga {
 
@@ -2469,11 +2470,14 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
         zW[k - 1] = TW ? V.z(g + 1) : 0;
         if (TW) sig[k - 1] = k == 1 ? segAt(i) : seg_cat(sig[k - 2], V.edge(g - 1), segAt(g));
     }
-    // ---- forward: j = i + 1 .. L
+    // ---- forward: j = i + 1 .. L.  The step is written once; the first
+    // three steps (where the or-opt middles start) are peeled with their
+    // offset PH = j - i known at compile time, so that the main loop updates
+    // every summary unconditionally.
     Seg rev = TW ? segAt(i) : Seg{0, 0, 0, true};  // c_i .. c_j reversed
     Seg m1 = Seg{0, 0, 0, true}, m2 = m1, m3 = m1;  // c_{i+k} .. c_j (k = 1, 2, 3)
-#pragma unroll 1
-    for (int j = i + 1; j <= L; ++j) {
+    auto fwd = [&](int j, auto phc) {
+        constexpr int PH = decltype(phc)::value;  // j - i, or 4 for any j >= i + 4
         const int ej = V.edge(j), ejm = V.edge(j - 1);
         Seg sj = Seg{0, 0, 0, true};
         if (TW) {
@@ -2485,7 +2489,7 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
             const int d1 = V.dd(i - 1, j), d2 = V.dd(i, j + 1);
             const int dlt2 = d1 + d2 - eP - ej;
             int dS = dlt2, dA = 0, dB = 0;
-            if (j > i + 1) {
+            if (PH > 1) {
                 dA = V.dd(j, i + 1);
                 dB = V.dd(j - 1, i);
                 dS = d1 + dA + dB + d2 - eP - eI - ejm - ej;
@@ -2494,7 +2498,7 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
                 bool tw2 = true;
                 if (TW) tw2 = seg_pass(rev, depP + d1) + d2 <= V.z(j + 1);
                 bool twS = tw2;
-                if (TW && j > i + 1) {
+                if (TW && PH > 1) {
                     const int arr0 = depP + d1;
                     bool ok = arr0 <= V.l(j);
                     const int t0 = max(arr0, V.e(j)) + V.s(j);
@@ -2510,15 +2514,15 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
             }
         }
         if (TW) {
-            m1 = j == i + 1 ? sj : seg_cat(m1, ejm, sj);
-            if (j >= i + 2) m2 = j == i + 2 ? sj : seg_cat(m2, ejm, sj);
-            if (j >= i + 3) m3 = j == i + 3 ? sj : seg_cat(m3, ejm, sj);
+            m1 = PH == 1 ? sj : seg_cat(m1, ejm, sj);
+            if (PH >= 2) m2 = PH == 2 ? sj : seg_cat(m2, ejm, sj);
+            if (PH >= 3) m3 = PH == 3 ? sj : seg_cat(m3, ejm, sj);
         }
         if (opOr) {
             const int dVF = V.dd(j, i);
 #pragma unroll
             for (int k = 1; k <= 3; ++k) {
-                if (!okK[k - 1] || j < i + k) continue;
+                if (!okK[k - 1] || PH < k) continue;
                 const int dGV = V.dd(i + k - 1, j + 1);
                 const int dlt = baseK[k - 1] + dVF + dGV - ej;
                 if (dlt > bd) continue;
@@ -2532,13 +2536,18 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
                 if (tw) consider(dlt, ((16u + k) * uQ + refI) * uQ + refJ, bd, bid);
             }
         }
-    }
-    if (!opOr) return;
-    // ---- backward: j = i - 2 .. 0, middle c_{j+1} .. c_{i-1}
-    Seg mid = Seg{0, 0, 0, true};
+    };
+    if (i + 1 <= L) fwd(i + 1, std::integral_constant<int, 1>{});
+    if (i + 2 <= L) fwd(i + 2, std::integral_constant<int, 2>{});
+    if (i + 3 <= L) fwd(i + 3, std::integral_constant<int, 3>{});
 #pragma unroll 1
-    for (int j = i - 2; j >= 0; --j) {
-        if (TW) mid = j == i - 2 ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
+    for (int j = i + 4; j <= L; ++j) fwd(j, std::integral_constant<int, 4>{});
+    if (!opOr) return;
+    // ---- backward: j = i - 2 .. 0, middle c_{j+1} .. c_{i-1} (the first
+    // step, where the middle is c_{i-1} alone, peeled as above)
+    Seg mid = Seg{0, 0, 0, true};
+    auto bwd = [&](int j, auto firstc) {
+        if (TW) mid = decltype(firstc)::value ? segAt(i - 1) : seg_cat(segAt(j + 1), V.edge(j + 1), mid);
         const int dVF = V.dd(j, i), ej = V.edge(j);
         const int depJ = TW ? V.dep(j) : 0;
         const uint32_t refJ = ref(j);
@@ -2556,7 +2565,10 @@ __device__ __forceinline__ void intra_moves_joint(const SolDev &S, const RouteLd
             }
             if (tw) consider(dlt, ((16u + k) * uQ + refI) * uQ + refJ, bd, bid);
         }
-    }
+    };
+    if (i - 2 >= 0) bwd(i - 2, std::true_type{});
+#pragma unroll 1
+    for (int j = i - 3; j >= 0; --j) bwd(j, std::false_type{});
 }
 
 // bits [lo, hi) of a 64-bit word (lo and hi clamped to [0, 64])

@@ -1269,14 +1269,18 @@ __device__ __forceinline__ void inter_item(const SolDev &S, const InterItem &ite
                 int g3 = 0;
                 // four passes per iteration: the four window registers take
                 // turns, so the window is back in gp, g, gn without copies
-                while (x < xlim) {
+                for (int q = (xlim - x) >> 2; q > 0; --q) {  // whole groups of four rows
                     pass(ra, rb, ra2, rb2, gp, g, gn, g3);  // rows x - 1, x, x + 1; fetches x + 2
-                    if (x >= xlim) break;
                     pass(ra2, rb2, ra, rb, g, gn, g3, gp);
-                    if (x >= xlim) break;
                     pass(ra, rb, ra2, rb2, gn, g3, gp, g);
-                    if (x >= xlim) break;
                     pass(ra2, rb2, ra, rb, g3, gp, g, gn);
+                }
+                if (x < xlim) {  // the last one to three rows
+                    pass(ra, rb, ra2, rb2, gp, g, gn, g3);
+                    if (x < xlim) {
+                        pass(ra2, rb2, ra, rb, g, gn, g3, gp);
+                        if (x < xlim) pass(ra, rb, ra2, rb2, gn, g3, gp, g);
+                    }
                 }
                 // publish this wavefront's best to the workgroup (one lane, one
                 // LDS atomic, only when some lane improved on the shared value)

@@ -3,7 +3,10 @@
 Requests (an instance, a starting solution, a step cap) arrive over time.
 A request is admitted, first come first served, when its device bytes
 (distance matrix, node data, instance and solution workspaces) fit in the
-HBM budget still free and a slot of the engine is free.  Upload threads
+HBM budget still free and a slot of the engine is free.  Requests that
+arrive at the same time are taken largest first (most distance-matrix
+entries times step cap: the longest runs start first, so none of them
+starts late and runs on alone at the end).  Upload threads
 (each with its own copy stream) copy its data to the device while the
 compute stream keeps stepping the requests already there.
 
@@ -127,7 +130,8 @@ class Server:
     # ------------------------------------------------------------------ run
     def run(self, requests: list[ServeRequest], log=None) -> list[ServeResult]:
         """Serve every request in real time (arrival_s relative to the start)."""
-        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival_s, -(r.inst.n + 1) ** 2 * r.max_steps,
+                                                                   r.rid)))
         waiting: collections.deque = collections.deque()
         todo: queue_mod.Queue = queue_mod.Queue()
         ready: queue_mod.Queue = queue_mod.Queue()

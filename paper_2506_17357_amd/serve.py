@@ -83,14 +83,17 @@ class Server:
         self.device = device
         self.max_sum_q = int(max_sum_q)
         self.max_sum_r = int(max_sum_r)
-        # Engine schedule: by default the largest LDS budget per inter-route
-        # workgroup that still lets two of them share a compute unit, one
-        # launch per step (what the batch autotuner picks on full batches;
-        # autotuning the engine on the few members present early in a run
-        # picked smaller budgets that were slower once the engine filled up).
-        # autotune=True tunes once instead, when eight members are present.
+        # Engine schedule: by default the whole LDS for one inter-route
+        # workgroup per compute unit, one launch per step.  Requests of 5000
+        # to 10^4 customers then get two to three times the rows per
+        # sub-block that half the LDS gives (at 10^4: 6 against 2), which
+        # matters more for the served mix than a second workgroup per compute
+        # unit; autotuning the engine on the few members
+        # present early in a run had picked smaller budgets that were slower
+        # once the engine filled up.  autotune=True tunes once instead, when
+        # eight members are present.
         if schedule is None and not autotune:
-            schedule = {"lds_kb": tga.device_limits()[1] // 2 // 1024, "split": 0}
+            schedule = {"lds_kb": tga.device_limits()[1] // 1024, "split": 0}
         self.autotune = autotune and schedule is None
         self.schedule = schedule
         self.ticks_ahead = int(ticks_ahead)

@@ -66,6 +66,26 @@ def test_tick_length_does_not_change_results(env, steps_per_tick):
         assert r.customers.tolist() == cust.tolist()
 
 
+@pytest.mark.parametrize("half", [False, True])
+def test_engine_schedule_does_not_change_results(env, half):
+    """The engine on the whole LDS (the default) and on half of it (two
+    inter-route workgroups per compute unit, fewer rows per sub-block), with
+    requests that arrive together (taken largest first): results equal each
+    request's own run."""
+    tga, serve = env
+    reqs = make_requests(serve, count=6, seed=5, gap_s=0.0, max_steps=30, lo=200, hi=1200)
+    whole = tga.device_limits()[1] // 1024
+    sch = {"lds_kb": whole // 2 if half else whole, "split": 0}
+    print("engine schedule", sch, flush=True)
+    srv = serve.Server(hbm_budget_bytes=1 << 32, schedule=sch)
+    res = srv.run(reqs)
+    assert srv.config["lds_kb"] == sch["lds_kb"]
+    for r, req in zip(res, reqs):
+        steps, moves, cost, off, cust = alone(tga, req)
+        assert (r.steps, r.moves, r.cost) == (steps, moves, cost), (sch, r.rid)
+        assert r.customers.tolist() == cust.tolist()
+
+
 def test_admission_respects_budget(env):
     tga, serve = env
     reqs = make_requests(serve, count=8, seed=1, gap_s=0.0, max_steps=40)

@@ -1349,8 +1349,11 @@ extern "C" size_t tga_batch_workspace_bytes(const tga_solution_t *sols, int32_t 
 // LDS sub-block, or for large solutions (fewer than kItemRowsMin rows per
 // sub-block) several whole sub-blocks, so that the two boundary rows carried
 // from one sub-block to the next spare re-reading them (a one-row sub-block
-// would otherwise read every row three times).
-constexpr int kItemRowsMin = 16;
+// would otherwise read every row three times).  No more than that: a single
+// solution of 10^4 customers on the whole LDS (6-row sub-blocks) evaluates
+// in 147 us with 12-row items against 162 us with 18-row ones, which leave
+// its 256 workgroups about two items each.
+constexpr int kItemRowsMin = 12;
 static int default_item_rows(int tile_rows, int tuned) {
     if (tuned > 0)  // tuned: thin items within one sub-block, else whole sub-blocks
         return tuned <= tile_rows ? tuned : tile_rows * ((tuned + tile_rows - 1) / tile_rows);

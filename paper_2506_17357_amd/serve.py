@@ -88,10 +88,10 @@ class Server:
         # to 10^4 customers then get two to three times the rows per
         # sub-block that half the LDS gives (at 10^4: 6 against 2), which
         # matters more for the served mix than a second workgroup per compute
-        # unit; autotuning the engine on the few members
-        # present early in a run had picked smaller budgets that were slower
-        # once the engine filled up.  autotune=True tunes once instead, when
-        # eight members are present.
+        # unit.  Autotuning the engine on the few members present early in a
+        # run had picked smaller budgets that were slower once the engine
+        # filled up; autotune=True tunes once instead, when eight members are
+        # present.
         if schedule is None and not autotune:
             schedule = {"lds_kb": tga.device_limits()[1] // 1024, "split": 0}
         self.autotune = autotune and schedule is None

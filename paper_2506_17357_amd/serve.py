@@ -71,6 +71,13 @@ def device_bytes(inst, R: int) -> int:
             + int(L.tga_solution_workspace_bytes(inst.n, R)))
 
 
+def admission_order(requests):
+    """Requests in the order they are considered for admission: by arrival
+    time, and among requests that arrive together the largest first (most
+    distance-matrix entries times step cap), then by request id."""
+    return sorted(requests, key=lambda r: (r.arrival_s, -(r.inst.n + 1) ** 2 * r.max_steps, r.rid))
+
+
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
                  device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
@@ -133,8 +140,7 @@ class Server:
     # ------------------------------------------------------------------ run
     def run(self, requests: list[ServeRequest], log=None) -> list[ServeResult]:
         """Serve every request in real time (arrival_s relative to the start)."""
-        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival_s, -(r.inst.n + 1) ** 2 * r.max_steps,
-                                                                   r.rid)))
+        pending = collections.deque(admission_order(requests))
         waiting: collections.deque = collections.deque()
         todo: queue_mod.Queue = queue_mod.Queue()
         ready: queue_mod.Queue = queue_mod.Queue()

@@ -571,7 +571,7 @@ def main():
     ap.add_argument("--served", action="store_true", help="benchmark the served form instead")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--served-steps", type=int, default=500)
-    ap.add_argument("--steps-per-tick", type=int, default=2,
+    ap.add_argument("--steps-per-tick", type=int, default=4,
                     help="served form: local-search steps per scheduling tick (one poll per tick)")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     ap.add_argument("--served-leg-requests", type=int, default=100,

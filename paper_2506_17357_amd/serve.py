@@ -80,7 +80,7 @@ def admission_order(requests):
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, op_mask: int = tga.OPS_ALL,
-                 device: str = "cuda", steps_per_tick: int = 2, max_sum_q: int = 1 << 20,
+                 device: str = "cuda", steps_per_tick: int = 4, max_sum_q: int = 1 << 20,
                  max_sum_r: int = 1 << 17, autotune: bool = False, ticks_ahead: int = 2,
                  upload_workers: int = 4, schedule: dict | None = None):
         self.budget = int(hbm_budget_bytes)
